@@ -1,0 +1,199 @@
+/*
+ * msc.h - C ABI of the MI355X staged reach / path solver.
+ *
+ * The solver implements the data-parallel search of the gap map-seeking arm method
+ * (Arathorn, arXiv 1906.10678) on a voxel grid:
+ *   - an arm is a chain of segments whose directions are azimuth / elevation in the
+ *     global frame (Introduction, eq 1 and its vector-sum form);
+ *   - obstacles are a voxel grid, dilated for arm thickness (section "The
+ *     representations of the arm and obstacles", Fig 4);
+ *   - a segment collides if any of its S equally spaced sample points falls in a
+ *     blocked voxel (section "Testing for collisions");
+ *   - the reachable (joint voxel, orientation) states are expanded stage by stage
+ *     from the root (forward pathway) and from the target (backward pathway) and
+ *     intersected (section "The gap in gMS", eqs 5-8 for the distance pruning;
+ *     "The procedure for IK solution", Steps 1-3);
+ *   - one survivor is chosen as the reach pose, and a smooth waypoint path to it
+ *     is searched backward from the reach pose (sections "Smooth sequence
+ *     computation" and "Filtering for smoothness").
+ *
+ * Units and conventions
+ *   - Voxel coordinates are integers 0..n-1 per axis; x east, y north, z up.
+ *   - Angles are int32 centidegrees.  step_cdeg must divide 36000 and the number of
+ *     orientation bins 36000/step_cdeg must be <= 256.  Joint limits, the initial
+ *     orientation and start poses must be multiples of step_cdeg.
+ *   - A yaw joint adds its angle to the segment azimuth, a pitch joint to the
+ *     elevation; segment k points along (cos el cos az, cos el sin az, sin el).
+ *   - Segment mappings and sample points are rounded to the nearest voxel, exact
+ *     halves away from zero.
+ *
+ * Ownership
+ *   - Every input pointer is read during the call and not retained.
+ *   - Handles are created by *_create and released by *_destroy.
+ *   - Output pointers are caller-allocated host buffers of the documented size.
+ *   - Device memory is caller-provided: msc_ctx_create receives a device workspace
+ *     and msc_scene_create a device buffer for the occupancy grid.  The library
+ *     sub-allocates from them and calls no device allocator of its own.
+ *
+ * Errors
+ *   - 0 = success; positive = a valid "no answer" result; negative = error.
+ *   - On a negative status nothing is written to the outputs and msc_last_error()
+ *     returns a message.  No C++ exception crosses this interface.
+ *
+ * Synchronisation
+ *   - All device work is enqueued on the stream given to msc_ctx_create.  Every call
+ *     below returns after its results are on the host.
+ *   - One context per host thread; calls on one context must not overlap.
+ */
+#ifndef MSC_H
+#define MSC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MSC_MAX_DOF 16
+
+typedef enum {
+    MSC_OK = 0,          /* solution written */
+    MSC_NO_REACH = 1,    /* no pose reaches the target (empty surviving set) */
+    MSC_NO_PATH = 2,     /* reach poses exist, but no tube path within the retries */
+    MSC_E_ARG = -1,      /* invalid argument */
+    MSC_E_NOMEM = -2,    /* workspace or grid buffer too small */
+    MSC_E_HIP = -3,      /* HIP runtime error */
+    MSC_E_CAPACITY = -4, /* an internal table overflowed its planned capacity */
+    MSC_E_STATE = -5     /* call not valid in the current state */
+} msc_status;
+
+typedef enum { MSC_YAW = 0, MSC_PITCH = 1 } msc_joint;
+
+/* Arm chain.  Joint k (0-based) turns by an angle in [lo_cdeg[k], hi_cdeg[k]] and is
+ * followed by segment k of len_vox[k] voxels (>= 0).  dof in 1..MSC_MAX_DOF;
+ * samples (collision points per segment, S) >= 1; base = root voxel; the chain starts
+ * with azimuth az0_cdeg and elevation el0_cdeg (9000 = straight up). */
+typedef struct {
+    int32_t dof, step_cdeg, samples;
+    int32_t base[3];
+    int32_t az0_cdeg, el0_cdeg;
+    int32_t type[MSC_MAX_DOF];
+    int32_t len_vox[MSC_MAX_DOF];
+    int32_t lo_cdeg[MSC_MAX_DOF];
+    int32_t hi_cdeg[MSC_MAX_DOF];
+} msc_arm;
+
+/* Axis-aligned box covering voxels lo .. lo+ext-1 per axis (ext >= 1). */
+typedef struct { int32_t lo[3], ext[3]; } msc_box;
+/* Sphere of voxels within distance r of centre c (r >= 0). */
+typedef struct { int32_t c[3], r; } msc_sphere;
+
+#define MSC_CAPTURE_SETS 1u /* keep every stage set for msc_debug_set */
+#define MSC_NO_PRUNE 2u     /* disable the distance / orientation pruning (tests) */
+
+typedef struct {
+    int32_t split_m;       /* forward stages before the join: -1 = adaptive, else 0..dof */
+    int32_t tube_r0;       /* first tube radius of the path search, in steps (default 1) */
+    int32_t tube_r1;       /* relaxed tube radius after a failure (default 2) */
+    int32_t reach_retries; /* reach poses tried by msc_path, in canonical order (default 4) */
+    uint32_t flags;        /* MSC_CAPTURE_SETS | MSC_NO_PRUNE */
+} msc_opts;
+
+typedef struct msc_ctx msc_ctx;
+typedef struct msc_scene msc_scene;
+
+/* Fill *opts with the defaults {-1, 1, 2, 4, 0}. */
+void msc_opts_default(msc_opts* opts);
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream` (a hipStream_t,
+ * may be NULL for the null stream) and sub-allocates device memory from
+ * [dev_workspace, dev_workspace + ws_bytes) (256-byte aligned).  The workspace must stay
+ * valid until msc_ctx_destroy.  E_ARG if a pointer is NULL or ws_bytes < 64 MiB. */
+msc_status msc_ctx_create(int device, void* hip_stream, void* dev_workspace, uint64_t ws_bytes,
+                          msc_ctx** out);
+msc_status msc_ctx_destroy(msc_ctx* ctx);
+
+/* Device bytes needed by the occupancy grid of an n^3 scene. */
+uint64_t msc_scene_bytes(int32_t n);
+
+/* Rasterise a scene into the caller's device buffer dev_grid (msc_scene_bytes(n) bytes):
+ * a voxel is blocked when it lies within Euclidean distance dilate_r of a box or within
+ * r + dilate_r of a sphere centre ("The representations of the arm and obstacles":
+ * obstacles masked in a voxel array, dilated for thickness and clearance).  Voxels
+ * outside the grid count as blocked.  The grid is bit-packed, 64 x-voxels per 64-bit
+ * word, rows (z, y).  n in 1..1024, dilate_r >= 0. */
+msc_status msc_scene_create(msc_ctx* ctx, int32_t n, int32_t dilate_r, const msc_box* boxes,
+                            int32_t nbox, const msc_sphere* spheres, int32_t nsph, void* dev_grid,
+                            uint64_t grid_bytes, msc_scene** out);
+msc_status msc_scene_destroy(msc_scene* scene);
+
+/* Reach pose ("The procedure for IK solution", Steps 1-3).  Writes the first pose of
+ * the canonical order into angles_out[dof] (centidegrees): joint tuples ordered
+ * lexicographically, joint 1 first, each joint by |angle| then angle.  Returns
+ * MSC_NO_REACH if no pose ends on the target with every segment clear (also when the
+ * base or the target voxel is blocked).  opts may be NULL for the defaults. */
+msc_status msc_reach(msc_ctx* ctx, const msc_scene* scene, const msc_arm* arm,
+                     const int32_t target[3], const msc_opts* opts, int32_t* angles_out);
+
+/* Reach pose + smooth path ("Path Planning", "Smooth sequence computation",
+ * "Filtering for smoothness").  start_cdeg[dof] must be a valid pose within the limits.
+ * Every joint is limited to start +- waypoints*max_delta for the reach search, whose
+ * canonical order is centred on the start pose; the path is searched in a tube around
+ * the straight joint-space guide from the start to the reach pose, each move changing
+ * every joint by at most max_delta_cdeg, chosen backward from the reach pose (closest
+ * to the guide, L1 in steps, ties by joint values); the tube radius is relaxed from
+ * tube_r0 to tube_r1 after a failure, then the next reach pose is tried, up to
+ * reach_retries.  path_out receives (waypoints+1)*dof centidegrees, row 0 = start,
+ * last row = reach pose.  max_delta_cdeg must be a positive multiple of step_cdeg.
+ * Returns MSC_NO_REACH or MSC_NO_PATH when no result exists. */
+msc_status msc_path(msc_ctx* ctx, const msc_scene* scene, const msc_arm* arm,
+                    const int32_t* start_cdeg, const int32_t target[3], int32_t waypoints,
+                    int32_t max_delta_cdeg, const msc_opts* opts, int32_t* path_out);
+
+/* Forward-kinematics replay of `count` poses (poses_cdeg[count*dof]) on the GPU:
+ * valid_out[i] = 1 if the base is free and every segment sample is inside the grid
+ * and free, else 0; end_out[i*3..] = end voxel of the chain (computed even when
+ * invalid).  end_out may be NULL. */
+msc_status msc_pose_check(msc_ctx* ctx, const msc_scene* scene, const msc_arm* arm,
+                          const int32_t* poses_cdeg, int64_t count, uint8_t* valid_out,
+                          int32_t* end_out);
+
+/* Statistics of the last msc_reach / msc_path call on this context. */
+typedef struct {
+    int32_t split_m;                     /* split actually used */
+    int32_t dof;
+    int64_t fwd_count[MSC_MAX_DOF + 1];  /* |F_k|, k = 0..split_m */
+    int64_t bwd_count[MSC_MAX_DOF + 1];  /* |B_k|, k = split_m..dof */
+    int64_t join_count;                  /* |C_m| */
+    int32_t fwd_dense[MSC_MAX_DOF + 1];  /* 1 if F_k used a dense bitset, 0 if a hash set */
+    int32_t bwd_dense[MSC_MAX_DOF + 1];
+    int32_t attempts;                    /* path: tube searches run */
+    int32_t tube_r;                      /* path: tube radius of the returned path */
+    int32_t reach_index;                 /* path: index of the reach pose used (0 = first) */
+} msc_stats;
+msc_status msc_get_stats(msc_ctx* ctx, msc_stats* out);
+
+/* Debug: the tables of segment `stage` of arm (0-based), as built on the device:
+ * off[(ia*na + ie)*3 + c] = rounded segment offset, sweep[((ia*na + ie)*S + s)*3 + c]
+ * = rounded sample point s+1 of S, na = 36000/step_cdeg. */
+msc_status msc_debug_tables(msc_ctx* ctx, const msc_arm* arm, int32_t stage, int32_t* off,
+                            int32_t* sweep);
+
+/* Debug: copy the occupancy grid as one byte per voxel, index (z*n + y)*n + x, 1 = blocked. */
+msc_status msc_debug_raster(msc_ctx* ctx, const msc_scene* scene, uint8_t* occ_out);
+
+/* Debug: a stage set of the last msc_reach run with MSC_CAPTURE_SETS.  which: 0 = F_k
+ * (forward, k <= split), 1 = B_k (backward, k >= split), 2 = C (join, stage ignored),
+ * 3 = D_k (forward states on some solution).  Writes min(cap, size) keys, sorted
+ * ascending, key = ((z*n + y)*n + x) << 16 | ia << 8 | ie, and *count = size. */
+msc_status msc_debug_set(msc_ctx* ctx, int32_t which, int32_t stage, uint64_t* keys, uint64_t cap,
+                         uint64_t* count);
+
+/* Message of the last negative status on this context ("" if none). */
+const char* msc_last_error(msc_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MSC_H */

@@ -1,0 +1,239 @@
+"""Pins of the oracle's staged reach search.
+
+The staged search ("The procedure for IK solution": Step 1 forward from the root,
+Step 2 on to the gap, the backward pathway from the target of "The gap in gMS",
+distance pruning after eqs 5-8, Step 3 choosing one survivor) must reach exactly
+the plain definition: the set of joint tuples whose replay is clear and ends on the
+target, and its first element in the canonical order.  These tests check it
+against exhaustive enumeration on tiny arms and against invariants that hold at any
+size.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1906_10678_amd import synth
+
+from cases import tiny_case
+
+
+def pick_target(arm, scene, rng, occ, reachable=True):
+    """End voxel of the first valid drawn pose, or (reachable=False) a uniform voxel."""
+    q = synth.candidate_poses(rng, arm, 256)
+    if not reachable:
+        return tuple(int(v) for v in rng.integers(0, scene.n, size=3))
+    valid, ends = oracle.poses(arm, occ, q)
+    if valid.any():
+        return tuple(int(v) for v in ends[np.flatnonzero(valid)[0]])
+    return tuple(int(v) for v in ends[0])
+
+
+TINY = [(s, dof, step) for s in range(8) for dof, step in [(2, 3000), (3, 3000), (3, 4500), (4, 4500), (5, 4500), (5, 3000)]]
+
+
+@pytest.mark.parametrize("seed,dof,step", TINY)
+def test_canonical_pose_matches_brute_force(seed, dof, step):
+    arm, scene, rng = tiny_case(seed, dof, step)
+    occ = oracle.raster(scene)
+    target = pick_target(arm, scene, rng, occ, reachable=(seed % 4 != 3))
+    cnt, sols = oracle.brute_solutions(arm, occ, target, cap=6)
+    for m in range(dof + 1):
+        r = oracle.reach(arm, occ, target, m=m, want=6)
+        assert (r.status == oracle.OK) == (cnt > 0)
+        # exists <=> the join is not empty
+        assert (len(r.sets[("C", m)]) > 0) == (cnt > 0)
+        assert np.array_equal(r.sols, sols), (m, r.sols, sols)
+
+
+@pytest.mark.parametrize("seed,dof,step", TINY[:16])
+@pytest.mark.parametrize("prune", [True, False])
+def test_stage_sets_match_enumeration(seed, dof, step, prune):
+    """Per-stage sets with de-duplication equal the sets of prefix ends (forward) and
+    suffix starts (backward) found by exhaustive enumeration without staging."""
+    arm, scene, rng = tiny_case(seed, dof, step)
+    occ = oracle.raster(scene)
+    target = pick_target(arm, scene, rng, occ)
+    brute = oracle.brute_sets(arm, occ, target, kf=dof, kb=0, prune=prune)
+    for m in range(dof + 1):
+        r = oracle.reach(arm, occ, target, m=m, prune=prune)
+        for k in range(m + 1):
+            assert np.array_equal(r.sets[("F", k)], brute[("F", k)]), ("F", k, m)
+        for k in range(m, dof + 1):
+            assert np.array_equal(r.sets[("B", k)], brute[("B", k)]), ("B", k, m)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_pruning_never_changes_the_answer(seed):
+    arm, scene, rng = tiny_case(seed, 4, 4500)
+    occ = oracle.raster(scene)
+    target = pick_target(arm, scene, rng, occ)
+    a = oracle.reach(arm, occ, target, m=2, want=4, prune=True)
+    b = oracle.reach(arm, occ, target, m=2, want=4, prune=False)
+    assert a.status == b.status and np.array_equal(a.sols, b.sols)
+    # pruned sets are subsets of the unpruned ones
+    for key, v in a.sets.items():
+        assert np.isin(v, b.sets[key]).all()
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_d_sets_are_states_on_solutions(seed):
+    """D_k = forward states that lie on some solution: exactly the stage-k states of
+    the replays of all solution tuples."""
+    arm, scene, rng = tiny_case(seed, 3, 3000)
+    occ = oracle.raster(scene)
+    target = pick_target(arm, scene, rng, occ)
+    cnt, sols = oracle.brute_solutions(arm, occ, target, cap=1 << 16)
+    r = oracle.reach(arm, occ, target, m=3)
+    n = scene.n
+    na = 36000 // arm.step_cdeg
+    for k in range(4):
+        keys = set()
+        for q in sols:
+            ok, joints = oracle.pose_joints(arm, occ, q)
+            ia, ie = arm.az0_cdeg // arm.step_cdeg, arm.el0_cdeg // arm.step_cdeg
+            for j in range(k):
+                if arm.types[j] == synth.YAW:
+                    ia = (ia + q[j]) % na
+                else:
+                    ie = (ie + q[j]) % na
+            x, y, z = joints[k]
+            keys.add((((int(z) * n + int(y)) * n + int(x)) << 16) | (ia << 8) | ie)
+        assert sorted(keys) == [int(v) for v in r.sets[("D", k)]]
+
+
+def test_blocked_target_or_base_is_no_reach():
+    arm, scene, rng = tiny_case(0, 3, 3000)
+    occ = oracle.raster(scene)
+    t = pick_target(arm, scene, rng, occ)
+    occ2 = occ.copy()
+    occ2[t[2], t[1], t[0]] = 1
+    assert oracle.reach(arm, occ2, t).status == oracle.NO_REACH
+    occ3 = occ.copy()
+    b = arm.base
+    occ3[b[2], b[1], b[0]] = 1
+    assert oracle.reach(arm, occ3, t).status == oracle.NO_REACH
+
+
+def test_target_sealed_in_a_shell_is_no_reach():
+    arm, scene, rng = tiny_case(1, 3, 3000)
+    occ = oracle.raster(scene)
+    t = pick_target(arm, scene, rng, occ)
+    occ2 = occ.copy()
+    x, y, z = t
+    sl = occ2[max(z - 1, 0):z + 2, max(y - 1, 0):y + 2, max(x - 1, 0):x + 2]
+    sl[...] = 1
+    occ2[z, y, x] = 0
+    assert oracle.reach(arm, occ2, t).status == oracle.NO_REACH
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_monotone_in_obstacles(seed):
+    """Adding an obstacle never adds a state."""
+    arm, scene, rng = tiny_case(seed, 3, 3000, nbox=2)
+    occ = oracle.raster(scene)
+    t = pick_target(arm, scene, rng, occ)
+    more = synth.Scene(n=scene.n, dilate=scene.dilate,
+                       boxes=np.concatenate([scene.boxes, np.array([[3, 3, 5, 4, 4, 4]], np.int32)]),
+                       spheres=scene.spheres)
+    occ2 = oracle.raster(more)
+    occ2[t[2], t[1], t[0]] = occ[t[2], t[1], t[0]]
+    b = arm.base
+    occ2[b[2], b[1], b[0]] = occ[b[2], b[1], b[0]]
+    a = oracle.reach(arm, occ, t, m=2, prune=False)
+    c = oracle.reach(arm, occ2, t, m=2, prune=False)
+    for key in a.sets:
+        assert np.isin(c.sets[key], a.sets[key]).all(), key
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_mirror_symmetry(seed):
+    """Reflecting the scene, base and target in the plane y = base_y maps every state
+    (x, y, z, ia, ie) to (x, 2*base_y - y, z, -ia, ie) when the joint windows are
+    symmetric (a yaw of -a mirrors a yaw of a; pitch is unchanged)."""
+    rng = np.random.default_rng(100 + seed)
+    n = 17  # odd, base at the centre: the reflection maps the grid onto itself
+    na = 12
+    arm = synth.Arm(types=[0, 1, 0, 1], lens=[3, 4, 3, 2], lo_cdeg=[-9000, -6000, -9000, -6000],
+                    hi_cdeg=[9000, 6000, 9000, 6000], step_cdeg=3000, base=(8, 8, 0))
+    sc = synth.random_scene(rng, n, 0, 3, (1, 4), 1, (1, 2), base=arm.base, column=3)
+    occ = oracle.raster(sc)
+    occ_m = occ[:, ::-1, :].copy()
+    q = synth.candidate_poses(rng, arm, 64)
+    valid, ends = oracle.poses(arm, occ, q)
+    t = tuple(int(v) for v in ends[np.flatnonzero(valid)[0]]) if valid.any() else (8, 8, 8)
+    tm = (t[0], 2 * 8 - t[1], t[2])
+    a = oracle.reach(arm, occ, t, m=2, prune=False)
+    b = oracle.reach(arm, occ_m, tm, m=2, prune=False)
+    assert a.status == b.status
+
+    def mirror(keys):
+        x, y, z, ia, ie = oracle.key_fields(keys, n)
+        y2 = 2 * 8 - y
+        ia2 = (-ia) % na
+        return np.sort((((z * n + y2) * n + x) << 16) | (ia2 << 8) | ie).astype(np.uint64)
+
+    for key in a.sets:
+        assert np.array_equal(mirror(a.sets[key]), b.sets[key]), key
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_outputs_replay_onto_target(seed):
+    """Every returned pose replays clear onto the target, and its continuous FP64 end
+    is within n * sqrt(3)/2 of the target voxel (per-segment rounding bound)."""
+    arm, scene, rng = tiny_case(seed, 4, 4500, n=24)
+    occ = oracle.raster(scene)
+    t = pick_target(arm, scene, rng, occ)
+    r = oracle.reach(arm, occ, t, want=8)
+    for q in r.sols:
+        valid, ends = oracle.poses(arm, occ, q[None, :])
+        assert valid[0] and tuple(ends[0]) == t
+        cont = oracle.pose_continuous(arm, q)
+        assert np.linalg.norm(cont - np.array(t)) <= len(q) * np.sqrt(3) / 2 + 1e-9
+
+
+def test_c1_free_space_reduces_to_planar_two_link():
+    """With no obstacles the 3-DOF arm of the 64^3 workload is a base yaw plus a planar
+    2-link arm in the vertical plane at that azimuth; every one of its 36*19*19 = 12996
+    poses stays in the grid, so the last forward set holds exactly the distinct
+    (end voxel, orientation) pairs of the 12996 replays."""
+    arm = synth.arm_c1()
+    occ = np.zeros((64, 64, 64), np.uint8)
+    lo, hi = oracle.arm_limits(arm)
+    grids = np.meshgrid(*[np.arange(lo[k], hi[k] + 1) for k in range(3)], indexing="ij")
+    q = np.stack([g.ravel() for g in grids], 1).astype(np.int32)
+    assert q.shape[0] == 12996
+    valid, ends = oracle.poses(arm, occ, q)
+    # pitches of -90..90 on top of a vertical first segment never go below z = 0 here
+    assert valid.all()
+    na = 36
+    ia = q[:, 0] % na
+    ie = (9 + q[:, 1] + q[:, 2]) % na
+    keys = np.unique((((ends[:, 2] * 64 + ends[:, 1]) * 64 + ends[:, 0]) << 16) | (ia << 8) | ie).astype(np.uint64)
+    r = oracle.reach(arm, occ, (32, 32, 10), m=3, prune=False)
+    assert np.array_equal(r.sets[("F", 3)], keys)
+    # a planar 2-link arm reaches everything within [|8-6|, 8+6] of its shoulder
+    shoulder = np.array([32, 32, 10])
+    d = np.linalg.norm(ends - shoulder, axis=1)
+    assert d.min() >= 2 - 3 * np.sqrt(3) / 2 and d.max() <= 14 + 3 * np.sqrt(3) / 2
+
+
+def test_orientation_reachability():
+    """O_k for a yaw/pitch chain is the product of the reachable azimuth and elevation
+    index sets, each a Minkowski sum of the joint windows modulo the turn."""
+    arm = synth.Arm(types=[0, 1, 0, 1], lens=[1, 1, 1, 1], lo_cdeg=[-3000, 0, -6000, -3000],
+                    hi_cdeg=[3000, 3000, 3000, 0], step_cdeg=3000, base=(0, 0, 0))
+    O = oracle.orientations(arm)
+    na = 12
+    az = {0}
+    el = {3}
+    windows = [(-1, 1), (0, 1), (-2, 1), (-1, 0)]
+    for k, (lo, hi) in enumerate(windows):
+        if arm.types[k] == 0:
+            az = {(a + d) % na for a in az for d in range(lo, hi + 1)}
+        else:
+            el = {(e + d) % na for e in el for d in range(lo, hi + 1)}
+        expect = np.zeros((na, na), bool)
+        for a in az:
+            for e in el:
+                expect[a, e] = True
+        assert np.array_equal(O[k + 1], expect)
