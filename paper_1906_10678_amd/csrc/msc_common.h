@@ -1,0 +1,124 @@
+// Internal types shared by the HIP kernels and the host runtime of libmsc.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace msc {
+
+constexpr int kMaxDof = 16;
+constexpr int kMaxNa = 256;
+constexpr uint64_t kEmpty = ~0ull;        // free hash slot
+constexpr uint64_t kDead = 1ull << 63;    // hash entry removed from the set (key kept)
+
+// Internal state key: x | y << 10 | z << 20 | ia << 32 | ie << 40 (grids up to 1024^3).
+__host__ __device__ inline uint64_t pack_key(int x, int y, int z, int ia, int ie) {
+    return (uint64_t)(uint32_t)x | ((uint64_t)(uint32_t)y << 10) | ((uint64_t)(uint32_t)z << 20) |
+           ((uint64_t)(uint32_t)ia << 32) | ((uint64_t)(uint32_t)ie << 40);
+}
+__host__ __device__ inline void unpack_key(uint64_t k, int& x, int& y, int& z, int& ia, int& ie) {
+    x = (int)(k & 1023);
+    y = (int)((k >> 10) & 1023);
+    z = (int)((k >> 20) & 1023);
+    ia = (int)((k >> 32) & 255);
+    ie = (int)((k >> 40) & 255);
+}
+
+// Bit-packed occupancy: word (z*n + y)*wpr + x/64, bit x%64; 1 = blocked.
+struct GridView {
+    const uint64_t* occ;
+    int n;
+    int wpr;
+};
+
+// Rounded segment geometry of one joint: off[o] and sweep[o*S + s] (s = 0..S-1 is
+// sample s+1 of S), o = ia*na + ie.
+struct JointView {
+    const short4* off;
+    const short4* sweep;
+    int type;   // 0 yaw, 1 pitch
+    int lo, hi; // joint window in steps
+    int S;
+};
+
+// A stage set: a dense bitset over a voxel box x all orientations, or an open-addressing
+// hash set of keys.
+enum { kDense = 0, kHash = 1 };
+struct SetView {
+    uint64_t* words;  // dense bit words or hash slots
+    uint64_t cap;     // number of words / slots (hash: power of two)
+    int kind;
+    int fast_ia;      // dense: 1 -> orientation index ie*na + ia, 0 -> ia*na + ie
+    int na;
+    int x0, y0, z0, nx, ny, nz;  // dense box
+};
+
+__host__ __device__ inline uint64_t mix64(uint64_t v) {
+    v ^= v >> 33;
+    v *= 0xff51afd7ed558ccdull;
+    v ^= v >> 33;
+    v *= 0xc4ceb9fe1a85ec53ull;
+    v ^= v >> 33;
+    return v;
+}
+
+// Launch wrappers (msc_kernels.hip).  All enqueue on `st`.
+hipError_t launch_fill(uint64_t* p, uint64_t n, uint64_t value, hipStream_t st);
+hipError_t launch_tables(int na, int S, int L, short4* off, short4* sweep, unsigned int* maxn2,
+                         hipStream_t st);
+hipError_t launch_raster(uint64_t* occ, int n, int wpr, int r, const int32_t* boxes, int nbox,
+                         const int32_t* spheres, int nsph, hipStream_t st);
+hipError_t launch_orient(int n, int na, int ia0, int ie0, const int32_t* type, const int32_t* lo,
+                         const int32_t* hi, uint8_t* scratch, uint64_t* rows_ie, uint64_t* rows_ia,
+                         hipStream_t st);
+hipError_t launch_seed_fwd(SetView s, GridView g, int x, int y, int z, int ia, int ie,
+                           unsigned long long* counter, hipStream_t st);
+hipError_t launch_seed_bwd(SetView s, GridView g, int x, int y, int z, const uint64_t* rows_ie,
+                           int prune, unsigned long long* counter, hipStream_t st);
+hipError_t launch_expand_fwd(const uint64_t* in, uint64_t count, SetView out, GridView g, JointView j,
+                             int tx, int ty, int tz, long long r2, unsigned long long* counter,
+                             unsigned long long* overflow, hipStream_t st);
+hipError_t launch_expand_bwd(const uint64_t* in, uint64_t count, SetView out, GridView g, JointView j,
+                             int bx, int by, int bz, long long r2, const uint64_t* orows,
+                             unsigned long long* counter, unsigned long long* overflow,
+                             hipStream_t st);
+hipError_t launch_compact(SetView s, uint64_t* list, uint64_t cap, unsigned long long* counter,
+                          unsigned long long* overflow, hipStream_t st);
+hipError_t launch_join(const uint64_t* flist, uint64_t count, SetView f, SetView b,
+                       unsigned long long* counter, hipStream_t st);
+hipError_t launch_dmark(const uint64_t* flist, uint64_t count, SetView fprev, SetView fnext,
+                        GridView g, JointView j, unsigned long long* counter, hipStream_t st);
+
+struct DfsArgs {
+    const SetView* sets;       // sets[k] = D_k for k <= m, B_k for k > m (k = 0..n)
+    const JointView* joints;   // n joints
+    GridView g;
+    int n, m, na, want;
+    int ref[kMaxDof];
+    uint64_t root;             // root state key
+    int32_t* sols;             // want * n joint values (steps)
+    int32_t* nsol;
+};
+hipError_t launch_dfs(const DfsArgs& a, hipStream_t st);
+
+struct PoseArgs {
+    const JointView* joints;
+    GridView g;
+    int n, na, bx, by, bz, ia0, ie0;
+};
+hipError_t launch_pose_check(const PoseArgs& a, const int32_t* q, int64_t count, uint8_t* valid,
+                             int32_t* ends, hipStream_t st);
+
+struct TubeArgs {
+    const JointView* joints;
+    GridView g;
+    int n, na, bx, by, bz, ia0, ie0;
+    int W, delta, r;
+    int start[kMaxDof], goal[kMaxDof], lim_lo[kMaxDof], lim_hi[kMaxDof];
+    uint64_t slab;             // (2r+1)^n cells per waypoint
+};
+hipError_t launch_tube_valid(const TubeArgs& a, uint8_t* valid, hipStream_t st);
+hipError_t launch_tube_solve(const TubeArgs& a, const uint8_t* valid, uint8_t* reach, uint8_t* tmp0,
+                             uint8_t* tmp1, int32_t* path, int32_t* status, hipStream_t st);
+
+}  // namespace msc

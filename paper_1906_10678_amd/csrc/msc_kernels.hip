@@ -1,0 +1,1006 @@
+// HIP kernels of the staged reach / path solver (gfx950, wave64).
+//
+// The search works on states (joint voxel, orientation) after each segment.  A
+// segment is laid along the global direction of its orientation, its S sample
+// points are rounded to voxels and tested against the bit-packed occupancy grid
+// (paper, "Testing for collisions"); forward stages expand from the root, backward
+// stages from the target, and the two sets are intersected ("The gap in gMS",
+// "The procedure for IK solution").  Everything here is integer / bitwise work: no
+// kernel is a dense contraction, so none uses the matrix cores.
+#include <hip/hip_runtime.h>
+
+#include "msc_common.h"
+
+namespace msc {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ int wrap_na(int v, int na) {
+    v %= na;
+    return v < 0 ? v + na : v;
+}
+
+__device__ __forceinline__ bool cell_free(const GridView& g, int x, int y, int z) {
+    if ((unsigned)x >= (unsigned)g.n || (unsigned)y >= (unsigned)g.n || (unsigned)z >= (unsigned)g.n)
+        return false;
+    uint64_t w = g.occ[((size_t)z * g.n + y) * g.wpr + (x >> 6)];
+    return ((w >> (x & 63)) & 1ull) == 0;
+}
+
+// Segment of joint j laid from (x, y, z) along orientation o: clear when every
+// sample point is a free voxel inside the grid.
+__device__ __forceinline__ bool segment_clear(const GridView& g, const JointView& j, int o, int x, int y,
+                                              int z) {
+    const short4* sw = j.sweep + (size_t)o * j.S;
+    for (int s = j.S - 1; s >= 0; --s) {
+        short4 d = sw[s];
+        if (!cell_free(g, x + d.x, y + d.y, z + d.z)) return false;
+    }
+    return true;
+}
+
+__device__ __forceinline__ bool dense_bit(const SetView& s, int x, int y, int z, int ia, int ie,
+                                          uint64_t& bit) {
+    int dx = x - s.x0, dy = y - s.y0, dz = z - s.z0;
+    if ((unsigned)dx >= (unsigned)s.nx || (unsigned)dy >= (unsigned)s.ny || (unsigned)dz >= (unsigned)s.nz)
+        return false;
+    uint64_t vox = ((uint64_t)dz * s.ny + dy) * s.nx + dx;
+    int o = s.fast_ia ? ie * s.na + ia : ia * s.na + ie;
+    bit = vox * (uint64_t)(s.na * s.na) + (uint64_t)o;
+    return true;
+}
+
+__device__ __forceinline__ uint64_t load_relaxed(const uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// 1 = inserted, 0 = already present, -1 = table full.
+__device__ int hash_insert(const SetView& s, uint64_t key) {
+    const uint64_t mask = s.cap - 1;
+    uint64_t h = mix64(key) & mask;
+    for (uint64_t p = 0; p < s.cap; ++p) {
+        uint64_t cur = load_relaxed(&s.words[h]);
+        if (cur == kEmpty) {
+            uint64_t prev = atomicCAS((unsigned long long*)&s.words[h], (unsigned long long)kEmpty,
+                                      (unsigned long long)key);
+            if (prev == kEmpty) return 1;
+            cur = prev;
+        }
+        if ((cur & ~kDead) == key) return 0;
+        h = (h + 1) & mask;
+    }
+    return -1;
+}
+
+__device__ int64_t hash_find(const SetView& s, uint64_t key) {
+    const uint64_t mask = s.cap - 1;
+    uint64_t h = mix64(key) & mask;
+    for (uint64_t p = 0; p < s.cap; ++p) {
+        uint64_t cur = load_relaxed(&s.words[h]);
+        if (cur == kEmpty) return -1;
+        if ((cur & ~kDead) == key) return (int64_t)h;
+        h = (h + 1) & mask;
+    }
+    return -1;
+}
+
+// 1 = inserted, 0 = already present, -1 = no room (outside the dense box / table full).
+__device__ int set_insert(const SetView& s, int x, int y, int z, int ia, int ie) {
+    if (s.kind == kDense) {
+        uint64_t bit;
+        if (!dense_bit(s, x, y, z, ia, ie, bit)) return -1;
+        uint64_t m = 1ull << (bit & 63);
+        uint64_t old = atomicOr((unsigned long long*)&s.words[bit >> 6], (unsigned long long)m);
+        return (old & m) ? 0 : 1;
+    }
+    return hash_insert(s, pack_key(x, y, z, ia, ie));
+}
+
+__device__ bool set_member(const SetView& s, uint64_t key) {
+    if (s.kind == kDense) {
+        int x, y, z, ia, ie;
+        unpack_key(key, x, y, z, ia, ie);
+        uint64_t bit;
+        if (!dense_bit(s, x, y, z, ia, ie, bit)) return false;
+        return (load_relaxed(&s.words[bit >> 6]) >> (bit & 63)) & 1ull;
+    }
+    const uint64_t mask = s.cap - 1;
+    uint64_t h = mix64(key) & mask;
+    for (uint64_t p = 0; p < s.cap; ++p) {
+        uint64_t cur = load_relaxed(&s.words[h]);
+        if (cur == kEmpty) return false;
+        if ((cur & ~kDead) == key) return (cur & kDead) == 0;
+        h = (h + 1) & mask;
+    }
+    return false;
+}
+
+__device__ void set_remove(const SetView& s, uint64_t key) {
+    if (s.kind == kDense) {
+        int x, y, z, ia, ie;
+        unpack_key(key, x, y, z, ia, ie);
+        uint64_t bit;
+        if (!dense_bit(s, x, y, z, ia, ie, bit)) return;
+        atomicAnd((unsigned long long*)&s.words[bit >> 6], ~(unsigned long long)(1ull << (bit & 63)));
+        return;
+    }
+    int64_t slot = hash_find(s, key);
+    if (slot >= 0) atomicOr((unsigned long long*)&s.words[slot], (unsigned long long)kDead);
+}
+
+// Block-wide sum of a per-thread count, one atomic per block.
+__device__ void block_add(unsigned long long v, unsigned long long* dst) {
+    __shared__ unsigned long long part[kBlock / 64];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) part[wave] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += part[w];
+        if (t) atomicAdd(dst, t);
+    }
+}
+
+// Bits lo..hi (inclusive, 0 <= lo <= hi < 256) of a 256-bit mask.
+__device__ __forceinline__ void mask_range(uint64_t m[4], int lo, int hi) {
+    for (int w = 0; w < 4; ++w) {
+        int a = lo - 64 * w, b = hi - 64 * w;
+        if (b < 0 || a > 63) continue;
+        a = a < 0 ? 0 : a;
+        b = b > 63 ? 63 : b;
+        uint64_t top = (b == 63) ? ~0ull : ((1ull << (b + 1)) - 1);
+        uint64_t bot = (1ull << a) - 1;
+        m[w] |= top & ~bot;
+    }
+}
+
+uint32_t grid_for(uint64_t work, uint32_t block = kBlock, uint32_t max_blocks = 16384) {
+    uint64_t b = (work + block - 1) / block;
+    if (b < 1) b = 1;
+    if (b > max_blocks) b = max_blocks;
+    return (uint32_t)b;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Fill (used instead of a memset so that every clear is a kernel).
+// ---------------------------------------------------------------------------
+__global__ void k_fill(uint64_t* p, uint64_t n, uint64_t v) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+hipError_t launch_fill(uint64_t* p, uint64_t n, uint64_t value, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(n, kBlock, 8192)), dim3(kBlock), 0, st, p, n, value);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Segment tables: the direction of orientation (ia, ie) is
+// (cos el cos az, cos el sin az, sin el) with az = 2*pi*ia/na, el = 2*pi*ie/na; the
+// segment end and the S sample points at fractions s/S of the length are rounded to
+// the nearest voxel, halves away from zero (halves recognised within 1e-9, so that
+// FP64 evaluation order cannot split an exact tie such as 25*cos 60 deg).
+// ---------------------------------------------------------------------------
+__device__ int round_voxel(double v) {
+    double a = fabs(v);
+    double f = floor(a);
+    double frac = a - f;
+    int r = (int)f + ((frac > 0.5 - 1e-9) ? 1 : 0);
+    return v < 0 ? -r : r;
+}
+
+__global__ void k_tables(int na, int S, int L, short4* off, short4* sweep, unsigned int* maxn2) {
+    int o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= na * na) return;
+    int ia = o / na, ie = o % na;
+    double saz, caz, sel, cel;
+    sincospi(2.0 * (double)ia / (double)na, &saz, &caz);
+    sincospi(2.0 * (double)ie / (double)na, &sel, &cel);
+    double dx = cel * caz, dy = cel * saz, dz = sel;
+    int ex = round_voxel((double)L * dx), ey = round_voxel((double)L * dy), ez = round_voxel((double)L * dz);
+    off[o] = make_short4((short)ex, (short)ey, (short)ez, 0);
+    atomicMax(maxn2, (unsigned int)(ex * ex + ey * ey + ez * ez));
+    for (int s = 1; s <= S; ++s) {
+        double len = (double)(s * L) / (double)S;
+        sweep[(size_t)o * S + (s - 1)] = make_short4((short)round_voxel(len * dx), (short)round_voxel(len * dy),
+                                                     (short)round_voxel(len * dz), 0);
+    }
+}
+
+hipError_t launch_tables(int na, int S, int L, short4* off, short4* sweep, unsigned int* maxn2,
+                         hipStream_t st) {
+    int cnt = na * na;
+    hipLaunchKernelGGL(k_tables, dim3((cnt + 255) / 256), dim3(256), 0, st, na, S, L, off, sweep, maxn2);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Raster: one thread per 64-voxel word.  For a row (y, z) a box dilated by r
+// (Euclidean Minkowski sum) covers x in [lo_x - w, hi_x + w] with
+// w = floor(sqrt(r^2 - dy^2 - dz^2)), dy/dz the distances of the row to the box's
+// y/z ranges; a sphere of radius R dilated by r covers x in [cx - w, cx + w] with
+// w = floor(sqrt((R+r)^2 - dy^2 - dz^2)).  Bits past the grid edge are set.
+// ---------------------------------------------------------------------------
+__device__ long long isqrt_floor(long long v) {
+    long long s = (long long)sqrt((double)v);
+    while (s > 0 && s * s > v) --s;
+    while ((s + 1) * (s + 1) <= v) ++s;
+    return s;
+}
+
+__device__ uint64_t span_bits(long long lo, long long hi, long long x0) {
+    long long a = lo - x0, b = hi - x0;
+    if (b < 0 || a > 63) return 0;
+    if (a < 0) a = 0;
+    if (b > 63) b = 63;
+    uint64_t top = (b == 63) ? ~0ull : ((1ull << (b + 1)) - 1);
+    uint64_t bot = (1ull << a) - 1;
+    return top & ~bot;
+}
+
+__global__ void k_raster(uint64_t* occ, int n, int wpr, int r, const int32_t* boxes, int nbox,
+                         const int32_t* spheres, int nsph) {
+    uint64_t total = (uint64_t)n * n * wpr;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < total;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        int xw = (int)(i % wpr);
+        uint64_t row = i / wpr;
+        int y = (int)(row % n), z = (int)(row / n);
+        long long x0 = 64ll * xw;
+        uint64_t bits = 0;
+        for (int b = 0; b < nbox; ++b) {
+            const int32_t* B = boxes + 6 * b;
+            long long ylo = B[1], yhi = (long long)B[1] + B[4] - 1;
+            long long zlo = B[2], zhi = (long long)B[2] + B[5] - 1;
+            long long dy = y < ylo ? ylo - y : (y > yhi ? y - yhi : 0);
+            long long dz = z < zlo ? zlo - z : (z > zhi ? z - zhi : 0);
+            long long rem = (long long)r * r - dy * dy - dz * dz;
+            if (rem < 0) continue;
+            long long w = isqrt_floor(rem);
+            bits |= span_bits((long long)B[0] - w, (long long)B[0] + B[3] - 1 + w, x0);
+        }
+        for (int s = 0; s < nsph; ++s) {
+            const int32_t* P = spheres + 4 * s;
+            long long dy = y - P[1], dz = z - P[2];
+            long long rr = (long long)P[3] + r;
+            long long rem = rr * rr - dy * dy - dz * dz;
+            if (rem < 0) continue;
+            long long w = isqrt_floor(rem);
+            bits |= span_bits((long long)P[0] - w, (long long)P[0] + w, x0);
+        }
+        if (x0 + 64 > n) bits |= span_bits(n, x0 + 63, x0);
+        occ[i] = bits;
+    }
+}
+
+hipError_t launch_raster(uint64_t* occ, int n, int wpr, int r, const int32_t* boxes, int nbox,
+                         const int32_t* spheres, int nsph, hipStream_t st) {
+    uint64_t total = (uint64_t)n * n * wpr;
+    hipLaunchKernelGGL(k_raster, dim3(grid_for(total)), dim3(kBlock), 0, st, occ, n, wpr, r, boxes, nbox,
+                       spheres, nsph);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Orientation reachability O_k (k = 0..n): orientations the chain can have after k
+// joints, positions ignored.  One block; O_k in `scratch` as bytes, then as 256-bit
+// rows: rows_ie[(k*na + ia)*4 + w] holds bit ie, rows_ia[(k*na + ie)*4 + w] bit ia.
+// ---------------------------------------------------------------------------
+__global__ void k_orient(int n, int na, int ia0, int ie0, const int32_t* type, const int32_t* lo,
+                         const int32_t* hi, uint8_t* scratch, uint64_t* rows_ie, uint64_t* rows_ia) {
+    const int na2 = na * na;
+    for (int o = threadIdx.x; o < na2; o += blockDim.x) scratch[o] = (o == ia0 * na + ie0) ? 1 : 0;
+    __syncthreads();
+    for (int k = 1; k <= n; ++k) {
+        const uint8_t* prev = scratch + (size_t)(k - 1) * na2;
+        uint8_t* cur = scratch + (size_t)k * na2;
+        int t = type[k - 1];
+        for (int o = threadIdx.x; o < na2; o += blockDim.x) {
+            int ia = o / na, ie = o % na;
+            uint8_t any = 0;
+            for (int a = lo[k - 1]; a <= hi[k - 1] && !any; ++a) {
+                int pia = t == 0 ? wrap_na(ia - a, na) : ia;
+                int pie = t == 0 ? ie : wrap_na(ie - a, na);
+                any = prev[pia * na + pie];
+            }
+            cur[o] = any;
+        }
+        __syncthreads();
+    }
+    for (int idx = threadIdx.x; idx < (n + 1) * na * 4; idx += blockDim.x) {
+        int w = idx & 3;
+        int rowi = idx >> 2;
+        int k = rowi / na, v = rowi % na;
+        const uint8_t* O = scratch + (size_t)k * na2;
+        uint64_t bie = 0, bia = 0;
+        for (int b = 0; b < 64; ++b) {
+            int u = 64 * w + b;
+            if (u >= na) break;
+            if (O[v * na + u]) bie |= 1ull << b;   // row over ie for ia = v
+            if (O[u * na + v]) bia |= 1ull << b;   // row over ia for ie = v
+        }
+        rows_ie[idx] = bie;
+        rows_ia[idx] = bia;
+    }
+}
+
+hipError_t launch_orient(int n, int na, int ia0, int ie0, const int32_t* type, const int32_t* lo,
+                         const int32_t* hi, uint8_t* scratch, uint64_t* rows_ie, uint64_t* rows_ia,
+                         hipStream_t st) {
+    hipLaunchKernelGGL(k_orient, dim3(1), dim3(1024), 0, st, n, na, ia0, ie0, type, lo, hi, scratch, rows_ie,
+                       rows_ia);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Seeds: F_0 = {(base, o0)} if the base is free; B_n = {(target, o) : o in O_n} if
+// the target is free.
+// ---------------------------------------------------------------------------
+__global__ void k_seed_fwd(SetView s, GridView g, int x, int y, int z, int ia, int ie,
+                           unsigned long long* counter) {
+    if (threadIdx.x == 0 && blockIdx.x == 0 && cell_free(g, x, y, z)) {
+        if (set_insert(s, x, y, z, ia, ie) > 0) atomicAdd(counter, 1ull);
+    }
+}
+
+__global__ void k_seed_bwd(SetView s, GridView g, int x, int y, int z, const uint64_t* rows_ie, int prune,
+                           unsigned long long* counter) {
+    const int na = s.na;
+    unsigned long long added = 0;
+    if (cell_free(g, x, y, z)) {
+        for (int o = blockIdx.x * blockDim.x + threadIdx.x; o < na * na; o += gridDim.x * blockDim.x) {
+            int ia = o / na, ie = o % na;
+            bool ok = !prune || ((rows_ie[ia * 4 + (ie >> 6)] >> (ie & 63)) & 1ull);
+            if (ok && set_insert(s, x, y, z, ia, ie) > 0) ++added;
+        }
+    }
+    block_add(added, counter);
+}
+
+hipError_t launch_seed_fwd(SetView s, GridView g, int x, int y, int z, int ia, int ie,
+                           unsigned long long* counter, hipStream_t st) {
+    hipLaunchKernelGGL(k_seed_fwd, dim3(1), dim3(64), 0, st, s, g, x, y, z, ia, ie, counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_seed_bwd(SetView s, GridView g, int x, int y, int z, const uint64_t* rows_ie, int prune,
+                           unsigned long long* counter, hipStream_t st) {
+    hipLaunchKernelGGL(k_seed_bwd, dim3(grid_for((uint64_t)s.na * s.na)), dim3(kBlock), 0, st, s, g, x, y, z,
+                       rows_ie, prune, counter);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Forward stage (Steps 1 and 2A): every state of the input list is tried against
+// every angle of the joint window; the successor is kept if it lies within the
+// forward pruning radius of the target (eqs 5-6) and the new segment is clear.
+// One work item per (state, angle).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_expand_fwd(const uint64_t* __restrict__ in, uint64_t count,
+                                                       SetView out, GridView g, JointView j, int tx, int ty,
+                                                       int tz, long long r2, unsigned long long* counter,
+                                                       unsigned long long* overflow) {
+    const int na = out.na;
+    const uint32_t nA = (uint32_t)(j.hi - j.lo + 1);
+    const uint64_t total = count * nA;
+    unsigned long long added = 0, ovf = 0;
+    for (uint64_t idx = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (uint64_t)gridDim.x * blockDim.x) {
+        uint64_t i = idx / nA;
+        int a = j.lo + (int)(idx - i * nA);
+        int x, y, z, ia, ie;
+        unpack_key(in[i], x, y, z, ia, ie);
+        if (ia >= na || ie >= na) continue;
+        if (j.type == 0)
+            ia = wrap_na(ia + a, na);
+        else
+            ie = wrap_na(ie + a, na);
+        const int o = ia * na + ie;
+        const short4 d = j.off[o];
+        const int x2 = x + d.x, y2 = y + d.y, z2 = z + d.z;
+        if (r2 >= 0) {
+            long long ex = x2 - tx, ey = y2 - ty, ez = z2 - tz;
+            if (ex * ex + ey * ey + ez * ez > r2) continue;
+        }
+        if (!segment_clear(g, j, o, x, y, z)) continue;
+        int r = set_insert(out, x2, y2, z2, ia, ie);
+        if (r > 0)
+            ++added;
+        else if (r < 0)
+            ++ovf;
+    }
+    block_add(added, counter);
+    if (ovf) atomicAdd(overflow, ovf);
+}
+
+hipError_t launch_expand_fwd(const uint64_t* in, uint64_t count, SetView out, GridView g, JointView j,
+                             int tx, int ty, int tz, long long r2, unsigned long long* counter,
+                             unsigned long long* overflow, hipStream_t st) {
+    uint64_t work = count * (uint64_t)(j.hi - j.lo + 1);
+    if (work == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_expand_fwd, dim3(grid_for(work)), dim3(kBlock), 0, st, in, count, out, g, j, tx, ty, tz,
+                       r2, counter, overflow);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Backward stage: for a state (p', o') after segment k, the start p = p' - off[o']
+// of segment k is the same for every angle of joint k, so the clearance of the
+// segment is tested once; the predecessors are (p, o' turned back by a) for every
+// a in the window, a cyclic run along the joint's axis, filtered by O_{k-1} and the
+// backward pruning radius around the base (eqs 7-8).  In a dense output whose
+// fastest orientation axis is the joint's axis the run is set with at most a few
+// masked atomicOr.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_expand_bwd(const uint64_t* __restrict__ in, uint64_t count,
+                                                       SetView out, GridView g, JointView j, int bx, int by,
+                                                       int bz, long long r2, const uint64_t* __restrict__ orows,
+                                                       unsigned long long* counter,
+                                                       unsigned long long* overflow) {
+    const int na = out.na;
+    const int nA = j.hi - j.lo + 1;
+    const bool yaw = j.type == 0;
+    const bool run_dense = out.kind == kDense && ((out.fast_ia != 0) == yaw);
+    unsigned long long added = 0, ovf = 0;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < count;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        int x2, y2, z2, ia2, ie2;
+        unpack_key(in[i], x2, y2, z2, ia2, ie2);
+        if (ia2 >= na || ie2 >= na) continue;
+        const int o2 = ia2 * na + ie2;
+        const short4 d = j.off[o2];
+        const int x = x2 - d.x, y = y2 - d.y, z = z2 - d.z;
+        if (!cell_free(g, x, y, z)) continue;
+        if (r2 >= 0) {
+            long long ex = x - bx, ey = y - by, ez = z - bz;
+            if (ex * ex + ey * ey + ez * ez > r2) continue;
+        }
+        if (!segment_clear(g, j, o2, x, y, z)) continue;
+        const int v = yaw ? ia2 : ie2;
+        const int other = yaw ? ie2 : ia2;
+        uint64_t m[4] = {0, 0, 0, 0};
+        if (nA >= na) {
+            mask_range(m, 0, na - 1);
+        } else {
+            int s = wrap_na(v - j.hi, na);
+            int e = s + nA - 1;
+            if (e < na) {
+                mask_range(m, s, e);
+            } else {
+                mask_range(m, s, na - 1);
+                mask_range(m, 0, e - na);
+            }
+        }
+        if (orows) {
+            const uint64_t* row = orows + (size_t)other * 4;
+            for (int w = 0; w < 4; ++w) m[w] &= row[w];
+        }
+        if (run_dense) {
+            uint64_t bit0;
+            if (!dense_bit(out, x, y, z, yaw ? 0 : ia2, yaw ? ie2 : 0, bit0)) {
+                ++ovf;
+                continue;
+            }
+            for (int w = 0; w < 4; ++w) {
+                if (!m[w]) continue;
+                uint64_t pos = bit0 + 64ull * w;
+                uint64_t word = pos >> 6;
+                int sh = (int)(pos & 63);
+                uint64_t lo_part = m[w] << sh;
+                uint64_t old = atomicOr((unsigned long long*)&out.words[word], (unsigned long long)lo_part);
+                added += __popcll(lo_part & ~old);
+                if (sh) {
+                    uint64_t hi_part = m[w] >> (64 - sh);
+                    if (hi_part) {
+                        old = atomicOr((unsigned long long*)&out.words[word + 1], (unsigned long long)hi_part);
+                        added += __popcll(hi_part & ~old);
+                    }
+                }
+            }
+        } else {
+            for (int w = 0; w < 4; ++w) {
+                uint64_t bits = m[w];
+                while (bits) {
+                    int b = __ffsll((unsigned long long)bits) - 1;
+                    bits &= bits - 1;
+                    int u = 64 * w + b;
+                    int r = set_insert(out, x, y, z, yaw ? u : ia2, yaw ? ie2 : u);
+                    if (r > 0)
+                        ++added;
+                    else if (r < 0)
+                        ++ovf;
+                }
+            }
+        }
+    }
+    block_add(added, counter);
+    if (ovf) atomicAdd(overflow, ovf);
+}
+
+hipError_t launch_expand_bwd(const uint64_t* in, uint64_t count, SetView out, GridView g, JointView j,
+                             int bx, int by, int bz, long long r2, const uint64_t* orows,
+                             unsigned long long* counter, unsigned long long* overflow, hipStream_t st) {
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_expand_bwd, dim3(grid_for(count)), dim3(kBlock), 0, st, in, count, out, g, j, bx, by, bz,
+                       r2, orows, counter, overflow);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Compaction: the members of a set into a list.  Each lane owns one word (dense:
+// its set bits; hash: an occupied, not removed slot); a wave prefix sum of the
+// lanes' counts gives every lane its output offset after one atomicAdd per wave.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_compact(SetView s, uint64_t* list, uint64_t cap,
+                                                    unsigned long long* counter,
+                                                    unsigned long long* overflow) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t na2 = (uint64_t)s.na * s.na;
+    for (uint64_t base = blockIdx.x * (uint64_t)blockDim.x; base < s.cap;
+         base += (uint64_t)gridDim.x * blockDim.x) {
+        uint64_t i = base + threadIdx.x;
+        uint64_t w = i < s.cap ? s.words[i] : (s.kind == kDense ? 0ull : kEmpty);
+        int c;
+        if (s.kind == kDense)
+            c = __popcll(w);
+        else
+            c = (w != kEmpty && !(w & kDead)) ? 1 : 0;
+        int scan = c;
+        for (int off = 1; off < 64; off <<= 1) {
+            int t = __shfl_up(scan, off, 64);
+            if (lane >= off) scan += t;
+        }
+        unsigned long long wbase = 0;
+        if (lane == 63 && scan) wbase = atomicAdd(counter, (unsigned long long)scan);
+        wbase = __shfl(wbase, 63, 64);
+        uint64_t pos = wbase + (uint64_t)(scan - c);
+        if (!c) continue;
+        if (s.kind == kDense) {
+            uint64_t bits = w;
+            while (bits) {
+                int b = __ffsll((unsigned long long)bits) - 1;
+                bits &= bits - 1;
+                uint64_t bit = i * 64 + (uint64_t)b;
+                uint64_t vox = bit / na2;
+                int o = (int)(bit - vox * na2);
+                int dx = (int)(vox % (uint64_t)s.nx);
+                uint64_t r = vox / (uint64_t)s.nx;
+                int dy = (int)(r % (uint64_t)s.ny);
+                int dz = (int)(r / (uint64_t)s.ny);
+                int hi = o / s.na, lo = o % s.na;
+                int ia = s.fast_ia ? lo : hi;
+                int ie = s.fast_ia ? hi : lo;
+                if (pos < cap)
+                    list[pos] = pack_key(s.x0 + dx, s.y0 + dy, s.z0 + dz, ia, ie);
+                else
+                    atomicAdd(overflow, 1ull);
+                ++pos;
+            }
+        } else {
+            if (pos < cap)
+                list[pos] = w;
+            else
+                atomicAdd(overflow, 1ull);
+        }
+    }
+}
+
+hipError_t launch_compact(SetView s, uint64_t* list, uint64_t cap, unsigned long long* counter,
+                          unsigned long long* overflow, hipStream_t st) {
+    hipLaunchKernelGGL(k_compact, dim3(grid_for(s.cap, kBlock, 8192)), dim3(kBlock), 0, st, s, list, cap, counter,
+                       overflow);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Join: C_m = F_m intersected with B_m, in place in F_m's structure; counts |C_m|.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_join(const uint64_t* __restrict__ flist, uint64_t count, SetView f,
+                                                 SetView b, unsigned long long* counter) {
+    unsigned long long kept = 0;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < count;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        uint64_t key = flist[i];
+        if (set_member(b, key))
+            ++kept;
+        else
+            set_remove(f, key);
+    }
+    block_add(kept, counter);
+}
+
+hipError_t launch_join(const uint64_t* flist, uint64_t count, SetView f, SetView b,
+                       unsigned long long* counter, hipStream_t st) {
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_join, dim3(grid_for(count)), dim3(kBlock), 0, st, flist, count, f, b, counter);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// D_{k-1} = states of F_{k-1} with a clear move of joint k into D_k (already marked
+// in fnext); the others are removed from fprev in place.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_dmark(const uint64_t* __restrict__ flist, uint64_t count,
+                                                  SetView fprev, SetView fnext, GridView g, JointView j,
+                                                  unsigned long long* counter) {
+    const int na = fnext.na;
+    unsigned long long kept = 0;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < count;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        uint64_t key = flist[i];
+        int x, y, z, ia, ie;
+        unpack_key(key, x, y, z, ia, ie);
+        bool found = false;
+        if (ia >= na || ie >= na) continue;
+        for (int a = j.lo; a <= j.hi && !found; ++a) {
+            int ia2 = ia, ie2 = ie;
+            if (j.type == 0)
+                ia2 = wrap_na(ia + a, na);
+            else
+                ie2 = wrap_na(ie + a, na);
+            int o = ia2 * na + ie2;
+            short4 d = j.off[o];
+            if (!set_member(fnext, pack_key(x + d.x, y + d.y, z + d.z, ia2, ie2))) continue;
+            if (!segment_clear(g, j, o, x, y, z)) continue;
+            found = true;
+        }
+        if (found)
+            ++kept;
+        else
+            set_remove(fprev, key);
+    }
+    block_add(kept, counter);
+}
+
+hipError_t launch_dmark(const uint64_t* flist, uint64_t count, SetView fprev, SetView fnext, GridView g,
+                        JointView j, unsigned long long* counter, hipStream_t st) {
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_dmark, dim3(grid_for(count)), dim3(kBlock), 0, st, flist, count, fprev, fnext, g, j,
+                       counter);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Reach poses (Step 3): depth-first walk from the root over the joint angles in the
+// canonical order (distance to the reference angle, then value), stepping only into
+// states that extend to a full solution (D_k on the forward side, B_k on the
+// backward side).  Every such state has at least one valid child, so the walk emits
+// the solutions in lexicographic order; it stops after `want` of them.  One block:
+// the candidates of a node are tested in parallel, one lane per angle.
+// ---------------------------------------------------------------------------
+constexpr int kDfsThreads = 256;
+
+__global__ void __launch_bounds__(kDfsThreads) k_dfs(DfsArgs a) {
+    __shared__ short order[kMaxDof][kMaxNa + 1];
+    __shared__ int olen[kMaxDof];
+    __shared__ uint64_t state[kMaxDof + 1];
+    __shared__ uint64_t cmask[kMaxDof][4];
+    __shared__ int pick[kMaxDof];
+    __shared__ int depth, nsol, done, need_eval;
+    __shared__ long long steps;
+    const int tid = threadIdx.x;
+    const int na = a.na;
+    for (int k = 0; k < a.n; ++k) {
+        const JointView J = a.joints[k];
+        const int L = J.hi - J.lo + 1;
+        const int ref = a.ref[k];
+        for (int t = tid; t < L; t += blockDim.x) {
+            int v = J.lo + t;
+            int dv = abs(v - ref);
+            int rank = 0;
+            for (int u = J.lo; u <= J.hi; ++u) {
+                int du = abs(u - ref);
+                if (du < dv || (du == dv && u < v)) ++rank;
+            }
+            order[k][rank] = (short)v;
+        }
+        if (tid == 0) olen[k] = L;
+    }
+    if (tid == 0) {
+        state[0] = a.root;
+        depth = 0;
+        nsol = 0;
+        done = 0;
+        need_eval = 1;
+        steps = 0;
+    }
+    __syncthreads();
+    while (true) {
+        if (need_eval) {
+            const int d = depth;
+            const JointView J = a.joints[d];
+            int x, y, z, ia, ie;
+            unpack_key(state[d], x, y, z, ia, ie);
+            bool ok = false;
+            if (tid < olen[d]) {
+                int av = order[d][tid];
+                int ia2 = ia, ie2 = ie;
+                if (J.type == 0)
+                    ia2 = wrap_na(ia + av, na);
+                else
+                    ie2 = wrap_na(ie + av, na);
+                int o = ia2 * na + ie2;
+                short4 dd = J.off[o];
+                uint64_t key = pack_key(x + dd.x, y + dd.y, z + dd.z, ia2, ie2);
+                ok = set_member(a.sets[d + 1], key) && segment_clear(a.g, J, o, x, y, z);
+            }
+            unsigned long long b = __ballot(ok);
+            if ((tid & 63) == 0) cmask[d][tid >> 6] = b;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            need_eval = 0;
+            while (true) {
+                // every state offered to the walk extends to a solution, so a walk
+                // needs at most n steps per solution; a much longer one is an error
+                if (++steps > (long long)(a.want + 1) * 4096 * (a.n + 1)) {
+                    nsol = -1;
+                    done = 1;
+                    break;
+                }
+                if (depth == a.n) {
+                    for (int k = 0; k < a.n; ++k) a.sols[nsol * a.n + k] = pick[k];
+                    ++nsol;
+                    if (nsol >= a.want) {
+                        done = 1;
+                        break;
+                    }
+                    --depth;
+                    continue;
+                }
+                int j = -1;
+                for (int w = 0; w < 4; ++w) {
+                    if (cmask[depth][w]) {
+                        int b = __ffsll((unsigned long long)cmask[depth][w]) - 1;
+                        cmask[depth][w] &= cmask[depth][w] - 1;
+                        j = 64 * w + b;
+                        break;
+                    }
+                }
+                if (j < 0) {
+                    if (depth == 0) {
+                        done = 1;
+                        break;
+                    }
+                    --depth;
+                    continue;
+                }
+                const JointView J = a.joints[depth];
+                int av = order[depth][j];
+                pick[depth] = av;
+                int x, y, z, ia, ie;
+                unpack_key(state[depth], x, y, z, ia, ie);
+                if (J.type == 0)
+                    ia = wrap_na(ia + av, na);
+                else
+                    ie = wrap_na(ie + av, na);
+                short4 dd = J.off[ia * na + ie];
+                state[depth + 1] = pack_key(x + dd.x, y + dd.y, z + dd.z, ia, ie);
+                ++depth;
+                if (depth < a.n) {
+                    need_eval = 1;
+                    break;
+                }
+            }
+            *a.nsol = nsol;
+        }
+        __syncthreads();
+        if (done) break;
+    }
+}
+
+hipError_t launch_dfs(const DfsArgs& a, hipStream_t st) {
+    hipLaunchKernelGGL(k_dfs, dim3(1), dim3(kDfsThreads), 0, st, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Pose replay: one thread per pose.
+// ---------------------------------------------------------------------------
+__device__ bool replay(const PoseArgs& a, const int32_t* q, int32_t* end) {
+    int x = a.bx, y = a.by, z = a.bz, ia = a.ia0, ie = a.ie0;
+    bool ok = cell_free(a.g, x, y, z);
+    for (int k = 0; k < a.n; ++k) {
+        const JointView J = a.joints[k];
+        if (J.type == 0)
+            ia = wrap_na(ia + q[k], a.na);
+        else
+            ie = wrap_na(ie + q[k], a.na);
+        int o = ia * a.na + ie;
+        if (ok && !segment_clear(a.g, J, o, x, y, z)) ok = false;
+        short4 d = J.off[o];
+        x += d.x;
+        y += d.y;
+        z += d.z;
+    }
+    if (end) {
+        end[0] = x;
+        end[1] = y;
+        end[2] = z;
+    }
+    return ok;
+}
+
+__global__ void k_pose_check(PoseArgs a, const int32_t* q, int64_t count, uint8_t* valid, int32_t* ends) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        bool ok = replay(a, q + i * a.n, ends ? ends + i * 3 : nullptr);
+        valid[i] = ok ? 1 : 0;
+    }
+}
+
+hipError_t launch_pose_check(const PoseArgs& a, const int32_t* q, int64_t count, uint8_t* valid, int32_t* ends,
+                             hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pose_check, dim3(grid_for((uint64_t)count)), dim3(kBlock), 0, st, a, q, count, valid,
+                       ends);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Tube path search ("Smooth sequence computation", "Filtering for smoothness").
+// Waypoint w has the frame g_w - r .. g_w + r per joint, g_w the guide
+// start + round_half_away(w*(goal - start)/W); cell digits are base 2r+1 with joint 0
+// most significant, so the cell index orders poses lexicographically.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int guide_at(const TubeArgs& a, int w, int k) {
+    long long num = (long long)w * (a.goal[k] - a.start[k]);
+    long long mag = (2 * (num < 0 ? -num : num) + a.W) / (2ll * a.W);
+    return a.start[k] + (int)(num < 0 ? -mag : mag);
+}
+
+__device__ bool tube_pose(const TubeArgs& a, int w, uint64_t cell, int32_t* q) {
+    const int B = 2 * a.r + 1;
+    bool in = true;
+    for (int k = a.n - 1; k >= 0; --k) {
+        int d = (int)(cell % B);
+        cell /= B;
+        q[k] = guide_at(a, w, k) - a.r + d;
+        if (w == 0) in = in && q[k] == a.start[k];
+        else if (w == a.W) in = in && q[k] == a.goal[k];
+        else in = in && q[k] >= a.lim_lo[k] && q[k] <= a.lim_hi[k];
+    }
+    return in;
+}
+
+__global__ void k_tube_valid(TubeArgs a, uint8_t* valid) {
+    const uint64_t total = (uint64_t)(a.W + 1) * a.slab;
+    PoseArgs p;
+    p.joints = a.joints;
+    p.g = a.g;
+    p.n = a.n;
+    p.na = a.na;
+    p.bx = a.bx;
+    p.by = a.by;
+    p.bz = a.bz;
+    p.ia0 = a.ia0;
+    p.ie0 = a.ie0;
+    for (uint64_t idx = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (uint64_t)gridDim.x * blockDim.x) {
+        int w = (int)(idx / a.slab);
+        uint64_t cell = idx - (uint64_t)w * a.slab;
+        int32_t q[kMaxDof];
+        bool ok = tube_pose(a, w, cell, q) && replay(p, q, nullptr);
+        valid[idx] = ok ? 1 : 0;
+    }
+}
+
+hipError_t launch_tube_valid(const TubeArgs& a, uint8_t* valid, hipStream_t st) {
+    uint64_t total = (uint64_t)(a.W + 1) * a.slab;
+    hipLaunchKernelGGL(k_tube_valid, dim3(grid_for(total)), dim3(kBlock), 0, st, a, valid);
+    return hipGetLastError();
+}
+
+constexpr int kTubeThreads = 1024;
+
+// One block: R_0 = {start}; R_w = valid_w AND (R_{w-1} dilated by delta in every joint,
+// moved from frame w-1 to frame w one joint at a time); then the backward choice from
+// the goal: at each waypoint the reachable pose within delta of the next one that is
+// closest (L1) to the guide, ties by the lexicographically smallest pose.
+__global__ void __launch_bounds__(kTubeThreads) k_tube_solve(TubeArgs a, const uint8_t* valid, uint8_t* reach,
+                                                             uint8_t* tmp0, uint8_t* tmp1, int32_t* path,
+                                                             int32_t* status) {
+    const int tid = threadIdx.x;
+    const int B = 2 * a.r + 1;
+    const uint64_t slab = a.slab;
+    __shared__ uint64_t stride[kMaxDof];
+    __shared__ unsigned long long best_part[kTubeThreads / 64];
+    __shared__ int qcur[kMaxDof];
+    if (tid == 0) {
+        uint64_t s = 1;
+        for (int k = a.n - 1; k >= 0; --k) {
+            stride[k] = s;
+            s *= B;
+        }
+    }
+    for (uint64_t c = tid; c < slab; c += blockDim.x) reach[c] = valid[c];
+    __syncthreads();
+    for (int w = 1; w <= a.W; ++w) {
+        const uint8_t* prev = reach + (uint64_t)(w - 1) * slab;
+        for (int k = 0; k < a.n; ++k) {
+            const uint8_t* src = (k == 0) ? prev : ((k & 1) ? tmp0 : tmp1);
+            uint8_t* dst = (k == a.n - 1) ? reach + (uint64_t)w * slab : ((k & 1) ? tmp1 : tmp0);
+            const int shift = guide_at(a, w, k) - guide_at(a, w - 1, k);
+            for (uint64_t c = tid; c < slab; c += blockDim.x) {
+                int d = (int)((c / stride[k]) % B);
+                uint8_t any = 0;
+                for (int e = -a.delta; e <= a.delta && !any; ++e) {
+                    int dp = d + shift + e;
+                    if (dp < 0 || dp >= B) continue;
+                    any = src[c + (int64_t)(dp - d) * (int64_t)stride[k]];
+                }
+                if (k == a.n - 1) any = any && valid[(uint64_t)w * slab + c];
+                dst[c] = any;
+            }
+            __syncthreads();
+        }
+    }
+    // goal cell: every digit = r (the guide at w = W is the goal)
+    uint64_t gcell = 0;
+    for (int k = 0; k < a.n; ++k) gcell += (uint64_t)a.r * stride[k];
+    if (!reach[(uint64_t)a.W * slab + gcell]) {
+        if (tid == 0) *status = 0;
+        return;
+    }
+    if (tid < a.n) {
+        qcur[tid] = a.goal[tid];
+        path[a.W * a.n + tid] = a.goal[tid];
+    }
+    __syncthreads();
+    for (int w = a.W; w >= 1; --w) {
+        const uint8_t* R = reach + (uint64_t)(w - 1) * slab;
+        unsigned long long best = ~0ull;
+        for (uint64_t c = tid; c < slab; c += blockDim.x) {
+            if (!R[c]) continue;
+            uint64_t cc = c;
+            int l1 = 0;
+            bool near = true;
+            for (int k = a.n - 1; k >= 0; --k) {
+                int d = (int)(cc % B);
+                cc /= B;
+                int g = guide_at(a, w - 1, k);
+                int q = g - a.r + d;
+                int dq = q - qcur[k];
+                if (dq < -a.delta || dq > a.delta) near = false;
+                l1 += abs(q - g);
+            }
+            if (!near) continue;
+            unsigned long long key = ((unsigned long long)l1 << 40) | c;
+            best = key < best ? key : best;
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            unsigned long long o = __shfl_xor(best, off, 64);
+            best = o < best ? o : best;
+        }
+        if ((tid & 63) == 0) best_part[tid >> 6] = best;
+        __syncthreads();
+        if (tid == 0) {
+            unsigned long long b = ~0ull;
+            for (int i = 0; i < (int)(blockDim.x >> 6); ++i) b = best_part[i] < b ? best_part[i] : b;
+            uint64_t c = b & ((1ull << 40) - 1);
+            for (int k = a.n - 1; k >= 0; --k) {
+                int d = (int)(c % B);
+                c /= B;
+                qcur[k] = guide_at(a, w - 1, k) - a.r + d;
+                path[(w - 1) * a.n + k] = qcur[k];
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0) *status = 1;
+}
+
+hipError_t launch_tube_solve(const TubeArgs& a, const uint8_t* valid, uint8_t* reach, uint8_t* tmp0,
+                             uint8_t* tmp1, int32_t* path, int32_t* status, hipStream_t st) {
+    hipLaunchKernelGGL(k_tube_solve, dim3(1), dim3(kTubeThreads), 0, st, a, valid, reach, tmp0, tmp1, path, status);
+    return hipGetLastError();
+}
+
+}  // namespace msc

@@ -1,0 +1,51 @@
+"""The C-ABI library loads and exports every function that include/msc.h declares
+(no compute call: this runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1906_10678_amd import msc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    hdr = open(os.path.join(ROOT, "include", "msc.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:[\w\*]+\s+)+\**(msc_\w+)\s*\(", hdr, re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("msc_ctx_create", "msc_scene_create", "msc_reach", "msc_path", "msc_pose_check",
+                 "msc_debug_set", "msc_last_error"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(msc.LIB_PATH):
+        pytest.fail("libmsc.so is not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(msc.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert sorted(msc.EXPORTS) == declared_functions()
+
+
+def test_struct_layouts_match_header_sizes():
+    # msc_arm: 3 + 3 + 2 + 4*16 int32 = 72 * 4 bytes; msc_opts: 5 * 4 bytes
+    assert ctypes.sizeof(msc.MscArm) == 4 * (3 + 3 + 2 + 4 * 16)
+    assert ctypes.sizeof(msc.MscOpts) == 20
+    assert ctypes.sizeof(msc.MscBox) == 24 and ctypes.sizeof(msc.MscSphere) == 16
+
+
+def test_host_only_entry_points():
+    lib = msc.load_library()
+    assert lib.msc_scene_bytes(256) == 256 * 256 * 4 * 8
+    assert lib.msc_scene_bytes(100) == 100 * 100 * 2 * 8
+    o = msc.MscOpts()
+    lib.msc_opts_default(ctypes.byref(o))
+    assert (o.split_m, o.tube_r0, o.tube_r1, o.reach_retries, o.flags) == (-1, 1, 2, 4, 0)
+    # a NULL context is rejected without touching the device
+    assert lib.msc_reach(None, None, None, None, None, None) == msc.E_ARG
+    assert lib.msc_last_error(None) == b"NULL context"
