@@ -90,6 +90,7 @@ typedef struct { int32_t c[3], r; } msc_sphere;
 
 #define MSC_CAPTURE_SETS 1u /* keep every stage set for msc_debug_set */
 #define MSC_NO_PRUNE 2u     /* disable the distance / orientation pruning (tests) */
+#define MSC_PROFILE 4u      /* time every kernel launch of the call with HIP events */
 
 typedef struct {
     int32_t split_m;       /* forward stages before the join: -1 = adaptive, else 0..dof */
@@ -158,6 +159,52 @@ msc_status msc_pose_check(msc_ctx* ctx, const msc_scene* scene, const msc_arm* a
                           const int32_t* poses_cdeg, int64_t count, uint8_t* valid_out,
                           int32_t* end_out);
 
+/* Worker lanes for msc_batch and the server.  The workspace, minus a region for the
+ * shared segment tables, is split into 1 + nworkers equal windows: one for this
+ * context's own calls, one per worker lane.  Each worker lane has its own HIP stream
+ * (default priority) and host thread, so the stages of different queries overlap on
+ * the device.  Not allowed while a batch or the server runs (E_STATE).  nworkers in
+ * 0..64. */
+msc_status msc_ctx_set_lanes(msc_ctx* ctx, int32_t nworkers);
+/* Workspace bytes of one lane window (what one query may use). */
+uint64_t msc_lane_bytes(msc_ctx* ctx);
+
+/* One query of a batch or of the server.  The caller owns the struct and the arrays it
+ * points to until the query completes. */
+typedef struct {
+    const msc_scene* scene;
+    const msc_arm* arm;
+    int32_t kind;                /* 0 = reach pose (msc_reach), 1 = reach + path (msc_path) */
+    int32_t target[3];
+    const int32_t* start_cdeg;   /* path: [dof] start pose */
+    int32_t waypoints;           /* path: moves W */
+    int32_t max_delta_cdeg;      /* path: max joint change per move */
+    int32_t* out;                /* reach: [dof]; path: [(waypoints+1)*dof] centidegrees */
+    msc_status status;           /* written when the query completes */
+    float latency_ms;            /* written: submission (server) or batch start to completion */
+} msc_query;
+
+/* Batched execution: solve nq independent queries; every worker lane takes the next
+ * unsolved query when it finishes one (with no worker lanes, the context's own lane
+ * solves them in order).  Results are those of msc_reach / msc_path for each query
+ * alone.  Returns MSC_OK once every query ran; per-query results are in q[i].status. */
+msc_status msc_batch(msc_ctx* ctx, msc_query* q, int32_t nq, const msc_opts* opts);
+
+/* Device-memory estimate of one query (bytes), used for admission. */
+uint64_t msc_query_bytes(const msc_query* q);
+
+/* Server with continuous batching over the worker lanes (msc_ctx_set_lanes first).
+ * Queries submitted while others run are admitted as lanes free up, their stages
+ * overlapping on the device; each query is solved exactly as msc_reach / msc_path
+ * would solve it alone (its scene fixes the obstacle grid of its logical tick).
+ * submit returns E_NOMEM if the query's estimate exceeds a lane window and E_STATE if
+ * the server is not running.  poll sets *done = 1 once q->status is written. */
+msc_status msc_server_start(msc_ctx* ctx, const msc_opts* opts);
+msc_status msc_server_submit(msc_ctx* ctx, msc_query* q, uint64_t* ticket);
+msc_status msc_server_poll(msc_ctx* ctx, uint64_t ticket, int32_t* done);
+msc_status msc_server_wait(msc_ctx* ctx, uint64_t ticket);
+msc_status msc_server_stop(msc_ctx* ctx);
+
 /* Statistics of the last msc_reach / msc_path call on this context. */
 typedef struct {
     int32_t split_m;                     /* split actually used */
@@ -172,6 +219,23 @@ typedef struct {
     int32_t reach_index;                 /* path: index of the reach pose used (0 = first) */
 } msc_stats;
 msc_status msc_get_stats(msc_ctx* ctx, msc_stats* out);
+
+/* Kernel launch records of the last call made with MSC_PROFILE, in launch order.  Each
+ * launch is bracketed by two HIP events recorded on the context's stream. */
+typedef enum {
+    MSC_K_FILL = 0, MSC_K_TABLES, MSC_K_RASTER, MSC_K_ORIENT, MSC_K_SEED, MSC_K_EXPAND_FWD,
+    MSC_K_EXPAND_BWD, MSC_K_COMPACT, MSC_K_JOIN, MSC_K_DMARK, MSC_K_DFS, MSC_K_POSE,
+    MSC_K_TUBE_VALID, MSC_K_TUBE_SOLVE, MSC_K_COUNT
+} msc_kernel;
+typedef struct {
+    int32_t kernel;     /* msc_kernel */
+    int32_t stage;      /* stage produced (expansions), else -1 */
+    int64_t in_count;   /* input states (expansions, compaction, join, marking), else 0 */
+    int64_t out_count;  /* new states (expansions), survivors (join, marking), else 0 */
+    float ms;           /* event-to-event duration */
+} msc_timing;
+/* Copy up to cap records into out and set *count to the number recorded. */
+msc_status msc_get_timings(msc_ctx* ctx, msc_timing* out, int32_t cap, int32_t* count);
 
 /* Debug: the tables of segment `stage` of arm (0-based), as built on the device:
  * off[(ia*na + ie)*3 + c] = rounded segment offset, sweep[((ia*na + ie)*S + s)*3 + c]

@@ -68,9 +68,13 @@ hipError_t launch_tables(int na, int S, int L, short4* off, short4* sweep, unsig
                          hipStream_t st);
 hipError_t launch_raster(uint64_t* occ, int n, int wpr, int r, const int32_t* boxes, int nbox,
                          const int32_t* spheres, int nsph, hipStream_t st);
-hipError_t launch_orient(int n, int na, int ia0, int ie0, const int32_t* type, const int32_t* lo,
-                         const int32_t* hi, uint8_t* scratch, uint64_t* rows_ie, uint64_t* rows_ia,
-                         hipStream_t st);
+struct OrientArgs {
+    int n, na, ia0, ie0;
+    int type[kMaxDof], lo[kMaxDof], hi[kMaxDof];
+};
+hipError_t launch_orient(const OrientArgs& a, uint64_t* rows_ie, uint64_t* rows_ia, hipStream_t st);
+// Copy n counters to (host-mapped) memory with one small kernel.
+hipError_t launch_publish(const unsigned long long* src, unsigned long long* dst, int n, hipStream_t st);
 hipError_t launch_seed_fwd(SetView s, GridView g, int x, int y, int z, int ia, int ie,
                            unsigned long long* counter, hipStream_t st);
 hipError_t launch_seed_bwd(SetView s, GridView g, int x, int y, int z, const uint64_t* rows_ie,
@@ -86,12 +90,15 @@ hipError_t launch_compact(SetView s, uint64_t* list, uint64_t cap, unsigned long
                           unsigned long long* overflow, hipStream_t st);
 hipError_t launch_join(const uint64_t* flist, uint64_t count, SetView f, SetView b,
                        unsigned long long* counter, hipStream_t st);
+hipError_t launch_meet(const uint64_t* flist, uint64_t count, SetView fprev, SetView b, SetView c, GridView g,
+                       JointView j, int count_only, unsigned long long* c_count, unsigned long long* kept_count,
+                       unsigned long long* overflow, hipStream_t st);
 hipError_t launch_dmark(const uint64_t* flist, uint64_t count, SetView fprev, SetView fnext,
                         GridView g, JointView j, unsigned long long* counter, hipStream_t st);
 
 struct DfsArgs {
-    const SetView* sets;       // sets[k] = D_k for k <= m, B_k for k > m (k = 0..n)
-    const JointView* joints;   // n joints
+    SetView sets[kMaxDof + 1];  // sets[k] = D_k for k <= m, B_k for k > m (k = 0..n)
+    JointView joints[kMaxDof];
     GridView g;
     int n, m, na, want;
     int ref[kMaxDof];
@@ -102,7 +109,7 @@ struct DfsArgs {
 hipError_t launch_dfs(const DfsArgs& a, hipStream_t st);
 
 struct PoseArgs {
-    const JointView* joints;
+    JointView joints[kMaxDof];
     GridView g;
     int n, na, bx, by, bz, ia0, ie0;
 };
@@ -110,7 +117,7 @@ hipError_t launch_pose_check(const PoseArgs& a, const int32_t* q, int64_t count,
                              int32_t* ends, hipStream_t st);
 
 struct TubeArgs {
-    const JointView* joints;
+    JointView joints[kMaxDof];
     GridView g;
     int n, na, bx, by, bz, ia0, ie0;
     int W, delta, r;

@@ -9,6 +9,8 @@
 // kernel is a dense contraction, so none uses the matrix cores.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "msc_common.h"
 
 namespace msc {
@@ -133,6 +135,7 @@ __device__ void set_remove(const SetView& s, uint64_t key) {
 // Block-wide sum of a per-thread count, one atomic per block.
 __device__ void block_add(unsigned long long v, unsigned long long* dst) {
     __shared__ unsigned long long part[kBlock / 64];
+    __syncthreads();  // the array may still be read by a previous call
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
     int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (lane == 0) part[wave] = v;
@@ -245,36 +248,61 @@ __device__ uint64_t span_bits(long long lo, long long hi, long long x0) {
     return top & ~bot;
 }
 
+constexpr int kObsChunk = 256;
+
 __global__ void k_raster(uint64_t* occ, int n, int wpr, int r, const int32_t* boxes, int nbox,
                          const int32_t* spheres, int nsph) {
-    uint64_t total = (uint64_t)n * n * wpr;
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < total;
-         i += (uint64_t)gridDim.x * blockDim.x) {
-        int xw = (int)(i % wpr);
-        uint64_t row = i / wpr;
-        int y = (int)(row % n), z = (int)(row / n);
-        long long x0 = 64ll * xw;
+    // obstacle lists (possibly in mapped host memory) are staged through LDS in chunks
+    __shared__ int32_t sb[kObsChunk * 6];
+    __shared__ int32_t ss[kObsChunk * 4];
+    const uint64_t total = (uint64_t)n * n * wpr;
+    for (uint64_t base = blockIdx.x * (uint64_t)blockDim.x; base < total; base += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t i = base + threadIdx.x;
+        const bool live = i < total;
+        int xw = 0, y = 0, z = 0;
+        if (live) {
+            xw = (int)(i % wpr);
+            uint64_t row = i / wpr;
+            y = (int)(row % n);
+            z = (int)(row / n);
+        }
+        const long long x0 = 64ll * xw;
         uint64_t bits = 0;
-        for (int b = 0; b < nbox; ++b) {
-            const int32_t* B = boxes + 6 * b;
-            long long ylo = B[1], yhi = (long long)B[1] + B[4] - 1;
-            long long zlo = B[2], zhi = (long long)B[2] + B[5] - 1;
-            long long dy = y < ylo ? ylo - y : (y > yhi ? y - yhi : 0);
-            long long dz = z < zlo ? zlo - z : (z > zhi ? z - zhi : 0);
-            long long rem = (long long)r * r - dy * dy - dz * dz;
-            if (rem < 0) continue;
-            long long w = isqrt_floor(rem);
-            bits |= span_bits((long long)B[0] - w, (long long)B[0] + B[3] - 1 + w, x0);
+        for (int b0 = 0; b0 < nbox; b0 += kObsChunk) {
+            const int cnt = min(kObsChunk, nbox - b0);
+            __syncthreads();
+            for (int t = threadIdx.x; t < cnt * 6; t += blockDim.x) sb[t] = boxes[b0 * 6 + t];
+            __syncthreads();
+            if (!live) continue;
+            for (int b = 0; b < cnt; ++b) {
+                const int32_t* B = sb + 6 * b;
+                long long ylo = B[1], yhi = (long long)B[1] + B[4] - 1;
+                long long zlo = B[2], zhi = (long long)B[2] + B[5] - 1;
+                long long dy = y < ylo ? ylo - y : (y > yhi ? y - yhi : 0);
+                long long dz = z < zlo ? zlo - z : (z > zhi ? z - zhi : 0);
+                long long rem = (long long)r * r - dy * dy - dz * dz;
+                if (rem < 0) continue;
+                long long w = isqrt_floor(rem);
+                bits |= span_bits((long long)B[0] - w, (long long)B[0] + B[3] - 1 + w, x0);
+            }
         }
-        for (int s = 0; s < nsph; ++s) {
-            const int32_t* P = spheres + 4 * s;
-            long long dy = y - P[1], dz = z - P[2];
-            long long rr = (long long)P[3] + r;
-            long long rem = rr * rr - dy * dy - dz * dz;
-            if (rem < 0) continue;
-            long long w = isqrt_floor(rem);
-            bits |= span_bits((long long)P[0] - w, (long long)P[0] + w, x0);
+        for (int s0 = 0; s0 < nsph; s0 += kObsChunk) {
+            const int cnt = min(kObsChunk, nsph - s0);
+            __syncthreads();
+            for (int t = threadIdx.x; t < cnt * 4; t += blockDim.x) ss[t] = spheres[s0 * 4 + t];
+            __syncthreads();
+            if (!live) continue;
+            for (int b = 0; b < cnt; ++b) {
+                const int32_t* P = ss + 4 * b;
+                long long dy = y - P[1], dz = z - P[2];
+                long long rr = (long long)P[3] + r;
+                long long rem = rr * rr - dy * dy - dz * dz;
+                if (rem < 0) continue;
+                long long w = isqrt_floor(rem);
+                bits |= span_bits((long long)P[0] - w, (long long)P[0] + w, x0);
+            }
         }
+        if (!live) continue;
         if (x0 + 64 > n) bits |= span_bits(n, x0 + 63, x0);
         occ[i] = bits;
     }
@@ -290,52 +318,68 @@ hipError_t launch_raster(uint64_t* occ, int n, int wpr, int r, const int32_t* bo
 
 // ---------------------------------------------------------------------------
 // Orientation reachability O_k (k = 0..n): orientations the chain can have after k
-// joints, positions ignored.  One block; O_k in `scratch` as bytes, then as 256-bit
-// rows: rows_ie[(k*na + ia)*4 + w] holds bit ie, rows_ia[(k*na + ie)*4 + w] bit ia.
+// joints, positions ignored.  Yaw joints move only the azimuth index and pitch joints
+// only the elevation index, so O_k = IA_k x IE_k with IA_k (IE_k) the start index
+// plus the cyclic Minkowski sum of the yaw (pitch) windows so far.  One block;
+// written as 256-bit rows: rows_ie[(k*na + ia)*4 + w] holds bit ie,
+// rows_ia[(k*na + ie)*4 + w] holds bit ia.
 // ---------------------------------------------------------------------------
-__global__ void k_orient(int n, int na, int ia0, int ie0, const int32_t* type, const int32_t* lo,
-                         const int32_t* hi, uint8_t* scratch, uint64_t* rows_ie, uint64_t* rows_ia) {
-    const int na2 = na * na;
-    for (int o = threadIdx.x; o < na2; o += blockDim.x) scratch[o] = (o == ia0 * na + ie0) ? 1 : 0;
+__global__ void k_orient(OrientArgs oa, uint64_t* rows_ie, uint64_t* rows_ia) {
+    const int n = oa.n, na = oa.na, ia0 = oa.ia0, ie0 = oa.ie0;
+    __shared__ uint8_t A[kMaxNa], E[kMaxNa], T[kMaxNa];
+    __shared__ uint64_t Abits[4], Ebits[4];
+    const int tid = threadIdx.x;
+    for (int t = tid; t < na; t += blockDim.x) {
+        A[t] = (t == ia0);
+        E[t] = (t == ie0);
+    }
     __syncthreads();
-    for (int k = 1; k <= n; ++k) {
-        const uint8_t* prev = scratch + (size_t)(k - 1) * na2;
-        uint8_t* cur = scratch + (size_t)k * na2;
-        int t = type[k - 1];
-        for (int o = threadIdx.x; o < na2; o += blockDim.x) {
-            int ia = o / na, ie = o % na;
-            uint8_t any = 0;
-            for (int a = lo[k - 1]; a <= hi[k - 1] && !any; ++a) {
-                int pia = t == 0 ? wrap_na(ia - a, na) : ia;
-                int pie = t == 0 ? ie : wrap_na(ie - a, na);
-                any = prev[pia * na + pie];
+    for (int k = 0; k <= n; ++k) {
+        if (k > 0) {
+            const bool yaw = oa.type[k - 1] == 0;
+            const int lo = oa.lo[k - 1], hi = oa.hi[k - 1];
+            uint8_t* S = yaw ? A : E;
+            for (int t = tid; t < na; t += blockDim.x) {
+                uint8_t any = 0;
+                for (int a = lo; a <= hi && !any; ++a) any = S[wrap_na(t - a, na)];
+                T[t] = any;
             }
-            cur[o] = any;
+            __syncthreads();
+            for (int t = tid; t < na; t += blockDim.x) S[t] = T[t];
+            __syncthreads();
+        }
+        if (tid < 4) {
+            uint64_t a = 0, e = 0;
+            for (int b = 0; b < 64; ++b) {
+                int u = 64 * tid + b;
+                if (u >= na) break;
+                if (A[u]) a |= 1ull << b;
+                if (E[u]) e |= 1ull << b;
+            }
+            Abits[tid] = a;
+            Ebits[tid] = e;
+        }
+        __syncthreads();
+        for (int idx = tid; idx < na * 4; idx += blockDim.x) {
+            int v = idx >> 2, w = idx & 3;
+            rows_ie[((size_t)k * na + v) * 4 + w] = A[v] ? Ebits[w] : 0ull;
+            rows_ia[((size_t)k * na + v) * 4 + w] = E[v] ? Abits[w] : 0ull;
         }
         __syncthreads();
     }
-    for (int idx = threadIdx.x; idx < (n + 1) * na * 4; idx += blockDim.x) {
-        int w = idx & 3;
-        int rowi = idx >> 2;
-        int k = rowi / na, v = rowi % na;
-        const uint8_t* O = scratch + (size_t)k * na2;
-        uint64_t bie = 0, bia = 0;
-        for (int b = 0; b < 64; ++b) {
-            int u = 64 * w + b;
-            if (u >= na) break;
-            if (O[v * na + u]) bie |= 1ull << b;   // row over ie for ia = v
-            if (O[u * na + v]) bia |= 1ull << b;   // row over ia for ie = v
-        }
-        rows_ie[idx] = bie;
-        rows_ia[idx] = bia;
-    }
 }
 
-hipError_t launch_orient(int n, int na, int ia0, int ie0, const int32_t* type, const int32_t* lo,
-                         const int32_t* hi, uint8_t* scratch, uint64_t* rows_ie, uint64_t* rows_ia,
-                         hipStream_t st) {
-    hipLaunchKernelGGL(k_orient, dim3(1), dim3(1024), 0, st, n, na, ia0, ie0, type, lo, hi, scratch, rows_ie,
-                       rows_ia);
+hipError_t launch_orient(const OrientArgs& a, uint64_t* rows_ie, uint64_t* rows_ia, hipStream_t st) {
+    hipLaunchKernelGGL(k_orient, dim3(1), dim3(256), 0, st, a, rows_ie, rows_ia);
+    return hipGetLastError();
+}
+
+__global__ void k_publish(const unsigned long long* src, unsigned long long* dst, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+}
+
+hipError_t launch_publish(const unsigned long long* src, unsigned long long* dst, int n, hipStream_t st) {
+    hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, st, src, dst, n);
     return hipGetLastError();
 }
 
@@ -534,68 +578,114 @@ hipError_t launch_expand_bwd(const uint64_t* in, uint64_t count, SetView out, Gr
 }
 
 // ---------------------------------------------------------------------------
-// Compaction: the members of a set into a list.  Each lane owns one word (dense:
-// its set bits; hash: an occupied, not removed slot); a wave prefix sum of the
-// lanes' counts gives every lane its output offset after one atomicAdd per wave.
+// Compaction: the members of a set into a list.  A block takes tiles of
+// kBlock * kCompactWords words (each thread keeps its words in registers), counts
+// their members (dense: set bits; hash: occupied, not removed slots), computes a
+// block-wide exclusive scan and reserves the tile's output range with one atomicAdd.
 // ---------------------------------------------------------------------------
+constexpr int kCompactWords = 16;
+
+// q = n / d, r = n % d for n < 2^53, via a double reciprocal and one correction step.
+__device__ __forceinline__ void divmod_big(uint64_t n, uint32_t d, double inv, uint64_t& q, uint32_t& r) {
+    uint64_t qq = (uint64_t)((double)n * inv);
+    int64_t rr = (int64_t)(n - qq * (uint64_t)d);
+    while (rr < 0) {
+        --qq;
+        rr += d;
+    }
+    while (rr >= (int64_t)d) {
+        ++qq;
+        rr -= d;
+    }
+    q = qq;
+    r = (uint32_t)rr;
+}
+
+__device__ __forceinline__ int member_count(const SetView& s, uint64_t w) {
+    if (s.kind == kDense) return __popcll(w);
+    return (w != kEmpty && !(w & kDead)) ? 1 : 0;
+}
+
 __global__ void __launch_bounds__(kBlock) k_compact(SetView s, uint64_t* list, uint64_t cap,
                                                     unsigned long long* counter,
                                                     unsigned long long* overflow) {
-    const int lane = threadIdx.x & 63;
-    const uint64_t na2 = (uint64_t)s.na * s.na;
-    for (uint64_t base = blockIdx.x * (uint64_t)blockDim.x; base < s.cap;
-         base += (uint64_t)gridDim.x * blockDim.x) {
-        uint64_t i = base + threadIdx.x;
-        uint64_t w = i < s.cap ? s.words[i] : (s.kind == kDense ? 0ull : kEmpty);
-        int c;
-        if (s.kind == kDense)
-            c = __popcll(w);
-        else
-            c = (w != kEmpty && !(w & kDead)) ? 1 : 0;
-        int scan = c;
+    __shared__ unsigned int wave_off[kBlock / 64];
+    __shared__ unsigned long long tile_base;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t na2 = (uint32_t)(s.na * s.na);
+    const double inv_na2 = 1.0 / (double)na2;
+    const uint64_t tile = (uint64_t)kBlock * kCompactWords;
+    for (uint64_t t0 = blockIdx.x * tile; t0 < s.cap; t0 += (uint64_t)gridDim.x * tile) {
+        uint64_t wv[kCompactWords];
+        unsigned int c = 0;
+#pragma unroll
+        for (int j = 0; j < kCompactWords; ++j) {
+            uint64_t i = t0 + (uint64_t)j * kBlock + tid;
+            wv[j] = i < s.cap ? s.words[i] : (s.kind == kDense ? 0ull : kEmpty);
+            c += member_count(s, wv[j]);
+        }
+        unsigned int incl = c;
         for (int off = 1; off < 64; off <<= 1) {
-            int t = __shfl_up(scan, off, 64);
-            if (lane >= off) scan += t;
+            unsigned int t = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += t;
         }
-        unsigned long long wbase = 0;
-        if (lane == 63 && scan) wbase = atomicAdd(counter, (unsigned long long)scan);
-        wbase = __shfl(wbase, 63, 64);
-        uint64_t pos = wbase + (uint64_t)(scan - c);
-        if (!c) continue;
-        if (s.kind == kDense) {
-            uint64_t bits = w;
-            while (bits) {
-                int b = __ffsll((unsigned long long)bits) - 1;
-                bits &= bits - 1;
-                uint64_t bit = i * 64 + (uint64_t)b;
-                uint64_t vox = bit / na2;
-                int o = (int)(bit - vox * na2);
-                int dx = (int)(vox % (uint64_t)s.nx);
-                uint64_t r = vox / (uint64_t)s.nx;
-                int dy = (int)(r % (uint64_t)s.ny);
-                int dz = (int)(r / (uint64_t)s.ny);
-                int hi = o / s.na, lo = o % s.na;
-                int ia = s.fast_ia ? lo : hi;
-                int ie = s.fast_ia ? hi : lo;
-                if (pos < cap)
-                    list[pos] = pack_key(s.x0 + dx, s.y0 + dy, s.z0 + dz, ia, ie);
-                else
-                    atomicAdd(overflow, 1ull);
-                ++pos;
+        if (lane == 63) wave_off[wave] = incl;
+        __syncthreads();
+        if (tid == 0) {
+            unsigned int tot = 0;
+            for (int w = 0; w < kBlock / 64; ++w) {
+                unsigned int v = wave_off[w];
+                wave_off[w] = tot;
+                tot += v;
             }
-        } else {
-            if (pos < cap)
-                list[pos] = w;
-            else
-                atomicAdd(overflow, 1ull);
+            tile_base = tot ? atomicAdd(counter, (unsigned long long)tot) : 0ull;
         }
+        __syncthreads();
+        uint64_t pos = tile_base + wave_off[wave] + (incl - c);
+        if (c) {
+#pragma unroll
+            for (int j = 0; j < kCompactWords; ++j) {
+                uint64_t w = wv[j];
+                uint64_t i = t0 + (uint64_t)j * kBlock + tid;
+                if (s.kind == kDense) {
+                    while (w) {
+                        int b = __ffsll((unsigned long long)w) - 1;
+                        w &= w - 1;
+                        uint64_t vox;
+                        uint32_t o;
+                        divmod_big(i * 64 + (uint64_t)b, na2, inv_na2, vox, o);
+                        uint32_t v32 = (uint32_t)vox;
+                        uint32_t dx = v32 % (uint32_t)s.nx;
+                        uint32_t r2 = v32 / (uint32_t)s.nx;
+                        uint32_t dy = r2 % (uint32_t)s.ny;
+                        uint32_t dz = r2 / (uint32_t)s.ny;
+                        uint32_t hi = o / (uint32_t)s.na, lo = o % (uint32_t)s.na;
+                        int ia = s.fast_ia ? (int)lo : (int)hi;
+                        int ie = s.fast_ia ? (int)hi : (int)lo;
+                        if (pos < cap)
+                            list[pos] = pack_key(s.x0 + (int)dx, s.y0 + (int)dy, s.z0 + (int)dz, ia, ie);
+                        else
+                            atomicAdd(overflow, 1ull);
+                        ++pos;
+                    }
+                } else if (member_count(s, w)) {
+                    if (pos < cap)
+                        list[pos] = w;
+                    else
+                        atomicAdd(overflow, 1ull);
+                    ++pos;
+                }
+            }
+        }
+        __syncthreads();
     }
 }
 
 hipError_t launch_compact(SetView s, uint64_t* list, uint64_t cap, unsigned long long* counter,
                           unsigned long long* overflow, hipStream_t st) {
-    hipLaunchKernelGGL(k_compact, dim3(grid_for(s.cap, kBlock, 8192)), dim3(kBlock), 0, st, s, list, cap, counter,
-                       overflow);
+    uint64_t tiles = (s.cap + (uint64_t)kBlock * kCompactWords - 1) / ((uint64_t)kBlock * kCompactWords);
+    uint32_t blocks = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(tiles, 1), 4096);
+    hipLaunchKernelGGL(k_compact, dim3(blocks), dim3(kBlock), 0, st, s, list, cap, counter, overflow);
     return hipGetLastError();
 }
 
@@ -620,6 +710,68 @@ hipError_t launch_join(const uint64_t* flist, uint64_t count, SetView f, SetView
                        unsigned long long* counter, hipStream_t st) {
     if (count == 0) return hipSuccess;
     hipLaunchKernelGGL(k_join, dim3(grid_for(count)), dim3(kBlock), 0, st, flist, count, f, b, counter);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Meet of the two pathways at the transition into stage m: every state of F_{m-1}
+// is tried against every angle of joint m; a successor counts only if it is in B_m
+// (tested first, before the segment test) and the segment is clear.  The hits are
+// C_m = F_m intersected with B_m (inserted into `c`); the states of F_{m-1} without a
+// hit are removed from `fprev`, which leaves D_{m-1}.  F_m is never built.  With
+// count_only the kernel only counts the hits (duplicates included), which sizes C.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_meet(const uint64_t* __restrict__ flist, uint64_t count, SetView fprev,
+                                                 SetView b, SetView c, GridView g, JointView j, int count_only,
+                                                 unsigned long long* c_count, unsigned long long* kept_count,
+                                                 unsigned long long* overflow) {
+    const int na = b.na;
+    unsigned long long added = 0, kept = 0, ovf = 0;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < count;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t key = flist[i];
+        int x, y, z, ia, ie;
+        unpack_key(key, x, y, z, ia, ie);
+        if (ia >= na || ie >= na) continue;
+        bool hit = false;
+        for (int a = j.lo; a <= j.hi; ++a) {
+            int ia2 = ia, ie2 = ie;
+            if (j.type == 0)
+                ia2 = wrap_na(ia + a, na);
+            else
+                ie2 = wrap_na(ie + a, na);
+            const int o = ia2 * na + ie2;
+            const short4 d = j.off[o];
+            const int x2 = x + d.x, y2 = y + d.y, z2 = z + d.z;
+            if (!set_member(b, pack_key(x2, y2, z2, ia2, ie2))) continue;
+            if (!segment_clear(g, j, o, x, y, z)) continue;
+            hit = true;
+            if (count_only) {
+                ++added;
+                continue;
+            }
+            int r = set_insert(c, x2, y2, z2, ia2, ie2);
+            if (r > 0)
+                ++added;
+            else if (r < 0)
+                ++ovf;
+        }
+        if (hit)
+            ++kept;
+        else if (!count_only)
+            set_remove(fprev, key);
+    }
+    block_add(added, c_count);
+    block_add(kept, kept_count);
+    if (ovf) atomicAdd(overflow, ovf);
+}
+
+hipError_t launch_meet(const uint64_t* flist, uint64_t count, SetView fprev, SetView b, SetView c, GridView g,
+                       JointView j, int count_only, unsigned long long* c_count, unsigned long long* kept_count,
+                       unsigned long long* overflow, hipStream_t st) {
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_meet, dim3(grid_for(count)), dim3(kBlock), 0, st, flist, count, fprev, b, c, g, j,
+                       count_only, c_count, kept_count, overflow);
     return hipGetLastError();
 }
 
@@ -804,7 +956,8 @@ hipError_t launch_dfs(const DfsArgs& a, hipStream_t st) {
 // ---------------------------------------------------------------------------
 // Pose replay: one thread per pose.
 // ---------------------------------------------------------------------------
-__device__ bool replay(const PoseArgs& a, const int32_t* q, int32_t* end) {
+template <class Args>
+__device__ bool replay(const Args& a, const int32_t* q, int32_t* end) {
     int x = a.bx, y = a.by, z = a.bz, ia = a.ia0, ie = a.ie0;
     bool ok = cell_free(a.g, x, y, z);
     for (int k = 0; k < a.n; ++k) {
@@ -872,22 +1025,12 @@ __device__ bool tube_pose(const TubeArgs& a, int w, uint64_t cell, int32_t* q) {
 
 __global__ void k_tube_valid(TubeArgs a, uint8_t* valid) {
     const uint64_t total = (uint64_t)(a.W + 1) * a.slab;
-    PoseArgs p;
-    p.joints = a.joints;
-    p.g = a.g;
-    p.n = a.n;
-    p.na = a.na;
-    p.bx = a.bx;
-    p.by = a.by;
-    p.bz = a.bz;
-    p.ia0 = a.ia0;
-    p.ie0 = a.ie0;
     for (uint64_t idx = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; idx < total;
          idx += (uint64_t)gridDim.x * blockDim.x) {
         int w = (int)(idx / a.slab);
         uint64_t cell = idx - (uint64_t)w * a.slab;
         int32_t q[kMaxDof];
-        bool ok = tube_pose(a, w, cell, q) && replay(p, q, nullptr);
+        bool ok = tube_pose(a, w, cell, q) && replay(a, q, nullptr);
         valid[idx] = ok ? 1 : 0;
     }
 }
@@ -899,80 +1042,95 @@ hipError_t launch_tube_valid(const TubeArgs& a, uint8_t* valid, hipStream_t st) 
 }
 
 constexpr int kTubeThreads = 1024;
+constexpr uint32_t kSmallSlab = 8192;
 
-// One block: R_0 = {start}; R_w = valid_w AND (R_{w-1} dilated by delta in every joint,
-// moved from frame w-1 to frame w one joint at a time); then the backward choice from
-// the goal: at each waypoint the reachable pose within delta of the next one that is
-// closest (L1) to the guide, ties by the lexicographically smallest pose.
-__global__ void __launch_bounds__(kTubeThreads) k_tube_solve(TubeArgs a, const uint8_t* valid, uint8_t* reach,
-                                                             uint8_t* tmp0, uint8_t* tmp1, int32_t* path,
-                                                             int32_t* status) {
-    const int tid = threadIdx.x;
-    const int B = 2 * a.r + 1;
-    const uint64_t slab = a.slab;
-    __shared__ uint64_t stride[kMaxDof];
+// Dilation of one frame cell along joint k: R(c) = OR over e in [-delta, delta] of the
+// source cell whose digit k is d + shift + e (the previous frame is shifted by
+// `shift` = g_w[k] - g_{w-1}[k] against the current one).
+__device__ __forceinline__ uint8_t dilate_cell(const uint8_t* src, uint32_t c, uint32_t stride, int B, int shift,
+                                               int delta) {
+    int d = (int)((c / stride) % (uint32_t)B);
+    uint8_t any = 0;
+    for (int e = -delta; e <= delta && !any; ++e) {
+        int dp = d + shift + e;
+        if (dp < 0 || dp >= B) continue;
+        any = src[(int64_t)c + (int64_t)(dp - d) * (int64_t)stride];
+    }
+    return any;
+}
+
+__device__ __forceinline__ void tube_strides(const TubeArgs& a, uint32_t* stride) {
+    uint32_t s = 1;
+    for (int k = a.n - 1; k >= 0; --k) {
+        stride[k] = s;
+        s *= (uint32_t)(2 * a.r + 1);
+    }
+}
+
+// Backward choice ("Smooth sequence computation": work backward from the reach pose,
+// at each waypoint the solution closest in configuration to the one found): among the
+// reachable poses of frame w-1 within delta of the current pose, the one with the
+// smallest L1 distance to the guide, ties by the smallest pose (= smallest cell).
+// Runs in one block; `frame0` is frame 0's array, `reach` the frames 1..W.
+__device__ void tube_trace_block(const TubeArgs& a, const uint8_t* frame0, const uint8_t* reach, int32_t* path,
+                                 int32_t* status, const uint32_t* dig) {
     __shared__ unsigned long long best_part[kTubeThreads / 64];
     __shared__ int qcur[kMaxDof];
+    __shared__ int flo[kMaxDof];   // frame origin g_{w-1} - r of the waypoint being chosen
+    __shared__ uint32_t stride[kMaxDof];
+    __shared__ int fail;
+    const int tid = threadIdx.x;
+    const int B = 2 * a.r + 1;
+    const uint32_t slab = (uint32_t)a.slab;
     if (tid == 0) {
-        uint64_t s = 1;
-        for (int k = a.n - 1; k >= 0; --k) {
-            stride[k] = s;
-            s *= B;
-        }
-    }
-    for (uint64_t c = tid; c < slab; c += blockDim.x) reach[c] = valid[c];
-    __syncthreads();
-    for (int w = 1; w <= a.W; ++w) {
-        const uint8_t* prev = reach + (uint64_t)(w - 1) * slab;
-        for (int k = 0; k < a.n; ++k) {
-            const uint8_t* src = (k == 0) ? prev : ((k & 1) ? tmp0 : tmp1);
-            uint8_t* dst = (k == a.n - 1) ? reach + (uint64_t)w * slab : ((k & 1) ? tmp1 : tmp0);
-            const int shift = guide_at(a, w, k) - guide_at(a, w - 1, k);
-            for (uint64_t c = tid; c < slab; c += blockDim.x) {
-                int d = (int)((c / stride[k]) % B);
-                uint8_t any = 0;
-                for (int e = -a.delta; e <= a.delta && !any; ++e) {
-                    int dp = d + shift + e;
-                    if (dp < 0 || dp >= B) continue;
-                    any = src[c + (int64_t)(dp - d) * (int64_t)stride[k]];
-                }
-                if (k == a.n - 1) any = any && valid[(uint64_t)w * slab + c];
-                dst[c] = any;
-            }
-            __syncthreads();
-        }
-    }
-    // goal cell: every digit = r (the guide at w = W is the goal)
-    uint64_t gcell = 0;
-    for (int k = 0; k < a.n; ++k) gcell += (uint64_t)a.r * stride[k];
-    if (!reach[(uint64_t)a.W * slab + gcell]) {
-        if (tid == 0) *status = 0;
-        return;
+        tube_strides(a, stride);
+        fail = 0;
     }
     if (tid < a.n) {
         qcur[tid] = a.goal[tid];
         path[a.W * a.n + tid] = a.goal[tid];
     }
     __syncthreads();
+    // candidates: the (2 delta + 1)^n box around the current pose, or the whole frame
+    uint64_t ncand = 1;
+    for (int k = 0; k < a.n && ncand <= slab; ++k) ncand *= (uint64_t)(2 * a.delta + 1);
+    const bool by_box = ncand <= slab && !dig;
+    if (!by_box) ncand = slab;
+    const uint32_t span = (uint32_t)(2 * a.delta + 1);
     for (int w = a.W; w >= 1; --w) {
-        const uint8_t* R = reach + (uint64_t)(w - 1) * slab;
+        const uint8_t* R = (w - 1 == 0) ? frame0 : reach + (uint64_t)(w - 1) * slab;
+        if (tid < a.n) flo[tid] = guide_at(a, w - 1, tid) - a.r;
+        __syncthreads();
         unsigned long long best = ~0ull;
-        for (uint64_t c = tid; c < slab; c += blockDim.x) {
-            if (!R[c]) continue;
-            uint64_t cc = c;
+        for (uint32_t t = tid; t < ncand; t += blockDim.x) {
+            uint32_t cell = 0;
             int l1 = 0;
-            bool near = true;
+            bool ok = true;
+            uint32_t rest = t;
             for (int k = a.n - 1; k >= 0; --k) {
-                int d = (int)(cc % B);
-                cc /= B;
-                int g = guide_at(a, w - 1, k);
-                int q = g - a.r + d;
-                int dq = q - qcur[k];
-                if (dq < -a.delta || dq > a.delta) near = false;
-                l1 += abs(q - g);
+                int d;
+                if (by_box) {
+                    uint32_t q = rest / span;
+                    int e = (int)(rest - q * span) - a.delta;
+                    rest = q;
+                    d = qcur[k] + e - flo[k];
+                    if (d < 0 || d >= B) ok = false;
+                } else {
+                    if (dig) {
+                        d = B == 1 ? 0 : (int)((dig[t] >> (4 * k)) & 15u);
+                    } else {
+                        uint32_t q = rest / (uint32_t)B;
+                        d = (int)(rest - q * (uint32_t)B);
+                        rest = q;
+                    }
+                    int dq = flo[k] + d - qcur[k];
+                    if (dq < -a.delta || dq > a.delta) ok = false;
+                }
+                cell += (uint32_t)(d < 0 ? 0 : d) * stride[k];
+                l1 += abs(d - a.r);   // |q - g| with q = g - r + d
             }
-            if (!near) continue;
-            unsigned long long key = ((unsigned long long)l1 << 40) | c;
+            if (!ok || !R[cell]) continue;
+            unsigned long long key = ((unsigned long long)l1 << 40) | cell;
             best = key < best ? key : best;
         }
         for (int off = 32; off > 0; off >>= 1) {
@@ -984,22 +1142,140 @@ __global__ void __launch_bounds__(kTubeThreads) k_tube_solve(TubeArgs a, const u
         if (tid == 0) {
             unsigned long long b = ~0ull;
             for (int i = 0; i < (int)(blockDim.x >> 6); ++i) b = best_part[i] < b ? best_part[i] : b;
-            uint64_t c = b & ((1ull << 40) - 1);
-            for (int k = a.n - 1; k >= 0; --k) {
-                int d = (int)(c % B);
-                c /= B;
-                qcur[k] = guide_at(a, w - 1, k) - a.r + d;
-                path[(w - 1) * a.n + k] = qcur[k];
+            if (b == ~0ull) {
+                fail = 1;
+            } else {
+                uint32_t c = (uint32_t)(b & ((1ull << 40) - 1));
+                for (int k = a.n - 1; k >= 0; --k) {
+                    int d = (int)(c % (uint32_t)B);
+                    c /= (uint32_t)B;
+                    qcur[k] = flo[k] + d;
+                    path[(w - 1) * a.n + k] = qcur[k];
+                }
             }
         }
         __syncthreads();
+        if (fail) break;
     }
-    if (tid == 0) *status = 1;
+    if (tid == 0) *status = fail ? 0 : 1;
+}
+
+// Small frames: the whole dynamic program in one block, working arrays in LDS.
+// R_0 = {start}; R_w = valid_w AND (R_{w-1} dilated by delta in every joint, moved from
+// frame w-1 to frame w one joint at a time); frames 1..W are kept for the choice.
+__global__ void __launch_bounds__(kTubeThreads) k_tube_small(TubeArgs a, const uint8_t* valid, uint8_t* reach,
+                                                             int32_t* path, int32_t* status) {
+    __shared__ uint8_t A[kSmallSlab], T0[kSmallSlab], T1[kSmallSlab];
+    __shared__ uint32_t dig[kSmallSlab];   // digits of every cell, 4 bits per joint
+    __shared__ uint32_t stride[kMaxDof];
+    const int tid = threadIdx.x;
+    const int B = 2 * a.r + 1;
+    const uint32_t slab = (uint32_t)a.slab;
+    if (tid == 0) tube_strides(a, stride);
+    for (uint32_t c = tid; c < slab; c += blockDim.x) {
+        A[c] = valid[c];
+        uint32_t packed = 0, rest = c;
+        if (B > 1) {
+            for (int k = a.n - 1; k >= 0; --k) {
+                packed |= (rest % (uint32_t)B) << (4 * k);
+                rest /= (uint32_t)B;
+            }
+        }
+        dig[c] = packed;
+    }
+    __syncthreads();
+    for (int w = 1; w <= a.W; ++w) {
+        const uint8_t* vw = valid + (uint64_t)w * slab;
+        for (int k = 0; k < a.n; ++k) {
+            const uint8_t* src = (k == 0) ? A : ((k & 1) ? T0 : T1);
+            uint8_t* dst = (k == a.n - 1) ? A : ((k & 1) ? T1 : T0);
+            const int shift = guide_at(a, w, k) - guide_at(a, w - 1, k);
+            // the last pass writes A in place of R_{w-1}: read every source cell of
+            // this pass before any thread writes
+            constexpr int kPer = (kSmallSlab + kTubeThreads - 1) / kTubeThreads;
+            uint8_t vals[kPer];
+#pragma unroll
+            for (int i = 0; i < kPer; ++i) {
+                uint32_t c = tid + (uint32_t)i * kTubeThreads;
+                uint8_t any = 0;
+                if (c < slab) {
+                    const int d = B == 1 ? 0 : (int)((dig[c] >> (4 * k)) & 15u);
+                    for (int e = -a.delta; e <= a.delta && !any; ++e) {
+                        int dp = d + shift + e;
+                        if (dp < 0 || dp >= B) continue;
+                        any = src[(int)c + (dp - d) * (int)stride[k]];
+                    }
+                    if (k == a.n - 1) any = any && vw[c];
+                }
+                vals[i] = any;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < kPer; ++i) {
+                uint32_t c = tid + (uint32_t)i * kTubeThreads;
+                if (c < slab) dst[c] = vals[i];
+            }
+            __syncthreads();
+        }
+        uint8_t* rw = reach + (uint64_t)w * slab;
+        for (uint32_t c = tid; c < slab; c += blockDim.x) rw[c] = A[c];
+        __syncthreads();
+    }
+    // goal cell: every digit = r (the guide at w = W is the goal)
+    uint32_t gcell = 0;
+    for (int k = 0; k < a.n; ++k) gcell += (uint32_t)a.r * stride[k];
+    if (!A[gcell]) {
+        if (tid == 0) *status = 0;
+        return;
+    }
+    tube_trace_block(a, valid, reach, path, status, dig);
+}
+
+// Large frames: one pass of one joint over the whole frame, many blocks.
+__global__ void k_tube_pass(TubeArgs a, int w, int k, const uint8_t* src, uint8_t* dst, const uint8_t* valid_w) {
+    const int B = 2 * a.r + 1;
+    uint32_t stride = 1;
+    for (int j = a.n - 1; j > k; --j) stride *= (uint32_t)B;
+    const int shift = guide_at(a, w, k) - guide_at(a, w - 1, k);
+    const uint32_t slab = (uint32_t)a.slab;
+    for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < slab; c += gridDim.x * blockDim.x) {
+        uint8_t any = dilate_cell(src, c, stride, B, shift, a.delta);
+        if (valid_w) any = any && valid_w[c];
+        dst[c] = any;
+    }
+}
+
+__global__ void __launch_bounds__(kTubeThreads) k_tube_trace(TubeArgs a, const uint8_t* valid, const uint8_t* reach,
+                                                             int32_t* path, int32_t* status) {
+    uint32_t gcell = 0, s = 1;
+    for (int k = a.n - 1; k >= 0; --k) {
+        gcell += (uint32_t)a.r * s;
+        s *= (uint32_t)(2 * a.r + 1);
+    }
+    if (!reach[(uint64_t)a.W * a.slab + gcell]) {
+        if (threadIdx.x == 0) *status = 0;
+        return;
+    }
+    tube_trace_block(a, valid, reach, path, status, nullptr);
 }
 
 hipError_t launch_tube_solve(const TubeArgs& a, const uint8_t* valid, uint8_t* reach, uint8_t* tmp0,
                              uint8_t* tmp1, int32_t* path, int32_t* status, hipStream_t st) {
-    hipLaunchKernelGGL(k_tube_solve, dim3(1), dim3(kTubeThreads), 0, st, a, valid, reach, tmp0, tmp1, path, status);
+    if (a.slab <= kSmallSlab) {
+        hipLaunchKernelGGL(k_tube_small, dim3(1), dim3(kTubeThreads), 0, st, a, valid, reach, path, status);
+        return hipGetLastError();
+    }
+    const uint32_t blocks = grid_for(a.slab);
+    for (int w = 1; w <= a.W; ++w) {
+        const uint8_t* prev = (w == 1) ? valid : reach + (uint64_t)(w - 1) * a.slab;
+        for (int k = 0; k < a.n; ++k) {
+            const uint8_t* src = (k == 0) ? prev : ((k & 1) ? tmp0 : tmp1);
+            uint8_t* dst = (k == a.n - 1) ? reach + (uint64_t)w * a.slab : ((k & 1) ? tmp1 : tmp0);
+            const uint8_t* vw = (k == a.n - 1) ? valid + (uint64_t)w * a.slab : nullptr;
+            hipLaunchKernelGGL(k_tube_pass, dim3(blocks), dim3(kBlock), 0, st, a, w, k, src, dst, vw);
+        }
+    }
+    hipLaunchKernelGGL(k_tube_trace, dim3(1), dim3(kTubeThreads), 0, st, a, valid, reach, path, status);
     return hipGetLastError();
 }
 

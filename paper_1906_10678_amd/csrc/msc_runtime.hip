@@ -8,8 +8,13 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <atomic>
+#include <condition_variable>
+#include <deque>
 #include <map>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -17,6 +22,8 @@
 #include "msc_common.h"
 
 using namespace msc;
+
+struct ServerState;
 
 namespace {
 
@@ -40,27 +47,53 @@ struct StageSet {
 
 }  // namespace
 
-struct msc_ctx {
+// One execution lane: a stream, a window of the workspace, pinned staging, counters
+// and the bookkeeping of the call running on it.  The context's API calls use the
+// control lane; batches and the server run one query at a time on each worker lane.
+struct Lane {
+    msc_ctx* owner = nullptr;
+    int index = 0;
     int device = 0;
     hipStream_t stream = nullptr;
-    char* ws = nullptr;
-    uint64_t ws_bytes = 0;
-    uint64_t lo = 0;   // per-call region grows up from 0
-    uint64_t hi = 0;   // persistent region grows down from ws_bytes
+    bool own_stream = false;
+    char* ws = nullptr;       // this lane's window of the workspace
+    uint64_t lo = 0;          // per-call region grows up from 0
+    uint64_t hi = 0;          // window size
     std::string err;
-    std::map<std::tuple<int, int, int>, TableEntry> tables;
-    unsigned long long* counters = nullptr;  // device, persistent
+    unsigned long long* counters = nullptr;  // device
     int next_counter = 0;
     unsigned long long* ovf = nullptr;       // overflow counter of the current call
-    char* staging = nullptr;                 // pinned host
+    char* staging = nullptr;                 // pinned, mapped host memory
+    char* staging_dev = nullptr;             // its device address
     size_t staging_used = 0;
     msc_stats stats{};
     std::map<std::pair<int, int>, std::vector<uint64_t>> captured;
     int captured_n = 0;
+    // MSC_PROFILE: one event pair per launch of the current call
+    bool profiling = false;
+    std::vector<hipEvent_t> events;
+    std::vector<msc_timing> recs;
+    int last_rec = -1;
+};
+
+struct msc_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;  // the caller's stream (control lane)
+    char* ws = nullptr;
+    uint64_t ws_bytes = 0;
+    uint64_t table_lo = 0;         // tables grow down from ws_bytes to table_lo
+    uint64_t table_top = 0;
+    std::mutex table_mu;
+    std::map<std::tuple<int, int, int>, TableEntry> tables;
+    Lane* control = nullptr;
+    std::vector<Lane*> workers;
+    std::string err;
+    ServerState* server = nullptr;
 };
 
 struct msc_scene {
     msc_ctx* ctx = nullptr;
+    int64_t tick = 0;
     int n = 0, wpr = 0, dilate = 0;
     uint64_t* grid = nullptr;
     uint64_t bytes = 0;
@@ -68,7 +101,7 @@ struct msc_scene {
 
 namespace {
 
-msc_status fail(msc_ctx* c, msc_status st, const char* fmt, ...) {
+msc_status fail(Lane* c, msc_status st, const char* fmt, ...) {
     char buf[512];
     va_list ap;
     va_start(ap, fmt);
@@ -92,7 +125,59 @@ msc_status fail(msc_ctx* c, msc_status st, const char* fmt, ...) {
 
 uint64_t align_up(uint64_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
-msc_status arena_alloc(msc_ctx* c, uint64_t bytes, void** out) {
+// Launch timing (MSC_PROFILE).
+int prof_begin(Lane* c, int kernel, int stage, int64_t in) {
+    c->last_rec = -1;
+    if (!c->profiling) return -1;
+    size_t idx = c->recs.size();
+    while (c->events.size() < 2 * (idx + 1)) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return -1;
+        c->events.push_back(e);
+    }
+    if (hipEventRecord(c->events[2 * idx], c->stream) != hipSuccess) return -1;
+    msc_timing t{};
+    t.kernel = kernel;
+    t.stage = stage;
+    t.in_count = in;
+    t.out_count = 0;
+    t.ms = -1.0f;
+    c->recs.push_back(t);
+    c->last_rec = (int)idx;
+    return (int)idx;
+}
+
+void prof_end(Lane* c, int idx) {
+    if (idx >= 0) (void)hipEventRecord(c->events[2 * idx + 1], c->stream);
+}
+
+void prof_out(Lane* c, int idx, int64_t out) {
+    if (idx >= 0 && idx < (int)c->recs.size()) c->recs[idx].out_count = out;
+}
+
+void prof_finish(Lane* c) {
+    if (!c->profiling) return;
+    (void)hipStreamSynchronize(c->stream);
+    for (size_t i = 0; i < c->recs.size(); ++i) {
+        float ms = -1.0f;
+        if (hipEventElapsedTime(&ms, c->events[2 * i], c->events[2 * i + 1]) == hipSuccess) c->recs[i].ms = ms;
+    }
+}
+
+void prof_reset(Lane* c, uint32_t flags) {
+    c->profiling = (flags & MSC_PROFILE) != 0;
+    c->recs.clear();
+    c->last_rec = -1;
+}
+
+#define LAUNCH(kind, stage, in, expr)                       \
+    do {                                                    \
+        int pi_ = prof_begin(c, (kind), (stage), (in));     \
+        HIP_TRY(expr);                                      \
+        prof_end(c, pi_);                                   \
+    } while (0)
+
+msc_status arena_alloc(Lane* c, uint64_t bytes, void** out) {
     uint64_t b = align_up(bytes ? bytes : 1);
     if (c->lo + b > c->hi) {
         return fail(c, MSC_E_NOMEM, "workspace exhausted: need %llu more bytes (used %llu of %llu)",
@@ -103,41 +188,54 @@ msc_status arena_alloc(msc_ctx* c, uint64_t bytes, void** out) {
     return MSC_OK;
 }
 
-msc_status persist_alloc(msc_ctx* c, uint64_t bytes, void** out) {
+// Shared table region at the top of the workspace (caller holds owner->table_mu).
+msc_status persist_alloc(Lane* c, uint64_t bytes, void** out) {
+    msc_ctx* o = c->owner;
     uint64_t b = align_up(bytes ? bytes : 1);
-    if (c->hi < b || c->hi - b < c->lo) return fail(c, MSC_E_NOMEM, "workspace exhausted (persistent tables)");
-    c->hi -= b;
-    *out = c->ws + c->hi;
+    if (o->table_top < b || o->table_top - b < o->table_lo) return fail(c, MSC_E_NOMEM, "table region exhausted");
+    o->table_top -= b;
+    *out = o->ws + o->table_top;
     return MSC_OK;
 }
 
-void begin_call(msc_ctx* c) {
+void begin_call(Lane* c) {
     c->lo = 0;
     c->staging_used = 0;
     c->next_counter = 0;
     c->err.clear();
 }
 
-// Upload a small host array through the pinned staging buffer (no host sync).
-msc_status upload(msc_ctx* c, const void* src, size_t bytes, void** dev) {
+// A region of the pinned, device-mapped staging buffer: kernels read inputs from it
+// and write small results into it directly (no copy); valid until the call ends.
+msc_status host_area(Lane* c, size_t bytes, void** host, void** dev) {
     size_t b = (bytes + 255) & ~(size_t)255;
     if (c->staging_used + b > kStagingBytes - 4096) return fail(c, MSC_E_NOMEM, "staging buffer exhausted");
-    char* h = c->staging + c->staging_used;
+    *host = c->staging + c->staging_used;
+    *dev = c->staging_dev + c->staging_used;
     c->staging_used += b;
+    return MSC_OK;
+}
+
+// Upload a small host array through the pinned staging buffer (no host sync).
+msc_status upload(Lane* c, const void* src, size_t bytes, void** dev) {
+    void *h, *hd;
+    MSC_TRY(host_area(c, bytes, &h, &hd));
     std::memcpy(h, src, bytes);
     MSC_TRY(arena_alloc(c, bytes, dev));
     HIP_TRY(hipMemcpyAsync(*dev, h, bytes, hipMemcpyHostToDevice, c->stream));
     return MSC_OK;
 }
 
-unsigned long long* take_counter(msc_ctx* c) {
+unsigned long long* take_counter(Lane* c) {
     if (c->next_counter >= kCounters) return nullptr;
     return c->counters + c->next_counter++;
 }
 
-msc_status read_counter(msc_ctx* c, unsigned long long* dev, uint64_t* out) {
-    unsigned long long* h = (unsigned long long*)(c->staging + kStagingBytes - 64);
-    HIP_TRY(hipMemcpyAsync(h, dev, sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream));
+// Counter value on the host: a one-thread kernel stores it into mapped pinned memory.
+msc_status read_counter(Lane* c, unsigned long long* dev, uint64_t* out) {
+    volatile unsigned long long* h = (volatile unsigned long long*)(c->staging + kStagingBytes - 64);
+    unsigned long long* hd = (unsigned long long*)(c->staging_dev + kStagingBytes - 64);
+    HIP_TRY(launch_publish(dev, hd, 1, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     *out = *h;
     return MSC_OK;
@@ -172,7 +270,7 @@ struct Plan {
     int split;   // -1 adaptive
 };
 
-msc_status check_arm(msc_ctx* c, const msc_arm* arm, int grid_n) {
+msc_status check_arm(Lane* c, const msc_arm* arm, int grid_n) {
     if (!arm) return fail(c, MSC_E_ARG, "arm is NULL");
     if (arm->dof < 1 || arm->dof > MSC_MAX_DOF) return fail(c, MSC_E_ARG, "dof %d outside 1..%d", arm->dof, MSC_MAX_DOF);
     if (arm->step_cdeg <= 0 || 36000 % arm->step_cdeg) return fail(c, MSC_E_ARG, "step_cdeg must divide 36000");
@@ -217,10 +315,13 @@ void make_plan(const msc_arm* arm, const int32_t* target, Plan& p) {
     p.split = -1;
 }
 
-msc_status get_table(msc_ctx* c, int na, int S, int L, TableEntry* out) {
+msc_status get_table(Lane* c, int na, int S, int L, TableEntry* out) {
+    // tables are shared by all lanes: built once per (na, S, L) under the owner's lock
+    std::lock_guard<std::mutex> lock(c->owner->table_mu);
+    auto& tables = c->owner->tables;
     auto key = std::make_tuple(na, S, L);
-    auto it = c->tables.find(key);
-    if (it != c->tables.end()) {
+    auto it = tables.find(key);
+    if (it != tables.end()) {
         *out = it->second;
         return MSC_OK;
     }
@@ -239,7 +340,7 @@ msc_status get_table(msc_ctx* c, int na, int S, int L, TableEntry* out) {
     HIP_TRY(hipMemcpyAsync(h, d_max, sizeof(unsigned int), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     t.maxn2 = *h;
-    c->tables[key] = t;
+    tables[key] = t;
     *out = t;
     return MSC_OK;
 }
@@ -280,7 +381,7 @@ Box stage_box(const Plan& p, int N, const std::vector<int64_t>& R, int k) {
 
 // Allocate and clear the structure of one stage set: a dense bitset over the stage box
 // when it is no larger than a hash table sized for `upper` states, else the hash table.
-msc_status make_set(msc_ctx* c, const Plan& p, const Box& box, uint64_t upper, int fast_ia, bool force_dense,
+msc_status make_set(Lane* c, const Plan& p, const Box& box, uint64_t upper, int fast_ia, bool force_dense,
                     StageSet& s) {
     const uint64_t na2 = (uint64_t)p.na * p.na;
     uint64_t dense_words = box.empty() ? 0 : (box.voxels() * na2 + 63) / 64 + 1;
@@ -302,31 +403,31 @@ msc_status make_set(msc_ctx* c, const Plan& p, const Box& box, uint64_t upper, i
         s.view.cap = dense_words;
         MSC_TRY(arena_alloc(c, dense_words * 8, &mem));
         s.view.words = (uint64_t*)mem;
-        HIP_TRY(launch_fill(s.view.words, dense_words, 0ull, c->stream));
+        LAUNCH(MSC_K_FILL, -1, 0, launch_fill(s.view.words, dense_words, 0ull, c->stream));
     } else {
         s.view.kind = kHash;
         s.view.cap = hash_slots;
         MSC_TRY(arena_alloc(c, hash_slots * 8, &mem));
         s.view.words = (uint64_t*)mem;
-        HIP_TRY(launch_fill(s.view.words, hash_slots, kEmpty, c->stream));
+        LAUNCH(MSC_K_FILL, -1, 0, launch_fill(s.view.words, hash_slots, kEmpty, c->stream));
     }
     return MSC_OK;
 }
 
-msc_status ensure_list(msc_ctx* c, StageSet& s) {
+msc_status ensure_list(Lane* c, StageSet& s) {
     if (s.listed) return MSC_OK;
     void* mem;
     MSC_TRY(arena_alloc(c, std::max<uint64_t>(s.count, 1) * 8, &mem));
     s.list = (uint64_t*)mem;
     unsigned long long* ctr = take_counter(c);
     if (!ctr) return fail(c, MSC_E_CAPACITY, "out of counters");
-    HIP_TRY(launch_compact(s.view, s.list, s.count, ctr, c->ovf, c->stream));
+    LAUNCH(MSC_K_COMPACT, -1, (int64_t)s.count, launch_compact(s.view, s.list, s.count, ctr, c->ovf, c->stream));
     s.listed = true;
     return MSC_OK;
 }
 
 // Copy a set's members to the host as sorted keys ((z*N + y)*N + x) << 16 | ia << 8 | ie.
-msc_status capture_set(msc_ctx* c, StageSet& s, int N, int which, int stage) {
+msc_status capture_set(Lane* c, StageSet& s, int N, int which, int stage) {
     std::vector<uint64_t> keys;
     if (s.count) {
         void* mem;
@@ -356,7 +457,7 @@ struct ReachOut {
     int nsol = 0;
 };
 
-msc_status check_overflow(msc_ctx* c, unsigned long long* ovf, const char* what) {
+msc_status check_overflow(Lane* c, unsigned long long* ovf, const char* what) {
     uint64_t v = 0;
     MSC_TRY(read_counter(c, ovf, &v));
     if (v) return fail(c, MSC_E_CAPACITY, "%s overflowed (%llu states without room)", what, (unsigned long long)v);
@@ -365,7 +466,7 @@ msc_status check_overflow(msc_ctx* c, unsigned long long* ovf, const char* what)
 
 // The staged reach search.  Returns MSC_OK with up to `want` solutions (steps) in the
 // canonical order, or MSC_NO_REACH.
-msc_status run_reach(msc_ctx* c, const msc_scene* sc, const Plan& p, int want, bool capture, ReachOut& out) {
+msc_status run_reach(Lane* c, const msc_scene* sc, const Plan& p, int want, bool capture, ReachOut& out) {
     const int n = p.n, na = p.na, N = sc->n;
     const GridView g = grid_view(sc);
     std::memset(&c->stats, 0, sizeof c->stats);
@@ -374,7 +475,7 @@ msc_status run_reach(msc_ctx* c, const msc_scene* sc, const Plan& p, int want, b
     c->captured_n = N;
     out = ReachOut();
 
-    HIP_TRY(launch_fill((uint64_t*)c->counters, kCounters, 0ull, c->stream));
+    LAUNCH(MSC_K_FILL, -1, 0, launch_fill((uint64_t*)c->counters, kCounters, 0ull, c->stream));
     c->ovf = take_counter(c);
 
     // Tables and pruning radii R_j = ceil(max_o |off_j[o]|).
@@ -389,17 +490,22 @@ msc_status run_reach(msc_ctx* c, const msc_scene* sc, const Plan& p, int want, b
     // Orientation reachability rows O_k (k = 0..n).
     uint64_t *rows_ie = nullptr, *rows_ia = nullptr;
     {
-        void *d_type, *d_lo, *d_hi, *scratch, *m1, *m2;
-        MSC_TRY(upload(c, p.type, sizeof(int32_t) * n, &d_type));
-        MSC_TRY(upload(c, p.lo, sizeof(int32_t) * n, &d_lo));
-        MSC_TRY(upload(c, p.hi, sizeof(int32_t) * n, &d_hi));
-        MSC_TRY(arena_alloc(c, (uint64_t)(n + 1) * na * na, &scratch));
+        void *m1, *m2;
         MSC_TRY(arena_alloc(c, (uint64_t)(n + 1) * na * 4 * 8, &m1));
         MSC_TRY(arena_alloc(c, (uint64_t)(n + 1) * na * 4 * 8, &m2));
         rows_ie = (uint64_t*)m1;
         rows_ia = (uint64_t*)m2;
-        HIP_TRY(launch_orient(n, na, p.ia0, p.ie0, (const int32_t*)d_type, (const int32_t*)d_lo,
-                              (const int32_t*)d_hi, (uint8_t*)scratch, rows_ie, rows_ia, c->stream));
+        OrientArgs oa{};
+        oa.n = n;
+        oa.na = na;
+        oa.ia0 = p.ia0;
+        oa.ie0 = p.ie0;
+        for (int k = 0; k < n; ++k) {
+            oa.type[k] = p.type[k];
+            oa.lo[k] = p.lo[k];
+            oa.hi[k] = p.hi[k];
+        }
+        LAUNCH(MSC_K_ORIENT, -1, 0, launch_orient(oa, rows_ie, rows_ia, c->stream));
     }
     auto rows_for = [&](int stage, int yaw) -> const uint64_t* {
         if (!p.prune) return nullptr;
@@ -415,43 +521,55 @@ msc_status run_reach(msc_ctx* c, const msc_scene* sc, const Plan& p, int want, b
         Box b0{p.base[0], p.base[1], p.base[2], 1, 1, 1};
         MSC_TRY(make_set(c, p, b0, 1, 0, false, F[0]));
         unsigned long long* ctr = take_counter(c);
-        HIP_TRY(launch_seed_fwd(F[0].view, g, p.base[0], p.base[1], p.base[2], p.ia0, p.ie0, ctr, c->stream));
+        LAUNCH(MSC_K_SEED, 0, 0, launch_seed_fwd(F[0].view, g, p.base[0], p.base[1], p.base[2], p.ia0, p.ie0, ctr, c->stream));
         MSC_TRY(read_counter(c, ctr, &F[0].count));
         Box bn{p.target[0], p.target[1], p.target[2], 1, 1, 1};
         int fast = p.type[n - 1] == MSC_YAW ? 1 : 0;
         MSC_TRY(make_set(c, p, bn, (uint64_t)na * na, fast, true, B[n]));
         ctr = take_counter(c);
-        HIP_TRY(launch_seed_bwd(B[n].view, g, p.target[0], p.target[1], p.target[2], rows_for(n, 0), p.prune, ctr,
-                                c->stream));
+        LAUNCH(MSC_K_SEED, n, 0,
+               launch_seed_bwd(B[n].view, g, p.target[0], p.target[1], p.target[2], rows_for(n, 0), p.prune, ctr,
+                               c->stream));
         MSC_TRY(read_counter(c, ctr, &B[n].count));
     }
     bool empty = F[0].count == 0 || B[n].count == 0;
     int kf = 0, kb = n;
     unsigned long long* ovf = c->ovf;
-    while (!empty && kf < kb) {
+    // Forward stage k from F_{k-1}'s list into `out`.
+    auto expand_forward = [&](int k, StageSet& out) -> msc_status {
+        MSC_TRY(ensure_list(c, F[k - 1]));
+        uint64_t upper = F[k - 1].count * (uint64_t)(p.hi[k - 1] - p.lo[k - 1] + 1);
+        int fast = (k < n && p.type[k] == MSC_YAW) ? 1 : 0;
+        MSC_TRY(make_set(c, p, box[k], upper, fast, false, out));
+        int64_t rt = 0;
+        for (int j = k; j < n; ++j) rt += R[j];
+        long long r2 = p.prune ? (long long)(rt * rt) : -1;
+        unsigned long long* ctr = take_counter(c);
+        if (!ctr) return fail(c, MSC_E_CAPACITY, "out of counters");
+        LAUNCH(MSC_K_EXPAND_FWD, k, (int64_t)F[k - 1].count,
+               launch_expand_fwd(F[k - 1].list, F[k - 1].count, out.view, g, jv[k - 1], p.target[0], p.target[1],
+                                 p.target[2], r2, ctr, ovf, c->stream));
+        const int rec = c->last_rec;
+        MSC_TRY(read_counter(c, ctr, &out.count));
+        prof_out(c, rec, (int64_t)out.count);
+        return MSC_OK;
+    };
+    // The two pathways are expanded until they are one transition apart, then met
+    // (split 0: the backward pathway runs down to the root and is joined with F_0).
+    auto finished = [&]() { return p.split == 0 ? kb == 0 : kb - kf == 1; };
+    while (!empty && !finished()) {
         bool forward;
         if (p.split >= 0) {
-            forward = kf < p.split;
+            forward = p.split >= 1 && kf < p.split - 1;
         } else {
             double cf = (double)F[kf].count * (p.hi[kf] - p.lo[kf] + 1);
             double cb = (double)B[kb].count * 3.0;
             forward = cf <= cb;
         }
         if (forward) {
-            const int k = kf + 1;  // joint k-1 (0-based) lays segment k
-            MSC_TRY(ensure_list(c, F[kf]));
-            uint64_t upper = F[kf].count * (uint64_t)(p.hi[k - 1] - p.lo[k - 1] + 1);
-            MSC_TRY(make_set(c, p, box[k], upper, 0, false, F[k]));
-            int64_t rt = 0;
-            for (int j = k; j < n; ++j) rt += R[j];
-            long long r2 = p.prune ? (long long)(rt * rt) : -1;
-            unsigned long long* ctr = take_counter(c);
-            if (!ctr) return fail(c, MSC_E_CAPACITY, "out of counters");
-            HIP_TRY(launch_expand_fwd(F[kf].list, F[kf].count, F[k].view, g, jv[k - 1], p.target[0], p.target[1],
-                                      p.target[2], r2, ctr, ovf, c->stream));
-            MSC_TRY(read_counter(c, ctr, &F[k].count));
-            kf = k;
-            empty = F[k].count == 0;
+            MSC_TRY(expand_forward(kf + 1, F[kf + 1]));
+            kf = kf + 1;
+            empty = F[kf].count == 0;
         } else {
             const int k = kb;  // joint k-1 (0-based) lays segment k; produce B_{k-1}
             MSC_TRY(ensure_list(c, B[kb]));
@@ -463,15 +581,18 @@ msc_status run_reach(msc_ctx* c, const msc_scene* sc, const Plan& p, int want, b
             long long r2 = p.prune ? (long long)(rb * rb) : -1;
             unsigned long long* ctr = take_counter(c);
             if (!ctr) return fail(c, MSC_E_CAPACITY, "out of counters");
-            HIP_TRY(launch_expand_bwd(B[kb].list, B[kb].count, B[k - 1].view, g, jv[k - 1], p.base[0], p.base[1],
-                                      p.base[2], r2, rows_for(k - 1, yaw), ctr, ovf, c->stream));
+            LAUNCH(MSC_K_EXPAND_BWD, k - 1, (int64_t)B[kb].count,
+                   launch_expand_bwd(B[kb].list, B[kb].count, B[k - 1].view, g, jv[k - 1], p.base[0], p.base[1],
+                                     p.base[2], r2, rows_for(k - 1, yaw), ctr, ovf, c->stream));
+            const int rec = c->last_rec;
             MSC_TRY(read_counter(c, ctr, &B[k - 1].count));
+            prof_out(c, rec, (int64_t)B[k - 1].count);
             kb = k - 1;
             empty = B[k - 1].count == 0;
         }
     }
     MSC_TRY(check_overflow(c, ovf, "a stage set"));
-    const int m = kf;
+    const int m = kb;
     c->stats.split_m = m;
     for (int k = 0; k <= n; ++k) {
         c->stats.fwd_count[k] = F[k].used ? (int64_t)F[k].count : -1;
@@ -487,38 +608,70 @@ msc_status run_reach(msc_ctx* c, const msc_scene* sc, const Plan& p, int want, b
     }
     if (empty) return MSC_NO_REACH;
 
-    // Join and D marking.
-    MSC_TRY(ensure_list(c, F[m]));
-    unsigned long long* jc = take_counter(c);
-    HIP_TRY(launch_join(F[m].list, F[m].count, F[m].view, B[m].view, jc, c->stream));
+    // C_m and the D sets.  Stage sets used by the canonical walk: D_k (k < m) in F_k's
+    // structure, C_m = D_m, B_k for k > m.
+    StageSet Cset;
     uint64_t joined = 0;
-    MSC_TRY(read_counter(c, jc, &joined));
+    if (m == 0) {
+        MSC_TRY(ensure_list(c, F[0]));
+        unsigned long long* jc = take_counter(c);
+        LAUNCH(MSC_K_JOIN, 0, (int64_t)F[0].count, launch_join(F[0].list, F[0].count, F[0].view, B[0].view, jc, c->stream));
+        MSC_TRY(read_counter(c, jc, &joined));
+        Cset = F[0];
+    } else {
+        if (capture) {
+            // F_m itself is only built for the dump
+            StageSet Fm;
+            MSC_TRY(expand_forward(m, Fm));
+            MSC_TRY(capture_set(c, Fm, N, 0, m));
+        }
+        MSC_TRY(ensure_list(c, F[m - 1]));
+        unsigned long long* hc = take_counter(c);
+        unsigned long long* kc = take_counter(c);
+        if (!hc || !kc) return fail(c, MSC_E_CAPACITY, "out of counters");
+        LAUNCH(MSC_K_JOIN, m, (int64_t)F[m - 1].count,
+               launch_meet(F[m - 1].list, F[m - 1].count, F[m - 1].view, B[m].view, B[m].view, g, jv[m - 1], 1, hc,
+                           kc, ovf, c->stream));
+        uint64_t hits = 0;
+        MSC_TRY(read_counter(c, hc, &hits));
+        if (hits) {
+            int fast = (m < n && p.type[m] == MSC_YAW) ? 1 : 0;
+            MSC_TRY(make_set(c, p, box[m], hits, fast, false, Cset));
+            unsigned long long* cc = take_counter(c);
+            unsigned long long* kc2 = take_counter(c);
+            if (!cc || !kc2) return fail(c, MSC_E_CAPACITY, "out of counters");
+            LAUNCH(MSC_K_JOIN, m, (int64_t)F[m - 1].count,
+                   launch_meet(F[m - 1].list, F[m - 1].count, F[m - 1].view, B[m].view, Cset.view, g, jv[m - 1], 0,
+                               cc, kc2, ovf, c->stream));
+            const int jrec = c->last_rec;
+            MSC_TRY(read_counter(c, cc, &joined));
+            prof_out(c, jrec, (int64_t)joined);
+            Cset.count = joined;
+        }
+    }
     c->stats.join_count = (int64_t)joined;
-    if (capture) {
-        StageSet tmp = F[m];
-        tmp.count = F[m].count;
-        MSC_TRY(capture_set(c, tmp, N, 2, m));
+    if (capture && joined) {
+        MSC_TRY(capture_set(c, Cset, N, 2, m));
         c->captured[{3, m}] = c->captured[{2, m}];
+        if (m >= 1) MSC_TRY(capture_set(c, F[m - 1], N, 3, m - 1));
     }
     if (joined == 0) return MSC_NO_REACH;
-    for (int k = m; k >= 1; --k) {
-        MSC_TRY(ensure_list(c, F[k - 1]));
+    for (int k = m - 1; k >= 1; --k) {
+        // D_{k-1} from D_k (D_k is Cset for k == m, else F_k's marked structure)
         unsigned long long* dc = take_counter(c);
-        HIP_TRY(launch_dmark(F[k - 1].list, F[k - 1].count, F[k - 1].view, F[k].view, g, jv[k - 1], dc, c->stream));
+        LAUNCH(MSC_K_DMARK, k - 1, (int64_t)F[k - 1].count,
+               launch_dmark(F[k - 1].list, F[k - 1].count, F[k - 1].view, F[k].view, g, jv[k - 1], dc, c->stream));
         if (capture) MSC_TRY(capture_set(c, F[k - 1], N, 3, k - 1));
     }
 
     // Canonical reach poses.
-    std::vector<SetView> sets(n + 1);
-    for (int k = 0; k <= n; ++k) sets[k] = (k <= m) ? F[k].view : B[k].view;
-    void *d_sets, *d_joints, *d_sols, *d_nsol;
-    MSC_TRY(upload(c, sets.data(), sizeof(SetView) * (n + 1), &d_sets));
-    MSC_TRY(upload(c, jv.data(), sizeof(JointView) * n, &d_joints));
-    MSC_TRY(arena_alloc(c, (uint64_t)want * n * 4, &d_sols));
-    MSC_TRY(arena_alloc(c, 4, &d_nsol));
+    void *h_sols, *d_sols, *h_nsol, *d_nsol;
+    MSC_TRY(host_area(c, (size_t)want * n * 4, &h_sols, &d_sols));
+    MSC_TRY(host_area(c, 4, &h_nsol, &d_nsol));
+    *(volatile int32_t*)h_nsol = 0;
     DfsArgs da{};
-    da.sets = (const SetView*)d_sets;
-    da.joints = (const JointView*)d_joints;
+    for (int k = 0; k <= n; ++k) da.sets[k] = (k < m) ? F[k].view : (k == m ? Cset.view : B[k].view);
+    for (int k = 0; k < n; ++k) da.joints[k] = jv[k];
     da.g = g;
     da.n = n;
     da.m = m;
@@ -528,20 +681,16 @@ msc_status run_reach(msc_ctx* c, const msc_scene* sc, const Plan& p, int want, b
     da.root = pack_key(p.base[0], p.base[1], p.base[2], p.ia0, p.ie0);
     da.sols = (int32_t*)d_sols;
     da.nsol = (int32_t*)d_nsol;
-    HIP_TRY(launch_dfs(da, c->stream));
-    int32_t nsol = 0;
-    HIP_TRY(hipMemcpyAsync(&nsol, d_nsol, 4, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    MSC_TRY(check_overflow(c, ovf, "a stage set"));
+    LAUNCH(MSC_K_DFS, -1, 0, launch_dfs(da, c->stream));
+    MSC_TRY(check_overflow(c, ovf, "a stage set"));   // synchronises the stream
+    int32_t nsol = *(volatile int32_t*)h_nsol;
     if (nsol <= 0) return fail(c, MSC_E_STATE, "join not empty but no pose traced");
     out.nsol = std::min(nsol, want);
-    out.sols.resize((size_t)out.nsol * n);
-    HIP_TRY(hipMemcpyAsync(out.sols.data(), d_sols, out.sols.size() * 4, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
+    out.sols.assign((const int32_t*)h_sols, (const int32_t*)h_sols + (size_t)out.nsol * n);
     return MSC_OK;
 }
 
-msc_status joint_views(msc_ctx* c, const Plan& p, std::vector<JointView>& jv) {
+msc_status joint_views(Lane* c, const Plan& p, std::vector<JointView>& jv) {
     jv.resize(p.n);
     for (int k = 0; k < p.n; ++k) {
         TableEntry t;
@@ -551,18 +700,41 @@ msc_status joint_views(msc_ctx* c, const Plan& p, std::vector<JointView>& jv) {
     return MSC_OK;
 }
 
-msc_status pose_check_steps(msc_ctx* c, const msc_scene* sc, const Plan& p, const int32_t* q_steps, int64_t count,
+msc_status pose_check_steps(Lane* c, const msc_scene* sc, const Plan& p, const int32_t* q_steps, int64_t count,
                             uint8_t* valid, int32_t* ends) {
     std::vector<JointView> jv;
     MSC_TRY(joint_views(c, p, jv));
-    void *d_joints, *d_q, *d_valid, *d_ends = nullptr;
-    MSC_TRY(upload(c, jv.data(), sizeof(JointView) * p.n, &d_joints));
+    PoseArgs a{};
+    for (int k = 0; k < p.n; ++k) a.joints[k] = jv[k];
+    const size_t qbytes = (size_t)count * p.n * 4, ebytes = (size_t)count * 12;
+    if (qbytes + ebytes + (size_t)count + 1024 <= kStagingBytes / 2) {
+        // small batch: the kernel reads the poses from and writes the results to mapped
+        // host memory
+        void *hq, *dq, *hv, *dv, *he = nullptr, *de = nullptr;
+        MSC_TRY(host_area(c, qbytes, &hq, &dq));
+        MSC_TRY(host_area(c, (size_t)count, &hv, &dv));
+        if (ends) MSC_TRY(host_area(c, ebytes, &he, &de));
+        std::memcpy(hq, q_steps, qbytes);
+        a.g = grid_view(sc);
+        a.n = p.n;
+        a.na = p.na;
+        a.bx = p.base[0];
+        a.by = p.base[1];
+        a.bz = p.base[2];
+        a.ia0 = p.ia0;
+        a.ie0 = p.ie0;
+        LAUNCH(MSC_K_POSE, -1, count,
+               launch_pose_check(a, (const int32_t*)dq, count, (uint8_t*)dv, (int32_t*)de, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        std::memcpy(valid, hv, (size_t)count);
+        if (ends) std::memcpy(ends, he, ebytes);
+        return MSC_OK;
+    }
+    void *d_q, *d_valid, *d_ends = nullptr;
     MSC_TRY(arena_alloc(c, (uint64_t)count * p.n * 4, &d_q));
     MSC_TRY(arena_alloc(c, (uint64_t)count, &d_valid));
     if (ends) MSC_TRY(arena_alloc(c, (uint64_t)count * 12, &d_ends));
-    HIP_TRY(hipMemcpyAsync(d_q, q_steps, (size_t)count * p.n * 4, hipMemcpyHostToDevice, c->stream));
-    PoseArgs a{};
-    a.joints = (const JointView*)d_joints;
+    HIP_TRY(hipMemcpyAsync(d_q, q_steps, qbytes, hipMemcpyHostToDevice, c->stream));
     a.g = grid_view(sc);
     a.n = p.n;
     a.na = p.na;
@@ -571,16 +743,16 @@ msc_status pose_check_steps(msc_ctx* c, const msc_scene* sc, const Plan& p, cons
     a.bz = p.base[2];
     a.ia0 = p.ia0;
     a.ie0 = p.ie0;
-    HIP_TRY(launch_pose_check(a, (const int32_t*)d_q, count, (uint8_t*)d_valid, (int32_t*)d_ends, c->stream));
+    LAUNCH(MSC_K_POSE, -1, count, launch_pose_check(a, (const int32_t*)d_q, count, (uint8_t*)d_valid, (int32_t*)d_ends, c->stream));
     HIP_TRY(hipMemcpyAsync(valid, d_valid, (size_t)count, hipMemcpyDeviceToHost, c->stream));
     if (ends) HIP_TRY(hipMemcpyAsync(ends, d_ends, (size_t)count * 12, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     return MSC_OK;
 }
 
-msc_status check_scene(msc_ctx* c, const msc_scene* s) {
+msc_status check_scene(Lane* c, const msc_scene* s) {
     if (!s) return fail(c, MSC_E_ARG, "scene is NULL");
-    if (s->ctx != c) return fail(c, MSC_E_ARG, "scene belongs to another context");
+    if (s->ctx != c->owner) return fail(c, MSC_E_ARG, "scene belongs to another context");
     return MSC_OK;
 }
 
@@ -595,115 +767,81 @@ msc_opts opts_or_default(const msc_opts* o) {
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
-extern "C" {
+namespace {
 
-void msc_opts_default(msc_opts* o) {
-    if (!o) return;
-    o->split_m = -1;
-    o->tube_r0 = 1;
-    o->tube_r1 = 2;
-    o->reach_retries = 4;
-    o->flags = 0;
-}
+// ---------------------------------------------------------------------------
+// Lanes
+// ---------------------------------------------------------------------------
+constexpr uint64_t kLaneReserved = 64 * 1024;   // counters at the start of each window
 
-msc_status msc_ctx_create(int device, void* hip_stream, void* dev_workspace, uint64_t ws_bytes, msc_ctx** out) {
-    if (!out || !dev_workspace) return MSC_E_ARG;
-    if (ws_bytes < (64ull << 20)) return MSC_E_ARG;
-    if ((uintptr_t)dev_workspace % kAlign) return MSC_E_ARG;
-    msc_ctx* c = new (std::nothrow) msc_ctx();
-    if (!c) return MSC_E_NOMEM;
-    c->device = device;
-    c->stream = (hipStream_t)hip_stream;
-    c->ws = (char*)dev_workspace;
-    c->ws_bytes = ws_bytes;
-    c->hi = ws_bytes;
-    if (hipSetDevice(device) != hipSuccess || hipHostMalloc((void**)&c->staging, kStagingBytes, hipHostMallocDefault) != hipSuccess) {
-        delete c;
-        return MSC_E_HIP;
-    }
-    void* p;
-    if (persist_alloc(c, kCounters * sizeof(unsigned long long), &p) != MSC_OK) {
-        (void)hipHostFree(c->staging);
-        delete c;
-        return MSC_E_NOMEM;
-    }
-    c->counters = (unsigned long long*)p;
-    *out = c;
+msc_status lane_init(Lane* L, msc_ctx* o, int index, hipStream_t stream, bool own, char* base, uint64_t size) {
+    L->owner = o;
+    L->index = index;
+    L->device = o->device;
+    L->stream = stream;
+    L->own_stream = own;
+    if (size <= kLaneReserved + (1u << 20)) return MSC_E_NOMEM;
+    L->counters = (unsigned long long*)base;
+    L->ws = base + kLaneReserved;
+    L->hi = size - kLaneReserved;
+    L->lo = 0;
+    if (hipHostMalloc((void**)&L->staging, kStagingBytes, hipHostMallocMapped) != hipSuccess) return MSC_E_HIP;
+    if (hipHostGetDevicePointer((void**)&L->staging_dev, L->staging, 0) != hipSuccess) return MSC_E_HIP;
     return MSC_OK;
 }
 
-msc_status msc_ctx_destroy(msc_ctx* c) {
-    if (!c) return MSC_E_ARG;
-    (void)hipSetDevice(c->device);
-    (void)hipStreamSynchronize(c->stream);
-    if (c->staging) (void)hipHostFree(c->staging);
-    delete c;
-    return MSC_OK;
+void lane_free(Lane* L) {
+    if (!L) return;
+    (void)hipStreamSynchronize(L->stream);
+    if (L->staging) (void)hipHostFree(L->staging);
+    for (hipEvent_t e : L->events) (void)hipEventDestroy(e);
+    if (L->own_stream) (void)hipStreamDestroy(L->stream);
+    delete L;
 }
 
-uint64_t msc_scene_bytes(int32_t n) {
-    if (n <= 0) return 0;
-    uint64_t wpr = ((uint64_t)n + 63) / 64;
-    return (uint64_t)n * n * wpr * 8;
-}
-
-msc_status msc_scene_create(msc_ctx* c, int32_t n, int32_t dilate_r, const msc_box* boxes, int32_t nbox,
-                            const msc_sphere* spheres, int32_t nsph, void* dev_grid, uint64_t grid_bytes,
-                            msc_scene** out) {
-    if (!c) return MSC_E_ARG;
-    if (!out || !dev_grid) return fail(c, MSC_E_ARG, "NULL output or grid buffer");
-    if (n < 1 || n > 1024) return fail(c, MSC_E_ARG, "grid size %d outside 1..1024", n);
-    if (dilate_r < 0 || nbox < 0 || nsph < 0) return fail(c, MSC_E_ARG, "negative dilation or count");
-    if ((nbox && !boxes) || (nsph && !spheres)) return fail(c, MSC_E_ARG, "NULL obstacle array");
-    for (int i = 0; i < nbox; ++i)
-        for (int a = 0; a < 3; ++a)
-            if (boxes[i].ext[a] < 1) return fail(c, MSC_E_ARG, "box %d has an extent < 1", i);
-    for (int i = 0; i < nsph; ++i)
-        if (spheres[i].r < 0) return fail(c, MSC_E_ARG, "sphere %d has a negative radius", i);
-    if (grid_bytes < msc_scene_bytes(n)) return fail(c, MSC_E_NOMEM, "grid buffer too small");
-    if (hipSetDevice(c->device) != hipSuccess) return fail(c, MSC_E_HIP, "hipSetDevice");
-    begin_call(c);
-    std::vector<int32_t> hb((size_t)std::max(nbox, 1) * 6), hs((size_t)std::max(nsph, 1) * 4);
-    for (int i = 0; i < nbox; ++i)
-        for (int a = 0; a < 3; ++a) {
-            hb[i * 6 + a] = boxes[i].lo[a];
-            hb[i * 6 + 3 + a] = boxes[i].ext[a];
+// Split [0, table_lo) into 1 + nworkers equal windows (control lane first).
+msc_status layout_lanes(msc_ctx* o, int nworkers) {
+    for (Lane* w : o->workers) lane_free(w);
+    o->workers.clear();
+    const uint64_t total = o->table_lo;
+    const uint64_t win = (total / (uint64_t)(nworkers + 1)) & ~(kAlign - 1);
+    if (!o->control) {
+        o->control = new (std::nothrow) Lane();
+        if (!o->control) return MSC_E_NOMEM;
+        msc_status st = lane_init(o->control, o, 0, o->stream, false, o->ws, win);
+        if (st != MSC_OK) return st;
+    } else {
+        o->control->counters = (unsigned long long*)o->ws;
+        o->control->ws = o->ws + kLaneReserved;
+        o->control->hi = win - kLaneReserved;
+        o->control->lo = 0;
+    }
+    for (int i = 0; i < nworkers; ++i) {
+        Lane* L = new (std::nothrow) Lane();
+        if (!L) return MSC_E_NOMEM;
+        hipStream_t st = nullptr;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+            delete L;
+            return MSC_E_HIP;
         }
-    for (int i = 0; i < nsph; ++i) {
-        for (int a = 0; a < 3; ++a) hs[i * 4 + a] = spheres[i].c[a];
-        hs[i * 4 + 3] = spheres[i].r;
+        msc_status r = lane_init(L, o, i + 1, st, true, o->ws + (uint64_t)(i + 1) * win, win);
+        o->workers.push_back(L);
+        if (r != MSC_OK) return r;
     }
-    void *db, *ds;
-    MSC_TRY(upload(c, hb.data(), hb.size() * 4, &db));
-    MSC_TRY(upload(c, hs.data(), hs.size() * 4, &ds));
-    msc_scene* s = new (std::nothrow) msc_scene();
-    if (!s) return fail(c, MSC_E_NOMEM, "host allocation");
-    s->ctx = c;
-    s->n = n;
-    s->wpr = (n + 63) / 64;
-    s->dilate = dilate_r;
-    s->grid = (uint64_t*)dev_grid;
-    s->bytes = grid_bytes;
-    hipError_t e = launch_raster(s->grid, n, s->wpr, dilate_r, (const int32_t*)db, nbox, (const int32_t*)ds, nsph,
-                                 c->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    if (e != hipSuccess) {
-        delete s;
-        return fail(c, MSC_E_HIP, "raster: %s", hipGetErrorString(e));
-    }
-    *out = s;
     return MSC_OK;
 }
 
-msc_status msc_scene_destroy(msc_scene* s) {
-    if (!s) return MSC_E_ARG;
-    delete s;
-    return MSC_OK;
+msc_status ctx_fail(msc_ctx* o, msc_status st, const char* msg) {
+    if (o) o->err = msg;
+    return st;
 }
 
-msc_status msc_reach(msc_ctx* c, const msc_scene* sc, const msc_arm* arm, const int32_t target[3],
-                     const msc_opts* opts, int32_t* angles_out) {
-    if (!c) return MSC_E_ARG;
+// ---------------------------------------------------------------------------
+// One query on one lane
+// ---------------------------------------------------------------------------
+msc_status reach_on(Lane* c, const msc_scene* sc, const msc_arm* arm, const int32_t target[3], const msc_opts* opts,
+                    int32_t* angles_out) {
+
     MSC_TRY(check_scene(c, sc));
     MSC_TRY(check_arm(c, arm, sc->n));
     if (!target || !angles_out) return fail(c, MSC_E_ARG, "NULL target or output");
@@ -724,10 +862,10 @@ msc_status msc_reach(msc_ctx* c, const msc_scene* sc, const msc_arm* arm, const 
     return MSC_OK;
 }
 
-msc_status msc_path(msc_ctx* c, const msc_scene* sc, const msc_arm* arm, const int32_t* start_cdeg,
-                    const int32_t target[3], int32_t waypoints, int32_t max_delta_cdeg, const msc_opts* opts,
-                    int32_t* path_out) {
-    if (!c) return MSC_E_ARG;
+msc_status path_on(Lane* c, const msc_scene* sc, const msc_arm* arm, const int32_t* start_cdeg,
+                   const int32_t target[3], int32_t waypoints, int32_t max_delta_cdeg, const msc_opts* opts,
+                   int32_t* path_out) {
+
     MSC_TRY(check_scene(c, sc));
     MSC_TRY(check_arm(c, arm, sc->n));
     if (!start_cdeg || !target || !path_out) return fail(c, MSC_E_ARG, "NULL argument");
@@ -781,15 +919,15 @@ msc_status msc_path(msc_ctx* c, const msc_scene* sc, const msc_arm* arm, const i
         p.hi[k] = lim_hi[k];
     }
     MSC_TRY(joint_views(c, p, jv));
-    void* d_joints;
-    MSC_TRY(upload(c, jv.data(), sizeof(JointView) * n, &d_joints));
     const uint64_t mark = c->lo;
+    const size_t stage_mark = c->staging_used;
     int radii[2] = {o.tube_r0, o.tube_r1};
     int nr = o.tube_r1 == o.tube_r0 ? 1 : 2;
     std::vector<int32_t> path((size_t)(waypoints + 1) * n);
     for (int i = 0; i < r.nsol; ++i) {
         for (int ri = 0; ri < nr; ++ri) {
             c->lo = mark;
+            c->staging_used = stage_mark;
             const int rad = radii[ri];
             uint64_t slab = 1;
             for (int k = 0; k < n; ++k) {
@@ -797,7 +935,7 @@ msc_status msc_path(msc_ctx* c, const msc_scene* sc, const msc_arm* arm, const i
                 if (slab > (1ull << 28)) return fail(c, MSC_E_CAPACITY, "tube of radius %d too large", rad);
             }
             TubeArgs ta{};
-            ta.joints = (const JointView*)d_joints;
+            for (int k = 0; k < n; ++k) ta.joints[k] = jv[k];
             ta.g = grid_view(sc);
             ta.n = n;
             ta.na = p.na;
@@ -816,24 +954,24 @@ msc_status msc_path(msc_ctx* c, const msc_scene* sc, const msc_arm* arm, const i
                 ta.lim_hi[k] = lim_hi[k];
             }
             ta.slab = slab;
-            void *d_valid, *d_reach, *d_t0, *d_t1, *d_path, *d_status;
+            void *d_valid, *d_reach, *d_t0, *d_t1, *h_path, *d_path, *h_status, *d_status;
             uint64_t cells = (uint64_t)(waypoints + 1) * slab;
             MSC_TRY(arena_alloc(c, cells, &d_valid));
             MSC_TRY(arena_alloc(c, cells, &d_reach));
             MSC_TRY(arena_alloc(c, slab, &d_t0));
             MSC_TRY(arena_alloc(c, slab, &d_t1));
-            MSC_TRY(arena_alloc(c, path.size() * 4, &d_path));
-            MSC_TRY(arena_alloc(c, 4, &d_status));
-            HIP_TRY(launch_tube_valid(ta, (uint8_t*)d_valid, c->stream));
-            HIP_TRY(launch_tube_solve(ta, (const uint8_t*)d_valid, (uint8_t*)d_reach, (uint8_t*)d_t0, (uint8_t*)d_t1,
-                                      (int32_t*)d_path, (int32_t*)d_status, c->stream));
-            int32_t ok2 = 0;
-            HIP_TRY(hipMemcpyAsync(&ok2, d_status, 4, hipMemcpyDeviceToHost, c->stream));
+            MSC_TRY(host_area(c, path.size() * 4, &h_path, &d_path));
+            MSC_TRY(host_area(c, 4, &h_status, &d_status));
+            *(volatile int32_t*)h_status = 0;
+            LAUNCH(MSC_K_TUBE_VALID, rad, (int64_t)cells, launch_tube_valid(ta, (uint8_t*)d_valid, c->stream));
+            LAUNCH(MSC_K_TUBE_SOLVE, rad, (int64_t)cells,
+                   launch_tube_solve(ta, (const uint8_t*)d_valid, (uint8_t*)d_reach, (uint8_t*)d_t0, (uint8_t*)d_t1,
+                                     (int32_t*)d_path, (int32_t*)d_status, c->stream));
             HIP_TRY(hipStreamSynchronize(c->stream));
+            int32_t ok2 = *(volatile int32_t*)h_status;
             c->stats.attempts++;
             if (ok2) {
-                HIP_TRY(hipMemcpyAsync(path.data(), d_path, path.size() * 4, hipMemcpyDeviceToHost, c->stream));
-                HIP_TRY(hipStreamSynchronize(c->stream));
+                std::memcpy(path.data(), h_path, path.size() * 4);
                 for (size_t j = 0; j < path.size(); ++j) path_out[j] = path[j] * arm->step_cdeg;
                 c->stats.tube_r = rad;
                 c->stats.reach_index = i;
@@ -844,9 +982,343 @@ msc_status msc_path(msc_ctx* c, const msc_scene* sc, const msc_arm* arm, const i
     return MSC_NO_PATH;
 }
 
-msc_status msc_pose_check(msc_ctx* c, const msc_scene* sc, const msc_arm* arm, const int32_t* poses_cdeg,
+msc_status query_on(Lane* L, msc_query* q, const msc_opts* opts) {
+    if (!q->scene || !q->arm || !q->out) return fail(L, MSC_E_ARG, "query with a NULL scene, arm or output");
+    prof_reset(L, opts ? opts->flags : 0u);
+    msc_status st;
+    if (q->kind == 0)
+        st = reach_on(L, q->scene, q->arm, q->target, opts, q->out);
+    else if (q->kind == 1)
+        st = path_on(L, q->scene, q->arm, q->start_cdeg, q->target, q->waypoints, q->max_delta_cdeg, opts, q->out);
+    else
+        st = fail(L, MSC_E_ARG, "query kind %d", q->kind);
+    prof_finish(L);
+    return st;
+}
+
+double now_ms() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Server state: a FIFO of submitted queries served by one host thread per worker lane.
+// ---------------------------------------------------------------------------
+struct ServerState {
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<std::pair<uint64_t, msc_query*>> queue;
+    std::map<uint64_t, double> submitted;   // ticket -> submission time (ms)
+    std::map<uint64_t, int> done;            // ticket -> 1 once finished
+    std::condition_variable done_cv;
+    std::vector<std::thread> threads;
+    msc_opts opts{};
+    bool stop = false;
+    uint64_t next_ticket = 1;
+};
+
+extern "C" {
+
+void msc_opts_default(msc_opts* o) {
+    if (!o) return;
+    o->split_m = -1;
+    o->tube_r0 = 1;
+    o->tube_r1 = 2;
+    o->reach_retries = 4;
+    o->flags = 0;
+}
+
+msc_status msc_ctx_create(int device, void* hip_stream, void* dev_workspace, uint64_t ws_bytes, msc_ctx** out) {
+    if (!out || !dev_workspace) return MSC_E_ARG;
+    if (ws_bytes < (64ull << 20)) return MSC_E_ARG;
+    if ((uintptr_t)dev_workspace % kAlign) return MSC_E_ARG;
+    if (hipSetDevice(device) != hipSuccess) return MSC_E_HIP;
+    msc_ctx* o = new (std::nothrow) msc_ctx();
+    if (!o) return MSC_E_NOMEM;
+    o->device = device;
+    o->stream = (hipStream_t)hip_stream;
+    o->ws = (char*)dev_workspace;
+    o->ws_bytes = ws_bytes;
+    uint64_t table_bytes = std::min<uint64_t>(256ull << 20, ws_bytes / 8) & ~(kAlign - 1);
+    o->table_lo = ws_bytes - table_bytes;
+    o->table_top = ws_bytes;
+    msc_status st = layout_lanes(o, 0);
+    if (st != MSC_OK) {
+        lane_free(o->control);
+        delete o;
+        return st;
+    }
+    *out = o;
+    return MSC_OK;
+}
+
+msc_status msc_ctx_destroy(msc_ctx* o) {
+    if (!o) return MSC_E_ARG;
+    (void)hipSetDevice(o->device);
+    if (o->server) msc_server_stop(o);
+    for (Lane* w : o->workers) lane_free(w);
+    lane_free(o->control);
+    delete o;
+    return MSC_OK;
+}
+
+msc_status msc_ctx_set_lanes(msc_ctx* o, int32_t nworkers) {
+    if (!o) return MSC_E_ARG;
+    if (nworkers < 0 || nworkers > 64) return ctx_fail(o, MSC_E_ARG, "nworkers outside 0..64");
+    if (o->server) return ctx_fail(o, MSC_E_STATE, "the server is running");
+    if (hipSetDevice(o->device) != hipSuccess) return MSC_E_HIP;
+    (void)hipStreamSynchronize(o->stream);
+    return layout_lanes(o, nworkers);
+}
+
+uint64_t msc_lane_bytes(msc_ctx* o) { return (o && o->control) ? o->control->hi : 0; }
+
+uint64_t msc_scene_bytes(int32_t n) {
+    if (n <= 0) return 0;
+    uint64_t wpr = ((uint64_t)n + 63) / 64;
+    return (uint64_t)n * n * wpr * 8;
+}
+
+msc_status msc_scene_create(msc_ctx* o, int32_t n, int32_t dilate_r, const msc_box* boxes, int32_t nbox,
+                            const msc_sphere* spheres, int32_t nsph, void* dev_grid, uint64_t grid_bytes,
+                            msc_scene** out) {
+    if (!o) return MSC_E_ARG;
+    Lane* c = o->control;
+
+    if (!out || !dev_grid) return fail(c, MSC_E_ARG, "NULL output or grid buffer");
+    if (n < 1 || n > 1024) return fail(c, MSC_E_ARG, "grid size %d outside 1..1024", n);
+    if (dilate_r < 0 || nbox < 0 || nsph < 0) return fail(c, MSC_E_ARG, "negative dilation or count");
+    if ((nbox && !boxes) || (nsph && !spheres)) return fail(c, MSC_E_ARG, "NULL obstacle array");
+    for (int i = 0; i < nbox; ++i)
+        for (int a = 0; a < 3; ++a)
+            if (boxes[i].ext[a] < 1) return fail(c, MSC_E_ARG, "box %d has an extent < 1", i);
+    for (int i = 0; i < nsph; ++i)
+        if (spheres[i].r < 0) return fail(c, MSC_E_ARG, "sphere %d has a negative radius", i);
+    if (grid_bytes < msc_scene_bytes(n)) return fail(c, MSC_E_NOMEM, "grid buffer too small");
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, MSC_E_HIP, "hipSetDevice");
+    begin_call(c);
+    std::vector<int32_t> hb((size_t)std::max(nbox, 1) * 6), hs((size_t)std::max(nsph, 1) * 4);
+    for (int i = 0; i < nbox; ++i)
+        for (int a = 0; a < 3; ++a) {
+            hb[i * 6 + a] = boxes[i].lo[a];
+            hb[i * 6 + 3 + a] = boxes[i].ext[a];
+        }
+    for (int i = 0; i < nsph; ++i) {
+        for (int a = 0; a < 3; ++a) hs[i * 4 + a] = spheres[i].c[a];
+        hs[i * 4 + 3] = spheres[i].r;
+    }
+    // the raster kernel reads the obstacle lists from mapped host memory when they fit
+    // the staging buffer, else from a device copy
+    void *hbp, *db, *hsp, *ds;
+    const size_t obytes = (hb.size() + hs.size()) * 4;
+    if (obytes + 1024 <= kStagingBytes / 2) {
+        MSC_TRY(host_area(c, hb.size() * 4, &hbp, &db));
+        MSC_TRY(host_area(c, hs.size() * 4, &hsp, &ds));
+        std::memcpy(hbp, hb.data(), hb.size() * 4);
+        std::memcpy(hsp, hs.data(), hs.size() * 4);
+    } else {
+        MSC_TRY(arena_alloc(c, hb.size() * 4, &db));
+        MSC_TRY(arena_alloc(c, hs.size() * 4, &ds));
+        HIP_TRY(hipMemcpyAsync(db, hb.data(), hb.size() * 4, hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(hipMemcpyAsync(ds, hs.data(), hs.size() * 4, hipMemcpyHostToDevice, c->stream));
+    }
+    msc_scene* s = new (std::nothrow) msc_scene();
+    if (!s) return fail(c, MSC_E_NOMEM, "host allocation");
+    s->ctx = c->owner;
+    s->n = n;
+    s->wpr = (n + 63) / 64;
+    s->dilate = dilate_r;
+    s->grid = (uint64_t*)dev_grid;
+    s->bytes = grid_bytes;
+    hipError_t e = launch_raster(s->grid, n, s->wpr, dilate_r, (const int32_t*)db, nbox, (const int32_t*)ds, nsph,
+                                 c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        delete s;
+        return fail(c, MSC_E_HIP, "raster: %s", hipGetErrorString(e));
+    }
+    *out = s;
+    return MSC_OK;
+}
+
+msc_status msc_scene_destroy(msc_scene* s) {
+    if (!s) return MSC_E_ARG;
+    delete s;
+    return MSC_OK;
+}
+
+msc_status msc_reach(msc_ctx* o, const msc_scene* sc, const msc_arm* arm, const int32_t target[3],
+                     const msc_opts* opts, int32_t* angles_out) {
+    if (!o) return MSC_E_ARG;
+    Lane* c = o->control;
+    prof_reset(c, opts ? opts->flags : 0u);
+    msc_status st = reach_on(c, sc, arm, target, opts, angles_out);
+    prof_finish(c);
+    return st;
+}
+
+msc_status msc_path(msc_ctx* o, const msc_scene* sc, const msc_arm* arm, const int32_t* start_cdeg,
+                    const int32_t target[3], int32_t waypoints, int32_t max_delta_cdeg, const msc_opts* opts,
+                    int32_t* path_out) {
+    if (!o) return MSC_E_ARG;
+    Lane* c = o->control;
+    prof_reset(c, opts ? opts->flags : 0u);
+    msc_status st = path_on(c, sc, arm, start_cdeg, target, waypoints, max_delta_cdeg, opts, path_out);
+    prof_finish(c);
+    return st;
+}
+
+msc_status msc_get_timings(msc_ctx* o, msc_timing* out, int32_t cap, int32_t* count) {
+    if (!o || !count || cap < 0 || (cap && !out)) return MSC_E_ARG;
+    Lane* c = o->control;
+    *count = (int32_t)c->recs.size();
+    for (int32_t i = 0; i < cap && i < (int32_t)c->recs.size(); ++i) out[i] = c->recs[i];
+    return MSC_OK;
+}
+
+msc_status msc_batch(msc_ctx* o, msc_query* q, int32_t nq, const msc_opts* opts) {
+    if (!o) return MSC_E_ARG;
+    if (nq < 0 || (nq && !q)) return ctx_fail(o, MSC_E_ARG, "bad query array");
+    if (o->server) return ctx_fail(o, MSC_E_STATE, "the server is running");
+    const double t0 = now_ms();
+    if (o->workers.empty()) {
+        for (int32_t i = 0; i < nq; ++i) {
+            q[i].status = query_on(o->control, &q[i], opts);
+            q[i].latency_ms = (float)(now_ms() - t0);
+        }
+        return MSC_OK;
+    }
+    std::atomic<int32_t> next{0};
+    std::vector<std::thread> threads;
+    for (Lane* L : o->workers) {
+        threads.emplace_back([&, L]() {
+            (void)hipSetDevice(o->device);
+            for (int32_t i = next.fetch_add(1); i < nq; i = next.fetch_add(1)) {
+                q[i].status = query_on(L, &q[i], opts);
+                q[i].latency_ms = (float)(now_ms() - t0);
+            }
+        });
+    }
+    for (auto& t : threads) t.join();
+    return MSC_OK;
+}
+
+uint64_t msc_query_bytes(const msc_query* q) {
+    if (!q || !q->arm || !q->scene) return 0;
+    // two dense stage sets over a middle-stage pruning box, the tube arrays at radius 2,
+    // lists and tables
+    const msc_arm* a = q->arm;
+    const int n = a->dof;
+    if (a->step_cdeg <= 0) return 0;
+    const uint64_t na = 36000 / (uint64_t)a->step_cdeg;
+    int64_t reach = 0;
+    for (int k = (n + 1) / 2; k < n; ++k) reach += a->len_vox[k] + 1;
+    uint64_t edge = std::min<uint64_t>(2 * (uint64_t)reach + 1, (uint64_t)q->scene->n);
+    uint64_t dense = edge * edge * edge * na * na / 8;
+    uint64_t tube = 0;
+    if (q->kind == 1) {
+        uint64_t slab = 1;
+        for (int k = 0; k < n && slab < (1ull << 40); ++k) slab *= 5;
+        tube = 2 * slab * (uint64_t)(q->waypoints + 1);
+    }
+    return 3 * dense + tube + (64ull << 20);
+}
+
+static void server_worker(msc_ctx* o, Lane* L) {
+    (void)hipSetDevice(o->device);
+    ServerState* S = o->server;
+    while (true) {
+        std::pair<uint64_t, msc_query*> job;
+        {
+            std::unique_lock<std::mutex> lock(S->mu);
+            S->cv.wait(lock, [&] { return S->stop || !S->queue.empty(); });
+            if (S->queue.empty()) return;  // stop requested and nothing left
+            job = S->queue.front();
+            S->queue.pop_front();
+        }
+        msc_query* q = job.second;
+        q->status = query_on(L, q, &S->opts);
+        {
+            std::lock_guard<std::mutex> lock(S->mu);
+            q->latency_ms = (float)(now_ms() - S->submitted[job.first]);
+            S->submitted.erase(job.first);
+            S->done[job.first] = 1;
+        }
+        S->done_cv.notify_all();
+    }
+}
+
+msc_status msc_server_start(msc_ctx* o, const msc_opts* opts) {
+    if (!o) return MSC_E_ARG;
+    if (o->server) return ctx_fail(o, MSC_E_STATE, "the server is already running");
+    if (o->workers.empty()) return ctx_fail(o, MSC_E_STATE, "no worker lanes (msc_ctx_set_lanes)");
+    ServerState* S = new (std::nothrow) ServerState();
+    if (!S) return MSC_E_NOMEM;
+    msc_opts_default(&S->opts);
+    if (opts) S->opts = *opts;
+    o->server = S;
+    for (Lane* L : o->workers) S->threads.emplace_back(server_worker, o, L);
+    return MSC_OK;
+}
+
+msc_status msc_server_submit(msc_ctx* o, msc_query* q, uint64_t* ticket) {
+    if (!o || !q || !ticket) return MSC_E_ARG;
+    ServerState* S = o->server;
+    if (!S) return ctx_fail(o, MSC_E_STATE, "the server is not running");
+    // admission by memory: a query must fit one lane window
+    if (msc_query_bytes(q) > o->control->hi) return ctx_fail(o, MSC_E_NOMEM, "query exceeds a lane window");
+    {
+        std::lock_guard<std::mutex> lock(S->mu);
+        *ticket = S->next_ticket++;
+        S->submitted[*ticket] = now_ms();
+        S->queue.emplace_back(*ticket, q);
+    }
+    S->cv.notify_one();
+    return MSC_OK;
+}
+
+msc_status msc_server_poll(msc_ctx* o, uint64_t ticket, int32_t* done) {
+    if (!o || !done) return MSC_E_ARG;
+    ServerState* S = o->server;
+    if (!S) return ctx_fail(o, MSC_E_STATE, "the server is not running");
+    std::lock_guard<std::mutex> lock(S->mu);
+    auto it = S->done.find(ticket);
+    *done = it != S->done.end() ? 1 : 0;
+    if (*done) S->done.erase(it);
+    return MSC_OK;
+}
+
+msc_status msc_server_wait(msc_ctx* o, uint64_t ticket) {
+    if (!o) return MSC_E_ARG;
+    ServerState* S = o->server;
+    if (!S) return ctx_fail(o, MSC_E_STATE, "the server is not running");
+    std::unique_lock<std::mutex> lock(S->mu);
+    S->done_cv.wait(lock, [&] { return S->done.count(ticket) > 0; });
+    S->done.erase(ticket);
+    return MSC_OK;
+}
+
+msc_status msc_server_stop(msc_ctx* o) {
+    if (!o) return MSC_E_ARG;
+    ServerState* S = o->server;
+    if (!S) return MSC_OK;
+    {
+        std::lock_guard<std::mutex> lock(S->mu);
+        S->stop = true;
+    }
+    S->cv.notify_all();
+    for (auto& t : S->threads) t.join();
+    delete S;
+    o->server = nullptr;
+    return MSC_OK;
+}
+
+msc_status msc_pose_check(msc_ctx* o, const msc_scene* sc, const msc_arm* arm, const int32_t* poses_cdeg,
                           int64_t count, uint8_t* valid_out, int32_t* end_out) {
-    if (!c) return MSC_E_ARG;
+    if (!o) return MSC_E_ARG;
+    Lane* c = o->control;
+
     MSC_TRY(check_scene(c, sc));
     MSC_TRY(check_arm(c, arm, sc->n));
     if (count < 0 || (count && (!poses_cdeg || !valid_out))) return fail(c, MSC_E_ARG, "bad pose arrays");
@@ -868,14 +1340,16 @@ msc_status msc_pose_check(msc_ctx* c, const msc_scene* sc, const msc_arm* arm, c
     return MSC_OK;
 }
 
-msc_status msc_get_stats(msc_ctx* c, msc_stats* out) {
-    if (!c || !out) return MSC_E_ARG;
-    *out = c->stats;
+msc_status msc_get_stats(msc_ctx* o, msc_stats* out) {
+    if (!o || !out) return MSC_E_ARG;
+    *out = o->control->stats;
     return MSC_OK;
 }
 
-msc_status msc_debug_tables(msc_ctx* c, const msc_arm* arm, int32_t stage, int32_t* off, int32_t* sweep) {
-    if (!c) return MSC_E_ARG;
+msc_status msc_debug_tables(msc_ctx* o, const msc_arm* arm, int32_t stage, int32_t* off, int32_t* sweep) {
+    if (!o) return MSC_E_ARG;
+    Lane* c = o->control;
+
     MSC_TRY(check_arm(c, arm, 1 << 30));
     if (stage < 0 || stage >= arm->dof || !off || !sweep) return fail(c, MSC_E_ARG, "bad stage or output");
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, MSC_E_HIP, "hipSetDevice");
@@ -900,8 +1374,10 @@ msc_status msc_debug_tables(msc_ctx* c, const msc_arm* arm, int32_t stage, int32
     return MSC_OK;
 }
 
-msc_status msc_debug_raster(msc_ctx* c, const msc_scene* sc, uint8_t* occ_out) {
-    if (!c) return MSC_E_ARG;
+msc_status msc_debug_raster(msc_ctx* o, const msc_scene* sc, uint8_t* occ_out) {
+    if (!o) return MSC_E_ARG;
+    Lane* c = o->control;
+
     MSC_TRY(check_scene(c, sc));
     if (!occ_out) return fail(c, MSC_E_ARG, "NULL output");
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, MSC_E_HIP, "hipSetDevice");
@@ -918,8 +1394,10 @@ msc_status msc_debug_raster(msc_ctx* c, const msc_scene* sc, uint8_t* occ_out) {
     return MSC_OK;
 }
 
-msc_status msc_debug_set(msc_ctx* c, int32_t which, int32_t stage, uint64_t* keys, uint64_t cap, uint64_t* count) {
-    if (!c || !count) return MSC_E_ARG;
+msc_status msc_debug_set(msc_ctx* o, int32_t which, int32_t stage, uint64_t* keys, uint64_t cap, uint64_t* count) {
+    if (!o || !count) return MSC_E_ARG;
+    Lane* c = o->control;
+
     if (which == 2) {
         for (auto& kv : c->captured)
             if (kv.first.first == 2) {
@@ -934,6 +1412,10 @@ msc_status msc_debug_set(msc_ctx* c, int32_t which, int32_t stage, uint64_t* key
     return MSC_OK;
 }
 
-const char* msc_last_error(msc_ctx* c) { return c ? c->err.c_str() : "NULL context"; }
+const char* msc_last_error(msc_ctx* o) {
+    if (!o) return "NULL context";
+    if (!o->err.empty()) return o->err.c_str();
+    return o->control->err.c_str();
+}
 
 }  // extern "C"

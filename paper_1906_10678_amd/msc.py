@@ -20,13 +20,17 @@ LIB_PATH = os.path.join(HERE, "libmsc.so")
 MAX_DOF = 16
 OK, NO_REACH, NO_PATH = 0, 1, 2
 E_ARG, E_NOMEM, E_HIP, E_CAPACITY, E_STATE = -1, -2, -3, -4, -5
-CAPTURE_SETS, NO_PRUNE = 1, 2
+CAPTURE_SETS, NO_PRUNE, PROFILE = 1, 2, 4
+KERNELS = ["fill", "tables", "raster", "orient", "seed", "expand_fwd", "expand_bwd", "compact", "join", "dmark",
+           "dfs", "pose", "tube_valid", "tube_solve"]
 SET_F, SET_B, SET_C, SET_D = 0, 1, 2, 3
 
 EXPORTS = [
     "msc_opts_default", "msc_ctx_create", "msc_ctx_destroy", "msc_scene_bytes", "msc_scene_create",
     "msc_scene_destroy", "msc_reach", "msc_path", "msc_pose_check", "msc_get_stats",
-    "msc_debug_tables", "msc_debug_raster", "msc_debug_set", "msc_last_error",
+    "msc_debug_tables", "msc_debug_raster", "msc_debug_set", "msc_last_error", "msc_get_timings",
+    "msc_ctx_set_lanes", "msc_lane_bytes", "msc_batch", "msc_query_bytes", "msc_server_start",
+    "msc_server_submit", "msc_server_poll", "msc_server_wait", "msc_server_stop",
 ]
 
 
@@ -43,6 +47,18 @@ class MscBox(ctypes.Structure):
 
 class MscSphere(ctypes.Structure):
     _fields_ = [("c", ctypes.c_int32 * 3), ("r", ctypes.c_int32)]
+
+
+class MscTiming(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int32), ("stage", ctypes.c_int32), ("in_count", ctypes.c_int64),
+                ("out_count", ctypes.c_int64), ("ms", ctypes.c_float)]
+
+
+class MscQuery(ctypes.Structure):
+    _fields_ = [("scene", ctypes.c_void_p), ("arm", ctypes.POINTER(MscArm)), ("kind", ctypes.c_int32),
+                ("target", ctypes.c_int32 * 3), ("start_cdeg", ctypes.POINTER(ctypes.c_int32)),
+                ("waypoints", ctypes.c_int32), ("max_delta_cdeg", ctypes.c_int32),
+                ("out", ctypes.POINTER(ctypes.c_int32)), ("status", ctypes.c_int), ("latency_ms", ctypes.c_float)]
 
 
 class MscOpts(ctypes.Structure):
@@ -87,10 +103,23 @@ def load_library(path: str = LIB_PATH):
     L.msc_debug_tables.argtypes = [c_void_p, P(MscArm), i32, P(i32), P(i32)]
     L.msc_debug_raster.argtypes = [c_void_p, c_void_p, P(ctypes.c_uint8)]
     L.msc_debug_set.argtypes = [c_void_p, i32, i32, P(u64), u64, P(u64)]
+    L.msc_get_timings.argtypes = [c_void_p, P(MscTiming), i32, P(i32)]
+    L.msc_ctx_set_lanes.argtypes = [c_void_p, i32]
+    L.msc_lane_bytes.argtypes = [c_void_p]
+    L.msc_lane_bytes.restype = u64
+    L.msc_batch.argtypes = [c_void_p, P(MscQuery), i32, P(MscOpts)]
+    L.msc_query_bytes.argtypes = [P(MscQuery)]
+    L.msc_query_bytes.restype = u64
+    L.msc_server_start.argtypes = [c_void_p, P(MscOpts)]
+    L.msc_server_submit.argtypes = [c_void_p, P(MscQuery), P(u64)]
+    L.msc_server_poll.argtypes = [c_void_p, u64, P(i32)]
+    L.msc_server_wait.argtypes = [c_void_p, u64]
+    L.msc_server_stop.argtypes = [c_void_p]
     L.msc_last_error.argtypes = [c_void_p]
     L.msc_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
-        if name not in ("msc_opts_default", "msc_scene_bytes", "msc_last_error"):
+        if name not in ("msc_opts_default", "msc_scene_bytes", "msc_last_error", "msc_lane_bytes",
+                        "msc_query_bytes"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -124,6 +153,42 @@ def make_opts(split_m: int = -1, tube_r0: int = 1, tube_r1: int = 2, retries: in
     o = MscOpts()
     o.split_m, o.tube_r0, o.tube_r1, o.reach_retries, o.flags = split_m, tube_r0, tube_r1, retries, flags
     return o
+
+
+class QuerySpec:
+    """A reach (kind 0) or reach + path (kind 1) query for msc_batch / the server; owns
+    the ctypes buffers until the query completes."""
+
+    def __init__(self, scene: "Scene", arm, target, start=None, waypoints: int = 0, delta: int = 0):
+        self.scene = scene
+        self.arm_c = make_arm(arm)
+        self.dof = self.arm_c.dof
+        self.step = self.arm_c.step_cdeg
+        self.kind = 0 if start is None else 1
+        self.waypoints = int(waypoints)
+        rows = (self.waypoints + 1) if self.kind == 1 else 1
+        self.out = np.zeros(rows * self.dof, np.int32)
+        self.start = None if start is None else np.ascontiguousarray(np.asarray(start, np.int32) * self.step)
+        q = MscQuery()
+        q.scene = scene.handle
+        q.arm = ctypes.pointer(self.arm_c)
+        q.kind = self.kind
+        for i in range(3):
+            q.target[i] = int(target[i])
+        q.start_cdeg = _ptr(self.start, ctypes.c_int32) if self.start is not None else None
+        q.waypoints = self.waypoints
+        q.max_delta_cdeg = int(delta) * self.step
+        q.out = _ptr(self.out, ctypes.c_int32)
+        q.status = -100
+        self.c = q
+
+    def result(self):
+        """(status, joint values in steps: [dof] for reach, [(W+1), dof] for path, latency ms)."""
+        st = self.c.status
+        if st != OK:
+            return st, None, self.c.latency_ms
+        v = self.out // self.step
+        return st, (v if self.kind == 0 else v.reshape(self.waypoints + 1, self.dof)), self.c.latency_ms
 
 
 class MscError(RuntimeError):
@@ -269,6 +334,61 @@ class Solver:
                     bwd_count=list(s.bwd_count[:n + 1]), join_count=s.join_count,
                     fwd_dense=list(s.fwd_dense[:n + 1]), bwd_dense=list(s.bwd_dense[:n + 1]),
                     attempts=s.attempts, tube_r=s.tube_r, reach_index=s.reach_index)
+
+    def timings(self) -> list:
+        """Launch records of the last call made with PROFILE: (kernel, stage, in, out, ms)."""
+        cnt = ctypes.c_int32()
+        self._check(self.lib.msc_get_timings(self.ctx, None, 0, ctypes.byref(cnt)), "msc_get_timings")
+        buf = (MscTiming * max(1, cnt.value))()
+        self._check(self.lib.msc_get_timings(self.ctx, buf, cnt.value, ctypes.byref(cnt)), "msc_get_timings")
+        return [(KERNELS[t.kernel], t.stage, t.in_count, t.out_count, t.ms) for t in buf[:cnt.value]]
+
+    # -- lanes, batches, server ----------------------------------------------
+    def set_lanes(self, nworkers: int):
+        self._check(self.lib.msc_ctx_set_lanes(self.ctx, int(nworkers)), "msc_ctx_set_lanes")
+
+    def lane_bytes(self) -> int:
+        return int(self.lib.msc_lane_bytes(self.ctx))
+
+    def batch(self, specs, split_m: int = -1, flags: int = 0):
+        """Solve QuerySpecs with msc_batch; returns their results."""
+        arr = (MscQuery * max(1, len(specs)))()
+        for i, sp in enumerate(specs):
+            arr[i] = sp.c
+        o = make_opts(split_m=split_m, flags=flags)
+        self._check(self.lib.msc_batch(self.ctx, arr, len(specs), ctypes.byref(o)), "msc_batch")
+        for i, sp in enumerate(specs):
+            sp.c.status = arr[i].status
+            sp.c.latency_ms = arr[i].latency_ms
+        return [sp.result() for sp in specs]
+
+    def query_bytes(self, spec: QuerySpec) -> int:
+        return int(self.lib.msc_query_bytes(ctypes.byref(spec.c)))
+
+    def server_start(self, split_m: int = -1, flags: int = 0):
+        o = make_opts(split_m=split_m, flags=flags)
+        self._check(self.lib.msc_server_start(self.ctx, ctypes.byref(o)), "msc_server_start")
+        self._inflight = {}
+
+    def submit(self, spec: QuerySpec) -> int:
+        t = ctypes.c_uint64()
+        self._check(self.lib.msc_server_submit(self.ctx, ctypes.byref(spec.c), ctypes.byref(t)), "msc_server_submit")
+        self._inflight[t.value] = spec
+        return t.value
+
+    def poll(self, ticket: int) -> bool:
+        d = ctypes.c_int32()
+        self._check(self.lib.msc_server_poll(self.ctx, ticket, ctypes.byref(d)), "msc_server_poll")
+        if d.value:
+            self._inflight.pop(ticket, None)
+        return bool(d.value)
+
+    def wait(self, ticket: int):
+        self._check(self.lib.msc_server_wait(self.ctx, ticket), "msc_server_wait")
+        return self._inflight.pop(ticket).result()
+
+    def server_stop(self):
+        self._check(self.lib.msc_server_stop(self.ctx), "msc_server_stop")
 
     # -- debug --------------------------------------------------------------
     def debug_tables(self, arm, stage: int):
