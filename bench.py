@@ -1,18 +1,24 @@
 """Benchmark: 8-DOF reach + 16-waypoint path solves on one MI355X.
 
-A step is one whole query of the 256^3 workload: rasterise its scene, run the
-windowed staged reach search (tables, orientation sets, forward / backward stage
-expansion, compaction, join, D marking, canonical reach pose) and the tube path
-search, with the result copied back to the host.  The steps cycle over Q seeded
-synthetic queries (scene seeds 0..Q-1), prepared before the timed region.
+A query rasterises its scene, runs the windowed staged reach search (tables,
+orientation sets, forward / backward stage expansion, compaction, the meet of the
+pathways, D marking, canonical reach pose) and the tube path search, with the result
+on the host.  Queries cycle over Q seeded synthetic queries (scene seeds 0..Q-1)
+prepared before any timing.
 
-Prints one JSON line.  `roofline` is for the expansion kernel (the stage
-expansions dominate device time): achieved = algorithmic bytes / kernel time, both
-summed over the expansion launches of the timed region, the time from HIP events
-recorded on the library's stream around each launch; algorithmic bytes per launch
-= 8 * (non-zero 64-bit words of the input set + of the output set + occupancy words
-of the active box) in the layout [orientation][z][y][x/64].  `cpu_baseline` times
-the CPU oracle on one query of the same workload.
+Two phases:
+  plain   -- one query per call (msc_path), every launch timed with HIP events on
+             the library's stream; gives `plain` and `roofline`;
+  batched -- a step is one batch of queries (its scenes rasterised in the step)
+             solved by msc_batch over worker lanes; gives `value`, p50/p99 (per
+             query, from batch start to completion).
+
+`roofline` is for the stage expansions (k_expand_fwd + k_expand_bwd): achieved =
+algorithmic bytes / kernel time summed over the expansion launches of the plain timed
+region; algorithmic bytes per launch = 8 * (non-zero 64-bit words of the input set +
+of the output set + occupancy words of the active box) in the layout
+[orientation][z][y][x/64], from captured stage sets of the same queries.
+`cpu_baseline` times the CPU oracle on one query of the same workload.
 """
 from __future__ import annotations
 
@@ -94,19 +100,94 @@ def cpu_baseline(queries, split):
                       "%.1f s, status %d" % (split, dt, st)}
 
 
+def bench_c3(args):
+    """Batched reach poses: 64 scenes (128^3 or 256^3, 10..60 boxes), 8 queries each, DOF
+    5..8 unwindowed (+-170 deg in 5 deg steps); targets are ends of random poses, so
+    some have no answer.  All queries in one msc_batch call per step."""
+    import torch
+
+    from paper_1906_10678_amd import msc, synth
+
+    solver = msc.Solver(0, workspace_bytes=args.workspace_gb << 30)
+    qs = synth.queries_c3(solver.pose_fn_for, scenes=args.c3_scenes, per_scene=8)
+    print("c3: %d queries" % len(qs), file=sys.stderr, flush=True)
+
+    def step():
+        scenes, specs = {}, []
+        for q in qs:
+            if id(q.scene) not in scenes:
+                scenes[id(q.scene)] = solver.scene(q.scene)
+            specs.append(msc.QuerySpec(scenes[id(q.scene)], q.arm, q.target))
+        return solver.batch(specs)
+
+    lanes = args.lanes if args.lanes > 0 else 8
+    solver.set_lanes(lanes)
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = []
+    for _ in range(args.steps):
+        res = step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sts = [r[0] for r in res]
+    lat = np.array([r[2] for r in res])
+    out = {"metric": "batched reach solves/sec", "value": round(args.steps * len(qs) / wall, 3), "unit": "solves/s",
+           "steps": args.steps, "ms_per_step": round(1e3 * wall / args.steps, 3), "lanes": lanes,
+           "queries": len(qs), "solved_fraction": round(sts.count(msc.OK) / len(sts), 4),
+           "statuses": {str(k): sts.count(k) for k in set(sts)},
+           "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+           "config": {"workload": "batched reach: 64 scenes 128^3/256^3, 8 queries each, DOF 5..8, unwindowed, 5 deg"}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_c5(args):
+    """Serving with dynamic obstacles: Poisson arrivals, 70% reach / 30% path, moving
+    boxes re-rasterised every 10 ms tick, midcourse replanning; p50/p99 per class."""
+    from paper_1906_10678_amd import msc, serve
+
+    solver = msc.Solver(0, workspace_bytes=args.workspace_gb << 30)
+    lanes = args.lanes if args.lanes > 0 else 8
+    solver.set_lanes(lanes)
+    rows = []
+    for rate in args.c5_rates:
+        loop = serve.ServingLoop(solver, nscenes=16, seed=0, rate=rate, templates=args.c5_templates)
+        rep = loop.run(seconds=args.c5_seconds, warmup_s=1.0)
+        row = {"rate_per_s": rate}
+        row.update(rep.summary())
+        rows.append(row)
+        print(json.dumps(row), file=sys.stderr, flush=True)
+    out = {"metric": "served solves/sec and p50/p99 ms", "lanes": lanes, "seconds": args.c5_seconds, "rows": rows,
+           "config": {"workload": "serving: 16 scenes 256^3 + 1..8 moving boxes, 70% reach / 30% path (8..32 "
+                                  "waypoints), DOF 6..8, 10 ms ticks, replans on collision"}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--workload", choices=["c2", "c3", "c5"], default="c2",
+                    help="c2: 8-DOF reach + path (default); c3: batched reach; c5: serving")
+    ap.add_argument("--c3-scenes", type=int, default=64)
+    ap.add_argument("--c5-rates", type=float, nargs="+", default=[200.0, 500.0, 1000.0, 2000.0])
+    ap.add_argument("--c5-seconds", type=float, default=10.0)
+    ap.add_argument("--c5-templates", type=int, default=3000)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=16)
-    ap.add_argument("--queries", type=int, default=8)
-    ap.add_argument("--workspace-gb", type=int, default=32)
+    ap.add_argument("--steps", type=int, default=8, help="timed batches")
+    ap.add_argument("--warmup", type=int, default=2, help="untimed batches")
+    ap.add_argument("--batch", type=int, default=64, help="queries per batch")
+    ap.add_argument("--lanes", type=int, default=0, help="worker lanes (0: pick the best of a short sweep)")
+    ap.add_argument("--queries", type=int, default=16, help="distinct seeded queries")
+    ap.add_argument("--plain-steps", type=int, default=100)
+    ap.add_argument("--workspace-gb", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-profile", action="store_true", help="time without HIP events (no roofline)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the solver has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "c3":
+        return bench_c3(args)
+    if args.workload == "c5":
+        return bench_c5(args)
 
     import torch
 
@@ -119,8 +200,7 @@ def main():
     n, na = queries[0].scene.n, arm.na
 
     # Algorithmic bytes per expansion launch, from one captured run of each query.
-    alg = []
-    splits = []
+    alg, splits = [], []
     for q in queries:
         scene = solver.scene(q.scene)
         st, _ = solver.path(scene, q.arm, q.start, q.target, q.waypoints, q.max_delta, flags=msc.CAPTURE_SETS)
@@ -129,76 +209,126 @@ def main():
         alg.append(expansion_bytes(solver, msc, n, na, stats))
     print("captured stage sets; splits", splits, file=sys.stderr, flush=True)
 
-    flags = 0 if args.no_profile else msc.PROFILE
-
-    def step(i):
+    # ---- plain: one query per call, every launch timed with HIP events --------------
+    # A query answered NO_REACH / NO_PATH is a complete solve (every retry was run);
+    # only negative statuses are errors.
+    statuses = {}
+    def plain_step(i):
         q = queries[i % len(queries)]
         scene = solver.scene(q.scene)
-        st, path = solver.path(scene, q.arm, q.start, q.target, q.waypoints, q.max_delta, flags=flags)
-        if st != msc.OK:
-            raise RuntimeError("query %d: status %d" % (i % len(queries), st))
-        return solver.timings() if flags else []
+        st, path = solver.path(scene, q.arm, q.start, q.target, q.waypoints, q.max_delta, flags=msc.PROFILE)
+        if st < 0:
+            raise RuntimeError("query %d: error status %d" % (i % len(queries), st))
+        statuses[i % len(queries)] = st
+        return solver.timings()
 
-    for i in range(args.warmup):
-        step(i)
+    for i in range(len(queries)):
+        plain_step(i)
     torch.cuda.synchronize()
-    lat = []
-    launches = []
-    t_start = time.perf_counter()
-    for i in range(args.steps):
-        t0 = time.perf_counter()
-        recs = step(i)
-        lat.append(time.perf_counter() - t0)
+    lat, launches = [], []
+    t0 = time.perf_counter()
+    for i in range(args.plain_steps):
+        ts = time.perf_counter()
+        recs = plain_step(i)
+        lat.append(time.perf_counter() - ts)
         launches.append((i % len(queries), recs))
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t_start
-
+    plain_wall = time.perf_counter() - t0
     per_kernel = {}
     for _, recs in launches:
         for kname, stage, nin, nout, ms in recs:
             t = per_kernel.setdefault(kname, [0.0, 0])
             t[0] += ms
             t[1] += 1
-    roofline = None
-    if launches and launches[0][1]:
-        b_sum, ms_sum, cnt = 0.0, 0.0, 0
-        for qi, recs in launches:
-            for kname, stage, nin, nout, ms in recs:
-                if kname in ("expand_fwd", "expand_bwd"):
-                    b_sum += alg[qi][(kname, stage)]
-                    ms_sum += ms
-                    cnt += 1
-        achieved = b_sum / (ms_sum * 1e-3) / 1e9
-        roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
-                    "kernel": "expand (k_expand_fwd + k_expand_bwd)", "launches": cnt,
-                    "avg_launch_us": round(1e3 * ms_sum / max(cnt, 1), 2),
-                    "alg_bytes_per_launch": round(b_sum / max(cnt, 1))}
+    b_sum, ms_sum, cnt = 0.0, 0.0, 0
+    for qi, recs in launches:
+        for kname, stage, nin, nout, ms in recs:
+            if kname in ("expand_fwd", "expand_bwd"):
+                b_sum += alg[qi][(kname, stage)]
+                ms_sum += ms
+                cnt += 1
+    achieved = b_sum / (ms_sum * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                "kernel": "expand (k_expand_fwd + k_expand_bwd)", "launches": cnt,
+                "avg_launch_us": round(1e3 * ms_sum / max(cnt, 1), 2),
+                "alg_bytes_per_launch": round(b_sum / max(cnt, 1))}
+    plain_lat = np.array(lat) * 1e3
+    plain = {"solves_per_s": round(args.plain_steps / plain_wall, 3),
+             "p50_ms": round(float(np.percentile(plain_lat, 50)), 4),
+             "p99_ms": round(float(np.percentile(plain_lat, 99)), 4),
+             "kernel_ms_per_query": {k: round(v[0] / args.plain_steps, 4) for k, v in sorted(per_kernel.items())}}
+    print("plain", plain["solves_per_s"], "solves/s", file=sys.stderr, flush=True)
 
-    lat_ms = np.array(lat) * 1e3
+    # ---- batched: each step rasterises the scenes of a batch and solves it with msc_batch
+    def batch_step(b):
+        specs = []
+        scenes = {}
+        for j in range(args.batch):
+            q = queries[(b * args.batch + j) % len(queries)]
+            key = q.seed
+            if key not in scenes:
+                scenes[key] = solver.scene(q.scene)
+            specs.append(msc.QuerySpec(scenes[key], q.arm, q.target, start=q.start, waypoints=q.waypoints,
+                                       delta=q.max_delta))
+        res = solver.batch(specs)
+        for j, (st, _, _) in enumerate(res):
+            qi = (b * args.batch + j) % len(queries)
+            if st != statuses[qi]:
+                raise RuntimeError("batched query %d: status %d, alone %d" % (qi, st, statuses[qi]))
+        return [r[2] for r in res]
+
+    lanes = args.lanes
+    sweep = {}
+    if lanes <= 0:
+        for L in (2, 4, 8, 12, 16):
+            solver.set_lanes(L)
+            batch_step(0)
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            batch_step(1)
+            torch.cuda.synchronize()
+            sweep[L] = args.batch / (time.perf_counter() - ts)
+        lanes = max(sweep, key=sweep.get)
+        print("lane sweep", {k: round(v, 1) for k, v in sweep.items()}, "->", lanes, file=sys.stderr, flush=True)
+    solver.set_lanes(lanes)
+    for b in range(args.warmup):
+        batch_step(b)
+    torch.cuda.synchronize()
+    qlat = []
+    t0 = time.perf_counter()
+    for b in range(args.steps):
+        qlat.extend(batch_step(b))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    solver.set_lanes(0)
+    qlat = np.array(qlat)
+
     result = {
         "metric": "8-DOF reach+path solves/sec",
-        "value": round(args.steps / wall, 3),
+        "value": round(args.steps * args.batch / wall, 3),
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(1e3 * wall / args.steps, 4),
-        "p50_ms": round(float(np.percentile(lat_ms, 50)), 4),
-        "p99_ms": round(float(np.percentile(lat_ms, 99)), 4),
+        "p50_ms": round(float(np.percentile(qlat, 50)), 4),
+        "p99_ms": round(float(np.percentile(qlat, 99)), 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": "plain single query, reach pose + 16-waypoint path: 8-DOF alternating "
-                               "yaw/pitch chain 30,30,25,25,20,20,15,10 voxels, +-170 deg in 5 deg steps, "
-                               "256^3 bit-packed grid, dilation 2, 32 boxes + 8 spheres, max 5 deg per joint "
-                               "per waypoint; one query per step, scene raster included",
+        "config": {"workload": "8-DOF reach pose + 16-waypoint path queries: alternating yaw/pitch chain "
+                               "30,30,25,25,20,20,15,10 voxels, +-170 deg in 5 deg steps, 256^3 bit-packed grid, "
+                               "dilation 2, 32 boxes + 8 spheres, max 5 deg per joint per waypoint; a step is one "
+                               "batch (scenes rasterised in the step) solved with msc_batch over worker lanes",
+                   "batch": args.batch, "lanes": lanes, "lane_sweep": {str(k): round(v, 1) for k, v in sweep.items()},
                    "queries": len(queries), "grid": n, "dof": arm.dof, "waypoints": queries[0].waypoints,
-                   "splits": splits},
+                   "splits": splits, "statuses": [statuses[i] for i in range(len(queries))],
+                   "p_latency": "per query, from batch start to its completion"},
+        "plain": plain,
         "roofline": roofline,
-        "kernel_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in sorted(per_kernel.items())},
     }
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(queries, splits[0])

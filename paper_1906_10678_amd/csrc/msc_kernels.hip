@@ -43,6 +43,39 @@ __device__ __forceinline__ bool segment_clear(const GridView& g, const JointView
     return true;
 }
 
+// Same test with every sample load issued before any is checked (one memory round trip;
+// for latency-bound kernels).
+__device__ __forceinline__ bool segment_clear_all(const GridView& g, const JointView& j, int o, int x, int y,
+                                                  int z) {
+    const short4* sw = j.sweep + (size_t)o * j.S;
+    for (int s0 = 0; s0 < j.S; s0 += 8) {
+        uint64_t w[8];
+        int bit[8];
+        bool in[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            in[t] = false;
+            w[t] = 0;
+            bit[t] = 0;
+            if (s0 + t < j.S) {
+                const short4 d = sw[s0 + t];
+                const int px = x + d.x, py = y + d.y, pz = z + d.z;
+                in[t] = (unsigned)px < (unsigned)g.n && (unsigned)py < (unsigned)g.n && (unsigned)pz < (unsigned)g.n;
+                if (in[t]) {
+                    w[t] = g.occ[((size_t)pz * g.n + py) * g.wpr + (px >> 6)];
+                    bit[t] = px & 63;
+                }
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            if (s0 + t >= j.S) break;
+            if (!in[t] || ((w[t] >> bit[t]) & 1ull)) return false;
+        }
+    }
+    return true;
+}
+
 __device__ __forceinline__ bool dense_bit(const SetView& s, int x, int y, int z, int ia, int ie,
                                           uint64_t& bit) {
     int dx = x - s.x0, dy = y - s.y0, dz = z - s.z0;
@@ -59,7 +92,7 @@ __device__ __forceinline__ uint64_t load_relaxed(const uint64_t* p) {
 }
 
 // 1 = inserted, 0 = already present, -1 = table full.
-__device__ int hash_insert(const SetView& s, uint64_t key) {
+__device__ __forceinline__ int hash_insert(const SetView& s, uint64_t key) {
     const uint64_t mask = s.cap - 1;
     uint64_t h = mix64(key) & mask;
     for (uint64_t p = 0; p < s.cap; ++p) {
@@ -76,7 +109,7 @@ __device__ int hash_insert(const SetView& s, uint64_t key) {
     return -1;
 }
 
-__device__ int64_t hash_find(const SetView& s, uint64_t key) {
+__device__ __forceinline__ int64_t hash_find(const SetView& s, uint64_t key) {
     const uint64_t mask = s.cap - 1;
     uint64_t h = mix64(key) & mask;
     for (uint64_t p = 0; p < s.cap; ++p) {
@@ -89,7 +122,7 @@ __device__ int64_t hash_find(const SetView& s, uint64_t key) {
 }
 
 // 1 = inserted, 0 = already present, -1 = no room (outside the dense box / table full).
-__device__ int set_insert(const SetView& s, int x, int y, int z, int ia, int ie) {
+__device__ __forceinline__ int set_insert(const SetView& s, int x, int y, int z, int ia, int ie) {
     if (s.kind == kDense) {
         uint64_t bit;
         if (!dense_bit(s, x, y, z, ia, ie, bit)) return -1;
@@ -100,7 +133,7 @@ __device__ int set_insert(const SetView& s, int x, int y, int z, int ia, int ie)
     return hash_insert(s, pack_key(x, y, z, ia, ie));
 }
 
-__device__ bool set_member(const SetView& s, uint64_t key) {
+__device__ __forceinline__ bool set_member(const SetView& s, uint64_t key) {
     if (s.kind == kDense) {
         int x, y, z, ia, ie;
         unpack_key(key, x, y, z, ia, ie);
@@ -119,7 +152,7 @@ __device__ bool set_member(const SetView& s, uint64_t key) {
     return false;
 }
 
-__device__ void set_remove(const SetView& s, uint64_t key) {
+__device__ __forceinline__ void set_remove(const SetView& s, uint64_t key) {
     if (s.kind == kDense) {
         int x, y, z, ia, ie;
         unpack_key(key, x, y, z, ia, ie);
@@ -348,16 +381,16 @@ __global__ void k_orient(OrientArgs oa, uint64_t* rows_ie, uint64_t* rows_ia) {
             for (int t = tid; t < na; t += blockDim.x) S[t] = T[t];
             __syncthreads();
         }
-        if (tid < 4) {
-            uint64_t a = 0, e = 0;
-            for (int b = 0; b < 64; ++b) {
-                int u = 64 * tid + b;
-                if (u >= na) break;
-                if (A[u]) a |= 1ull << b;
-                if (E[u]) e |= 1ull << b;
+        {
+            // one ballot per wave gathers 64 bits of each set (256 threads cover na <= 256)
+            const bool a = tid < na && A[tid];
+            const bool e = tid < na && E[tid];
+            const unsigned long long ab = __ballot(a);
+            const unsigned long long eb = __ballot(e);
+            if ((tid & 63) == 0) {
+                Abits[tid >> 6] = ab;
+                Ebits[tid >> 6] = eb;
             }
-            Abits[tid] = a;
-            Ebits[tid] = e;
         }
         __syncthreads();
         for (int idx = tid; idx < na * 4; idx += blockDim.x) {
@@ -744,7 +777,7 @@ __global__ void __launch_bounds__(kBlock) k_meet(const uint64_t* __restrict__ fl
             const short4 d = j.off[o];
             const int x2 = x + d.x, y2 = y + d.y, z2 = z + d.z;
             if (!set_member(b, pack_key(x2, y2, z2, ia2, ie2))) continue;
-            if (!segment_clear(g, j, o, x, y, z)) continue;
+            if (!segment_clear_all(g, j, o, x, y, z)) continue;
             hit = true;
             if (count_only) {
                 ++added;
@@ -800,7 +833,7 @@ __global__ void __launch_bounds__(kBlock) k_dmark(const uint64_t* __restrict__ f
             int o = ia2 * na + ie2;
             short4 d = j.off[o];
             if (!set_member(fnext, pack_key(x + d.x, y + d.y, z + d.z, ia2, ie2))) continue;
-            if (!segment_clear(g, j, o, x, y, z)) continue;
+            if (!segment_clear_all(g, j, o, x, y, z)) continue;
             found = true;
         }
         if (found)
@@ -881,7 +914,7 @@ __global__ void __launch_bounds__(kDfsThreads) k_dfs(DfsArgs a) {
                 int o = ia2 * na + ie2;
                 short4 dd = J.off[o];
                 uint64_t key = pack_key(x + dd.x, y + dd.y, z + dd.z, ia2, ie2);
-                ok = set_member(a.sets[d + 1], key) && segment_clear(a.g, J, o, x, y, z);
+                ok = set_member(a.sets[d + 1], key) && segment_clear_all(a.g, J, o, x, y, z);
             }
             unsigned long long b = __ballot(ok);
             if ((tid & 63) == 0) cmask[d][tid >> 6] = b;
@@ -1257,6 +1290,219 @@ __global__ void __launch_bounds__(kTubeThreads) k_tube_trace(TubeArgs a, const u
         return;
     }
     tube_trace_block(a, valid, reach, path, status, nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// Bit-parallel tube search for small frames.  A frame is a bitset of B^n cells (bit c
+// of word c/64); the dilation of one joint is the OR over t in [sh-delta, sh+delta]
+// of the frame shifted by t cell strides, masked to the cells whose digit stays in
+// range (masks precomputed in LDS); the whole dynamic program runs in one block.
+// ---------------------------------------------------------------------------
+constexpr int kBitThreads = 256;
+
+// validity of every cell of every waypoint as bits: word (w*nw + i), cells >= slab are 0
+__global__ void k_tube_valid_bits(TubeArgs a, uint32_t nw, uint64_t* vbits) {
+    const uint64_t total = (uint64_t)(a.W + 1) * nw * 64;
+    for (uint64_t base = blockIdx.x * (uint64_t)blockDim.x; base < total; base += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t idx = base + threadIdx.x;
+        bool ok = false;
+        if (idx < total) {
+            const int w = (int)(idx / ((uint64_t)nw * 64));
+            const uint64_t cell = idx - (uint64_t)w * nw * 64;
+            if (cell < a.slab) {
+                int32_t q[kMaxDof];
+                ok = tube_pose(a, w, cell, q) && replay(a, q, nullptr);
+            }
+        }
+        unsigned long long b = __ballot(ok);
+        if ((threadIdx.x & 63) == 0 && idx < total) vbits[idx >> 6] = b;
+    }
+}
+
+// bits of `src` shifted so that bit c of the result is bit c + x of src (x may be < 0)
+__device__ __forceinline__ uint64_t shifted_word(const uint64_t* src, int nw, int i, int64_t x) {
+    const int64_t X = 64 * (int64_t)i + x;
+    const int64_t j = X >= 0 ? X / 64 : -((-X + 63) / 64);
+    const int u = (int)(X - 64 * j);
+    const uint64_t lo = (j >= 0 && j < nw) ? src[j] : 0ull;
+    const uint64_t hi = (j + 1 >= 0 && j + 1 < nw) ? src[j + 1] : 0ull;
+    return u ? ((lo >> u) | (hi << (64 - u))) : lo;
+}
+
+__global__ void __launch_bounds__(kBitThreads) k_tube_bits(TubeArgs a, uint32_t nw_u, const uint64_t* vbits,
+                                                           uint64_t* rbits, int32_t* path, int32_t* status) {
+    extern __shared__ uint64_t sm[];
+    const int nw = (int)nw_u;
+    const int n = a.n, B = 2 * a.r + 1, dl = a.delta;
+    const int T = 4 * dl + 1;                       // t in [-2 delta, 2 delta]
+    uint64_t* cur = sm;
+    uint64_t* ta = sm + nw;
+    uint64_t* tb = sm + 2 * nw;
+    uint64_t* mask = sm + 3 * nw;                   // [k][t + 2 delta][word]
+    __shared__ uint32_t stride[kMaxDof];
+    __shared__ int flo[kMaxDof], qcur[kMaxDof];
+    __shared__ unsigned long long best_part[kBitThreads / 64];
+    __shared__ int fail;
+    const int tid = threadIdx.x;
+    const uint32_t slab = (uint32_t)a.slab;
+    if (tid == 0) {
+        tube_strides(a, stride);
+        fail = 0;
+    }
+    __syncthreads();
+    // masks: cell c keeps shift t along joint k when 0 <= d_k(c) + t < B
+    for (int i = tid; i < nw; i += blockDim.x) {
+        const uint32_t c0 = 64u * (uint32_t)i;
+        for (int k = 0; k < n; ++k) {
+            const uint32_t sk = stride[k];
+            int d = (int)((c0 / sk) % (uint32_t)B);
+            uint32_t pos = c0 % sk;
+            uint64_t mk[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+            for (int b = 0; b < 64; ++b) {
+                if (c0 + (uint32_t)b >= slab) break;
+#pragma unroll
+                for (int t = 0; t < 9; ++t) {
+                    int dd = d + t - 2 * dl;
+                    if (t < T && dd >= 0 && dd < B) mk[t] |= 1ull << b;
+                }
+                if (++pos == sk) {
+                    pos = 0;
+                    if (++d == B) d = 0;
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < 9; ++t)
+                if (t < T) mask[((size_t)k * T + t) * nw + i] = mk[t];
+        }
+        cur[i] = vbits[i];          // R_0 = {start}
+        rbits[i] = vbits[i];
+    }
+    __syncthreads();
+    for (int w = 1; w <= a.W; ++w) {
+        for (int k = 0; k < n; ++k) {
+            const uint64_t* src = (k == 0) ? cur : ((k & 1) ? ta : tb);
+            uint64_t* dst = (k & 1) ? tb : ta;
+            const int sh = guide_at(a, w, k) - guide_at(a, w - 1, k);
+            const int64_t s = (int64_t)stride[k];
+            uint64_t outv[(16384 / 64 + kBitThreads - 1) / kBitThreads];
+            int j = 0;
+            for (int i = tid; i < nw; i += blockDim.x, ++j) {
+                uint64_t acc = 0;
+                for (int e = -dl; e <= dl; ++e) {
+                    const int t = sh + e;
+                    if (t < -2 * dl || t > 2 * dl) continue;  // cannot happen: |sh| <= delta
+                    acc |= shifted_word(src, nw, i, (int64_t)t * s) & mask[((size_t)k * T + (t + 2 * dl)) * nw + i];
+                }
+                if (k == n - 1) acc &= vbits[(size_t)w * nw + i];
+                outv[j] = acc;
+            }
+            __syncthreads();
+            j = 0;
+            for (int i = tid; i < nw; i += blockDim.x, ++j) {
+                if (k == n - 1) {
+                    cur[i] = outv[j];
+                    rbits[(size_t)w * nw + i] = outv[j];
+                } else {
+                    dst[i] = outv[j];
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // the goal: every digit = r
+    uint32_t gcell = 0;
+    for (int k = 0; k < n; ++k) gcell += (uint32_t)a.r * stride[k];
+    if (!((cur[gcell >> 6] >> (gcell & 63)) & 1ull)) {
+        if (tid == 0) *status = 0;
+        return;
+    }
+    if (tid < n) {
+        qcur[tid] = a.goal[tid];
+        path[a.W * n + tid] = a.goal[tid];
+    }
+    __syncthreads();
+    // backward choice over the (2 delta + 1)^n box around the current pose
+    const uint32_t span = (uint32_t)(2 * dl + 1);
+    uint32_t ncand = 1;
+    for (int k = 0; k < n; ++k) ncand *= span;
+    const uint32_t per = (ncand + blockDim.x - 1) / blockDim.x;
+    for (int w = a.W; w >= 1; --w) {
+        const uint64_t* R = rbits + (size_t)(w - 1) * nw;
+        if (tid < n) flo[tid] = guide_at(a, w - 1, tid) - a.r;
+        __syncthreads();
+        unsigned long long best = ~0ull;
+        const uint32_t t0 = tid * per;
+        if (t0 < ncand) {
+            int e[kMaxDof];
+            uint32_t rest = t0;
+            for (int k = n - 1; k >= 0; --k) {
+                e[k] = (int)(rest % span);
+                rest /= span;
+            }
+            for (uint32_t t = t0; t < t0 + per && t < ncand; ++t) {
+                uint32_t cell = 0;
+                int l1 = 0;
+                bool ok = true;
+                for (int k = 0; k < n; ++k) {
+                    int d = qcur[k] + e[k] - dl - flo[k];
+                    if (d < 0 || d >= B) ok = false;
+                    cell += (uint32_t)(d < 0 ? 0 : d) * stride[k];
+                    l1 += abs(d - a.r);
+                }
+                if (ok && ((R[cell >> 6] >> (cell & 63)) & 1ull)) {
+                    unsigned long long key = ((unsigned long long)l1 << 40) | cell;
+                    best = key < best ? key : best;
+                }
+                for (int k = n - 1; k >= 0; --k) {
+                    if (++e[k] < (int)span) break;
+                    e[k] = 0;
+                }
+            }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            unsigned long long o = __shfl_xor(best, off, 64);
+            best = o < best ? o : best;
+        }
+        if ((tid & 63) == 0) best_part[tid >> 6] = best;
+        __syncthreads();
+        if (tid == 0) {
+            unsigned long long b = ~0ull;
+            for (int i = 0; i < (int)(blockDim.x >> 6); ++i) b = best_part[i] < b ? best_part[i] : b;
+            if (b == ~0ull) {
+                fail = 1;
+            } else {
+                uint32_t c = (uint32_t)(b & ((1ull << 40) - 1));
+                for (int k = n - 1; k >= 0; --k) {
+                    int d = (int)(c % (uint32_t)B);
+                    c /= (uint32_t)B;
+                    qcur[k] = flo[k] + d;
+                    path[(w - 1) * n + k] = qcur[k];
+                }
+            }
+        }
+        __syncthreads();
+        if (fail) break;
+    }
+    if (tid == 0) *status = fail ? 0 : 1;
+}
+
+// LDS bytes of the bit-parallel search, or 0 when it does not apply.
+size_t tube_bits_lds(const TubeArgs& a) {
+    if (a.slab > 16384 || a.n > 8 || a.delta > 2) return 0;
+    const size_t nw = (a.slab + 63) / 64;
+    const size_t T = 4 * a.delta + 1;
+    const size_t bytes = (3 + (size_t)a.n * T) * nw * 8;
+    return bytes <= 60 * 1024 ? bytes : 0;
+}
+
+hipError_t launch_tube_bits(const TubeArgs& a, uint64_t* vbits, uint64_t* rbits, int32_t* path, int32_t* status,
+                            hipStream_t st) {
+    const uint32_t nw = (uint32_t)((a.slab + 63) / 64);
+    const uint64_t total = (uint64_t)(a.W + 1) * nw * 64;
+    hipLaunchKernelGGL(k_tube_valid_bits, dim3(grid_for(total)), dim3(kBlock), 0, st, a, nw, vbits);
+    hipLaunchKernelGGL(k_tube_bits, dim3(1), dim3(kBitThreads), tube_bits_lds(a), st, a, nw, vbits, rbits, path,
+                       status);
+    return hipGetLastError();
 }
 
 hipError_t launch_tube_solve(const TubeArgs& a, const uint8_t* valid, uint8_t* reach, uint8_t* tmp0,

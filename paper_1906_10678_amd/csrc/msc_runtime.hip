@@ -626,17 +626,25 @@ msc_status run_reach(Lane* c, const msc_scene* sc, const Plan& p, int want, bool
             MSC_TRY(capture_set(c, Fm, N, 0, m));
         }
         MSC_TRY(ensure_list(c, F[m - 1]));
-        unsigned long long* hc = take_counter(c);
-        unsigned long long* kc = take_counter(c);
-        if (!hc || !kc) return fail(c, MSC_E_CAPACITY, "out of counters");
-        LAUNCH(MSC_K_JOIN, m, (int64_t)F[m - 1].count,
-               launch_meet(F[m - 1].list, F[m - 1].count, F[m - 1].view, B[m].view, B[m].view, g, jv[m - 1], 1, hc,
-                           kc, ovf, c->stream));
-        uint64_t hits = 0;
-        MSC_TRY(read_counter(c, hc, &hits));
+        const int fast = (m < n && p.type[m] == MSC_YAW) ? 1 : 0;
+        // C_m is a dense bitset over the stage box when pruning bounds the box (one pass);
+        // otherwise a hash set sized by a first, counting pass
+        const uint64_t box_words = box[m].voxels() * (uint64_t)na * na / 64;
+        const bool dense_c = p.prune && !box[m].empty() && box_words <= (1ull << 31);
+        uint64_t hits = 1;
+        if (dense_c) {
+            MSC_TRY(make_set(c, p, box[m], 0, fast, true, Cset));
+        } else {
+            unsigned long long* hc = take_counter(c);
+            unsigned long long* kc = take_counter(c);
+            if (!hc || !kc) return fail(c, MSC_E_CAPACITY, "out of counters");
+            LAUNCH(MSC_K_JOIN, m, (int64_t)F[m - 1].count,
+                   launch_meet(F[m - 1].list, F[m - 1].count, F[m - 1].view, B[m].view, B[m].view, g, jv[m - 1], 1,
+                               hc, kc, ovf, c->stream));
+            MSC_TRY(read_counter(c, hc, &hits));
+            if (hits) MSC_TRY(make_set(c, p, box[m], hits, fast, false, Cset));
+        }
         if (hits) {
-            int fast = (m < n && p.type[m] == MSC_YAW) ? 1 : 0;
-            MSC_TRY(make_set(c, p, box[m], hits, fast, false, Cset));
             unsigned long long* cc = take_counter(c);
             unsigned long long* kc2 = take_counter(c);
             if (!cc || !kc2) return fail(c, MSC_E_CAPACITY, "out of counters");
@@ -954,19 +962,31 @@ msc_status path_on(Lane* c, const msc_scene* sc, const msc_arm* arm, const int32
                 ta.lim_hi[k] = lim_hi[k];
             }
             ta.slab = slab;
-            void *d_valid, *d_reach, *d_t0, *d_t1, *h_path, *d_path, *h_status, *d_status;
+            void *h_path, *d_path, *h_status, *d_status;
             uint64_t cells = (uint64_t)(waypoints + 1) * slab;
-            MSC_TRY(arena_alloc(c, cells, &d_valid));
-            MSC_TRY(arena_alloc(c, cells, &d_reach));
-            MSC_TRY(arena_alloc(c, slab, &d_t0));
-            MSC_TRY(arena_alloc(c, slab, &d_t1));
             MSC_TRY(host_area(c, path.size() * 4, &h_path, &d_path));
             MSC_TRY(host_area(c, 4, &h_status, &d_status));
             *(volatile int32_t*)h_status = 0;
-            LAUNCH(MSC_K_TUBE_VALID, rad, (int64_t)cells, launch_tube_valid(ta, (uint8_t*)d_valid, c->stream));
-            LAUNCH(MSC_K_TUBE_SOLVE, rad, (int64_t)cells,
-                   launch_tube_solve(ta, (const uint8_t*)d_valid, (uint8_t*)d_reach, (uint8_t*)d_t0, (uint8_t*)d_t1,
-                                     (int32_t*)d_path, (int32_t*)d_status, c->stream));
+            if (tube_bits_lds(ta)) {
+                // small frames: bit-parallel search in one block
+                void *d_vbits, *d_rbits;
+                uint64_t words = (uint64_t)(waypoints + 1) * ((slab + 63) / 64);
+                MSC_TRY(arena_alloc(c, words * 8, &d_vbits));
+                MSC_TRY(arena_alloc(c, words * 8, &d_rbits));
+                LAUNCH(MSC_K_TUBE_SOLVE, rad, (int64_t)cells,
+                       launch_tube_bits(ta, (uint64_t*)d_vbits, (uint64_t*)d_rbits, (int32_t*)d_path,
+                                        (int32_t*)d_status, c->stream));
+            } else {
+                void *d_valid, *d_reach, *d_t0, *d_t1;
+                MSC_TRY(arena_alloc(c, cells, &d_valid));
+                MSC_TRY(arena_alloc(c, cells, &d_reach));
+                MSC_TRY(arena_alloc(c, slab, &d_t0));
+                MSC_TRY(arena_alloc(c, slab, &d_t1));
+                LAUNCH(MSC_K_TUBE_VALID, rad, (int64_t)cells, launch_tube_valid(ta, (uint8_t*)d_valid, c->stream));
+                LAUNCH(MSC_K_TUBE_SOLVE, rad, (int64_t)cells,
+                       launch_tube_solve(ta, (const uint8_t*)d_valid, (uint8_t*)d_reach, (uint8_t*)d_t0,
+                                         (uint8_t*)d_t1, (int32_t*)d_path, (int32_t*)d_status, c->stream));
+            }
             HIP_TRY(hipStreamSynchronize(c->stream));
             int32_t ok2 = *(volatile int32_t*)h_status;
             c->stats.attempts++;
@@ -1212,8 +1232,10 @@ uint64_t msc_query_bytes(const msc_query* q) {
     const int n = a->dof;
     if (a->step_cdeg <= 0) return 0;
     const uint64_t na = 36000 / (uint64_t)a->step_cdeg;
+    // the pathways meet late (the backward side starts from every orientation), about
+    // 5/8 of the way: the dense sets cover a box of the remaining segments' reach
     int64_t reach = 0;
-    for (int k = (n + 1) / 2; k < n; ++k) reach += a->len_vox[k] + 1;
+    for (int k = (5 * n + 7) / 8; k < n; ++k) reach += a->len_vox[k] + 1;
     uint64_t edge = std::min<uint64_t>(2 * (uint64_t)reach + 1, (uint64_t)q->scene->n);
     uint64_t dense = edge * edge * edge * na * na / 8;
     uint64_t tube = 0;

@@ -256,3 +256,74 @@ def query_c2(seed: int, pose_fn_for: Callable[[Arm, Scene], PoseFn], waypoints: 
     _, end = walk_target(rng_for(2, seed, 2), arm, start, waypoints, delta, pf)
     return Query(arm=arm, scene=scene, target=tuple(int(v) for v in end), start=start,
                  waypoints=waypoints, max_delta=delta, seed=(2, seed))
+
+
+# --------------------------------------------------------------------------
+# Batched and larger workloads
+# --------------------------------------------------------------------------
+
+def scene_c3(scene_seed: int, n: Optional[int] = None) -> Scene:
+    """One of the 64 scenes of the batched-reach workload: grid 128^3 or 256^3 (uniform),
+    10..60 boxes with edges 5..40 scaled by n/256, dilation round(2 n/256)."""
+    rng = rng_for(3, scene_seed, 0)
+    if n is None:
+        n = int(rng.choice([128, 256]))
+    else:
+        rng.choice([128, 256])
+    nbox = int(rng.integers(10, 61))
+    lo_e = max(1, int(round(5 * n / 256)))
+    hi_e = max(lo_e, int(round(40 * n / 256)))
+    dilate = int(round(2 * n / 256))
+    base = (n // 2, n // 2, 0)
+    return random_scene(rng, n, dilate, nbox, (lo_e, hi_e), base=base, column=scaled_lens(n, 1)[0])
+
+
+def queries_c3(pose_fn_for: Callable[[Arm, Scene], PoseFn], scenes: int = 64, per_scene: int = 8,
+               n: Optional[int] = None, max_dof: int = 8, step_cdeg: int = 500) -> List[Query]:
+    """Batched reach poses: per scene, `per_scene` queries with DOF uniform 5..max_dof
+    (prefix of the 8-DOF chain, lengths scaled by n/256), joints +-170 deg; the target is
+    the end voxel (inside the grid) of a uniformly drawn pose, valid or not, so some
+    queries have no answer."""
+    out = []
+    for s in range(scenes):
+        sc = scene_c3(s, n)
+        rng = rng_for(3, s, 1)
+        for j in range(per_scene):
+            dof = int(rng.integers(5, max_dof + 1))
+            arm = arm_chain(dof, scaled_lens(sc.n, dof), step_cdeg, 17000, (sc.n // 2, sc.n // 2, 0))
+            pf = pose_fn_for(arm, sc)
+            while True:  # redraw poses whose end voxel lies outside the grid
+                q = candidate_poses(rng, arm, 1)
+                _, end = pf(q)
+                end = np.asarray(end)[0]
+                if np.all(end >= 0) and np.all(end < sc.n):
+                    break
+            out.append(Query(arm=arm, scene=sc, target=tuple(int(v) for v in end), seed=(3, s, j)))
+    return out
+
+
+def queries_c4(pose_fn_for: Callable[[Arm, Scene], PoseFn], scenes: int = 8, per_scene: int = 32,
+               n: int = 512, step_cdeg: int = 250, lens_scale: float = 2.0, w_range: Tuple[int, int] = (8, 64),
+               dof: int = 8) -> List[Query]:
+    """Batched paths: 8 shared 512^3 scenes (40 boxes with edges 10..80, 16 spheres of
+    radius 8..40, dilation 4), 8-DOF chain with the segment lengths doubled, 2.5 deg
+    steps, +-170 deg, 8..64 waypoints of at most one step per joint.  The scale knobs
+    give the shrunken variants used by the parity tests."""
+    out = []
+    f = n / 512
+    for s in range(scenes):
+        rng = rng_for(4, s, 0)
+        lens = [max(1, int(round(l * lens_scale * f))) for l in C2_LENS[:dof]]
+        base = (n // 2, n // 2, 0)
+        sc = random_scene(rng, n, max(0, int(round(4 * f))), 40, (max(1, int(10 * f)), max(1, int(80 * f))),
+                          16, (max(1, int(8 * f)), max(1, int(40 * f))), base=base, column=lens[0])
+        arm = arm_chain(dof, lens, step_cdeg, 17000, base)
+        pf = pose_fn_for(arm, sc)
+        for j in range(per_scene):
+            r = rng_for(4, s, 1 + j)
+            start, _, _ = first_valid_pose(r, arm, pf, batch=1024)
+            W = int(r.integers(w_range[0], w_range[1] + 1))
+            _, end = walk_target(r, arm, start, W, 1, pf)
+            out.append(Query(arm=arm, scene=sc, target=tuple(int(v) for v in end), start=start, waypoints=W,
+                             max_delta=1, seed=(4, s, j)))
+    return out
