@@ -20,8 +20,23 @@ namespace {
 constexpr int kBlock = 256;
 
 __device__ __forceinline__ int wrap_na(int v, int na) {
-    v %= na;
-    return v < 0 ? v + na : v;
+    // joint angles stay within one turn, so v is almost always in (-na, 2 na)
+    v += v < 0 ? na : 0;
+    v -= v >= na ? na : 0;
+    if ((unsigned)v >= (unsigned)na) {
+        v %= na;
+        v += v < 0 ? na : 0;
+    }
+    return v;
+}
+
+// Lanes that share one state when a kernel tries a joint's whole window for it: the
+// window size rounded up to a power of two, at most a wave; lane l of the group takes
+// the angles lo + l, lo + l + G, ...
+__device__ __forceinline__ int group_log2(int nA) {
+    int lg = 0;
+    while ((1 << lg) < nA && lg < 6) ++lg;
+    return lg;
 }
 
 __device__ __forceinline__ bool cell_free(const GridView& g, int x, int y, int z) {
@@ -191,6 +206,12 @@ __device__ __forceinline__ void mask_range(uint64_t m[4], int lo, int hi) {
         uint64_t bot = (1ull << a) - 1;
         m[w] |= top & ~bot;
     }
+}
+
+int host_group_log2(int nA) {
+    int lg = 0;
+    while ((1 << lg) < nA && lg < 6) ++lg;
+    return lg;
 }
 
 uint32_t grid_for(uint64_t work, uint32_t block = kBlock, uint32_t max_blocks = 16384) {
@@ -466,12 +487,17 @@ __global__ void __launch_bounds__(kBlock) k_expand_fwd(const uint64_t* __restric
                                                        unsigned long long* overflow) {
     const int na = out.na;
     const uint32_t nA = (uint32_t)(j.hi - j.lo + 1);
-    const uint64_t total = count * nA;
     unsigned long long added = 0, ovf = 0;
-    for (uint64_t idx = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; idx < total;
-         idx += (uint64_t)gridDim.x * blockDim.x) {
-        uint64_t i = idx / nA;
-        int a = j.lo + (int)(idx - i * nA);
+    // Work item idx = i * nA + ai walks the grid stride as (state, angle) pairs: one
+    // 64-bit division per thread, none per item.
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t idx0 = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    const uint64_t si = stride / nA;
+    const uint32_t sa = (uint32_t)(stride - si * nA);
+    uint64_t i = idx0 / nA;
+    uint32_t ai = (uint32_t)(idx0 - i * nA);
+    for (; i < count; i += si, ai += sa, i += (ai >= nA) ? 1 : 0, ai -= (ai >= nA) ? nA : 0) {
+        int a = j.lo + (int)ai;
         int x, y, z, ia, ie;
         unpack_key(in[i], x, y, z, ia, ie);
         if (ia >= na || ie >= na) continue;
@@ -486,7 +512,7 @@ __global__ void __launch_bounds__(kBlock) k_expand_fwd(const uint64_t* __restric
             long long ex = x2 - tx, ey = y2 - ty, ez = z2 - tz;
             if (ex * ex + ey * ey + ez * ez > r2) continue;
         }
-        if (!segment_clear(g, j, o, x, y, z)) continue;
+        if (!segment_clear_all(g, j, o, x, y, z)) continue;
         int r = set_insert(out, x2, y2, z2, ia, ie);
         if (r > 0)
             ++added;
@@ -512,9 +538,9 @@ hipError_t launch_expand_fwd(const uint64_t* in, uint64_t count, SetView out, Gr
 // of segment k is the same for every angle of joint k, so the clearance of the
 // segment is tested once; the predecessors are (p, o' turned back by a) for every
 // a in the window, a cyclic run along the joint's axis, filtered by O_{k-1} and the
-// backward pruning radius around the base (eqs 7-8).  In a dense output whose
-// fastest orientation axis is the joint's axis the run is set with at most a few
-// masked atomicOr.
+// backward pruning radius around the base (eqs 7-8).  This kernel serves dense
+// outputs whose fastest orientation axis is the joint's axis: the run is set with at
+// most a few masked atomicOr (other outputs: k_expand_bwd_set).
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock) k_expand_bwd(const uint64_t* __restrict__ in, uint64_t count,
                                                        SetView out, GridView g, JointView j, int bx, int by,
@@ -524,7 +550,6 @@ __global__ void __launch_bounds__(kBlock) k_expand_bwd(const uint64_t* __restric
     const int na = out.na;
     const int nA = j.hi - j.lo + 1;
     const bool yaw = j.type == 0;
-    const bool run_dense = out.kind == kDense && ((out.fast_ia != 0) == yaw);
     unsigned long long added = 0, ovf = 0;
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < count;
          i += (uint64_t)gridDim.x * blockDim.x) {
@@ -539,7 +564,7 @@ __global__ void __launch_bounds__(kBlock) k_expand_bwd(const uint64_t* __restric
             long long ex = x - bx, ey = y - by, ez = z - bz;
             if (ex * ex + ey * ey + ez * ez > r2) continue;
         }
-        if (!segment_clear(g, j, o2, x, y, z)) continue;
+        if (!segment_clear_all(g, j, o2, x, y, z)) continue;
         const int v = yaw ? ia2 : ie2;
         const int other = yaw ? ie2 : ia2;
         uint64_t m[4] = {0, 0, 0, 0};
@@ -559,42 +584,72 @@ __global__ void __launch_bounds__(kBlock) k_expand_bwd(const uint64_t* __restric
             const uint64_t* row = orows + (size_t)other * 4;
             for (int w = 0; w < 4; ++w) m[w] &= row[w];
         }
-        if (run_dense) {
-            uint64_t bit0;
-            if (!dense_bit(out, x, y, z, yaw ? 0 : ia2, yaw ? ie2 : 0, bit0)) {
+        uint64_t bit0;
+        if (!dense_bit(out, x, y, z, yaw ? 0 : ia2, yaw ? ie2 : 0, bit0)) {
+            ++ovf;
+            continue;
+        }
+        for (int w = 0; w < 4; ++w) {
+            if (!m[w]) continue;
+            uint64_t pos = bit0 + 64ull * w;
+            uint64_t word = pos >> 6;
+            int sh = (int)(pos & 63);
+            uint64_t lo_part = m[w] << sh;
+            uint64_t old = atomicOr((unsigned long long*)&out.words[word], (unsigned long long)lo_part);
+            added += __popcll(lo_part & ~old);
+            if (sh) {
+                uint64_t hi_part = m[w] >> (64 - sh);
+                if (hi_part) {
+                    old = atomicOr((unsigned long long*)&out.words[word + 1], (unsigned long long)hi_part);
+                    added += __popcll(hi_part & ~old);
+                }
+            }
+        }
+    }
+    block_add(added, counter);
+    if (ovf) atomicAdd(overflow, ovf);
+}
+
+// The same stage into a hash set (or a dense set whose fast axis is not the joint's):
+// the predecessor run is inserted one orientation per lane, a group of lanes per state.
+__global__ void __launch_bounds__(kBlock) k_expand_bwd_set(const uint64_t* __restrict__ in, uint64_t count,
+                                                           SetView out, GridView g, JointView j, int bx, int by,
+                                                           int bz, long long r2, const uint64_t* __restrict__ orows,
+                                                           unsigned long long* counter,
+                                                           unsigned long long* overflow) {
+    const int na = out.na;
+    const bool yaw = j.type == 0;
+    const int lg = group_log2(j.hi - j.lo + 1), G = 1 << lg;
+    const int lane = threadIdx.x & 63, sub = lane & (G - 1), grp = lane >> lg;
+    const uint64_t per_wave = 64u >> lg;
+    const uint64_t wave = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) >> 6;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    unsigned long long added = 0, ovf = 0;
+    for (uint64_t base = wave * per_wave; base < count; base += nwaves * per_wave) {
+        const uint64_t i = base + (uint64_t)grp;
+        if (i >= count) continue;
+        int x2, y2, z2, ia2, ie2;
+        unpack_key(in[i], x2, y2, z2, ia2, ie2);
+        if (ia2 >= na || ie2 >= na) continue;
+        const int o2 = ia2 * na + ie2;
+        const short4 d = j.off[o2];
+        const int x = x2 - d.x, y = y2 - d.y, z = z2 - d.z;
+        if (!cell_free(g, x, y, z)) continue;
+        if (r2 >= 0) {
+            long long ex = x - bx, ey = y - by, ez = z - bz;
+            if (ex * ex + ey * ey + ez * ez > r2) continue;
+        }
+        if (!segment_clear_all(g, j, o2, x, y, z)) continue;
+        const int v = yaw ? ia2 : ie2;
+        const uint64_t* row = orows ? orows + (size_t)(yaw ? ie2 : ia2) * 4 : nullptr;
+        for (int a = j.lo + sub; a <= j.hi; a += G) {
+            const int u = wrap_na(v - a, na);
+            if (row && !((row[u >> 6] >> (u & 63)) & 1ull)) continue;
+            int r = set_insert(out, x, y, z, yaw ? u : ia2, yaw ? ie2 : u);
+            if (r > 0)
+                ++added;
+            else if (r < 0)
                 ++ovf;
-                continue;
-            }
-            for (int w = 0; w < 4; ++w) {
-                if (!m[w]) continue;
-                uint64_t pos = bit0 + 64ull * w;
-                uint64_t word = pos >> 6;
-                int sh = (int)(pos & 63);
-                uint64_t lo_part = m[w] << sh;
-                uint64_t old = atomicOr((unsigned long long*)&out.words[word], (unsigned long long)lo_part);
-                added += __popcll(lo_part & ~old);
-                if (sh) {
-                    uint64_t hi_part = m[w] >> (64 - sh);
-                    if (hi_part) {
-                        old = atomicOr((unsigned long long*)&out.words[word + 1], (unsigned long long)hi_part);
-                        added += __popcll(hi_part & ~old);
-                    }
-                }
-            }
-        } else {
-            for (int w = 0; w < 4; ++w) {
-                uint64_t bits = m[w];
-                while (bits) {
-                    int b = __ffsll((unsigned long long)bits) - 1;
-                    bits &= bits - 1;
-                    int u = 64 * w + b;
-                    int r = set_insert(out, x, y, z, yaw ? u : ia2, yaw ? ie2 : u);
-                    if (r > 0)
-                        ++added;
-                    else if (r < 0)
-                        ++ovf;
-                }
-            }
         }
     }
     block_add(added, counter);
@@ -605,8 +660,15 @@ hipError_t launch_expand_bwd(const uint64_t* in, uint64_t count, SetView out, Gr
                              int bx, int by, int bz, long long r2, const uint64_t* orows,
                              unsigned long long* counter, unsigned long long* overflow, hipStream_t st) {
     if (count == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_expand_bwd, dim3(grid_for(count)), dim3(kBlock), 0, st, in, count, out, g, j, bx, by, bz,
-                       r2, orows, counter, overflow);
+    const bool run_dense = out.kind == kDense && ((out.fast_ia != 0) == (j.type == 0));
+    if (run_dense) {
+        hipLaunchKernelGGL(k_expand_bwd, dim3(grid_for(count)), dim3(kBlock), 0, st, in, count, out, g, j, bx, by,
+                           bz, r2, orows, counter, overflow);
+    } else {
+        const uint64_t lanes = count * (uint64_t)(1u << host_group_log2(j.hi - j.lo + 1));
+        hipLaunchKernelGGL(k_expand_bwd_set, dim3(grid_for(lanes)), dim3(kBlock), 0, st, in, count, out, g, j, bx,
+                           by, bz, r2, orows, counter, overflow);
+    }
     return hipGetLastError();
 }
 
@@ -634,6 +696,44 @@ __device__ __forceinline__ void divmod_big(uint64_t n, uint32_t d, double inv, u
     r = (uint32_t)rr;
 }
 
+// Position of the r-th set bit (r < popcount) of w, by popcount bisection.
+__device__ __forceinline__ int select_bit(uint64_t w, unsigned int r) {
+    int pos = 0;
+    unsigned int c = (unsigned int)__popc((uint32_t)w);
+    if (r >= c) {
+        r -= c;
+        w >>= 32;
+        pos = 32;
+    }
+    uint32_t x = (uint32_t)w;
+    c = (unsigned int)__popc(x & 0xffffu);
+    if (r >= c) {
+        r -= c;
+        x >>= 16;
+        pos += 16;
+    }
+    c = (unsigned int)__popc(x & 0xffu);
+    if (r >= c) {
+        r -= c;
+        x >>= 8;
+        pos += 8;
+    }
+    c = (unsigned int)__popc(x & 0xfu);
+    if (r >= c) {
+        r -= c;
+        x >>= 4;
+        pos += 4;
+    }
+    c = (unsigned int)__popc(x & 0x3u);
+    if (r >= c) {
+        r -= c;
+        x >>= 2;
+        pos += 2;
+    }
+    if (r >= (x & 1u)) pos += 1;
+    return pos;
+}
+
 __device__ __forceinline__ int member_count(const SetView& s, uint64_t w) {
     if (s.kind == kDense) return __popcll(w);
     return (w != kEmpty && !(w & kDead)) ? 1 : 0;
@@ -647,6 +747,7 @@ __global__ void __launch_bounds__(kBlock) k_compact(SetView s, uint64_t* list, u
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t na2 = (uint32_t)(s.na * s.na);
     const double inv_na2 = 1.0 / (double)na2;
+    const float inv_na = 1.0f / (float)s.na;
     const uint64_t tile = (uint64_t)kBlock * kCompactWords;
     for (uint64_t t0 = blockIdx.x * tile; t0 < s.cap; t0 += (uint64_t)gridDim.x * tile) {
         uint64_t wv[kCompactWords];
@@ -674,34 +775,76 @@ __global__ void __launch_bounds__(kBlock) k_compact(SetView s, uint64_t* list, u
             tile_base = tot ? atomicAdd(counter, (unsigned long long)tot) : 0ull;
         }
         __syncthreads();
-        uint64_t pos = tile_base + wave_off[wave] + (incl - c);
-        if (c) {
+        if (s.kind == kDense) {
+            // Wave-balanced emission.  Round j covers the wave's 64 consecutive words;
+            // lane t of the round emits states t, t + 64, ... of the round, finding its
+            // word by bisection over the lanes' prefix counts and its bit by popcount
+            // bisection, so a few dense words do not serialise the wave.
+            uint64_t out = tile_base + wave_off[wave];
+            const uint32_t nx = (uint32_t)s.nx, ny = (uint32_t)s.ny;
 #pragma unroll
             for (int j = 0; j < kCompactWords; ++j) {
-                uint64_t w = wv[j];
-                uint64_t i = t0 + (uint64_t)j * kBlock + tid;
-                if (s.kind == kDense) {
-                    while (w) {
-                        int b = __ffsll((unsigned long long)w) - 1;
-                        w &= w - 1;
-                        uint64_t vox;
-                        uint32_t o;
-                        divmod_big(i * 64 + (uint64_t)b, na2, inv_na2, vox, o);
-                        uint32_t v32 = (uint32_t)vox;
-                        uint32_t dx = v32 % (uint32_t)s.nx;
-                        uint32_t r2 = v32 / (uint32_t)s.nx;
-                        uint32_t dy = r2 % (uint32_t)s.ny;
-                        uint32_t dz = r2 / (uint32_t)s.ny;
-                        uint32_t hi = o / (uint32_t)s.na, lo = o % (uint32_t)s.na;
-                        int ia = s.fast_ia ? (int)lo : (int)hi;
-                        int ie = s.fast_ia ? (int)hi : (int)lo;
-                        if (pos < cap)
-                            list[pos] = pack_key(s.x0 + (int)dx, s.y0 + (int)dy, s.z0 + (int)dz, ia, ie);
-                        else
-                            atomicAdd(overflow, 1ull);
-                        ++pos;
+                const uint64_t w = wv[j];
+                const unsigned int cj = (unsigned int)__popcll(w);
+                unsigned int ij = cj;
+                for (int off = 1; off < 64; off <<= 1) {
+                    const unsigned int t = __shfl_up(ij, off, 64);
+                    if (lane >= off) ij += t;
+                }
+                const unsigned int T = __shfl(ij, 63, 64);
+                if (T == 0) continue;
+                const unsigned int ex = ij - cj;
+                const uint64_t i = t0 + (uint64_t)j * kBlock + tid;
+                uint64_t vox;
+                uint32_t o0;
+                divmod_big(i * 64, na2, inv_na2, vox, o0);
+                const uint32_t v32 = (uint32_t)vox;
+                const uint32_t rest = v32 / nx;
+                const uint32_t dx0 = v32 - rest * nx, dy0 = rest % ny, dz0 = rest / ny;
+                const unsigned int rounds = (T + 63u) & ~63u;
+                for (unsigned int t = (unsigned int)lane; t < rounds; t += 64) {
+                    int L = 0;
+                    for (int step = 32; step > 0; step >>= 1) {
+                        const unsigned int e = __shfl(ex, L + step, 64);
+                        if (e <= t) L += step;
                     }
-                } else if (member_count(s, w)) {
+                    const uint64_t wl = __shfl(w, L, 64);
+                    const unsigned int r = t - __shfl(ex, L, 64);
+                    const int ol = __shfl((int)o0, L, 64);
+                    uint32_t dx = __shfl(dx0, L, 64), dy = __shfl(dy0, L, 64), dz = __shfl(dz0, L, 64);
+                    if (t >= T) continue;
+                    int o = ol + select_bit(wl, r);
+                    while (o >= (int)na2) {
+                        o -= (int)na2;
+                        if (++dx == nx) {
+                            dx = 0;
+                            if (++dy == ny) {
+                                dy = 0;
+                                ++dz;
+                            }
+                        }
+                    }
+                    // o / na by a float reciprocal (o < 2^16), corrected to the exact quotient
+                    int hi = (int)((float)o * inv_na);
+                    hi -= hi * s.na > o ? 1 : 0;
+                    hi += (hi + 1) * s.na <= o ? 1 : 0;
+                    const int lo = o - hi * s.na;
+                    const int ia = s.fast_ia ? lo : hi;
+                    const int ie = s.fast_ia ? hi : lo;
+                    const uint64_t p = out + t;
+                    if (p < cap)
+                        list[p] = pack_key(s.x0 + (int)dx, s.y0 + (int)dy, s.z0 + (int)dz, ia, ie);
+                    else
+                        atomicAdd(overflow, 1ull);
+                }
+                out += T;
+            }
+        } else if (c) {
+            uint64_t pos = tile_base + wave_off[wave] + (incl - c);
+#pragma unroll
+            for (int j = 0; j < kCompactWords; ++j) {
+                const uint64_t w = wv[j];
+                if (member_count(s, w)) {
                     if (pos < cap)
                         list[pos] = w;
                     else
@@ -759,40 +902,55 @@ __global__ void __launch_bounds__(kBlock) k_meet(const uint64_t* __restrict__ fl
                                                  unsigned long long* c_count, unsigned long long* kept_count,
                                                  unsigned long long* overflow) {
     const int na = b.na;
+    const int lg = group_log2(j.hi - j.lo + 1), G = 1 << lg;
+    const int lane = threadIdx.x & 63, sub = lane & (G - 1), grp = lane >> lg;
+    const uint64_t per_wave = 64u >> lg;
+    const uint64_t wave = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) >> 6;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
     unsigned long long added = 0, kept = 0, ovf = 0;
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < count;
-         i += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t key = flist[i];
-        int x, y, z, ia, ie;
-        unpack_key(key, x, y, z, ia, ie);
-        if (ia >= na || ie >= na) continue;
+    for (uint64_t base = wave * per_wave; base < count; base += nwaves * per_wave) {
+        const uint64_t i = base + (uint64_t)grp;
+        uint64_t key = 0;
+        int x = 0, y = 0, z = 0, ia = na, ie = na;
         bool hit = false;
-        for (int a = j.lo; a <= j.hi; ++a) {
-            int ia2 = ia, ie2 = ie;
-            if (j.type == 0)
-                ia2 = wrap_na(ia + a, na);
-            else
-                ie2 = wrap_na(ie + a, na);
-            const int o = ia2 * na + ie2;
-            const short4 d = j.off[o];
-            const int x2 = x + d.x, y2 = y + d.y, z2 = z + d.z;
-            if (!set_member(b, pack_key(x2, y2, z2, ia2, ie2))) continue;
-            if (!segment_clear_all(g, j, o, x, y, z)) continue;
-            hit = true;
-            if (count_only) {
-                ++added;
-                continue;
-            }
-            int r = set_insert(c, x2, y2, z2, ia2, ie2);
-            if (r > 0)
-                ++added;
-            else if (r < 0)
-                ++ovf;
+        if (i < count) {
+            key = flist[i];
+            unpack_key(key, x, y, z, ia, ie);
         }
-        if (hit)
-            ++kept;
-        else if (!count_only)
-            set_remove(fprev, key);
+        const bool live = i < count && ia < na && ie < na;
+        if (live) {
+            for (int a = j.lo + sub; a <= j.hi; a += G) {
+                int ia2 = ia, ie2 = ie;
+                if (j.type == 0)
+                    ia2 = wrap_na(ia + a, na);
+                else
+                    ie2 = wrap_na(ie + a, na);
+                const int o = ia2 * na + ie2;
+                const short4 d = j.off[o];
+                const int x2 = x + d.x, y2 = y + d.y, z2 = z + d.z;
+                if (!set_member(b, pack_key(x2, y2, z2, ia2, ie2))) continue;
+                if (!segment_clear_all(g, j, o, x, y, z)) continue;
+                hit = true;
+                if (count_only) {
+                    ++added;
+                    continue;
+                }
+                int r = set_insert(c, x2, y2, z2, ia2, ie2);
+                if (r > 0)
+                    ++added;
+                else if (r < 0)
+                    ++ovf;
+            }
+        }
+        // one decision per state: the OR of its group's hits
+        const uint64_t bal = __ballot(hit);
+        const uint64_t gm = lg == 6 ? bal : (bal >> (grp << lg)) & ((1ull << G) - 1);
+        if (live && sub == 0) {
+            if (gm)
+                ++kept;
+            else if (!count_only)
+                set_remove(fprev, key);
+        }
     }
     block_add(added, c_count);
     block_add(kept, kept_count);
@@ -803,7 +961,8 @@ hipError_t launch_meet(const uint64_t* flist, uint64_t count, SetView fprev, Set
                        JointView j, int count_only, unsigned long long* c_count, unsigned long long* kept_count,
                        unsigned long long* overflow, hipStream_t st) {
     if (count == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_meet, dim3(grid_for(count)), dim3(kBlock), 0, st, flist, count, fprev, b, c, g, j,
+    const uint64_t lanes = count * (uint64_t)(1u << std::min(6, host_group_log2(j.hi - j.lo + 1)));
+    hipLaunchKernelGGL(k_meet, dim3(grid_for(lanes)), dim3(kBlock), 0, st, flist, count, fprev, b, c, g, j,
                        count_only, c_count, kept_count, overflow);
     return hipGetLastError();
 }
@@ -816,30 +975,44 @@ __global__ void __launch_bounds__(kBlock) k_dmark(const uint64_t* __restrict__ f
                                                   SetView fprev, SetView fnext, GridView g, JointView j,
                                                   unsigned long long* counter) {
     const int na = fnext.na;
+    const int lg = group_log2(j.hi - j.lo + 1), G = 1 << lg;
+    const int lane = threadIdx.x & 63, sub = lane & (G - 1), grp = lane >> lg;
+    const uint64_t per_wave = 64u >> lg;
+    const uint64_t wave = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) >> 6;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
     unsigned long long kept = 0;
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < count;
-         i += (uint64_t)gridDim.x * blockDim.x) {
-        uint64_t key = flist[i];
-        int x, y, z, ia, ie;
-        unpack_key(key, x, y, z, ia, ie);
+    for (uint64_t base = wave * per_wave; base < count; base += nwaves * per_wave) {
+        const uint64_t i = base + (uint64_t)grp;
+        uint64_t key = 0;
+        int x = 0, y = 0, z = 0, ia = na, ie = na;
         bool found = false;
-        if (ia >= na || ie >= na) continue;
-        for (int a = j.lo; a <= j.hi && !found; ++a) {
-            int ia2 = ia, ie2 = ie;
-            if (j.type == 0)
-                ia2 = wrap_na(ia + a, na);
-            else
-                ie2 = wrap_na(ie + a, na);
-            int o = ia2 * na + ie2;
-            short4 d = j.off[o];
-            if (!set_member(fnext, pack_key(x + d.x, y + d.y, z + d.z, ia2, ie2))) continue;
-            if (!segment_clear_all(g, j, o, x, y, z)) continue;
-            found = true;
+        if (i < count) {
+            key = flist[i];
+            unpack_key(key, x, y, z, ia, ie);
         }
-        if (found)
-            ++kept;
-        else
-            set_remove(fprev, key);
+        const bool live = i < count && ia < na && ie < na;
+        if (live) {
+            for (int a = j.lo + sub; a <= j.hi && !found; a += G) {
+                int ia2 = ia, ie2 = ie;
+                if (j.type == 0)
+                    ia2 = wrap_na(ia + a, na);
+                else
+                    ie2 = wrap_na(ie + a, na);
+                const int o = ia2 * na + ie2;
+                const short4 d = j.off[o];
+                if (!set_member(fnext, pack_key(x + d.x, y + d.y, z + d.z, ia2, ie2))) continue;
+                if (!segment_clear_all(g, j, o, x, y, z)) continue;
+                found = true;
+            }
+        }
+        const uint64_t bal = __ballot(found);
+        const uint64_t gm = lg == 6 ? bal : (bal >> (grp << lg)) & ((1ull << G) - 1);
+        if (live && sub == 0) {
+            if (gm)
+                ++kept;
+            else
+                set_remove(fprev, key);
+        }
     }
     block_add(kept, counter);
 }
@@ -847,7 +1020,8 @@ __global__ void __launch_bounds__(kBlock) k_dmark(const uint64_t* __restrict__ f
 hipError_t launch_dmark(const uint64_t* flist, uint64_t count, SetView fprev, SetView fnext, GridView g,
                         JointView j, unsigned long long* counter, hipStream_t st) {
     if (count == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_dmark, dim3(grid_for(count)), dim3(kBlock), 0, st, flist, count, fprev, fnext, g, j,
+    const uint64_t lanes = count * (uint64_t)(1u << std::min(6, host_group_log2(j.hi - j.lo + 1)));
+    hipLaunchKernelGGL(k_dmark, dim3(grid_for(lanes)), dim3(kBlock), 0, st, flist, count, fprev, fnext, g, j,
                        counter);
     return hipGetLastError();
 }
@@ -1036,14 +1210,18 @@ hipError_t launch_pose_check(const PoseArgs& a, const int32_t* q, int64_t count,
 // start + round_half_away(w*(goal - start)/W); cell digits are base 2r+1 with joint 0
 // most significant, so the cell index orders poses lexicographically.
 // ---------------------------------------------------------------------------
+// 32-bit arithmetic is exact here: W <= 4096 and |goal - start| < 2 * 256 steps, so
+// 2 |w (goal - start)| + W < 2^31 (the host rejects larger W).
 __device__ __forceinline__ int guide_at(const TubeArgs& a, int w, int k) {
-    long long num = (long long)w * (a.goal[k] - a.start[k]);
-    long long mag = (2 * (num < 0 ? -num : num) + a.W) / (2ll * a.W);
-    return a.start[k] + (int)(num < 0 ? -mag : mag);
+    const int num = w * (a.goal[k] - a.start[k]);
+    const uint32_t mag = (2u * (uint32_t)(num < 0 ? -num : num) + (uint32_t)a.W) / (2u * (uint32_t)a.W);
+    return a.start[k] + (num < 0 ? -(int)mag : (int)mag);
 }
 
-__device__ bool tube_pose(const TubeArgs& a, int w, uint64_t cell, int32_t* q) {
-    const int B = 2 * a.r + 1;
+// slab <= 2^28 (checked on the host), so a cell index fits 32 bits
+__device__ bool tube_pose(const TubeArgs& a, int w, uint64_t cell64, int32_t* q) {
+    const uint32_t B = 2u * (uint32_t)a.r + 1u;
+    uint32_t cell = (uint32_t)cell64;
     bool in = true;
     for (int k = a.n - 1; k >= 0; --k) {
         int d = (int)(cell % B);
@@ -1299,6 +1477,7 @@ __global__ void __launch_bounds__(kTubeThreads) k_tube_trace(TubeArgs a, const u
 // range (masks precomputed in LDS); the whole dynamic program runs in one block.
 // ---------------------------------------------------------------------------
 constexpr int kBitThreads = 256;
+constexpr int kBitMaxB = 9;      // frame edge 2r+1 of the bit-parallel search (r <= 4)
 
 // validity of every cell of every waypoint as bits: word (w*nw + i), cells >= slab are 0
 __global__ void k_tube_valid_bits(TubeArgs a, uint32_t nw, uint64_t* vbits) {
@@ -1333,14 +1512,15 @@ __global__ void __launch_bounds__(kBitThreads) k_tube_bits(TubeArgs a, uint32_t 
                                                            uint64_t* rbits, int32_t* path, int32_t* status) {
     extern __shared__ uint64_t sm[];
     const int nw = (int)nw_u;
-    const int n = a.n, B = 2 * a.r + 1, dl = a.delta;
-    const int T = 4 * dl + 1;                       // t in [-2 delta, 2 delta]
+    const int n = a.n, B = 2 * a.r + 1, dl = a.delta, r = a.r;
+    const int nlev = n * r + 1;                     // L1 distances to the guide: 0 .. n r
     uint64_t* cur = sm;
     uint64_t* ta = sm + nw;
     uint64_t* tb = sm + 2 * nw;
-    uint64_t* mask = sm + 3 * nw;                   // [k][t + 2 delta][word]
+    uint64_t* eq = sm + 3 * nw;                     // [k][v][word]: cells whose digit k is v
+    uint64_t* lvl = eq + (size_t)n * B * nw;        // [l][word]: cells at L1 distance l from the guide
     __shared__ uint32_t stride[kMaxDof];
-    __shared__ int flo[kMaxDof], qcur[kMaxDof];
+    __shared__ int shw[kMaxDof], flo[kMaxDof], qcur[kMaxDof], dlo[kMaxDof], dhi[kMaxDof];
     __shared__ unsigned long long best_part[kBitThreads / 64];
     __shared__ int fail;
     const int tid = threadIdx.x;
@@ -1350,50 +1530,96 @@ __global__ void __launch_bounds__(kBitThreads) k_tube_bits(TubeArgs a, uint32_t 
         fail = 0;
     }
     __syncthreads();
-    // masks: cell c keeps shift t along joint k when 0 <= d_k(c) + t < B
+    // Digit masks, and the L1 distance |d - r| summed over the joints as a bit-sliced
+    // 5-plane counter (n r <= 31), from which the level masks are read off.
     for (int i = tid; i < nw; i += blockDim.x) {
         const uint32_t c0 = 64u * (uint32_t)i;
+        const uint32_t cnt = slab > c0 ? slab - c0 : 0u;
+        const uint64_t live = cnt >= 64 ? ~0ull : ((1ull << cnt) - 1);
+        uint64_t p0 = 0, p1 = 0, p2 = 0, p3 = 0, p4 = 0;
         for (int k = 0; k < n; ++k) {
             const uint32_t sk = stride[k];
-            int d = (int)((c0 / sk) % (uint32_t)B);
+            uint32_t d = (c0 / sk) % (uint32_t)B;
             uint32_t pos = c0 % sk;
-            uint64_t mk[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-            for (int b = 0; b < 64; ++b) {
-                if (c0 + (uint32_t)b >= slab) break;
+            uint64_t mk[kBitMaxB];
 #pragma unroll
-                for (int t = 0; t < 9; ++t) {
-                    int dd = d + t - 2 * dl;
-                    if (t < T && dd >= 0 && dd < B) mk[t] |= 1ull << b;
-                }
+            for (int v = 0; v < kBitMaxB; ++v) mk[v] = 0;
+            for (int b = 0; b < 64; ++b) {
+#pragma unroll
+                for (int v = 0; v < kBitMaxB; ++v)
+                    if ((uint32_t)v == d) mk[v] |= 1ull << b;
                 if (++pos == sk) {
                     pos = 0;
-                    if (++d == B) d = 0;
+                    if (++d == (uint32_t)B) d = 0;
                 }
             }
+            uint64_t u0 = 0, u1 = 0, u2 = 0;
 #pragma unroll
-            for (int t = 0; t < 9; ++t)
-                if (t < T) mask[((size_t)k * T + t) * nw + i] = mk[t];
+            for (int v = 0; v < kBitMaxB; ++v) {
+                if (v < B) {
+                    const uint64_t m = mk[v] & live;
+                    eq[((size_t)k * B + v) * nw + i] = m;
+                    const int u = v > r ? v - r : r - v;
+                    if (u & 1) u0 |= m;
+                    if (u & 2) u1 |= m;
+                    if (u & 4) u2 |= m;
+                }
+            }
+            const uint64_t c1 = p0 & u0;
+            p0 ^= u0;
+            const uint64_t s1 = p1 ^ u1, c2 = (p1 & u1) | (c1 & s1);
+            p1 = s1 ^ c1;
+            const uint64_t s2 = p2 ^ u2, c3 = (p2 & u2) | (c2 & s2);
+            p2 = s2 ^ c2;
+            const uint64_t c4 = p3 & c3;
+            p3 ^= c3;
+            p4 ^= c4;
+        }
+        for (int l = 0; l < nlev; ++l) {
+            uint64_t m = live;
+            m &= (l & 1) ? p0 : ~p0;
+            m &= (l & 2) ? p1 : ~p1;
+            m &= (l & 4) ? p2 : ~p2;
+            m &= (l & 8) ? p3 : ~p3;
+            m &= (l & 16) ? p4 : ~p4;
+            lvl[(size_t)l * nw + i] = m;
         }
         cur[i] = vbits[i];          // R_0 = {start}
         rbits[i] = vbits[i];
     }
     __syncthreads();
+    // Forward: R_w = valid_w AND the delta-dilation of R_{w-1}, one joint at a time.
+    // Along joint k, cell c takes the source cell whose digit is d + t, t = shift + e,
+    // when 0 <= d + t < B: the mask of those cells is an OR of digit masks.
+    constexpr int kPer = (16384 / 64 + kBitThreads - 1) / kBitThreads;
     for (int w = 1; w <= a.W; ++w) {
+        if (tid < n) shw[tid] = guide_at(a, w, tid) - guide_at(a, w - 1, tid);
+        uint64_t vw[kPer];
+        {
+            int j = 0;
+            for (int i = tid; i < nw; i += blockDim.x, ++j) vw[j] = vbits[(size_t)w * nw + i];
+        }
+        __syncthreads();
         for (int k = 0; k < n; ++k) {
             const uint64_t* src = (k == 0) ? cur : ((k & 1) ? ta : tb);
             uint64_t* dst = (k & 1) ? tb : ta;
-            const int sh = guide_at(a, w, k) - guide_at(a, w - 1, k);
+            const int sh = shw[k];
             const int64_t s = (int64_t)stride[k];
-            uint64_t outv[(16384 / 64 + kBitThreads - 1) / kBitThreads];
+            const uint64_t* eqk = eq + (size_t)k * B * nw;
+            uint64_t outv[kPer];
             int j = 0;
             for (int i = tid; i < nw; i += blockDim.x, ++j) {
                 uint64_t acc = 0;
                 for (int e = -dl; e <= dl; ++e) {
                     const int t = sh + e;
-                    if (t < -2 * dl || t > 2 * dl) continue;  // cannot happen: |sh| <= delta
-                    acc |= shifted_word(src, nw, i, (int64_t)t * s) & mask[((size_t)k * T + (t + 2 * dl)) * nw + i];
+                    const int vlo = t < 0 ? -t : 0;
+                    const int vhi = t > 0 ? B - 1 - t : B - 1;
+                    if (vlo > vhi) continue;
+                    uint64_t m = 0;
+                    for (int v = vlo; v <= vhi; ++v) m |= eqk[(size_t)v * nw + i];
+                    acc |= shifted_word(src, nw, i, (int64_t)t * s) & m;
                 }
-                if (k == n - 1) acc &= vbits[(size_t)w * nw + i];
+                if (k == n - 1) acc &= vw[j];
                 outv[j] = acc;
             }
             __syncthreads();
@@ -1411,7 +1637,7 @@ __global__ void __launch_bounds__(kBitThreads) k_tube_bits(TubeArgs a, uint32_t 
     }
     // the goal: every digit = r
     uint32_t gcell = 0;
-    for (int k = 0; k < n; ++k) gcell += (uint32_t)a.r * stride[k];
+    for (int k = 0; k < n; ++k) gcell += (uint32_t)r * stride[k];
     if (!((cur[gcell >> 6] >> (gcell & 63)) & 1ull)) {
         if (tid == 0) *status = 0;
         return;
@@ -1421,41 +1647,36 @@ __global__ void __launch_bounds__(kBitThreads) k_tube_bits(TubeArgs a, uint32_t 
         path[a.W * n + tid] = a.goal[tid];
     }
     __syncthreads();
-    // backward choice over the (2 delta + 1)^n box around the current pose
-    const uint32_t span = (uint32_t)(2 * dl + 1);
-    uint32_t ncand = 1;
-    for (int k = 0; k < n; ++k) ncand *= span;
-    const uint32_t per = (ncand + blockDim.x - 1) / blockDim.x;
+    // Backward choice: the reachable cells of frame w-1 whose digits lie within delta of
+    // the current pose (an AND over joints of ORs of digit masks); the smallest L1
+    // distance to the guide is the first level with a hit, ties by the smallest cell.
     for (int w = a.W; w >= 1; --w) {
-        const uint64_t* R = rbits + (size_t)(w - 1) * nw;
-        if (tid < n) flo[tid] = guide_at(a, w - 1, tid) - a.r;
+        if (tid < n) {
+            const int f = guide_at(a, w - 1, tid) - r;
+            const int lo = qcur[tid] - dl - f, hi = qcur[tid] + dl - f;
+            flo[tid] = f;
+            dlo[tid] = lo < 0 ? 0 : lo;
+            dhi[tid] = hi > B - 1 ? B - 1 : hi;
+        }
         __syncthreads();
+        const uint64_t* R = rbits + (size_t)(w - 1) * nw;
         unsigned long long best = ~0ull;
-        const uint32_t t0 = tid * per;
-        if (t0 < ncand) {
-            int e[kMaxDof];
-            uint32_t rest = t0;
-            for (int k = n - 1; k >= 0; --k) {
-                e[k] = (int)(rest % span);
-                rest /= span;
+        for (int i = tid; i < nw; i += blockDim.x) {
+            uint64_t m0 = R[i];
+            for (int k = 0; k < n && m0; ++k) {
+                uint64_t mk = 0;
+                for (int v = dlo[k]; v <= dhi[k]; ++v) mk |= eq[((size_t)k * B + v) * nw + i];
+                m0 &= mk;
             }
-            for (uint32_t t = t0; t < t0 + per && t < ncand; ++t) {
-                uint32_t cell = 0;
-                int l1 = 0;
-                bool ok = true;
-                for (int k = 0; k < n; ++k) {
-                    int d = qcur[k] + e[k] - dl - flo[k];
-                    if (d < 0 || d >= B) ok = false;
-                    cell += (uint32_t)(d < 0 ? 0 : d) * stride[k];
-                    l1 += abs(d - a.r);
-                }
-                if (ok && ((R[cell >> 6] >> (cell & 63)) & 1ull)) {
-                    unsigned long long key = ((unsigned long long)l1 << 40) | cell;
-                    best = key < best ? key : best;
-                }
-                for (int k = n - 1; k >= 0; --k) {
-                    if (++e[k] < (int)span) break;
-                    e[k] = 0;
+            if (m0) {
+                for (int l = 0; l < nlev; ++l) {
+                    const uint64_t m = m0 & lvl[(size_t)l * nw + i];
+                    if (m) {
+                        const unsigned long long key =
+                            ((unsigned long long)l << 40) | (64ull * (uint64_t)i + (uint64_t)(__ffsll((unsigned long long)m) - 1));
+                        best = key < best ? key : best;
+                        break;
+                    }
                 }
             }
         }
@@ -1488,10 +1709,10 @@ __global__ void __launch_bounds__(kBitThreads) k_tube_bits(TubeArgs a, uint32_t 
 
 // LDS bytes of the bit-parallel search, or 0 when it does not apply.
 size_t tube_bits_lds(const TubeArgs& a) {
-    if (a.slab > 16384 || a.n > 8 || a.delta > 2) return 0;
+    const int B = 2 * a.r + 1;
+    if (a.slab > 16384 || B > kBitMaxB || a.n * a.r > 31) return 0;
     const size_t nw = (a.slab + 63) / 64;
-    const size_t T = 4 * a.delta + 1;
-    const size_t bytes = (3 + (size_t)a.n * T) * nw * 8;
+    const size_t bytes = (3 + (size_t)a.n * B + (size_t)(a.n * a.r + 1)) * nw * 8;
     return bytes <= 60 * 1024 ? bytes : 0;
 }
 

@@ -386,7 +386,13 @@ msc_status make_set(Lane* c, const Plan& p, const Box& box, uint64_t upper, int 
     const uint64_t na2 = (uint64_t)p.na * p.na;
     uint64_t dense_words = box.empty() ? 0 : (box.voxels() * na2 + 63) / 64 + 1;
     uint64_t hash_slots = pow2_at_least(std::max<uint64_t>(2 * upper, 64));
-    bool dense = !box.empty() && (force_dense || dense_words <= hash_slots);
+    // Dense sets take a run of predecessors in 1-3 atomicOr and a membership test in one
+    // load, where a hash set needs a CAS chain per state: dense is preferred up to 8x the
+    // hash table's bytes, as long as it leaves half of the lane's free workspace.
+    const uint64_t free_bytes = c->hi > c->lo ? c->hi - c->lo : 0;
+    bool dense = !box.empty() &&
+                 (force_dense || (dense_words <= 8 * hash_slots && dense_words * 8 <= free_bytes / 2) ||
+                  dense_words <= hash_slots);
     s = StageSet();
     s.view.na = p.na;
     s.used = true;
@@ -557,10 +563,14 @@ msc_status run_reach(Lane* c, const msc_scene* sc, const Plan& p, int want, bool
     // The two pathways are expanded until they are one transition apart, then met
     // (split 0: the backward pathway runs down to the root and is joined with F_0).
     auto finished = [&]() { return p.split == 0 ? kb == 0 : kb - kf == 1; };
+    auto window = [&](int k) { return (double)(p.hi[k] - p.lo[k] + 1); };
+    bool backward_only = false;
     while (!empty && !finished()) {
         bool forward;
         if (p.split >= 0) {
             forward = p.split >= 1 && kf < p.split - 1;
+        } else if (backward_only) {
+            forward = false;
         } else {
             double cf = (double)F[kf].count * (p.hi[kf] - p.lo[kf] + 1);
             double cb = (double)B[kb].count * 3.0;
@@ -570,6 +580,25 @@ msc_status run_reach(Lane* c, const msc_scene* sc, const Plan& p, int want, bool
             MSC_TRY(expand_forward(kf + 1, F[kf + 1]));
             kf = kf + 1;
             empty = F[kf].count == 0;
+            // Adaptive split, the step before the meet: the meet tries every state of F_kf
+            // against the next joint's window.  When that is dearer than one more backward
+            // stage plus the meet from F_{kf-1}, the forward side steps back (F_kf stays
+            // built but unused).  Costs are rough per-item times on the device.
+            if (!empty && p.split < 0 && kb - kf == 1 && kf >= 1) {
+                constexpr double kMeetNs = 8.0, kBwdNs = 90.0, kFillBytesPerNs = 4000.0;
+                const double meet_here = (double)F[kf].count * window(kf) * kMeetNs;
+                const uint64_t upper = B[kb].count * (uint64_t)window(kb - 1);
+                const uint64_t dense_words = box[kb - 1].voxels() * (uint64_t)na * na / 64;
+                const uint64_t slots = pow2_at_least(std::max<uint64_t>(2 * upper, 64));
+                const uint64_t words = dense_words <= 8 * slots ? dense_words : slots;
+                const double fill_ns = 8.0 * (double)words / kFillBytesPerNs;
+                const double alt = (double)B[kb].count * kBwdNs + fill_ns +
+                                   (double)F[kf - 1].count * window(kf - 1) * kMeetNs;
+                if (alt < meet_here) {
+                    kf -= 1;
+                    backward_only = true;
+                }
+            }
         } else {
             const int k = kb;  // joint k-1 (0-based) lays segment k; produce B_{k-1}
             MSC_TRY(ensure_list(c, B[kb]));
