@@ -1498,11 +1498,12 @@ __global__ void k_tube_valid_bits(TubeArgs a, uint32_t nw, uint64_t* vbits) {
     }
 }
 
-// bits of `src` shifted so that bit c of the result is bit c + x of src (x may be < 0)
-__device__ __forceinline__ uint64_t shifted_word(const uint64_t* src, int nw, int i, int64_t x) {
-    const int64_t X = 64 * (int64_t)i + x;
-    const int64_t j = X >= 0 ? X / 64 : -((-X + 63) / 64);
-    const int u = (int)(X - 64 * j);
+// bits of `src` shifted so that bit c of the result is bit c + x of src (x may be < 0);
+// |64 i + x| < 2^31 for the frame sizes used here
+__device__ __forceinline__ uint64_t shifted_word(const uint64_t* src, int nw, int i, int x) {
+    const int X = 64 * i + x;
+    const int j = X >> 6;          // floor division (arithmetic shift)
+    const int u = X & 63;
     const uint64_t lo = (j >= 0 && j < nw) ? src[j] : 0ull;
     const uint64_t hi = (j + 1 >= 0 && j + 1 < nw) ? src[j + 1] : 0ull;
     return u ? ((lo >> u) | (hi << (64 - u))) : lo;
@@ -1514,13 +1515,12 @@ __global__ void __launch_bounds__(kBitThreads) k_tube_bits(TubeArgs a, uint32_t 
     const int nw = (int)nw_u;
     const int n = a.n, B = 2 * a.r + 1, dl = a.delta, r = a.r;
     const int nlev = n * r + 1;                     // L1 distances to the guide: 0 .. n r
-    uint64_t* cur = sm;
-    uint64_t* ta = sm + nw;
-    uint64_t* tb = sm + 2 * nw;
-    uint64_t* eq = sm + 3 * nw;                     // [k][v][word]: cells whose digit k is v
-    uint64_t* lvl = eq + (size_t)n * B * nw;        // [l][word]: cells at L1 distance l from the guide
+    uint64_t* fa = sm;                              // two frames, used in turn
+    uint64_t* fb = sm + nw;
+    uint64_t* ge = sm + 2 * nw;                     // [k][v][word], v = 0..B: cells whose digit k is >= v
+    uint64_t* lvl = ge + (size_t)n * (B + 1) * nw;  // [l][word]: cells at L1 distance l from the guide
     __shared__ uint32_t stride[kMaxDof];
-    __shared__ int shw[kMaxDof], flo[kMaxDof], qcur[kMaxDof], dlo[kMaxDof], dhi[kMaxDof];
+    __shared__ int shw[kMaxDof], dlo[kMaxDof], dhi[kMaxDof], flo[kMaxDof], qcur[kMaxDof];
     __shared__ unsigned long long best_part[kBitThreads / 64];
     __shared__ int fail;
     const int tid = threadIdx.x;
@@ -1530,35 +1530,42 @@ __global__ void __launch_bounds__(kBitThreads) k_tube_bits(TubeArgs a, uint32_t 
         fail = 0;
     }
     __syncthreads();
-    // Digit masks, and the L1 distance |d - r| summed over the joints as a bit-sliced
-    // 5-plane counter (n r <= 31), from which the level masks are read off.
-    for (int i = tid; i < nw; i += blockDim.x) {
+    // Digit masks from runs of equal digits (a run of joint k is stride[k] cells long),
+    // kept as "digit >= v" masks so that any digit range is two loads; and the L1
+    // distance |d - r| summed over the joints as a bit-sliced 5-plane counter
+    // (n r <= 31), from which the level masks are read off.
+    for (int i = tid; i < nw; i += kBitThreads) {
         const uint32_t c0 = 64u * (uint32_t)i;
         const uint32_t cnt = slab > c0 ? slab - c0 : 0u;
         const uint64_t live = cnt >= 64 ? ~0ull : ((1ull << cnt) - 1);
         uint64_t p0 = 0, p1 = 0, p2 = 0, p3 = 0, p4 = 0;
         for (int k = 0; k < n; ++k) {
             const uint32_t sk = stride[k];
-            uint32_t d = (c0 / sk) % (uint32_t)B;
-            uint32_t pos = c0 % sk;
+            const uint32_t q = c0 / sk;
+            uint32_t d = q % (uint32_t)B;
+            uint32_t len = sk - (c0 - q * sk);
             uint64_t mk[kBitMaxB];
 #pragma unroll
             for (int v = 0; v < kBitMaxB; ++v) mk[v] = 0;
-            for (int b = 0; b < 64; ++b) {
+            for (uint32_t b = 0; b < 64;) {
+                const uint32_t l = len < 64 - b ? len : 64 - b;
+                const uint64_t run = (l >= 64 ? ~0ull : ((1ull << l) - 1)) << b;
 #pragma unroll
                 for (int v = 0; v < kBitMaxB; ++v)
-                    if ((uint32_t)v == d) mk[v] |= 1ull << b;
-                if (++pos == sk) {
-                    pos = 0;
-                    if (++d == (uint32_t)B) d = 0;
-                }
+                    if ((uint32_t)v == d) mk[v] |= run;
+                b += l;
+                len = sk;
+                d = d + 1 == (uint32_t)B ? 0 : d + 1;
             }
-            uint64_t u0 = 0, u1 = 0, u2 = 0;
+            uint64_t u0 = 0, u1 = 0, u2 = 0, suffix = 0;
+            uint64_t* gk = ge + (size_t)k * (B + 1) * nw;
+            gk[(size_t)B * nw + i] = 0;
 #pragma unroll
-            for (int v = 0; v < kBitMaxB; ++v) {
+            for (int v = kBitMaxB - 1; v >= 0; --v) {
                 if (v < B) {
                     const uint64_t m = mk[v] & live;
-                    eq[((size_t)k * B + v) * nw + i] = m;
+                    suffix |= m;
+                    gk[(size_t)v * nw + i] = suffix;
                     const int u = v > r ? v - r : r - v;
                     if (u & 1) u0 |= m;
                     if (u & 2) u1 |= m;
@@ -1584,61 +1591,56 @@ __global__ void __launch_bounds__(kBitThreads) k_tube_bits(TubeArgs a, uint32_t 
             m &= (l & 16) ? p4 : ~p4;
             lvl[(size_t)l * nw + i] = m;
         }
-        cur[i] = vbits[i];          // R_0 = {start}
+        fa[i] = vbits[i];           // R_0 = {start}
         rbits[i] = vbits[i];
     }
     __syncthreads();
     // Forward: R_w = valid_w AND the delta-dilation of R_{w-1}, one joint at a time.
     // Along joint k, cell c takes the source cell whose digit is d + t, t = shift + e,
-    // when 0 <= d + t < B: the mask of those cells is an OR of digit masks.
+    // when 0 <= d + t < B, i.e. digit in [-t, B-1-t]: ge[max(0,-t)] & ~ge[min(B,B-t)].
+    // The two frames alternate as source and destination (one barrier per pass).
     constexpr int kPer = (16384 / 64 + kBitThreads - 1) / kBitThreads;
+    uint64_t* src = fa;
+    uint64_t* dst = fb;
     for (int w = 1; w <= a.W; ++w) {
         if (tid < n) shw[tid] = guide_at(a, w, tid) - guide_at(a, w - 1, tid);
         uint64_t vw[kPer];
         {
             int j = 0;
-            for (int i = tid; i < nw; i += blockDim.x, ++j) vw[j] = vbits[(size_t)w * nw + i];
+            for (int i = tid; i < nw; i += kBitThreads, ++j) vw[j] = vbits[(size_t)w * nw + i];
         }
         __syncthreads();
         for (int k = 0; k < n; ++k) {
-            const uint64_t* src = (k == 0) ? cur : ((k & 1) ? ta : tb);
-            uint64_t* dst = (k & 1) ? tb : ta;
             const int sh = shw[k];
-            const int64_t s = (int64_t)stride[k];
-            const uint64_t* eqk = eq + (size_t)k * B * nw;
-            uint64_t outv[kPer];
+            const int s = (int)stride[k];
+            const uint64_t* gk = ge + (size_t)k * (B + 1) * nw;
             int j = 0;
-            for (int i = tid; i < nw; i += blockDim.x, ++j) {
+            for (int i = tid; i < nw; i += kBitThreads, ++j) {
                 uint64_t acc = 0;
                 for (int e = -dl; e <= dl; ++e) {
                     const int t = sh + e;
                     const int vlo = t < 0 ? -t : 0;
-                    const int vhi = t > 0 ? B - 1 - t : B - 1;
-                    if (vlo > vhi) continue;
-                    uint64_t m = 0;
-                    for (int v = vlo; v <= vhi; ++v) m |= eqk[(size_t)v * nw + i];
-                    acc |= shifted_word(src, nw, i, (int64_t)t * s) & m;
+                    const int vend = t > 0 ? B - t : B;      // exclusive
+                    if (vlo >= vend) continue;
+                    const uint64_t m = gk[(size_t)vlo * nw + i] & ~gk[(size_t)vend * nw + i];
+                    acc |= shifted_word(src, nw, i, t * s) & m;
                 }
-                if (k == n - 1) acc &= vw[j];
-                outv[j] = acc;
-            }
-            __syncthreads();
-            j = 0;
-            for (int i = tid; i < nw; i += blockDim.x, ++j) {
                 if (k == n - 1) {
-                    cur[i] = outv[j];
-                    rbits[(size_t)w * nw + i] = outv[j];
-                } else {
-                    dst[i] = outv[j];
+                    acc &= vw[j];
+                    rbits[(size_t)w * nw + i] = acc;
                 }
+                dst[i] = acc;
             }
             __syncthreads();
+            uint64_t* tmp = src;
+            src = dst;
+            dst = tmp;
         }
     }
     // the goal: every digit = r
     uint32_t gcell = 0;
     for (int k = 0; k < n; ++k) gcell += (uint32_t)r * stride[k];
-    if (!((cur[gcell >> 6] >> (gcell & 63)) & 1ull)) {
+    if (!((src[gcell >> 6] >> (gcell & 63)) & 1ull)) {
         if (tid == 0) *status = 0;
         return;
     }
@@ -1646,9 +1648,8 @@ __global__ void __launch_bounds__(kBitThreads) k_tube_bits(TubeArgs a, uint32_t 
         qcur[tid] = a.goal[tid];
         path[a.W * n + tid] = a.goal[tid];
     }
-    __syncthreads();
     // Backward choice: the reachable cells of frame w-1 whose digits lie within delta of
-    // the current pose (an AND over joints of ORs of digit masks); the smallest L1
+    // the current pose (an AND over joints of digit-range masks); the smallest L1
     // distance to the guide is the first level with a hit, ties by the smallest cell.
     for (int w = a.W; w >= 1; --w) {
         if (tid < n) {
@@ -1656,24 +1657,25 @@ __global__ void __launch_bounds__(kBitThreads) k_tube_bits(TubeArgs a, uint32_t 
             const int lo = qcur[tid] - dl - f, hi = qcur[tid] + dl - f;
             flo[tid] = f;
             dlo[tid] = lo < 0 ? 0 : lo;
-            dhi[tid] = hi > B - 1 ? B - 1 : hi;
+            dhi[tid] = hi > B - 1 ? B : hi + 1;   // exclusive
         }
         __syncthreads();
         const uint64_t* R = rbits + (size_t)(w - 1) * nw;
         unsigned long long best = ~0ull;
-        for (int i = tid; i < nw; i += blockDim.x) {
+        for (int i = tid; i < nw; i += kBitThreads) {
             uint64_t m0 = R[i];
-            for (int k = 0; k < n && m0; ++k) {
-                uint64_t mk = 0;
-                for (int v = dlo[k]; v <= dhi[k]; ++v) mk |= eq[((size_t)k * B + v) * nw + i];
-                m0 &= mk;
+            for (int k = 0; k < n; ++k) {
+                const int lo = dlo[k], he = dhi[k];
+                const uint64_t* gk = ge + (size_t)k * (B + 1) * nw;
+                m0 &= lo < he ? (gk[(size_t)lo * nw + i] & ~gk[(size_t)he * nw + i]) : 0ull;
             }
             if (m0) {
                 for (int l = 0; l < nlev; ++l) {
                     const uint64_t m = m0 & lvl[(size_t)l * nw + i];
                     if (m) {
                         const unsigned long long key =
-                            ((unsigned long long)l << 40) | (64ull * (uint64_t)i + (uint64_t)(__ffsll((unsigned long long)m) - 1));
+                            ((unsigned long long)l << 40) |
+                            (64ull * (uint64_t)i + (uint64_t)(__ffsll((unsigned long long)m) - 1));
                         best = key < best ? key : best;
                         break;
                     }
@@ -1681,24 +1683,21 @@ __global__ void __launch_bounds__(kBitThreads) k_tube_bits(TubeArgs a, uint32_t 
             }
         }
         for (int off = 32; off > 0; off >>= 1) {
-            unsigned long long o = __shfl_xor(best, off, 64);
+            const unsigned long long o = __shfl_xor(best, off, 64);
             best = o < best ? o : best;
         }
         if ((tid & 63) == 0) best_part[tid >> 6] = best;
         __syncthreads();
-        if (tid == 0) {
+        if (tid < n) {
             unsigned long long b = ~0ull;
-            for (int i = 0; i < (int)(blockDim.x >> 6); ++i) b = best_part[i] < b ? best_part[i] : b;
+            for (int q = 0; q < kBitThreads / 64; ++q) b = best_part[q] < b ? best_part[q] : b;
             if (b == ~0ull) {
-                fail = 1;
+                if (tid == 0) fail = 1;
             } else {
-                uint32_t c = (uint32_t)(b & ((1ull << 40) - 1));
-                for (int k = n - 1; k >= 0; --k) {
-                    int d = (int)(c % (uint32_t)B);
-                    c /= (uint32_t)B;
-                    qcur[k] = flo[k] + d;
-                    path[(w - 1) * n + k] = qcur[k];
-                }
+                const uint32_t c = (uint32_t)(b & ((1ull << 40) - 1));
+                const int qk = flo[tid] + (int)((c / stride[tid]) % (uint32_t)B);
+                qcur[tid] = qk;
+                path[(w - 1) * n + tid] = qk;
             }
         }
         __syncthreads();
@@ -1712,7 +1711,7 @@ size_t tube_bits_lds(const TubeArgs& a) {
     const int B = 2 * a.r + 1;
     if (a.slab > 16384 || B > kBitMaxB || a.n * a.r > 31) return 0;
     const size_t nw = (a.slab + 63) / 64;
-    const size_t bytes = (3 + (size_t)a.n * B + (size_t)(a.n * a.r + 1)) * nw * 8;
+    const size_t bytes = (2 + (size_t)a.n * (B + 1) + (size_t)(a.n * a.r + 1)) * nw * 8;
     return bytes <= 60 * 1024 ? bytes : 0;
 }
 
