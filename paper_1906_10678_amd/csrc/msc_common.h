@@ -90,8 +90,9 @@ hipError_t launch_compact(SetView s, uint64_t* list, uint64_t cap, unsigned long
                           unsigned long long* overflow, hipStream_t st);
 hipError_t launch_join(const uint64_t* flist, uint64_t count, SetView f, SetView b,
                        unsigned long long* counter, hipStream_t st);
+constexpr int kMeetInsert = 0, kMeetCount = 1, kMeetMark = 2;
 hipError_t launch_meet(const uint64_t* flist, uint64_t count, SetView fprev, SetView b, SetView c, GridView g,
-                       JointView j, int count_only, unsigned long long* c_count, unsigned long long* kept_count,
+                       JointView j, int mode, unsigned long long* c_count, unsigned long long* kept_count,
                        unsigned long long* overflow, hipStream_t st);
 hipError_t launch_dmark(const uint64_t* flist, uint64_t count, SetView fprev, SetView fnext,
                         GridView g, JointView j, unsigned long long* counter, hipStream_t st);

@@ -232,9 +232,22 @@ __global__ void k_fill(uint64_t* p, uint64_t n, uint64_t v) {
         p[i] = v;
 }
 
+// 16-byte aligned buffers: pairs of words per store; the odd last word by one thread.
+__global__ void k_fill16(uint64_t* p, uint64_t n, uint64_t v) {
+    const uint64_t pairs = n >> 1;
+    ulonglong2* q = reinterpret_cast<ulonglong2*>(p);
+    const ulonglong2 vv = make_ulonglong2(v, v);
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < pairs;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        q[i] = vv;
+    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) p[n - 1] = v;
+}
 hipError_t launch_fill(uint64_t* p, uint64_t n, uint64_t value, hipStream_t st) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fill, dim3(grid_for(n, kBlock, 8192)), dim3(kBlock), 0, st, p, n, value);
+    if (((uintptr_t)p & 15) == 0 && n >= 2)
+        hipLaunchKernelGGL(k_fill16, dim3(grid_for(n >> 1, kBlock, 16384)), dim3(kBlock), 0, st, p, n, value);
+    else
+        hipLaunchKernelGGL(k_fill, dim3(grid_for(n, kBlock, 8192)), dim3(kBlock), 0, st, p, n, value);
     return hipGetLastError();
 }
 
@@ -895,10 +908,13 @@ hipError_t launch_join(const uint64_t* flist, uint64_t count, SetView f, SetView
 // (tested first, before the segment test) and the segment is clear.  The hits are
 // C_m = F_m intersected with B_m (inserted into `c`); the states of F_{m-1} without a
 // hit are removed from `fprev`, which leaves D_{m-1}.  F_m is never built.  With
-// count_only the kernel only counts the hits (duplicates included), which sizes C.
+// Modes: kMeetInsert inserts the hits into `c` and marks D_{m-1}; kMeetCount only
+// counts the hits (duplicates included), which sizes a hash C; kMeetMark only marks
+// D_{m-1} (the canonical walk then steps into B_m: a successor of a D_{m-1} state
+// with a clear segment that is in B_m is in C_m).
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock) k_meet(const uint64_t* __restrict__ flist, uint64_t count, SetView fprev,
-                                                 SetView b, SetView c, GridView g, JointView j, int count_only,
+                                                 SetView b, SetView c, GridView g, JointView j, int mode,
                                                  unsigned long long* c_count, unsigned long long* kept_count,
                                                  unsigned long long* overflow) {
     const int na = b.na;
@@ -931,8 +947,9 @@ __global__ void __launch_bounds__(kBlock) k_meet(const uint64_t* __restrict__ fl
                 if (!set_member(b, pack_key(x2, y2, z2, ia2, ie2))) continue;
                 if (!segment_clear_all(g, j, o, x, y, z)) continue;
                 hit = true;
-                if (count_only) {
+                if (mode != kMeetInsert) {
                     ++added;
+                    if (mode == kMeetMark) break;   // one hit decides the state
                     continue;
                 }
                 int r = set_insert(c, x2, y2, z2, ia2, ie2);
@@ -948,7 +965,7 @@ __global__ void __launch_bounds__(kBlock) k_meet(const uint64_t* __restrict__ fl
         if (live && sub == 0) {
             if (gm)
                 ++kept;
-            else if (!count_only)
+            else if (mode != kMeetCount)
                 set_remove(fprev, key);
         }
     }
@@ -958,12 +975,12 @@ __global__ void __launch_bounds__(kBlock) k_meet(const uint64_t* __restrict__ fl
 }
 
 hipError_t launch_meet(const uint64_t* flist, uint64_t count, SetView fprev, SetView b, SetView c, GridView g,
-                       JointView j, int count_only, unsigned long long* c_count, unsigned long long* kept_count,
+                       JointView j, int mode, unsigned long long* c_count, unsigned long long* kept_count,
                        unsigned long long* overflow, hipStream_t st) {
     if (count == 0) return hipSuccess;
     const uint64_t lanes = count * (uint64_t)(1u << std::min(6, host_group_log2(j.hi - j.lo + 1)));
     hipLaunchKernelGGL(k_meet, dim3(grid_for(lanes)), dim3(kBlock), 0, st, flist, count, fprev, b, c, g, j,
-                       count_only, c_count, kept_count, overflow);
+                       mode, c_count, kept_count, overflow);
     return hipGetLastError();
 }
 

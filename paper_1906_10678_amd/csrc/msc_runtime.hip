@@ -638,7 +638,7 @@ msc_status run_reach(Lane* c, const msc_scene* sc, const Plan& p, int want, bool
     if (empty) return MSC_NO_REACH;
 
     // C_m and the D sets.  Stage sets used by the canonical walk: D_k (k < m) in F_k's
-    // structure, C_m = D_m, B_k for k > m.
+    // structure, C_m (or B_m, equivalent for the walk) at stage m, B_k for k > m.
     StageSet Cset;
     uint64_t joined = 0;
     if (m == 0) {
@@ -656,20 +656,37 @@ msc_status run_reach(Lane* c, const msc_scene* sc, const Plan& p, int want, bool
         }
         MSC_TRY(ensure_list(c, F[m - 1]));
         const int fast = (m < n && p.type[m] == MSC_YAW) ? 1 : 0;
-        // C_m is a dense bitset over the stage box when pruning bounds the box (one pass);
-        // otherwise a hash set sized by a first, counting pass
+        if (!capture) {
+            // Only D_{m-1} is needed: the canonical walk steps from D_{m-1} into B_m,
+            // which for a clear move is the same as stepping into C_m; C is not built.
+            unsigned long long* hc = take_counter(c);
+            unsigned long long* kc = take_counter(c);
+            if (!hc || !kc) return fail(c, MSC_E_CAPACITY, "out of counters");
+            LAUNCH(MSC_K_JOIN, m, (int64_t)F[m - 1].count,
+                   launch_meet(F[m - 1].list, F[m - 1].count, F[m - 1].view, B[m].view, B[m].view, g, jv[m - 1],
+                               kMeetMark, hc, kc, ovf, c->stream));
+            const int jrec = c->last_rec;
+            MSC_TRY(read_counter(c, kc, &joined));
+            prof_out(c, jrec, (int64_t)joined);
+            Cset = B[m];
+        }
+        // With set capture C_m is built for the dump: a dense bitset over the stage box
+        // when pruning bounds the box (one pass), otherwise a hash set sized by a first,
+        // counting pass
         const uint64_t box_words = box[m].voxels() * (uint64_t)na * na / 64;
         const bool dense_c = p.prune && !box[m].empty() && box_words <= (1ull << 31);
         uint64_t hits = 1;
-        if (dense_c) {
+        if (!capture) {
+            hits = 0;
+        } else if (dense_c) {
             MSC_TRY(make_set(c, p, box[m], 0, fast, true, Cset));
         } else {
             unsigned long long* hc = take_counter(c);
             unsigned long long* kc = take_counter(c);
             if (!hc || !kc) return fail(c, MSC_E_CAPACITY, "out of counters");
             LAUNCH(MSC_K_JOIN, m, (int64_t)F[m - 1].count,
-                   launch_meet(F[m - 1].list, F[m - 1].count, F[m - 1].view, B[m].view, B[m].view, g, jv[m - 1], 1,
-                               hc, kc, ovf, c->stream));
+                   launch_meet(F[m - 1].list, F[m - 1].count, F[m - 1].view, B[m].view, B[m].view, g, jv[m - 1],
+                               kMeetCount, hc, kc, ovf, c->stream));
             MSC_TRY(read_counter(c, hc, &hits));
             if (hits) MSC_TRY(make_set(c, p, box[m], hits, fast, false, Cset));
         }
@@ -678,15 +695,15 @@ msc_status run_reach(Lane* c, const msc_scene* sc, const Plan& p, int want, bool
             unsigned long long* kc2 = take_counter(c);
             if (!cc || !kc2) return fail(c, MSC_E_CAPACITY, "out of counters");
             LAUNCH(MSC_K_JOIN, m, (int64_t)F[m - 1].count,
-                   launch_meet(F[m - 1].list, F[m - 1].count, F[m - 1].view, B[m].view, Cset.view, g, jv[m - 1], 0,
-                               cc, kc2, ovf, c->stream));
+                   launch_meet(F[m - 1].list, F[m - 1].count, F[m - 1].view, B[m].view, Cset.view, g, jv[m - 1],
+                               kMeetInsert, cc, kc2, ovf, c->stream));
             const int jrec = c->last_rec;
             MSC_TRY(read_counter(c, cc, &joined));
             prof_out(c, jrec, (int64_t)joined);
             Cset.count = joined;
         }
     }
-    c->stats.join_count = (int64_t)joined;
+    c->stats.join_count = (capture || m == 0) ? (int64_t)joined : -1;
     if (capture && joined) {
         MSC_TRY(capture_set(c, Cset, N, 2, m));
         c->captured[{3, m}] = c->captured[{2, m}];
