@@ -91,11 +91,13 @@ hipError_t launch_compact(SetView s, uint64_t* list, uint64_t cap, unsigned long
 hipError_t launch_join(const uint64_t* flist, uint64_t count, SetView f, SetView b,
                        unsigned long long* counter, hipStream_t st);
 constexpr int kMeetInsert = 0, kMeetCount = 1, kMeetMark = 2;
+// (tx, ty, tz), r2: the target and the squared forward pruning radius of stage m (r2 < 0: none)
 hipError_t launch_meet(const uint64_t* flist, uint64_t count, SetView fprev, SetView b, SetView c, GridView g,
                        JointView j, int mode, unsigned long long* c_count, unsigned long long* kept_count,
-                       unsigned long long* overflow, hipStream_t st);
-hipError_t launch_dmark(const uint64_t* flist, uint64_t count, SetView fprev, SetView fnext,
-                        GridView g, JointView j, unsigned long long* counter, hipStream_t st);
+                       unsigned long long* overflow, int tx, int ty, int tz, long long r2, hipStream_t st);
+hipError_t launch_dmark(const uint64_t* flist, uint64_t count, SetView fprev, SetView fnext, GridView g,
+                        JointView j, unsigned long long* counter, int tx, int ty, int tz, long long r2,
+                        hipStream_t st);
 
 struct DfsArgs {
     SetView sets[kMaxDof + 1];  // sets[k] = D_k for k <= m, B_k for k > m (k = 0..n)

@@ -30,14 +30,6 @@ __device__ __forceinline__ int wrap_na(int v, int na) {
     return v;
 }
 
-// Lanes that share one state when a kernel tries a joint's whole window for it: the
-// window size rounded up to a power of two, at most a wave; lane l of the group takes
-// the angles lo + l, lo + l + G, ...
-__device__ __forceinline__ int group_log2(int nA) {
-    int lg = 0;
-    while ((1 << lg) < nA && lg < 6) ++lg;
-    return lg;
-}
 
 __device__ __forceinline__ bool cell_free(const GridView& g, int x, int y, int z) {
     if ((unsigned)x >= (unsigned)g.n || (unsigned)y >= (unsigned)g.n || (unsigned)z >= (unsigned)g.n)
@@ -208,9 +200,16 @@ __device__ __forceinline__ void mask_range(uint64_t m[4], int lo, int hi) {
     }
 }
 
-int host_group_log2(int nA) {
+// Lanes that share one state when a kernel tries a joint's whole window for it (a
+// power of two G <= 64; lane l of a group takes the angles lo + l, lo + l + G, ...).
+// Small inputs get a lane per angle, so that the launch still fills the device; large
+// ones fewer lanes per state, so that lanes are not left idle by a window that is not
+// a power of two.
+int group_log2_for(uint64_t count, int nA) {
+    int cap = 0;
+    while ((1 << cap) < nA && cap < 6) ++cap;
     int lg = 0;
-    while ((1 << lg) < nA && lg < 6) ++lg;
+    while (lg < cap && count * (1ull << lg) < (1ull << 20)) ++lg;
     return lg;
 }
 
@@ -629,10 +628,10 @@ __global__ void __launch_bounds__(kBlock) k_expand_bwd_set(const uint64_t* __res
                                                            SetView out, GridView g, JointView j, int bx, int by,
                                                            int bz, long long r2, const uint64_t* __restrict__ orows,
                                                            unsigned long long* counter,
-                                                           unsigned long long* overflow) {
+                                                           unsigned long long* overflow, int lg) {
     const int na = out.na;
     const bool yaw = j.type == 0;
-    const int lg = group_log2(j.hi - j.lo + 1), G = 1 << lg;
+    const int G = 1 << lg;
     const int lane = threadIdx.x & 63, sub = lane & (G - 1), grp = lane >> lg;
     const uint64_t per_wave = 64u >> lg;
     const uint64_t wave = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) >> 6;
@@ -678,9 +677,9 @@ hipError_t launch_expand_bwd(const uint64_t* in, uint64_t count, SetView out, Gr
         hipLaunchKernelGGL(k_expand_bwd, dim3(grid_for(count)), dim3(kBlock), 0, st, in, count, out, g, j, bx, by,
                            bz, r2, orows, counter, overflow);
     } else {
-        const uint64_t lanes = count * (uint64_t)(1u << host_group_log2(j.hi - j.lo + 1));
-        hipLaunchKernelGGL(k_expand_bwd_set, dim3(grid_for(lanes)), dim3(kBlock), 0, st, in, count, out, g, j, bx,
-                           by, bz, r2, orows, counter, overflow);
+        const int lg = group_log2_for(count, j.hi - j.lo + 1);
+        hipLaunchKernelGGL(k_expand_bwd_set, dim3(grid_for(count << lg)), dim3(kBlock), 0, st, in, count, out, g, j,
+                           bx, by, bz, r2, orows, counter, overflow, lg);
     }
     return hipGetLastError();
 }
@@ -916,9 +915,10 @@ hipError_t launch_join(const uint64_t* flist, uint64_t count, SetView f, SetView
 __global__ void __launch_bounds__(kBlock) k_meet(const uint64_t* __restrict__ flist, uint64_t count, SetView fprev,
                                                  SetView b, SetView c, GridView g, JointView j, int mode,
                                                  unsigned long long* c_count, unsigned long long* kept_count,
-                                                 unsigned long long* overflow) {
+                                                 unsigned long long* overflow, int lg, int tx, int ty, int tz,
+                                                 long long r2) {
     const int na = b.na;
-    const int lg = group_log2(j.hi - j.lo + 1), G = 1 << lg;
+    const int G = 1 << lg;
     const int lane = threadIdx.x & 63, sub = lane & (G - 1), grp = lane >> lg;
     const uint64_t per_wave = 64u >> lg;
     const uint64_t wave = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) >> 6;
@@ -944,6 +944,10 @@ __global__ void __launch_bounds__(kBlock) k_meet(const uint64_t* __restrict__ fl
                 const int o = ia2 * na + ie2;
                 const short4 d = j.off[o];
                 const int x2 = x + d.x, y2 = y + d.y, z2 = z + d.z;
+                if (r2 >= 0) {   // B_m lies in the forward pruning ball of stage m
+                    const long long ex = x2 - tx, ey = y2 - ty, ez = z2 - tz;
+                    if (ex * ex + ey * ey + ez * ez > r2) continue;
+                }
                 if (!set_member(b, pack_key(x2, y2, z2, ia2, ie2))) continue;
                 if (!segment_clear_all(g, j, o, x, y, z)) continue;
                 hit = true;
@@ -976,11 +980,11 @@ __global__ void __launch_bounds__(kBlock) k_meet(const uint64_t* __restrict__ fl
 
 hipError_t launch_meet(const uint64_t* flist, uint64_t count, SetView fprev, SetView b, SetView c, GridView g,
                        JointView j, int mode, unsigned long long* c_count, unsigned long long* kept_count,
-                       unsigned long long* overflow, hipStream_t st) {
+                       unsigned long long* overflow, int tx, int ty, int tz, long long r2, hipStream_t st) {
     if (count == 0) return hipSuccess;
-    const uint64_t lanes = count * (uint64_t)(1u << std::min(6, host_group_log2(j.hi - j.lo + 1)));
-    hipLaunchKernelGGL(k_meet, dim3(grid_for(lanes)), dim3(kBlock), 0, st, flist, count, fprev, b, c, g, j,
-                       mode, c_count, kept_count, overflow);
+    const int lg = group_log2_for(count, j.hi - j.lo + 1);
+    hipLaunchKernelGGL(k_meet, dim3(grid_for(count << lg)), dim3(kBlock), 0, st, flist, count, fprev, b, c, g, j,
+                       mode, c_count, kept_count, overflow, lg, tx, ty, tz, r2);
     return hipGetLastError();
 }
 
@@ -990,9 +994,10 @@ hipError_t launch_meet(const uint64_t* flist, uint64_t count, SetView fprev, Set
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock) k_dmark(const uint64_t* __restrict__ flist, uint64_t count,
                                                   SetView fprev, SetView fnext, GridView g, JointView j,
-                                                  unsigned long long* counter) {
+                                                  unsigned long long* counter, int lg, int tx, int ty, int tz,
+                                                  long long r2) {
     const int na = fnext.na;
-    const int lg = group_log2(j.hi - j.lo + 1), G = 1 << lg;
+    const int G = 1 << lg;
     const int lane = threadIdx.x & 63, sub = lane & (G - 1), grp = lane >> lg;
     const uint64_t per_wave = 64u >> lg;
     const uint64_t wave = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) >> 6;
@@ -1017,6 +1022,10 @@ __global__ void __launch_bounds__(kBlock) k_dmark(const uint64_t* __restrict__ f
                     ie2 = wrap_na(ie + a, na);
                 const int o = ia2 * na + ie2;
                 const short4 d = j.off[o];
+                if (r2 >= 0) {   // F_k lies in the forward pruning ball of stage k
+                    const long long ex = x + d.x - tx, ey = y + d.y - ty, ez = z + d.z - tz;
+                    if (ex * ex + ey * ey + ez * ez > r2) continue;
+                }
                 if (!set_member(fnext, pack_key(x + d.x, y + d.y, z + d.z, ia2, ie2))) continue;
                 if (!segment_clear_all(g, j, o, x, y, z)) continue;
                 found = true;
@@ -1035,11 +1044,12 @@ __global__ void __launch_bounds__(kBlock) k_dmark(const uint64_t* __restrict__ f
 }
 
 hipError_t launch_dmark(const uint64_t* flist, uint64_t count, SetView fprev, SetView fnext, GridView g,
-                        JointView j, unsigned long long* counter, hipStream_t st) {
+                        JointView j, unsigned long long* counter, int tx, int ty, int tz, long long r2,
+                        hipStream_t st) {
     if (count == 0) return hipSuccess;
-    const uint64_t lanes = count * (uint64_t)(1u << std::min(6, host_group_log2(j.hi - j.lo + 1)));
-    hipLaunchKernelGGL(k_dmark, dim3(grid_for(lanes)), dim3(kBlock), 0, st, flist, count, fprev, fnext, g, j,
-                       counter);
+    const int lg = group_log2_for(count, j.hi - j.lo + 1);
+    hipLaunchKernelGGL(k_dmark, dim3(grid_for(count << lg)), dim3(kBlock), 0, st, flist, count, fprev, fnext, g, j,
+                       counter, lg, tx, ty, tz, r2);
     return hipGetLastError();
 }
 

@@ -656,6 +656,9 @@ msc_status run_reach(Lane* c, const msc_scene* sc, const Plan& p, int want, bool
         }
         MSC_TRY(ensure_list(c, F[m - 1]));
         const int fast = (m < n && p.type[m] == MSC_YAW) ? 1 : 0;
+        int64_t rt_m = 0;
+        for (int j = m; j < n; ++j) rt_m += R[j];
+        const long long meet_r2 = p.prune ? (long long)(rt_m * rt_m) : -1;
         if (!capture) {
             // Only D_{m-1} is needed: the canonical walk steps from D_{m-1} into B_m,
             // which for a clear move is the same as stepping into C_m; C is not built.
@@ -664,7 +667,7 @@ msc_status run_reach(Lane* c, const msc_scene* sc, const Plan& p, int want, bool
             if (!hc || !kc) return fail(c, MSC_E_CAPACITY, "out of counters");
             LAUNCH(MSC_K_JOIN, m, (int64_t)F[m - 1].count,
                    launch_meet(F[m - 1].list, F[m - 1].count, F[m - 1].view, B[m].view, B[m].view, g, jv[m - 1],
-                               kMeetMark, hc, kc, ovf, c->stream));
+                               kMeetMark, hc, kc, ovf, p.target[0], p.target[1], p.target[2], meet_r2, c->stream));
             const int jrec = c->last_rec;
             MSC_TRY(read_counter(c, kc, &joined));
             prof_out(c, jrec, (int64_t)joined);
@@ -686,7 +689,7 @@ msc_status run_reach(Lane* c, const msc_scene* sc, const Plan& p, int want, bool
             if (!hc || !kc) return fail(c, MSC_E_CAPACITY, "out of counters");
             LAUNCH(MSC_K_JOIN, m, (int64_t)F[m - 1].count,
                    launch_meet(F[m - 1].list, F[m - 1].count, F[m - 1].view, B[m].view, B[m].view, g, jv[m - 1],
-                               kMeetCount, hc, kc, ovf, c->stream));
+                               kMeetCount, hc, kc, ovf, p.target[0], p.target[1], p.target[2], meet_r2, c->stream));
             MSC_TRY(read_counter(c, hc, &hits));
             if (hits) MSC_TRY(make_set(c, p, box[m], hits, fast, false, Cset));
         }
@@ -696,7 +699,8 @@ msc_status run_reach(Lane* c, const msc_scene* sc, const Plan& p, int want, bool
             if (!cc || !kc2) return fail(c, MSC_E_CAPACITY, "out of counters");
             LAUNCH(MSC_K_JOIN, m, (int64_t)F[m - 1].count,
                    launch_meet(F[m - 1].list, F[m - 1].count, F[m - 1].view, B[m].view, Cset.view, g, jv[m - 1],
-                               kMeetInsert, cc, kc2, ovf, c->stream));
+                               kMeetInsert, cc, kc2, ovf, p.target[0], p.target[1], p.target[2], meet_r2,
+                               c->stream));
             const int jrec = c->last_rec;
             MSC_TRY(read_counter(c, cc, &joined));
             prof_out(c, jrec, (int64_t)joined);
@@ -713,8 +717,12 @@ msc_status run_reach(Lane* c, const msc_scene* sc, const Plan& p, int want, bool
     for (int k = m - 1; k >= 1; --k) {
         // D_{k-1} from D_k (D_k is Cset for k == m, else F_k's marked structure)
         unsigned long long* dc = take_counter(c);
+        int64_t rt_k = 0;
+        for (int j = k; j < n; ++j) rt_k += R[j];
+        const long long dr2 = p.prune ? (long long)(rt_k * rt_k) : -1;
         LAUNCH(MSC_K_DMARK, k - 1, (int64_t)F[k - 1].count,
-               launch_dmark(F[k - 1].list, F[k - 1].count, F[k - 1].view, F[k].view, g, jv[k - 1], dc, c->stream));
+               launch_dmark(F[k - 1].list, F[k - 1].count, F[k - 1].view, F[k].view, g, jv[k - 1], dc, p.target[0],
+                            p.target[1], p.target[2], dr2, c->stream));
         if (capture) MSC_TRY(capture_set(c, F[k - 1], N, 3, k - 1));
     }
 
