@@ -564,6 +564,26 @@ msc_status run_reach(Lane* c, const msc_scene* sc, const Plan& p, int want, bool
     // (split 0: the backward pathway runs down to the root and is joined with F_0).
     auto finished = [&]() { return p.split == 0 ? kb == 0 : kb - kf == 1; };
     auto window = [&](int k) { return (double)(p.hi[k] - p.lo[k] + 1); };
+    // Rough per-item device times that steer the split (the result does not depend on
+    // it): a forward candidate (state x angle), a backward input state (expansion plus
+    // its list), a meet candidate against a small dense B (cache resident) or against
+    // a large or hashed one, and fill bandwidth.
+    constexpr double kFwdNs = 33.0, kBwdNs = 100.0, kMeetSmallNs = 4.0, kMeetBigNs = 12.0;
+    constexpr double kFillBytesPerNs = 4500.0, kMallBytes = 256.0 * (1 << 20);
+    auto meet_ns = [&](const StageSet& b) {
+        return (b.view.kind == kDense && 8.0 * (double)b.view.cap <= kMallBytes) ? kMeetSmallNs : kMeetBigNs;
+    };
+    // Cost of one more backward stage from B_kb plus the meet from F_kf.
+    auto backward_then_meet = [&](int kf_, int kb_) {
+        const uint64_t upper = B[kb_].count * (uint64_t)window(kb_ - 1);
+        const uint64_t dense_words = box[kb_ - 1].voxels() * (uint64_t)na * na / 64;
+        const uint64_t slots = pow2_at_least(std::max<uint64_t>(2 * upper, 64));
+        const uint64_t words = dense_words <= 8 * slots ? dense_words : slots;
+        const bool dense = dense_words <= 8 * slots;
+        const double meet = (dense && 8.0 * (double)dense_words <= kMallBytes) ? kMeetSmallNs : kMeetBigNs;
+        return (double)B[kb_].count * kBwdNs + 8.0 * (double)words / kFillBytesPerNs +
+               (double)F[kf_].count * window(kf_) * meet;
+    };
     bool backward_only = false;
     while (!empty && !finished()) {
         bool forward;
@@ -572,29 +592,29 @@ msc_status run_reach(Lane* c, const msc_scene* sc, const Plan& p, int want, bool
         } else if (backward_only) {
             forward = false;
         } else {
-            double cf = (double)F[kf].count * (p.hi[kf] - p.lo[kf] + 1);
-            double cb = (double)B[kb].count * 3.0;
+            const double cf = (double)F[kf].count * window(kf);
+            const double cb = (double)B[kb].count * 3.0;
             forward = cf <= cb;
+            if (kb - kf == 2 && kf >= 1 && F[kf - 1].count > 0) {
+                // The last step before the meet decides which sets meet: estimate the next
+                // forward set from the last growth (damped: growth slows as the pruning
+                // ball shrinks) and compare the two ways to the meet.
+                const double grow = 0.5 * (double)F[kf].count / (double)F[kf - 1].count;
+                const double next = (double)F[kf].count * std::max(1.0, grow);
+                const double fwd = cf * kFwdNs + next * window(kf + 1) * meet_ns(B[kb]);
+                forward = fwd <= backward_then_meet(kf, kb);
+            }
         }
         if (forward) {
             MSC_TRY(expand_forward(kf + 1, F[kf + 1]));
             kf = kf + 1;
             empty = F[kf].count == 0;
-            // Adaptive split, the step before the meet: the meet tries every state of F_kf
-            // against the next joint's window.  When that is dearer than one more backward
-            // stage plus the meet from F_{kf-1}, the forward side steps back (F_kf stays
-            // built but unused).  Costs are rough per-item times on the device.
+            // The step before the meet, checked with the real size: when the meet from F_kf
+            // is dearer than one more backward stage plus the meet from F_{kf-1}, the
+            // forward side steps back (F_kf stays built but unused).
             if (!empty && p.split < 0 && kb - kf == 1 && kf >= 1) {
-                constexpr double kMeetNs = 8.0, kBwdNs = 90.0, kFillBytesPerNs = 4000.0;
-                const double meet_here = (double)F[kf].count * window(kf) * kMeetNs;
-                const uint64_t upper = B[kb].count * (uint64_t)window(kb - 1);
-                const uint64_t dense_words = box[kb - 1].voxels() * (uint64_t)na * na / 64;
-                const uint64_t slots = pow2_at_least(std::max<uint64_t>(2 * upper, 64));
-                const uint64_t words = dense_words <= 8 * slots ? dense_words : slots;
-                const double fill_ns = 8.0 * (double)words / kFillBytesPerNs;
-                const double alt = (double)B[kb].count * kBwdNs + fill_ns +
-                                   (double)F[kf - 1].count * window(kf - 1) * kMeetNs;
-                if (alt < meet_here) {
+                const double meet_here = (double)F[kf].count * window(kf) * meet_ns(B[kb]);
+                if (backward_then_meet(kf - 1, kb) < meet_here) {
                     kf -= 1;
                     backward_only = true;
                 }
