@@ -131,7 +131,7 @@ hipError_t launch_tube_valid(const TubeArgs& a, uint8_t* valid, hipStream_t st);
 // Bit-parallel search for small frames: LDS bytes it needs (0 = not applicable), and
 // the launch (validity bits + dynamic program + backward choice in one block).
 size_t tube_bits_lds(const TubeArgs& a);
-hipError_t launch_tube_bits(const TubeArgs& a, uint64_t* vbits, uint64_t* rbits, int32_t* path, int32_t* status,
+hipError_t launch_tube_bits(const TubeArgs& a, uint64_t* vbits, int32_t* path, int32_t* status,
                             hipStream_t st);
 hipError_t launch_tube_solve(const TubeArgs& a, const uint8_t* valid, uint8_t* reach, uint8_t* tmp0,
                              uint8_t* tmp1, int32_t* path, int32_t* status, hipStream_t st);

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "msc_common.h"
 
@@ -1245,37 +1246,118 @@ __device__ __forceinline__ int guide_at(const TubeArgs& a, int w, int k) {
     return a.start[k] + (num < 0 ? -(int)mag : (int)mag);
 }
 
-// slab <= 2^28 (checked on the host), so a cell index fits 32 bits
-__device__ bool tube_pose(const TubeArgs& a, int w, uint64_t cell64, int32_t* q) {
-    const uint32_t B = 2u * (uint32_t)a.r + 1u;
-    uint32_t cell = (uint32_t)cell64;
-    bool in = true;
-    for (int k = a.n - 1; k >= 0; --k) {
-        int d = (int)(cell % B);
-        cell /= B;
-        q[k] = guide_at(a, w, k) - a.r + d;
-        if (w == 0) in = in && q[k] == a.start[k];
-        else if (w == a.W) in = in && q[k] == a.goal[k];
-        else in = in && q[k] >= a.lim_lo[k] && q[k] <= a.lim_hi[k];
-    }
-    return in;
+
+// Tube validity by prefix.  A thread takes one pose prefix (joints 0 .. n-L-1) of one
+// waypoint frame, replays it once, then tries the B^L completions of the last L joints
+// (L <= 2), so that a segment shared by many cells is tested once.  A cell is valid
+// when every joint is in its range (the start pose at waypoint 0, the reach pose at
+// waypoint W) and the replay of the pose is clear.  Output: bytes, or bits OR-ed into a
+// zeroed bitset (completions of one prefix are consecutive cells).
+__device__ __forceinline__ bool tube_angle(const TubeArgs& a, int w, int k, int d, int& q) {
+    q = guide_at(a, w, k) - a.r + d;
+    if (w == 0) return q == a.start[k];
+    if (w == a.W) return q == a.goal[k];
+    return q >= a.lim_lo[k] && q <= a.lim_hi[k];
 }
 
-__global__ void k_tube_valid(TubeArgs a, uint8_t* valid) {
-    const uint64_t total = (uint64_t)(a.W + 1) * a.slab;
+struct FkState {
+    int x, y, z, ia, ie;
+};
+
+__device__ __forceinline__ bool fk_step(const TubeArgs& a, int k, int qk, FkState& s) {
+    const JointView& J = a.joints[k];
+    if (J.type == 0)
+        s.ia = wrap_na(s.ia + qk, a.na);
+    else
+        s.ie = wrap_na(s.ie + qk, a.na);
+    const int o = s.ia * a.na + s.ie;
+    const bool ok = segment_clear_all(a.g, J, o, s.x, s.y, s.z);
+    const short4 d = J.off[o];
+    s.x += d.x;
+    s.y += d.y;
+    s.z += d.z;
+    return ok;
+}
+
+__global__ void k_tube_valid_tree(TubeArgs a, int L, uint8_t* vbytes, uint64_t* vbits, uint32_t nw) {
+    const int n = a.n, B = 2 * a.r + 1, np = n - L;
+    uint32_t P = 1, BL = 1;
+    for (int k = 0; k < np; ++k) P *= (uint32_t)B;
+    for (int k = 0; k < L; ++k) BL *= (uint32_t)B;
+    const uint64_t total = (uint64_t)(a.W + 1) * P;
     for (uint64_t idx = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; idx < total;
          idx += (uint64_t)gridDim.x * blockDim.x) {
-        int w = (int)(idx / a.slab);
-        uint64_t cell = idx - (uint64_t)w * a.slab;
-        int32_t q[kMaxDof];
-        bool ok = tube_pose(a, w, cell, q) && replay(a, q, nullptr);
-        valid[idx] = ok ? 1 : 0;
+        const int w = (int)(idx / P);
+        const uint32_t pre = (uint32_t)(idx - (uint64_t)w * P);
+        FkState s{a.bx, a.by, a.bz, a.ia0, a.ie0};
+        bool ok = cell_free(a.g, s.x, s.y, s.z);
+        uint32_t rest = pre, div = P;
+        for (int k = 0; k < np && ok; ++k) {
+            div /= (uint32_t)B;
+            const int d = (int)(rest / div);
+            rest -= (uint32_t)d * div;
+            int qk;
+            ok = tube_angle(a, w, k, d, qk) && fk_step(a, k, qk, s);
+        }
+        uint32_t bits = 0;   // bit l: completion l (BL <= 32)
+        if (ok) {
+            if (L == 0) {
+                bits = 1;
+            } else if (L == 1) {
+                for (int d = 0; d < B; ++d) {
+                    FkState t = s;
+                    int qk;
+                    if (tube_angle(a, w, n - 1, d, qk) && fk_step(a, n - 1, qk, t)) bits |= 1u << d;
+                }
+            } else {
+                for (int d1 = 0; d1 < B; ++d1) {
+                    FkState t = s;
+                    int q1;
+                    if (!(tube_angle(a, w, n - 2, d1, q1) && fk_step(a, n - 2, q1, t))) continue;
+                    for (int d2 = 0; d2 < B; ++d2) {
+                        FkState u = t;
+                        int q2;
+                        if (tube_angle(a, w, n - 1, d2, q2) && fk_step(a, n - 1, q2, u)) bits |= 1u << (d1 * B + d2);
+                    }
+                }
+            }
+        }
+        const uint64_t cell0 = (uint64_t)pre * BL;
+        if (vbytes) {
+            uint8_t* out = vbytes + (uint64_t)w * a.slab + cell0;
+            for (uint32_t l = 0; l < BL; ++l) out[l] = (uint8_t)((bits >> l) & 1u);
+        } else if (bits) {
+            const uint64_t word = (uint64_t)w * nw + (cell0 >> 6);
+            const int sh = (int)(cell0 & 63);
+            atomicOr((unsigned long long*)&vbits[word], (unsigned long long)((uint64_t)bits << sh));
+            if (sh + (int)BL > 64) atomicOr((unsigned long long*)&vbits[word + 1], (unsigned long long)((uint64_t)bits >> (64 - sh)));
+        }
     }
 }
 
+uint64_t tube_prefix_threads(const TubeArgs& a, int L);
+
+// Completions per thread: one joint keeps the per-thread chain of segment tests short
+// (small frames are latency-bound); two joints halve the segment tests when the frame
+// count alone fills the device.
+int tube_leaf_joints(const TubeArgs& a) {
+    const int B = 2 * a.r + 1;
+    if (a.n >= 2 && B * B <= 32 && tube_prefix_threads(a, 1) > (2ull << 20)) return 2;
+    if (a.n >= 1 && B <= 32) return 1;
+    return 0;
+}
+
+uint64_t tube_prefix_threads(const TubeArgs& a, int L) {
+    uint64_t P = 1;
+    for (int k = 0; k < a.n - L; ++k) P *= (uint64_t)(2 * a.r + 1);
+    return (uint64_t)(a.W + 1) * P;
+}
+
+
 hipError_t launch_tube_valid(const TubeArgs& a, uint8_t* valid, hipStream_t st) {
-    uint64_t total = (uint64_t)(a.W + 1) * a.slab;
-    hipLaunchKernelGGL(k_tube_valid, dim3(grid_for(total)), dim3(kBlock), 0, st, a, valid);
+    const int L = tube_leaf_joints(a);
+    hipLaunchKernelGGL(k_tube_valid_tree, dim3(grid_for(tube_prefix_threads(a, L))), dim3(kBlock), 0, st, a, L, valid,
+                       (uint64_t*)nullptr, 0u);
     return hipGetLastError();
 }
 
@@ -1505,25 +1587,7 @@ __global__ void __launch_bounds__(kTubeThreads) k_tube_trace(TubeArgs a, const u
 // ---------------------------------------------------------------------------
 constexpr int kBitThreads = 256;
 constexpr int kBitMaxB = 9;      // frame edge 2r+1 of the bit-parallel search (r <= 4)
-
-// validity of every cell of every waypoint as bits: word (w*nw + i), cells >= slab are 0
-__global__ void k_tube_valid_bits(TubeArgs a, uint32_t nw, uint64_t* vbits) {
-    const uint64_t total = (uint64_t)(a.W + 1) * nw * 64;
-    for (uint64_t base = blockIdx.x * (uint64_t)blockDim.x; base < total; base += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t idx = base + threadIdx.x;
-        bool ok = false;
-        if (idx < total) {
-            const int w = (int)(idx / ((uint64_t)nw * 64));
-            const uint64_t cell = idx - (uint64_t)w * nw * 64;
-            if (cell < a.slab) {
-                int32_t q[kMaxDof];
-                ok = tube_pose(a, w, cell, q) && replay(a, q, nullptr);
-            }
-        }
-        unsigned long long b = __ballot(ok);
-        if ((threadIdx.x & 63) == 0 && idx < total) vbits[idx >> 6] = b;
-    }
-}
+constexpr size_t kBitLdsMax = 150 * 1024;   // dynamic LDS of the search (a CU has 160 KiB)
 
 // bits of `src` shifted so that bit c of the result is bit c + x of src (x may be < 0);
 // |64 i + x| < 2^31 for the frame sizes used here
@@ -1536,16 +1600,18 @@ __device__ __forceinline__ uint64_t shifted_word(const uint64_t* src, int nw, in
     return u ? ((lo >> u) | (hi << (64 - u))) : lo;
 }
 
+template <int DL>
 __global__ void __launch_bounds__(kBitThreads) k_tube_bits(TubeArgs a, uint32_t nw_u, const uint64_t* vbits,
-                                                           uint64_t* rbits, int32_t* path, int32_t* status) {
+                                                           int32_t* path, int32_t* status) {
     extern __shared__ uint64_t sm[];
     const int nw = (int)nw_u;
-    const int n = a.n, B = 2 * a.r + 1, dl = a.delta, r = a.r;
+    const int n = a.n, B = 2 * a.r + 1, dl = DL > 0 ? DL : a.delta, r = a.r;
     const int nlev = n * r + 1;                     // L1 distances to the guide: 0 .. n r
     uint64_t* fa = sm;                              // two frames, used in turn
     uint64_t* fb = sm + nw;
     uint64_t* ge = sm + 2 * nw;                     // [k][v][word], v = 0..B: cells whose digit k is >= v
     uint64_t* lvl = ge + (size_t)n * (B + 1) * nw;  // [l][word]: cells at L1 distance l from the guide
+    uint64_t* rbits = lvl + (size_t)(n * r + 1) * nw;   // [w][word]: the reachable sets R_0 .. R_W
     __shared__ uint32_t stride[kMaxDof];
     __shared__ int shw[kMaxDof], dlo[kMaxDof], dhi[kMaxDof], flo[kMaxDof], qcur[kMaxDof];
     __shared__ unsigned long long best_part[kBitThreads / 64];
@@ -1644,13 +1710,19 @@ __global__ void __launch_bounds__(kBitThreads) k_tube_bits(TubeArgs a, uint32_t 
             int j = 0;
             for (int i = tid; i < nw; i += kBitThreads, ++j) {
                 uint64_t acc = 0;
-                for (int e = -dl; e <= dl; ++e) {
+                auto take = [&](int e) {
                     const int t = sh + e;
                     const int vlo = t < 0 ? -t : 0;
                     const int vend = t > 0 ? B - t : B;      // exclusive
-                    if (vlo >= vend) continue;
+                    if (vlo >= vend) return;
                     const uint64_t m = gk[(size_t)vlo * nw + i] & ~gk[(size_t)vend * nw + i];
                     acc |= shifted_word(src, nw, i, t * s) & m;
+                };
+                if constexpr (DL > 0) {
+#pragma unroll
+                    for (int e = -DL; e <= DL; ++e) take(e);
+                } else {
+                    for (int e = -dl; e <= dl; ++e) take(e);
                 }
                 if (k == n - 1) {
                     acc &= vw[j];
@@ -1738,18 +1810,35 @@ size_t tube_bits_lds(const TubeArgs& a) {
     const int B = 2 * a.r + 1;
     if (a.slab > 16384 || B > kBitMaxB || a.n * a.r > 31) return 0;
     const size_t nw = (a.slab + 63) / 64;
-    const size_t bytes = (2 + (size_t)a.n * (B + 1) + (size_t)(a.n * a.r + 1)) * nw * 8;
-    return bytes <= 60 * 1024 ? bytes : 0;
+    const size_t frames = 2 + (size_t)a.n * (B + 1) + (size_t)(a.n * a.r + 1) + (size_t)(a.W + 1);
+    const size_t bytes = frames * nw * 8;
+    return bytes <= kBitLdsMax ? bytes : 0;
+}
+template <int DL>
+hipError_t launch_tube_bits_dl(const TubeArgs& a, uint32_t nw, const uint64_t* vbits, int32_t* path,
+                               int32_t* status, hipStream_t st) {
+    static std::once_flag once;
+    static hipError_t attr = hipSuccess;
+    std::call_once(once, [] {
+        attr = hipFuncSetAttribute((const void*)k_tube_bits<DL>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)kBitLdsMax);
+    });
+    if (attr != hipSuccess) return attr;
+    hipLaunchKernelGGL(k_tube_bits<DL>, dim3(1), dim3(kBitThreads), tube_bits_lds(a), st, a, nw, vbits, path, status);
+    return hipGetLastError();
 }
 
-hipError_t launch_tube_bits(const TubeArgs& a, uint64_t* vbits, uint64_t* rbits, int32_t* path, int32_t* status,
-                            hipStream_t st) {
+hipError_t launch_tube_bits(const TubeArgs& a, uint64_t* vbits, int32_t* path, int32_t* status, hipStream_t st) {
     const uint32_t nw = (uint32_t)((a.slab + 63) / 64);
-    const uint64_t total = (uint64_t)(a.W + 1) * nw * 64;
-    hipLaunchKernelGGL(k_tube_valid_bits, dim3(grid_for(total)), dim3(kBlock), 0, st, a, nw, vbits);
-    hipLaunchKernelGGL(k_tube_bits, dim3(1), dim3(kBitThreads), tube_bits_lds(a), st, a, nw, vbits, rbits, path,
-                       status);
-    return hipGetLastError();
+    const int L = tube_leaf_joints(a);
+    hipError_t e = launch_fill(vbits, (uint64_t)(a.W + 1) * nw, 0ull, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_tube_valid_tree, dim3(grid_for(tube_prefix_threads(a, L))), dim3(kBlock), 0, st, a, L,
+                       (uint8_t*)nullptr, vbits, nw);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (a.delta == 1) return launch_tube_bits_dl<1>(a, nw, vbits, path, status, st);
+    if (a.delta == 2) return launch_tube_bits_dl<2>(a, nw, vbits, path, status, st);
+    return launch_tube_bits_dl<0>(a, nw, vbits, path, status, st);
 }
 
 hipError_t launch_tube_solve(const TubeArgs& a, const uint8_t* valid, uint8_t* reach, uint8_t* tmp0,
