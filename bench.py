@@ -100,6 +100,179 @@ def cpu_baseline(queries, split):
                       "%.1f s, status %d" % (split, dt, st)}
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "expand_traffic_c2.md")
+KERNEL_SOURCES = ["paper_1906_10678_amd/csrc/msc_kernels.hip", "paper_1906_10678_amd/csrc/msc_runtime.hip",
+                  "paper_1906_10678_amd/csrc/msc_common.h"]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per expansion launch from the committed counter summary, or None when
+    the summary is missing or was taken on other kernel sources."""
+    try:
+        with open(TRAFFIC_PROFILE) as f:
+            text = f.read()
+    except OSError:
+        return None
+    fields = {}
+    for line in text.splitlines():
+        if line.startswith("- ") and ": " in line:
+            k, v = line[2:].split(": ", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    if fields.get("kernel sources sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(fields["HBM bytes per expansion launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def traffic_run(args):
+    """The program that the two rocprofv3 --pmc passes run: captured runs of the C2
+    queries (algorithmic bytes per expansion launch), a 1 GiB device copy as the
+    counter calibration, then one plain run of each query."""
+    import torch
+
+    from paper_1906_10678_amd import msc, synth
+
+    solver = msc.Solver(0, workspace_bytes=args.workspace_gb << 30)
+    queries = [synth.query_c2(s, solver.pose_fn_for) for s in range(args.queries)]
+    n, na = queries[0].scene.n, queries[0].arm.na
+    alg_total, launches = 0, 0
+    for q in queries:
+        sc = solver.scene(q.scene)
+        solver.path(sc, q.arm, q.start, q.target, q.waypoints, q.max_delta, flags=msc.CAPTURE_SETS)
+        st = solver.stats()
+        a = expansion_bytes(solver, msc, n, na, st)
+        used = {k: v for k, v in a.items() if not (k[0] == "expand_fwd" and k[1] == st["split_m"])}
+        alg_total += int(sum(used.values()))
+        launches += len(used)
+    torch.cuda.synchronize()
+    x = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    for q in queries:
+        sc = solver.scene(q.scene)
+        solver.path(sc, q.arm, q.start, q.target, q.waypoints, q.max_delta)
+    torch.cuda.synchronize()
+    out = {"alg_bytes_total": alg_total, "expand_launches": launches, "copy_bytes": 1 << 30,
+           "queries": len(queries)}
+    os.makedirs(os.path.dirname(args.traffic_out) or ".", exist_ok=True)
+    with open(args.traffic_out, "w") as f:
+        json.dump(out, f)
+    print("traffic run done", json.dumps(out), flush=True)
+
+
+def traffic_summary(args):
+    """Writes the expansion-traffic summary from the two counter CSVs of the traffic run."""
+    import csv
+    import collections
+
+    fetch_csv, write_csv, alg_json = args.traffic_summary
+    alg = json.load(open(alg_json))
+
+    def per_kernel(path, counter):
+        rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
+        rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+        copies = [r for r in rows if "copyBuffer" in r["Kernel_Name"]]
+        last = max(int(r["Dispatch_Id"]) for r in copies)
+        cal = [float(r["Counter_Value"]) for r in copies if int(r["Dispatch_Id"]) > last - 3]
+        per = collections.defaultdict(lambda: [0.0, 0])
+        for r in rows:
+            if int(r["Dispatch_Id"]) > last:
+                name = r["Kernel_Name"].split("(")[0]
+                per[name][0] += float(r["Counter_Value"])
+                per[name][1] += 1
+        return (alg["copy_bytes"] / 1024.0) / (sum(cal) / len(cal)), per
+
+    ff, fper = per_kernel(fetch_csv, "FETCH_SIZE")
+    wf, wper = per_kernel(write_csv, "WRITE_SIZE")
+    expand = ("msc::k_expand_fwd", "msc::k_expand_bwd", "msc::k_expand_bwd_set")
+    tot = sum(fper[k][0] * ff * 1024 + wper[k][0] * wf * 1024 for k in expand)
+    nl = sum(fper[k][1] for k in expand)
+    lines = ["# HBM traffic of the stage expansions, 8-DOF reach + path workload (%d queries)" % alg["queries"], "",
+             "Two rocprofv3 counter passes over the same program (`bench.py --traffic-run`):", "",
+             "```", "timeout -s KILL 240 rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o run "
+             "-- python -u bench.py --traffic-run",
+             "timeout -s KILL 240 rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o run "
+             "-- python -u bench.py --traffic-run",
+             "python bench.py --traffic-summary gpurun_out/pmc_fetch/run_counter_collection.csv "
+             "gpurun_out/pmc_write/run_counter_collection.csv gpurun_out/traffic_alg.json", "```", "",
+             "Counters are KiB per dispatch.  Calibration: a 1 GiB device-to-device copy reads "
+             "%.4f x its FETCH_SIZE and writes %.4f x its WRITE_SIZE; both factors are applied." % (ff, wf), "",
+             "| kernel | dispatches | fetch MB | write MB |", "|---|---|---|---|"]
+    for k in sorted(set(fper) | set(wper)):
+        lines.append("| %s | %d | %.1f | %.1f |" % (k, fper[k][1], fper[k][0] * ff * 1024 / 1e6,
+                                                    wper[k][0] * wf * 1024 / 1e6))
+    lines += ["", "- expansion launches: %d (algorithmic record: %d)" % (nl, alg["expand_launches"]),
+              "- algorithmic bytes per expansion launch: %.0f" % (alg["alg_bytes_total"] / alg["expand_launches"]),
+              "- HBM bytes per expansion launch: %.0f" % (tot / max(nl, 1)),
+              "- kernel sources sha256: `%s`" % kernel_source_hash(), ""]
+    with open(TRAFFIC_PROFILE, "w") as f:
+        f.write("\n".join(lines))
+    print("wrote", TRAFFIC_PROFILE, flush=True)
+
+
+TRACE_PROFILE = os.path.join(ROOT, "profiles", "expand_trace_c2.md")
+
+
+def trace_summary(args):
+    """Kernel-trace summary of a --plain-only run: per-kernel statistics over the whole
+    run, and the average duration of the expansion kernels over the plain timed region
+    (its last expansion dispatches), next to the HIP-event average the run printed."""
+    import csv
+    import collections
+
+    trace_csv, bench_json = args.trace_summary
+    res = None
+    for line in open(bench_json):
+        line = line.strip()
+        if line.startswith("{"):
+            res = json.loads(line)
+    rows = list(csv.DictReader(open(trace_csv)))
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    stats = collections.defaultdict(list)
+    for r in rows:
+        stats[r["Kernel_Name"].split("(")[0]].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    expand = ("msc::k_expand_fwd", "msc::k_expand_bwd", "msc::k_expand_bwd_set")
+    ex = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in rows
+          if r["Kernel_Name"].split("(")[0] in expand]
+    nl = res["roofline"]["launches"]
+    tail = ex[-nl:]
+    lines = ["# Kernel trace, 8-DOF reach + 16-waypoint path queries (plain phase of bench.py)", "",
+             "```", "rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof -o run "
+             "-- python -u bench.py --plain-only --no-cpu-baseline",
+             "python bench.py --trace-summary gpurun_out/prof/run_kernel_trace.csv gpurun_out/prof_bench.json", "```", "",
+             "The run captures stage sets of the %d queries (algorithmic bytes), warms up, then times %d "
+             "plain queries; the expansion kernels of that timed region are its last %d expansion dispatches."
+             % (res["queries"], args.plain_steps, nl), "",
+             "- expansion dispatches in the timed region: %d" % nl,
+             "- their average duration, kernel trace (us): %.2f" % (sum(tail) / max(len(tail), 1)),
+             "- their average duration, HIP events in the run (us): %.2f" % res["roofline"]["avg_launch_us"],
+             "- algorithmic bytes per expansion launch: %d" % res["roofline"]["alg_bytes_per_launch"],
+             "- plain solves/s in the traced run: %.1f" % res["plain"]["solves_per_s"], "",
+             "| kernel | calls | total ms | avg us | min us | max us |", "|---|---|---|---|---|---|"]
+    for k, v in sorted(stats.items(), key=lambda kv: -sum(kv[1])):
+        lines.append("| %s | %d | %.2f | %.1f | %.1f | %.1f |" % (k, len(v), sum(v) / 1e3, sum(v) / len(v), min(v),
+                                                               max(v)))
+    lines.append("")
+    with open(TRACE_PROFILE, "w") as f:
+        f.write("\n".join(lines))
+    print("wrote", TRACE_PROFILE, flush=True)
+
+
 def bench_c3(args):
     """Batched reach poses: 64 scenes (128^3 or 256^3, 10..60 boxes), 8 queries each, DOF
     5..8 unwindowed (+-170 deg in 5 deg steps); targets are ends of random poses, so
@@ -180,10 +353,25 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=100)
     ap.add_argument("--workspace-gb", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--plain-only", action="store_true",
+                    help="stop after the plain phase (the run profiled for profiles/expand_trace_c2.md)")
+    ap.add_argument("--trace-summary", nargs=2, metavar=("KERNEL_TRACE_CSV", "BENCH_JSON"),
+                    help="write profiles/expand_trace_c2.md from a kernel trace of a --plain-only run")
+    ap.add_argument("--traffic-run", action="store_true",
+                    help="run the program of the HBM counter passes (see profiles/expand_traffic_c2.md)")
+    ap.add_argument("--traffic-out", default="gpurun_out/traffic_alg.json")
+    ap.add_argument("--traffic-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "ALG_JSON"),
+                    help="write profiles/expand_traffic_c2.md from the counter passes")
     args = ap.parse_args()
+    if args.traffic_summary:
+        return traffic_summary(args)
+    if args.trace_summary:
+        return trace_summary(args)
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the solver has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.traffic_run:
+        return traffic_run(args)
     if args.workload == "c3":
         return bench_c3(args)
     if args.workload == "c5":
@@ -249,7 +437,7 @@ def main():
                 cnt += 1
     achieved = b_sum / (ms_sum * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": measured_traffic(),
                 "kernel": "expand (k_expand_fwd + k_expand_bwd)", "launches": cnt,
                 "avg_launch_us": round(1e3 * ms_sum / max(cnt, 1), 2),
                 "alg_bytes_per_launch": round(b_sum / max(cnt, 1))}
@@ -259,6 +447,11 @@ def main():
              "p99_ms": round(float(np.percentile(plain_lat, 99)), 4),
              "kernel_ms_per_query": {k: round(v[0] / args.plain_steps, 4) for k, v in sorted(per_kernel.items())}}
     print("plain", plain["solves_per_s"], "solves/s", file=sys.stderr, flush=True)
+    if args.plain_only:
+        # the run profiled for the kernel-trace summary: the plain phase is its last GPU work
+        print(json.dumps({"plain": plain, "roofline": roofline, "queries": len(queries), "splits": splits}),
+              flush=True)
+        return
 
     # ---- batched: each step rasterises the scenes of a batch and solves it with msc_batch
     def batch_step(b):
