@@ -74,7 +74,9 @@ struct OrientArgs {
 };
 hipError_t launch_orient(const OrientArgs& a, uint64_t* rows_ie, uint64_t* rows_ia, hipStream_t st);
 // Copy n counters to (host-mapped) memory with one small kernel.
-hipError_t launch_publish(const unsigned long long* src, unsigned long long* dst, int n, hipStream_t st);
+// flag / seq: see k_publish (flag may be null)
+hipError_t launch_publish(const unsigned long long* src, unsigned long long* dst, int n, unsigned long long* flag,
+                          unsigned long long seq, hipStream_t st);
 hipError_t launch_seed_fwd(SetView s, GridView g, int x, int y, int z, int ia, int ie,
                            unsigned long long* counter, hipStream_t st);
 hipError_t launch_seed_bwd(SetView s, GridView g, int x, int y, int z, const uint64_t* rows_ie,

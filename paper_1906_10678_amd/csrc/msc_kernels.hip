@@ -441,12 +441,22 @@ hipError_t launch_orient(const OrientArgs& a, uint64_t* rows_ie, uint64_t* rows_
     return hipGetLastError();
 }
 
-__global__ void k_publish(const unsigned long long* src, unsigned long long* dst, int n) {
+// Copies counters into mapped host memory, then (system-scope fence first) writes the
+// sequence number `seq` to `flag`, which the host polls instead of synchronising the
+// stream.
+__global__ void k_publish(const unsigned long long* src, unsigned long long* dst, int n, unsigned long long* flag,
+                          unsigned long long seq) {
     for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+    __syncthreads();
+    if (threadIdx.x == 0 && flag) {
+        __threadfence_system();
+        __hip_atomic_store(flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
 }
 
-hipError_t launch_publish(const unsigned long long* src, unsigned long long* dst, int n, hipStream_t st) {
-    hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, st, src, dst, n);
+hipError_t launch_publish(const unsigned long long* src, unsigned long long* dst, int n, unsigned long long* flag,
+                          unsigned long long seq, hipStream_t st) {
+    hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, st, src, dst, n, flag, seq);
     return hipGetLastError();
 }
 

@@ -5,11 +5,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
-#include <atomic>
-#include <condition_variable>
 #include <deque>
 #include <map>
 #include <mutex>
@@ -66,6 +67,7 @@ struct Lane {
     char* staging = nullptr;                 // pinned, mapped host memory
     char* staging_dev = nullptr;             // its device address
     size_t staging_used = 0;
+    unsigned long long publish_seq = 0;      // last sequence number given to k_publish
     msc_stats stats{};
     std::map<std::pair<int, int>, std::vector<uint64_t>> captured;
     int captured_n = 0;
@@ -232,14 +234,38 @@ unsigned long long* take_counter(Lane* c) {
 }
 
 // Counter value on the host: a one-thread kernel stores it into mapped pinned memory.
-msc_status read_counter(Lane* c, unsigned long long* dev, uint64_t* out) {
-    volatile unsigned long long* h = (volatile unsigned long long*)(c->staging + kStagingBytes - 64);
+// Stage sizes for the host: the publish kernel copies counters into mapped host memory
+// and then bumps a sequence flag, which is polled (a few microseconds after the stage
+// ends) instead of a stream synchronisation; after ~5 ms of polling the stream is
+// synchronised, which also reports a failed launch.
+msc_status publish_and_wait(Lane* c, unsigned long long* dev, int n) {
     unsigned long long* hd = (unsigned long long*)(c->staging_dev + kStagingBytes - 64);
-    HIP_TRY(launch_publish(dev, hd, 1, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    *out = *h;
+    volatile unsigned long long* hflag = (volatile unsigned long long*)(c->staging + kStagingBytes - 56);
+    unsigned long long* dflag = (unsigned long long*)(c->staging_dev + kStagingBytes - 56);
+    const unsigned long long seq = ++c->publish_seq;
+    HIP_TRY(launch_publish(dev, hd, n, dflag, seq, c->stream));
+    const auto t0 = std::chrono::steady_clock::now();
+    for (unsigned spins = 0; *hflag != seq; ++spins) {
+        if ((spins & 255) == 255 && std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(5)) {
+            HIP_TRY(hipStreamSynchronize(c->stream));
+            if (*hflag != seq) return fail(c, MSC_E_HIP, "stage counter was not published");
+            break;
+        }
+        __builtin_ia32_pause();
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
     return MSC_OK;
 }
+
+msc_status read_counter(Lane* c, unsigned long long* dev, uint64_t* out) {
+    MSC_TRY(publish_and_wait(c, dev, 1));
+    *out = *(volatile unsigned long long*)(c->staging + kStagingBytes - 64);
+    return MSC_OK;
+}
+
+// Waits until everything queued on the lane's stream so far has run (results that
+// kernels wrote to mapped host memory are then visible).
+msc_status sync_lane(Lane* c) { return publish_and_wait(c, nullptr, 0); }
 
 int64_t isqrt_ceil(int64_t v) {
     int64_t r = 0;
@@ -807,7 +833,7 @@ msc_status pose_check_steps(Lane* c, const msc_scene* sc, const Plan& p, const i
         a.ie0 = p.ie0;
         LAUNCH(MSC_K_POSE, -1, count,
                launch_pose_check(a, (const int32_t*)dq, count, (uint8_t*)dv, (int32_t*)de, c->stream));
-        HIP_TRY(hipStreamSynchronize(c->stream));
+        MSC_TRY(sync_lane(c));
         std::memcpy(valid, hv, (size_t)count);
         if (ends) std::memcpy(ends, he, ebytes);
         return MSC_OK;
@@ -867,8 +893,13 @@ msc_status lane_init(Lane* L, msc_ctx* o, int index, hipStream_t stream, bool ow
     L->ws = base + kLaneReserved;
     L->hi = size - kLaneReserved;
     L->lo = 0;
-    if (hipHostMalloc((void**)&L->staging, kStagingBytes, hipHostMallocMapped) != hipSuccess) return MSC_E_HIP;
+    // coherent: the host polls values that kernels write while the stream runs on
+    if (hipHostMalloc((void**)&L->staging, kStagingBytes, hipHostMallocMapped | hipHostMallocCoherent) !=
+        hipSuccess)
+        return MSC_E_HIP;
     if (hipHostGetDevicePointer((void**)&L->staging_dev, L->staging, 0) != hipSuccess) return MSC_E_HIP;
+    std::memset(L->staging, 0, kStagingBytes);
+    L->publish_seq = 0;
     return MSC_OK;
 }
 
@@ -1059,7 +1090,7 @@ msc_status path_on(Lane* c, const msc_scene* sc, const msc_arm* arm, const int32
                        launch_tube_solve(ta, (const uint8_t*)d_valid, (uint8_t*)d_reach, (uint8_t*)d_t0,
                                          (uint8_t*)d_t1, (int32_t*)d_path, (int32_t*)d_status, c->stream));
             }
-            HIP_TRY(hipStreamSynchronize(c->stream));
+            MSC_TRY(sync_lane(c));
             int32_t ok2 = *(volatile int32_t*)h_status;
             c->stats.attempts++;
             if (ok2) {
