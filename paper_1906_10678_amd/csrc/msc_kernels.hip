@@ -51,29 +51,53 @@ __device__ __forceinline__ bool segment_clear(const GridView& g, const JointView
     return true;
 }
 
-// Same test with every sample load issued before any is checked (one memory round trip;
-// for latency-bound kernels).
+// Same test with every load issued before any is checked (two memory round trips:
+// the sample offsets, then the occupancy words).  The loads are unconditional (an
+// out-of-grid sample reads word 0 and is then rejected), so that they can all be in
+// flight together.
 __device__ __forceinline__ bool segment_clear_all(const GridView& g, const JointView& j, int o, int x, int y,
                                                   int z) {
-    const short4* sw = j.sweep + (size_t)o * j.S;
-    for (int s0 = 0; s0 < j.S; s0 += 8) {
+    if (j.S == 8) {
+        // 8 short4 sample offsets = 4 x 16 bytes (the table rows are 64-byte aligned)
+        const uint4* sw4 = reinterpret_cast<const uint4*>(j.sweep + (size_t)o * 8);
+        uint4 q[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) q[t] = sw4[t];
         uint64_t w[8];
         int bit[8];
         bool in[8];
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
-            in[t] = false;
-            w[t] = 0;
-            bit[t] = 0;
-            if (s0 + t < j.S) {
-                const short4 d = sw[s0 + t];
-                const int px = x + d.x, py = y + d.y, pz = z + d.z;
-                in[t] = (unsigned)px < (unsigned)g.n && (unsigned)py < (unsigned)g.n && (unsigned)pz < (unsigned)g.n;
-                if (in[t]) {
-                    w[t] = g.occ[((size_t)pz * g.n + py) * g.wpr + (px >> 6)];
-                    bit[t] = px & 63;
-                }
-            }
+            const uint32_t xy = (t & 1) ? q[t >> 1].z : q[t >> 1].x;
+            const uint32_t zw = (t & 1) ? q[t >> 1].w : q[t >> 1].y;
+            const int px = x + (int)(int16_t)(xy & 0xffffu);
+            const int py = y + (int)(int16_t)(xy >> 16);
+            const int pz = z + (int)(int16_t)(zw & 0xffffu);
+            in[t] = (unsigned)px < (unsigned)g.n && (unsigned)py < (unsigned)g.n && (unsigned)pz < (unsigned)g.n;
+            const size_t idx = in[t] ? ((size_t)pz * g.n + py) * g.wpr + (px >> 6) : 0;
+            w[t] = g.occ[idx];
+            bit[t] = px & 63;
+        }
+        bool clear = true;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) clear = clear && in[t] && !((w[t] >> bit[t]) & 1ull);
+        return clear;
+    }
+    const short4* sw = j.sweep + (size_t)o * j.S;
+    for (int s0 = 0; s0 < j.S; s0 += 8) {
+        short4 d[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) d[t] = sw[s0 + t < j.S ? s0 + t : 0];
+        uint64_t w[8];
+        int bit[8];
+        bool in[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int px = x + d[t].x, py = y + d[t].y, pz = z + d[t].z;
+            in[t] = (unsigned)px < (unsigned)g.n && (unsigned)py < (unsigned)g.n && (unsigned)pz < (unsigned)g.n;
+            const size_t idx = in[t] ? ((size_t)pz * g.n + py) * g.wpr + (px >> 6) : 0;
+            w[t] = g.occ[idx];
+            bit[t] = px & 63;
         }
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
@@ -565,6 +589,7 @@ hipError_t launch_expand_fwd(const uint64_t* in, uint64_t count, SetView out, Gr
 // outputs whose fastest orientation axis is the joint's axis: the run is set with at
 // most a few masked atomicOr (other outputs: k_expand_bwd_set).
 // ---------------------------------------------------------------------------
+template <int NP>
 __global__ void __launch_bounds__(kBlock) k_expand_bwd(const uint64_t* __restrict__ in, uint64_t count,
                                                        SetView out, GridView g, JointView j, int bx, int by,
                                                        int bz, long long r2, const uint64_t* __restrict__ orows,
@@ -612,22 +637,30 @@ __global__ void __launch_bounds__(kBlock) k_expand_bwd(const uint64_t* __restric
             ++ovf;
             continue;
         }
-        for (int w = 0; w < 4; ++w) {
-            if (!m[w]) continue;
-            uint64_t pos = bit0 + 64ull * w;
-            uint64_t word = pos >> 6;
-            int sh = (int)(pos & 63);
-            uint64_t lo_part = m[w] << sh;
-            uint64_t old = atomicOr((unsigned long long*)&out.words[word], (unsigned long long)lo_part);
-            added += __popcll(lo_part & ~old);
-            if (sh) {
-                uint64_t hi_part = m[w] >> (64 - sh);
-                if (hi_part) {
-                    old = atomicOr((unsigned long long*)&out.words[word + 1], (unsigned long long)hi_part);
-                    added += __popcll(hi_part & ~old);
-                }
-            }
+        // the run as (up to) five word-aligned parts: all atomics are issued before any
+        // result is used, so that they are in flight together
+        const uint64_t word0 = bit0 >> 6;
+        const int sh = (int)(bit0 & 63);
+        uint64_t part[5];
+#pragma unroll
+        for (int w = 0; w < 5; ++w) {
+            const uint64_t cur = w < 4 ? m[w] : 0ull;
+            const uint64_t prev = w > 0 ? m[w - 1] : 0ull;
+            part[w] = (cur << sh) | (sh ? prev >> (64 - sh) : 0ull);
         }
+        // a row of na bits spans at most NP words (NP is fixed per launch from na); only
+        // non-empty parts are sent, and all of them are in flight before the first result
+        // is used (the empty asm statements keep the uses out of the conditional sends)
+        uint64_t old[NP];
+#pragma unroll
+        for (int w = 0; w < NP; ++w) {
+            old[w] = ~0ull;
+            if (part[w]) old[w] = atomicOr((unsigned long long*)&out.words[word0 + w], (unsigned long long)part[w]);
+        }
+#pragma unroll
+        for (int w = 0; w < NP; ++w) asm volatile("" : "+v"(old[w]));
+#pragma unroll
+        for (int w = 0; w < NP; ++w) added += __popcll(part[w] & ~old[w]);
     }
     block_add(added, counter);
     if (ovf) atomicAdd(overflow, ovf);
@@ -685,8 +718,20 @@ hipError_t launch_expand_bwd(const uint64_t* in, uint64_t count, SetView out, Gr
     if (count == 0) return hipSuccess;
     const bool run_dense = out.kind == kDense && ((out.fast_ia != 0) == (j.type == 0));
     if (run_dense) {
-        hipLaunchKernelGGL(k_expand_bwd, dim3(grid_for(count)), dim3(kBlock), 0, st, in, count, out, g, j, bx, by,
-                           bz, r2, orows, counter, overflow);
+        const int np = ((out.na + 63) >> 6) + 1;   // words a row of na bits can touch
+        const dim3 grid(grid_for(count));
+        if (np == 2)
+            hipLaunchKernelGGL(k_expand_bwd<2>, grid, dim3(kBlock), 0, st, in, count, out, g, j, bx, by, bz, r2, orows,
+                               counter, overflow);
+        else if (np == 3)
+            hipLaunchKernelGGL(k_expand_bwd<3>, grid, dim3(kBlock), 0, st, in, count, out, g, j, bx, by, bz, r2, orows,
+                               counter, overflow);
+        else if (np == 4)
+            hipLaunchKernelGGL(k_expand_bwd<4>, grid, dim3(kBlock), 0, st, in, count, out, g, j, bx, by, bz, r2, orows,
+                               counter, overflow);
+        else
+            hipLaunchKernelGGL(k_expand_bwd<5>, grid, dim3(kBlock), 0, st, in, count, out, g, j, bx, by, bz, r2, orows,
+                               counter, overflow);
     } else {
         const int lg = group_log2_for(count, j.hi - j.lo + 1);
         hipLaunchKernelGGL(k_expand_bwd_set, dim3(grid_for(count << lg)), dim3(kBlock), 0, st, in, count, out, g, j,

@@ -1165,7 +1165,7 @@ msc_status msc_ctx_create(int device, void* hip_stream, void* dev_workspace, uin
     o->ws_bytes = ws_bytes;
     uint64_t table_bytes = std::min<uint64_t>(256ull << 20, ws_bytes / 8) & ~(kAlign - 1);
     o->table_lo = ws_bytes - table_bytes;
-    o->table_top = ws_bytes;
+    o->table_top = ws_bytes & ~(kAlign - 1);   // keeps table rows aligned
     msc_status st = layout_lanes(o, 0);
     if (st != MSC_OK) {
         lane_free(o->control);
