@@ -488,37 +488,51 @@ hipError_t launch_publish(const unsigned long long* src, unsigned long long* dst
 // Seeds: F_0 = {(base, o0)} if the base is free; B_n = {(target, o) : o in O_n} if
 // the target is free.
 // ---------------------------------------------------------------------------
-__global__ void k_seed_fwd(SetView s, GridView g, int x, int y, int z, int ia, int ie,
+// The seeds also write their state lists (so that the first stages need no compaction).
+__global__ void k_seed_fwd(SetView s, GridView g, int x, int y, int z, int ia, int ie, uint64_t* list,
                            unsigned long long* counter) {
     if (threadIdx.x == 0 && blockIdx.x == 0 && cell_free(g, x, y, z)) {
-        if (set_insert(s, x, y, z, ia, ie) > 0) atomicAdd(counter, 1ull);
+        if (set_insert(s, x, y, z, ia, ie) > 0) {
+            list[0] = pack_key(x, y, z, ia, ie);
+            atomicAdd(counter, 1ull);
+        }
     }
 }
 
 __global__ void k_seed_bwd(SetView s, GridView g, int x, int y, int z, const uint64_t* rows_ie, int prune,
-                           unsigned long long* counter) {
+                           uint64_t* list, unsigned long long* counter) {
     const int na = s.na;
-    unsigned long long added = 0;
-    if (cell_free(g, x, y, z)) {
-        for (int o = blockIdx.x * blockDim.x + threadIdx.x; o < na * na; o += gridDim.x * blockDim.x) {
-            int ia = o / na, ie = o % na;
-            bool ok = !prune || ((rows_ie[ia * 4 + (ie >> 6)] >> (ie & 63)) & 1ull);
-            if (ok && set_insert(s, x, y, z, ia, ie) > 0) ++added;
+    const bool free_cell = cell_free(g, x, y, z);
+    const int lane = threadIdx.x & 63;
+    // a wave-uniform loop: every lane takes part in the ballot that places the keys
+    for (int o0 = (blockIdx.x * blockDim.x + threadIdx.x) & ~63; o0 < na * na; o0 += gridDim.x * blockDim.x) {
+        const int o = o0 + lane;
+        bool ok = false;
+        int ia = 0, ie = 0;
+        if (free_cell && o < na * na) {
+            ia = o / na;
+            ie = o % na;
+            ok = !prune || ((rows_ie[ia * 4 + (ie >> 6)] >> (ie & 63)) & 1ull);
+            ok = ok && set_insert(s, x, y, z, ia, ie) > 0;
         }
+        const uint64_t bal = __ballot(ok);
+        unsigned long long base = 0;
+        if (lane == 0 && bal) base = atomicAdd(counter, (unsigned long long)__popcll(bal));
+        base = __shfl(base, 0, 64);
+        if (ok) list[base + __popcll(bal & ((1ull << lane) - 1))] = pack_key(x, y, z, ia, ie);
     }
-    block_add(added, counter);
 }
 
-hipError_t launch_seed_fwd(SetView s, GridView g, int x, int y, int z, int ia, int ie,
+hipError_t launch_seed_fwd(SetView s, GridView g, int x, int y, int z, int ia, int ie, uint64_t* list,
                            unsigned long long* counter, hipStream_t st) {
-    hipLaunchKernelGGL(k_seed_fwd, dim3(1), dim3(64), 0, st, s, g, x, y, z, ia, ie, counter);
+    hipLaunchKernelGGL(k_seed_fwd, dim3(1), dim3(64), 0, st, s, g, x, y, z, ia, ie, list, counter);
     return hipGetLastError();
 }
 
 hipError_t launch_seed_bwd(SetView s, GridView g, int x, int y, int z, const uint64_t* rows_ie, int prune,
-                           unsigned long long* counter, hipStream_t st) {
+                           uint64_t* list, unsigned long long* counter, hipStream_t st) {
     hipLaunchKernelGGL(k_seed_bwd, dim3(grid_for((uint64_t)s.na * s.na)), dim3(kBlock), 0, st, s, g, x, y, z,
-                       rows_ie, prune, counter);
+                       rows_ie, prune, list, counter);
     return hipGetLastError();
 }
 

@@ -233,15 +233,15 @@ unsigned long long* take_counter(Lane* c) {
     return c->counters + c->next_counter++;
 }
 
-// Counter value on the host: a one-thread kernel stores it into mapped pinned memory.
 // Stage sizes for the host: the publish kernel copies counters into mapped host memory
 // and then bumps a sequence flag, which is polled (a few microseconds after the stage
 // ends) instead of a stream synchronisation; after ~5 ms of polling the stream is
 // synchronised, which also reports a failed launch.
+// n <= 6 counters land at staging[end - 64 ..], the flag at staging[end - 8]
 msc_status publish_and_wait(Lane* c, unsigned long long* dev, int n) {
     unsigned long long* hd = (unsigned long long*)(c->staging_dev + kStagingBytes - 64);
-    volatile unsigned long long* hflag = (volatile unsigned long long*)(c->staging + kStagingBytes - 56);
-    unsigned long long* dflag = (unsigned long long*)(c->staging_dev + kStagingBytes - 56);
+    volatile unsigned long long* hflag = (volatile unsigned long long*)(c->staging + kStagingBytes - 8);
+    unsigned long long* dflag = (unsigned long long*)(c->staging_dev + kStagingBytes - 8);
     const unsigned long long seq = ++c->publish_seq;
     HIP_TRY(launch_publish(dev, hd, n, dflag, seq, c->stream));
     const auto t0 = std::chrono::steady_clock::now();
@@ -548,21 +548,33 @@ msc_status run_reach(Lane* c, const msc_scene* sc, const Plan& p, int want, bool
     std::vector<Box> box(n + 1);
     for (int k = 0; k <= n; ++k) box[k] = stage_box(p, N, R, k);
 
-    // Seeds.
+    // Seeds: both sets with their lists, both counts in one host round trip.
     {
         Box b0{p.base[0], p.base[1], p.base[2], 1, 1, 1};
         MSC_TRY(make_set(c, p, b0, 1, 0, false, F[0]));
-        unsigned long long* ctr = take_counter(c);
-        LAUNCH(MSC_K_SEED, 0, 0, launch_seed_fwd(F[0].view, g, p.base[0], p.base[1], p.base[2], p.ia0, p.ie0, ctr, c->stream));
-        MSC_TRY(read_counter(c, ctr, &F[0].count));
         Box bn{p.target[0], p.target[1], p.target[2], 1, 1, 1};
         int fast = p.type[n - 1] == MSC_YAW ? 1 : 0;
         MSC_TRY(make_set(c, p, bn, (uint64_t)na * na, fast, true, B[n]));
-        ctr = take_counter(c);
-        LAUNCH(MSC_K_SEED, n, 0,
-               launch_seed_bwd(B[n].view, g, p.target[0], p.target[1], p.target[2], rows_for(n, 0), p.prune, ctr,
+        void *l0, *ln;
+        MSC_TRY(arena_alloc(c, 8, &l0));
+        MSC_TRY(arena_alloc(c, (uint64_t)na * na * 8, &ln));
+        unsigned long long* ctr = take_counter(c);
+        unsigned long long* ctr2 = take_counter(c);
+        if (!ctr || ctr2 != ctr + 1) return fail(c, MSC_E_CAPACITY, "out of counters");
+        LAUNCH(MSC_K_SEED, 0, 0,
+               launch_seed_fwd(F[0].view, g, p.base[0], p.base[1], p.base[2], p.ia0, p.ie0, (uint64_t*)l0, ctr,
                                c->stream));
-        MSC_TRY(read_counter(c, ctr, &B[n].count));
+        LAUNCH(MSC_K_SEED, n, 0,
+               launch_seed_bwd(B[n].view, g, p.target[0], p.target[1], p.target[2], rows_for(n, 0), p.prune,
+                               (uint64_t*)ln, ctr2, c->stream));
+        MSC_TRY(publish_and_wait(c, ctr, 2));
+        const volatile unsigned long long* h = (const volatile unsigned long long*)(c->staging + kStagingBytes - 64);
+        F[0].count = h[0];
+        B[n].count = h[1];
+        F[0].list = (uint64_t*)l0;
+        F[0].listed = true;
+        B[n].list = (uint64_t*)ln;
+        B[n].listed = true;
     }
     bool empty = F[0].count == 0 || B[n].count == 0;
     int kf = 0, kb = n;
