@@ -131,11 +131,18 @@ struct TubeArgs {
     uint64_t slab;             // (2r+1)^n cells per waypoint
 };
 hipError_t launch_tube_valid(const TubeArgs& a, uint8_t* valid, hipStream_t st);
-// Bit-parallel search for small frames: LDS bytes it needs (0 = not applicable), and
-// the launch (validity bits + dynamic program + backward choice in one block).
-size_t tube_bits_lds(const TubeArgs& a);
-hipError_t launch_tube_bits(const TubeArgs& a, uint64_t* vbits, int32_t* path, int32_t* status,
-                            hipStream_t st);
+// Bit-parallel search in the blocked frame layout: the plan (lds == 0: does not apply),
+// then the launch (validity bits + dynamic program + backward choice in one block).
+// vbits and rbits hold (W + 1) * nw words each.
+struct TubeBlk {
+    int q, no, b;              // inner joints, outer joints, words per block
+    uint32_t Bq, nblk;         // cells per block (B^q), blocks per frame (B^no)
+    uint64_t nw;               // words per frame
+    size_t lds;                // dynamic LDS bytes
+};
+TubeBlk tube_blk_plan(const TubeArgs& a);
+hipError_t launch_tube_bits(const TubeArgs& a, const TubeBlk& t, uint64_t* vbits, uint64_t* rbits, int32_t* path,
+                            int32_t* status, hipStream_t st);
 hipError_t launch_tube_solve(const TubeArgs& a, const uint8_t* valid, uint8_t* reach, uint8_t* tmp0,
                              uint8_t* tmp1, int32_t* path, int32_t* status, hipStream_t st);
 

@@ -1348,7 +1348,7 @@ __device__ __forceinline__ bool fk_step(const TubeArgs& a, int k, int qk, FkStat
     return ok;
 }
 
-__global__ void k_tube_valid_tree(TubeArgs a, int L, uint8_t* vbytes, uint64_t* vbits, uint32_t nw) {
+__global__ void k_tube_valid_tree(TubeArgs a, int L, uint8_t* vbytes, uint64_t* vbits, TubeBlk tb) {
     const int n = a.n, B = 2 * a.r + 1, np = n - L;
     uint32_t P = 1, BL = 1;
     for (int k = 0; k < np; ++k) P *= (uint32_t)B;
@@ -1396,8 +1396,13 @@ __global__ void k_tube_valid_tree(TubeArgs a, int L, uint8_t* vbytes, uint64_t* 
             uint8_t* out = vbytes + (uint64_t)w * a.slab + cell0;
             for (uint32_t l = 0; l < BL; ++l) out[l] = (uint8_t)((bits >> l) & 1u);
         } else if (bits) {
-            const uint64_t word = (uint64_t)w * nw + (cell0 >> 6);
-            const int sh = (int)(cell0 & 63);
+            // blocked layout: cell c is bit (c / Bq) 64 b + c % Bq of its frame (L <= q, so
+            // the completions of one prefix lie in one block)
+            const uint32_t blk = (uint32_t)cell0 / tb.Bq;
+            const uint32_t v0 = (uint32_t)cell0 - blk * tb.Bq;
+            const uint64_t pos = ((uint64_t)w * tb.nw + (uint64_t)blk * tb.b) * 64 + v0;
+            const uint64_t word = pos >> 6;
+            const int sh = (int)(pos & 63);
             atomicOr((unsigned long long*)&vbits[word], (unsigned long long)((uint64_t)bits << sh));
             if (sh + (int)BL > 64) atomicOr((unsigned long long*)&vbits[word + 1], (unsigned long long)((uint64_t)bits >> (64 - sh)));
         }
@@ -1426,7 +1431,7 @@ uint64_t tube_prefix_threads(const TubeArgs& a, int L) {
 hipError_t launch_tube_valid(const TubeArgs& a, uint8_t* valid, hipStream_t st) {
     const int L = tube_leaf_joints(a);
     hipLaunchKernelGGL(k_tube_valid_tree, dim3(grid_for(tube_prefix_threads(a, L))), dim3(kBlock), 0, st, a, L, valid,
-                       (uint64_t*)nullptr, 0u);
+                       (uint64_t*)nullptr, TubeBlk{});
     return hipGetLastError();
 }
 
@@ -1649,155 +1654,215 @@ __global__ void __launch_bounds__(kTubeThreads) k_tube_trace(TubeArgs a, const u
 }
 
 // ---------------------------------------------------------------------------
-// Bit-parallel tube search for small frames.  A frame is a bitset of B^n cells (bit c
-// of word c/64); the dilation of one joint is the OR over t in [sh-delta, sh+delta]
-// of the frame shifted by t cell strides, masked to the cells whose digit stays in
-// range (masks precomputed in LDS); the whole dynamic program runs in one block.
+// Bit-parallel tube search.  A frame is a bitset in a blocked layout: the last q joints
+// (inner, B^q <= 128 cells) form a block of b = 1 or 2 words; cell (u, v), u the index
+// of the outer digits and v of the inner ones, is bit u*64b + v.  Along an outer joint
+// a shift by t cells is a move of whole blocks, kept where the block's digit stays in
+// range (digits from a table in LDS); along an inner joint it is a shift inside the
+// block, masked by a pattern that every block shares.  Two frames alternate in LDS; the
+// reachable sets R_w go to global memory for the backward choice.  One block runs the
+// whole dynamic program.
 // ---------------------------------------------------------------------------
-constexpr int kBitThreads = 256;
-constexpr int kBitMaxB = 9;      // frame edge 2r+1 of the bit-parallel search (r <= 4)
-constexpr size_t kBitLdsMax = 150 * 1024;   // dynamic LDS of the search (a CU has 160 KiB)
+constexpr int kBlkThreads = 1024;
+constexpr int kBlkMaxB = 11;                  // frame edge 2r+1 (r <= 5)
+constexpr int kBlkPatterns = 24;              // q (B + 1) digit-at-least patterns
+constexpr int kBlkLevels = 16;                // inner L1 levels q r + 1
+constexpr size_t kBlkLdsMax = 150 * 1024;     // dynamic LDS (a CU has 160 KiB)
 
-// bits of `src` shifted so that bit c of the result is bit c + x of src (x may be < 0);
-// |64 i + x| < 2^31 for the frame sizes used here
-__device__ __forceinline__ uint64_t shifted_word(const uint64_t* src, int nw, int i, int x) {
-    const int X = 64 * i + x;
-    const int j = X >> 6;          // floor division (arithmetic shift)
-    const int u = X & 63;
-    const uint64_t lo = (j >= 0 && j < nw) ? src[j] : 0ull;
-    const uint64_t hi = (j + 1 >= 0 && j + 1 < nw) ? src[j + 1] : 0ull;
-    return u ? ((lo >> u) | (hi << (64 - u))) : lo;
+__host__ __device__ inline size_t align8(size_t v) { return (v + 7) & ~(size_t)7; }
+
+TubeBlk tube_blk_plan(const TubeArgs& a) {
+    TubeBlk t{};
+    const int B = 2 * a.r + 1;
+    if (a.n < 1 || B > kBlkMaxB) return t;
+    int q = 0;
+    uint32_t Bq = 1;
+    while (q < a.n && Bq * (uint32_t)B <= 128u) {
+        Bq *= (uint32_t)B;
+        ++q;
+    }
+    if (q < 1 || q * (B + 1) > kBlkPatterns || q * a.r + 1 > kBlkLevels) return t;
+    uint64_t nblk = 1;
+    for (int k = 0; k < a.n - q; ++k) {
+        nblk *= (uint64_t)B;
+        if (nblk > (1u << 20)) return TubeBlk{};
+    }
+    t.q = q;
+    t.no = a.n - q;
+    t.Bq = Bq;
+    t.b = Bq > 64 ? 2 : 1;
+    t.nblk = (uint32_t)nblk;
+    t.nw = nblk * (uint64_t)t.b;
+    const size_t bytes = 2 * t.nw * 8 + align8(nblk * (uint64_t)t.no) + align8(nblk);
+    t.lds = bytes <= kBlkLdsMax ? bytes : 0;
+    return t;
+}
+
+// (x1:x0) >> s and << s for 0 <= s < 128
+__device__ __forceinline__ void shr128(uint64_t x0, uint64_t x1, int s, uint64_t& y0, uint64_t& y1) {
+    if (s == 0) {
+        y0 = x0;
+        y1 = x1;
+    } else if (s < 64) {
+        y0 = (x0 >> s) | (x1 << (64 - s));
+        y1 = x1 >> s;
+    } else {
+        y0 = x1 >> (s - 64);
+        y1 = 0;
+    }
+}
+
+__device__ __forceinline__ void shl128(uint64_t x0, uint64_t x1, int s, uint64_t& y0, uint64_t& y1) {
+    if (s == 0) {
+        y0 = x0;
+        y1 = x1;
+    } else if (s < 64) {
+        y0 = x0 << s;
+        y1 = (x1 << s) | (x0 >> (64 - s));
+    } else {
+        y0 = 0;
+        y1 = x0 << (s - 64);
+    }
 }
 
 template <int DL>
-__global__ void __launch_bounds__(kBitThreads) k_tube_bits(TubeArgs a, uint32_t nw_u, const uint64_t* vbits,
-                                                           int32_t* path, int32_t* status) {
+__global__ void __launch_bounds__(kBlkThreads) k_tube_blk(TubeArgs a, TubeBlk tb, const uint64_t* vbits,
+                                                          uint64_t* rbits, int32_t* path, int32_t* status) {
     extern __shared__ uint64_t sm[];
-    const int nw = (int)nw_u;
-    const int n = a.n, B = 2 * a.r + 1, dl = DL > 0 ? DL : a.delta, r = a.r;
-    const int nlev = n * r + 1;                     // L1 distances to the guide: 0 .. n r
-    uint64_t* fa = sm;                              // two frames, used in turn
+    const int n = a.n, B = 2 * a.r + 1, r = a.r, dl = DL > 0 ? DL : a.delta;
+    const int no = tb.no, q = tb.q, b = tb.b;
+    const uint32_t nblk = tb.nblk, Bq = tb.Bq;
+    const int nw = (int)tb.nw;
+    uint64_t* fa = sm;
     uint64_t* fb = sm + nw;
-    uint64_t* ge = sm + 2 * nw;                     // [k][v][word], v = 0..B: cells whose digit k is >= v
-    uint64_t* lvl = ge + (size_t)n * (B + 1) * nw;  // [l][word]: cells at L1 distance l from the guide
-    uint64_t* rbits = lvl + (size_t)(n * r + 1) * nw;   // [w][word]: the reachable sets R_0 .. R_W
-    __shared__ uint32_t stride[kMaxDof];
+    uint8_t* dig = reinterpret_cast<uint8_t*>(sm + 2 * nw);       // [block][outer joint]
+    uint8_t* l1o = dig + align8((size_t)nblk * no);                // outer L1 distance per block
+    __shared__ uint32_t sblk[kMaxDof], scell[kMaxDof];
+    __shared__ unsigned long long pge[kBlkPatterns * 2];           // [inner joint][v <= B][word]
+    __shared__ unsigned long long plv[kBlkLevels * 2];             // [inner L1 level][word]
     __shared__ int shw[kMaxDof], dlo[kMaxDof], dhi[kMaxDof], flo[kMaxDof], qcur[kMaxDof];
-    __shared__ unsigned long long best_part[kBitThreads / 64];
+    __shared__ unsigned long long best_part[kBlkThreads / 64];
     __shared__ int fail;
     const int tid = threadIdx.x;
-    const uint32_t slab = (uint32_t)a.slab;
+    const int nthr = (int)blockDim.x;    // a multiple of 64, fewer for small frames
     if (tid == 0) {
-        tube_strides(a, stride);
+        uint32_t st = 1;
+        for (int k = n - 1; k >= no; --k) {
+            scell[k] = st;
+            st *= (uint32_t)B;
+        }
+        st = 1;
+        for (int k = no - 1; k >= 0; --k) {
+            sblk[k] = st;
+            st *= (uint32_t)B;
+        }
         fail = 0;
     }
     __syncthreads();
-    // Digit masks from runs of equal digits (a run of joint k is stride[k] cells long),
-    // kept as "digit >= v" masks so that any digit range is two loads; and the L1
-    // distance |d - r| summed over the joints as a bit-sliced 5-plane counter
-    // (n r <= 31), from which the level masks are read off.
-    for (int i = tid; i < nw; i += kBitThreads) {
-        const uint32_t c0 = 64u * (uint32_t)i;
-        const uint32_t cnt = slab > c0 ? slab - c0 : 0u;
-        const uint64_t live = cnt >= 64 ? ~0ull : ((1ull << cnt) - 1);
-        uint64_t p0 = 0, p1 = 0, p2 = 0, p3 = 0, p4 = 0;
-        for (int k = 0; k < n; ++k) {
-            const uint32_t sk = stride[k];
-            const uint32_t q = c0 / sk;
-            uint32_t d = q % (uint32_t)B;
-            uint32_t len = sk - (c0 - q * sk);
-            uint64_t mk[kBitMaxB];
-#pragma unroll
-            for (int v = 0; v < kBitMaxB; ++v) mk[v] = 0;
-            for (uint32_t b = 0; b < 64;) {
-                const uint32_t l = len < 64 - b ? len : 64 - b;
-                const uint64_t run = (l >= 64 ? ~0ull : ((1ull << l) - 1)) << b;
-#pragma unroll
-                for (int v = 0; v < kBitMaxB; ++v)
-                    if ((uint32_t)v == d) mk[v] |= run;
-                b += l;
-                len = sk;
-                d = d + 1 == (uint32_t)B ? 0 : d + 1;
-            }
-            uint64_t u0 = 0, u1 = 0, u2 = 0, suffix = 0;
-            uint64_t* gk = ge + (size_t)k * (B + 1) * nw;
-            gk[(size_t)B * nw + i] = 0;
-#pragma unroll
-            for (int v = kBitMaxB - 1; v >= 0; --v) {
-                if (v < B) {
-                    const uint64_t m = mk[v] & live;
-                    suffix |= m;
-                    gk[(size_t)v * nw + i] = suffix;
-                    const int u = v > r ? v - r : r - v;
-                    if (u & 1) u0 |= m;
-                    if (u & 2) u1 |= m;
-                    if (u & 4) u2 |= m;
-                }
-            }
-            const uint64_t c1 = p0 & u0;
-            p0 ^= u0;
-            const uint64_t s1 = p1 ^ u1, c2 = (p1 & u1) | (c1 & s1);
-            p1 = s1 ^ c1;
-            const uint64_t s2 = p2 ^ u2, c3 = (p2 & u2) | (c2 & s2);
-            p2 = s2 ^ c2;
-            const uint64_t c4 = p3 & c3;
-            p3 ^= c3;
-            p4 ^= c4;
+    // inner patterns, one thread per inner cell c: its bit goes into "digit of inner joint
+    // ki >= v" for v <= its digit, and into its inner L1 level
+    for (int i = tid; i < 2 * (kBlkPatterns + kBlkLevels); i += nthr) {
+        if (i < 2 * kBlkPatterns) pge[i] = 0; else plv[i - 2 * kBlkPatterns] = 0;
+    }
+    __syncthreads();
+    for (uint32_t c = tid; c < Bq; c += nthr) {
+        const int word = c >> 6;
+        const unsigned long long bit = 1ull << (c & 63);
+        int d1 = 0;
+        for (int ki = 0; ki < q; ++ki) {
+            const int d = (int)((c / scell[no + ki]) % (uint32_t)B);
+            d1 += d > r ? d - r : r - d;
+            for (int v = 0; v <= d; ++v) atomicOr(&pge[(ki * (B + 1) + v) * 2 + word], bit);
         }
-        for (int l = 0; l < nlev; ++l) {
-            uint64_t m = live;
-            m &= (l & 1) ? p0 : ~p0;
-            m &= (l & 2) ? p1 : ~p1;
-            m &= (l & 4) ? p2 : ~p2;
-            m &= (l & 8) ? p3 : ~p3;
-            m &= (l & 16) ? p4 : ~p4;
-            lvl[(size_t)l * nw + i] = m;
+        atomicOr(&plv[d1 * 2 + word], bit);
+    }
+    // outer digits and L1 distance per block; R_0 = {start}
+    for (uint32_t u = tid; u < nblk; u += nthr) {
+        int d1 = 0;
+        for (int k = 0; k < no; ++k) {
+            const int d = (int)((u / sblk[k]) % (uint32_t)B);
+            dig[(size_t)u * no + k] = (uint8_t)d;
+            d1 += d > r ? d - r : r - d;
         }
-        fa[i] = vbits[i];           // R_0 = {start}
+        l1o[u] = (uint8_t)d1;
+    }
+    for (int i = tid; i < nw; i += nthr) {
+        fa[i] = vbits[i];
         rbits[i] = vbits[i];
     }
     __syncthreads();
     // Forward: R_w = valid_w AND the delta-dilation of R_{w-1}, one joint at a time.
-    // Along joint k, cell c takes the source cell whose digit is d + t, t = shift + e,
-    // when 0 <= d + t < B, i.e. digit in [-t, B-1-t]: ge[max(0,-t)] & ~ge[min(B,B-t)].
-    // The two frames alternate as source and destination (one barrier per pass).
-    constexpr int kPer = (16384 / 64 + kBitThreads - 1) / kBitThreads;
     uint64_t* src = fa;
     uint64_t* dst = fb;
     for (int w = 1; w <= a.W; ++w) {
         if (tid < n) shw[tid] = guide_at(a, w, tid) - guide_at(a, w - 1, tid);
-        uint64_t vw[kPer];
-        {
-            int j = 0;
-            for (int i = tid; i < nw; i += kBitThreads, ++j) vw[j] = vbits[(size_t)w * nw + i];
-        }
         __syncthreads();
         for (int k = 0; k < n; ++k) {
             const int sh = shw[k];
-            const int s = (int)stride[k];
-            const uint64_t* gk = ge + (size_t)k * (B + 1) * nw;
-            int j = 0;
-            for (int i = tid; i < nw; i += kBitThreads, ++j) {
-                uint64_t acc = 0;
-                auto take = [&](int e) {
-                    const int t = sh + e;
-                    const int vlo = t < 0 ? -t : 0;
-                    const int vend = t > 0 ? B - t : B;      // exclusive
-                    if (vlo >= vend) return;
-                    const uint64_t m = gk[(size_t)vlo * nw + i] & ~gk[(size_t)vend * nw + i];
-                    acc |= shifted_word(src, nw, i, t * s) & m;
-                };
-                if constexpr (DL > 0) {
+            if (k < no) {
+                // outer joint: whole blocks move by t * S blocks
+                const int S = (int)sblk[k];
+                for (uint32_t u = tid; u < nblk; u += nthr) {
+                    const int d = dig[(size_t)u * no + k];
+                    uint64_t a0 = 0, a1 = 0;
+                    auto take = [&](int e) {
+                        const int t = sh + e;
+                        if (d + t < 0 || d + t >= B) return;
+                        const size_t from = ((size_t)u + (ptrdiff_t)t * S) * (size_t)b;
+                        a0 |= src[from];
+                        if (b == 2) a1 |= src[from + 1];
+                    };
+                    if constexpr (DL > 0) {
 #pragma unroll
-                    for (int e = -DL; e <= DL; ++e) take(e);
-                } else {
-                    for (int e = -dl; e <= dl; ++e) take(e);
+                        for (int e = -DL; e <= DL; ++e) take(e);
+                    } else {
+                        for (int e = -dl; e <= dl; ++e) take(e);
+                    }
+                    dst[(size_t)u * b] = a0;
+                    if (b == 2) dst[(size_t)u * b + 1] = a1;
                 }
-                if (k == n - 1) {
-                    acc &= vw[j];
-                    rbits[(size_t)w * nw + i] = acc;
+            } else {
+                // inner joint: a shift by t * s cells inside every block
+                const int ki = k - no;
+                const int s1 = (int)scell[k];
+                const bool last = k == n - 1;
+                for (uint32_t u = tid; u < nblk; u += nthr) {
+                    const size_t i0 = (size_t)u * b;
+                    const uint64_t x0 = src[i0], x1 = b == 2 ? src[i0 + 1] : 0ull;
+                    uint64_t a0 = 0, a1 = 0;
+                    auto take = [&](int e) {
+                        const int t = sh + e;
+                        const int vlo = t < 0 ? -t : 0;
+                        const int vend = t > 0 ? B - t : B;        // exclusive
+                        if (vlo >= vend) return;
+                        const int lo_i = (ki * (B + 1) + vlo) * 2, hi_i = (ki * (B + 1) + vend) * 2;
+                        const uint64_t m0 = pge[lo_i] & ~pge[hi_i], m1 = pge[lo_i + 1] & ~pge[hi_i + 1];
+                        uint64_t y0, y1;
+                        if (t >= 0)
+                            shr128(x0, x1, t * s1, y0, y1);
+                        else
+                            shl128(x0, x1, -t * s1, y0, y1);
+                        a0 |= y0 & m0;
+                        a1 |= y1 & m1;
+                    };
+                    if constexpr (DL > 0) {
+#pragma unroll
+                        for (int e = -DL; e <= DL; ++e) take(e);
+                    } else {
+                        for (int e = -dl; e <= dl; ++e) take(e);
+                    }
+                    if (last) {
+                        const size_t g0 = (size_t)w * nw + i0;
+                        a0 &= vbits[g0];
+                        rbits[g0] = a0;
+                        if (b == 2) {
+                            a1 &= vbits[g0 + 1];
+                            rbits[g0 + 1] = a1;
+                        }
+                    }
+                    dst[i0] = a0;
+                    if (b == 2) dst[i0 + 1] = a1;
                 }
-                dst[i] = acc;
             }
             __syncthreads();
             uint64_t* tmp = src;
@@ -1806,44 +1871,65 @@ __global__ void __launch_bounds__(kBitThreads) k_tube_bits(TubeArgs a, uint32_t 
         }
     }
     // the goal: every digit = r
-    uint32_t gcell = 0;
-    for (int k = 0; k < n; ++k) gcell += (uint32_t)r * stride[k];
-    if (!((src[gcell >> 6] >> (gcell & 63)) & 1ull)) {
-        if (tid == 0) *status = 0;
-        return;
+    {
+        uint32_t ug = 0, vg = 0;
+        for (int k = 0; k < no; ++k) ug += (uint32_t)r * sblk[k];
+        for (int k = no; k < n; ++k) vg += (uint32_t)r * scell[k];
+        const uint64_t word = src[(size_t)ug * b + (vg >> 6)];
+        if (!((word >> (vg & 63)) & 1ull)) {
+            if (tid == 0) *status = 0;
+            return;
+        }
     }
     if (tid < n) {
         qcur[tid] = a.goal[tid];
         path[a.W * n + tid] = a.goal[tid];
     }
-    // Backward choice: the reachable cells of frame w-1 whose digits lie within delta of
-    // the current pose (an AND over joints of digit-range masks); the smallest L1
-    // distance to the guide is the first level with a hit, ties by the smallest cell.
+    // Backward choice: among the reachable cells of frame w-1 whose digits lie within
+    // delta of the current pose, the smallest L1 distance to the guide, ties by the
+    // smallest cell (u Bq + v orders poses lexicographically).
     for (int w = a.W; w >= 1; --w) {
         if (tid < n) {
             const int f = guide_at(a, w - 1, tid) - r;
             const int lo = qcur[tid] - dl - f, hi = qcur[tid] + dl - f;
             flo[tid] = f;
             dlo[tid] = lo < 0 ? 0 : lo;
-            dhi[tid] = hi > B - 1 ? B : hi + 1;   // exclusive
+            dhi[tid] = hi > B - 1 ? B - 1 : hi;
         }
         __syncthreads();
+        uint64_t ib0 = Bq >= 64 ? ~0ull : ((1ull << Bq) - 1);
+        uint64_t ib1 = Bq > 64 ? (Bq >= 128 ? ~0ull : ((1ull << (Bq - 64)) - 1)) : 0ull;
+        for (int ki = 0; ki < q; ++ki) {
+            const int lo = dlo[no + ki], he = dhi[no + ki] + 1;
+            if (lo >= he) {
+                ib0 = ib1 = 0;
+                break;
+            }
+            const int lo_i = (ki * (B + 1) + lo) * 2, hi_i = (ki * (B + 1) + he) * 2;
+            ib0 &= pge[lo_i] & ~pge[hi_i];
+            ib1 &= pge[lo_i + 1] & ~pge[hi_i + 1];
+        }
         const uint64_t* R = rbits + (size_t)(w - 1) * nw;
         unsigned long long best = ~0ull;
-        for (int i = tid; i < nw; i += kBitThreads) {
-            uint64_t m0 = R[i];
-            for (int k = 0; k < n; ++k) {
-                const int lo = dlo[k], he = dhi[k];
-                const uint64_t* gk = ge + (size_t)k * (B + 1) * nw;
-                m0 &= lo < he ? (gk[(size_t)lo * nw + i] & ~gk[(size_t)he * nw + i]) : 0ull;
-            }
-            if (m0) {
-                for (int l = 0; l < nlev; ++l) {
-                    const uint64_t m = m0 & lvl[(size_t)l * nw + i];
-                    if (m) {
-                        const unsigned long long key =
-                            ((unsigned long long)l << 40) |
-                            (64ull * (uint64_t)i + (uint64_t)(__ffsll((unsigned long long)m) - 1));
+        if (ib0 | ib1) {
+            for (uint32_t u = tid; u < nblk; u += nthr) {
+                bool in = true;
+                for (int k = 0; k < no; ++k) {
+                    const int d = dig[(size_t)u * no + k];
+                    in = in && d >= dlo[k] && d <= dhi[k];
+                }
+                if (!in) continue;
+                const uint64_t m0 = R[(size_t)u * b] & ib0;
+                const uint64_t m1 = b == 2 ? (R[(size_t)u * b + 1] & ib1) : 0ull;
+                if (!(m0 | m1)) continue;
+                const unsigned long long lo1 = l1o[u];
+                for (int l = 0; l <= q * r; ++l) {
+                    const uint64_t h0 = m0 & plv[l * 2], h1 = m1 & plv[l * 2 + 1];
+                    if (h0 | h1) {
+                        const uint32_t v = h0 ? (uint32_t)(__ffsll((unsigned long long)h0) - 1)
+                                              : 64u + (uint32_t)(__ffsll((unsigned long long)h1) - 1);
+                        const unsigned long long key = ((lo1 + (unsigned long long)l) << 40) |
+                                                       ((unsigned long long)u * Bq + v);
                         best = key < best ? key : best;
                         break;
                     }
@@ -1857,15 +1943,16 @@ __global__ void __launch_bounds__(kBitThreads) k_tube_bits(TubeArgs a, uint32_t 
         if ((tid & 63) == 0) best_part[tid >> 6] = best;
         __syncthreads();
         if (tid < n) {
-            unsigned long long b = ~0ull;
-            for (int q = 0; q < kBitThreads / 64; ++q) b = best_part[q] < b ? best_part[q] : b;
-            if (b == ~0ull) {
+            unsigned long long bb = ~0ull;
+            for (int i = 0; i < nthr / 64; ++i) bb = best_part[i] < bb ? best_part[i] : bb;
+            if (bb == ~0ull) {
                 if (tid == 0) fail = 1;
             } else {
-                const uint32_t c = (uint32_t)(b & ((1ull << 40) - 1));
-                const int qk = flo[tid] + (int)((c / stride[tid]) % (uint32_t)B);
-                qcur[tid] = qk;
-                path[(w - 1) * n + tid] = qk;
+                const uint32_t c = (uint32_t)(bb & ((1ull << 40) - 1));
+                const uint32_t u = c / Bq, v = c - u * Bq;
+                const int d = tid < no ? (int)dig[(size_t)u * no + tid] : (int)((v / scell[tid]) % (uint32_t)B);
+                qcur[tid] = flo[tid] + d;
+                path[(w - 1) * n + tid] = qcur[tid];
             }
         }
         __syncthreads();
@@ -1874,40 +1961,33 @@ __global__ void __launch_bounds__(kBitThreads) k_tube_bits(TubeArgs a, uint32_t 
     if (tid == 0) *status = fail ? 0 : 1;
 }
 
-// LDS bytes of the bit-parallel search, or 0 when it does not apply.
-size_t tube_bits_lds(const TubeArgs& a) {
-    const int B = 2 * a.r + 1;
-    if (a.slab > 16384 || B > kBitMaxB || a.n * a.r > 31) return 0;
-    const size_t nw = (a.slab + 63) / 64;
-    const size_t frames = 2 + (size_t)a.n * (B + 1) + (size_t)(a.n * a.r + 1) + (size_t)(a.W + 1);
-    const size_t bytes = frames * nw * 8;
-    return bytes <= kBitLdsMax ? bytes : 0;
-}
 template <int DL>
-hipError_t launch_tube_bits_dl(const TubeArgs& a, uint32_t nw, const uint64_t* vbits, int32_t* path,
-                               int32_t* status, hipStream_t st) {
+hipError_t launch_tube_blk_dl(const TubeArgs& a, const TubeBlk& t, const uint64_t* vbits, uint64_t* rbits,
+                              int32_t* path, int32_t* status, hipStream_t st) {
     static std::once_flag once;
     static hipError_t attr = hipSuccess;
     std::call_once(once, [] {
-        attr = hipFuncSetAttribute((const void*)k_tube_bits<DL>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)kBitLdsMax);
+        attr = hipFuncSetAttribute((const void*)k_tube_blk<DL>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)kBlkLdsMax);
     });
     if (attr != hipSuccess) return attr;
-    hipLaunchKernelGGL(k_tube_bits<DL>, dim3(1), dim3(kBitThreads), tube_bits_lds(a), st, a, nw, vbits, path, status);
+    // threads: one per block of the frame, rounded to waves (barriers of idle waves cost)
+    const uint32_t threads = std::min<uint32_t>(kBlkThreads, std::max<uint32_t>(64u, (t.nblk + 63u) & ~63u));
+    hipLaunchKernelGGL(k_tube_blk<DL>, dim3(1), dim3(threads), t.lds, st, a, t, vbits, rbits, path, status);
     return hipGetLastError();
 }
 
-hipError_t launch_tube_bits(const TubeArgs& a, uint64_t* vbits, int32_t* path, int32_t* status, hipStream_t st) {
-    const uint32_t nw = (uint32_t)((a.slab + 63) / 64);
-    const int L = tube_leaf_joints(a);
-    hipError_t e = launch_fill(vbits, (uint64_t)(a.W + 1) * nw, 0ull, st);
+hipError_t launch_tube_bits(const TubeArgs& a, const TubeBlk& t, uint64_t* vbits, uint64_t* rbits, int32_t* path,
+                            int32_t* status, hipStream_t st) {
+    const int L = std::min(tube_leaf_joints(a), t.q);
+    hipError_t e = launch_fill(vbits, (uint64_t)(a.W + 1) * t.nw, 0ull, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_tube_valid_tree, dim3(grid_for(tube_prefix_threads(a, L))), dim3(kBlock), 0, st, a, L,
-                       (uint8_t*)nullptr, vbits, nw);
+                       (uint8_t*)nullptr, vbits, t);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (a.delta == 1) return launch_tube_bits_dl<1>(a, nw, vbits, path, status, st);
-    if (a.delta == 2) return launch_tube_bits_dl<2>(a, nw, vbits, path, status, st);
-    return launch_tube_bits_dl<0>(a, nw, vbits, path, status, st);
+    if (a.delta == 1) return launch_tube_blk_dl<1>(a, t, vbits, rbits, path, status, st);
+    if (a.delta == 2) return launch_tube_blk_dl<2>(a, t, vbits, rbits, path, status, st);
+    return launch_tube_blk_dl<0>(a, t, vbits, rbits, path, status, st);
 }
 
 hipError_t launch_tube_solve(const TubeArgs& a, const uint8_t* valid, uint8_t* reach, uint8_t* tmp0,

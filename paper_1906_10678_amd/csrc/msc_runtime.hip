@@ -1084,13 +1084,16 @@ msc_status path_on(Lane* c, const msc_scene* sc, const msc_arm* arm, const int32
             MSC_TRY(host_area(c, path.size() * 4, &h_path, &d_path));
             MSC_TRY(host_area(c, 4, &h_status, &d_status));
             *(volatile int32_t*)h_status = 0;
-            if (tube_bits_lds(ta)) {
-                // small frames: bit-parallel search in one block
-                void* d_vbits;
-                uint64_t words = (uint64_t)(waypoints + 1) * ((slab + 63) / 64);
+            const TubeBlk tb = tube_blk_plan(ta);
+            if (tb.lds) {
+                // frames that fit LDS: bit-parallel search in one block
+                void *d_vbits, *d_rbits;
+                const uint64_t words = (uint64_t)(waypoints + 1) * tb.nw;
                 MSC_TRY(arena_alloc(c, words * 8, &d_vbits));
+                MSC_TRY(arena_alloc(c, words * 8, &d_rbits));
                 LAUNCH(MSC_K_TUBE_SOLVE, rad, (int64_t)cells,
-                       launch_tube_bits(ta, (uint64_t*)d_vbits, (int32_t*)d_path, (int32_t*)d_status, c->stream));
+                       launch_tube_bits(ta, tb, (uint64_t*)d_vbits, (uint64_t*)d_rbits, (int32_t*)d_path,
+                                        (int32_t*)d_status, c->stream));
             } else {
                 void *d_valid, *d_reach, *d_t0, *d_t1;
                 MSC_TRY(arena_alloc(c, cells, &d_valid));
