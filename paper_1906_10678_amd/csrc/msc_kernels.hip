@@ -1131,7 +1131,7 @@ hipError_t launch_dmark(const uint64_t* flist, uint64_t count, SetView fprev, Se
 // the solutions in lexicographic order; it stops after `want` of them.  One block:
 // the candidates of a node are tested in parallel, one lane per angle.
 // ---------------------------------------------------------------------------
-constexpr int kDfsThreads = 256;
+constexpr int kDfsThreads = 64;      // one wave: barriers cost next to nothing
 
 __global__ void __launch_bounds__(kDfsThreads) k_dfs(DfsArgs a) {
     __shared__ short order[kMaxDof][kMaxNa + 1];
@@ -1170,25 +1170,34 @@ __global__ void __launch_bounds__(kDfsThreads) k_dfs(DfsArgs a) {
     __syncthreads();
     while (true) {
         if (need_eval) {
+            // one wave; lane l takes candidates l, l + 64, ...  The membership probe and
+            // the segment test are both issued (no short cut), so that their loads overlap.
             const int d = depth;
             const JointView J = a.joints[d];
             int x, y, z, ia, ie;
             unpack_key(state[d], x, y, z, ia, ie);
-            bool ok = false;
-            if (tid < olen[d]) {
-                int av = order[d][tid];
-                int ia2 = ia, ie2 = ie;
-                if (J.type == 0)
-                    ia2 = wrap_na(ia + av, na);
-                else
-                    ie2 = wrap_na(ie + av, na);
-                int o = ia2 * na + ie2;
-                short4 dd = J.off[o];
-                uint64_t key = pack_key(x + dd.x, y + dd.y, z + dd.z, ia2, ie2);
-                ok = set_member(a.sets[d + 1], key) && segment_clear_all(a.g, J, o, x, y, z);
+            for (int c0 = 0; c0 < olen[d]; c0 += kDfsThreads) {
+                const int c = c0 + tid;
+                bool ok = false;
+                if (c < olen[d]) {
+                    const int av = order[d][c];
+                    int ia2 = ia, ie2 = ie;
+                    if (J.type == 0)
+                        ia2 = wrap_na(ia + av, na);
+                    else
+                        ie2 = wrap_na(ie + av, na);
+                    const int o = ia2 * na + ie2;
+                    const short4 dd = J.off[o];
+                    const uint64_t key = pack_key(x + dd.x, y + dd.y, z + dd.z, ia2, ie2);
+                    const bool mem = set_member(a.sets[d + 1], key);
+                    const bool clear = segment_clear_all(a.g, J, o, x, y, z);
+                    ok = mem && clear;
+                }
+                const unsigned long long b = __ballot(ok);
+                if (tid == 0) cmask[d][c0 >> 6] = b;
             }
-            unsigned long long b = __ballot(ok);
-            if ((tid & 63) == 0) cmask[d][tid >> 6] = b;
+            if (tid == 0)
+                for (int w = (olen[d] + 63) >> 6; w < 4; ++w) cmask[d][w] = 0;
         }
         __syncthreads();
         if (tid == 0) {
