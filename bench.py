@@ -199,7 +199,7 @@ def traffic_summary(args):
 
     ff, fper = per_kernel(fetch_csv, "FETCH_SIZE")
     wf, wper = per_kernel(write_csv, "WRITE_SIZE")
-    expand = ("msc::k_expand_fwd", "msc::k_expand_bwd", "msc::k_expand_bwd_set")
+    expand = [k for k in fper if is_expansion(k)]
     tot = sum(fper[k][0] * ff * 1024 + wper[k][0] * wf * 1024 for k in expand)
     nl = sum(fper[k][1] for k in expand)
     lines = ["# HBM traffic of the stage expansions, 8-DOF reach + path workload (%d queries)" % alg["queries"], "",
@@ -228,6 +228,13 @@ def traffic_summary(args):
 TRACE_PROFILE = os.path.join(ROOT, "profiles", "expand_trace_c2.md")
 
 
+def is_expansion(kernel_name: str) -> bool:
+    """The stage-expansion kernels (forward, backward, backward into a hash set), whatever
+    their template arguments."""
+    name = kernel_name.split("(")[0]
+    return any(k in name for k in ("k_expand_fwd", "k_expand_bwd"))
+
+
 def trace_summary(args):
     """Kernel-trace summary of a --plain-only run: per-kernel statistics over the whole
     run, and the average duration of the expansion kernels over the plain timed region
@@ -246,9 +253,8 @@ def trace_summary(args):
     stats = collections.defaultdict(list)
     for r in rows:
         stats[r["Kernel_Name"].split("(")[0]].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
-    expand = ("msc::k_expand_fwd", "msc::k_expand_bwd", "msc::k_expand_bwd_set")
     ex = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in rows
-          if r["Kernel_Name"].split("(")[0] in expand]
+          if is_expansion(r["Kernel_Name"])]
     nl = res["roofline"]["launches"]
     tail = ex[-nl:]
     lines = ["# Kernel trace, 8-DOF reach + 16-waypoint path queries (plain phase of bench.py)", "",
