@@ -250,6 +250,28 @@ def test_path_tiny(solver, seed, dof, step, n, W):
             assert np.array_equal(path, rpath), (path, rpath)
 
 
+@pytest.mark.parametrize("seed,dof,delta", [(s, 4, 2) for s in range(3)] + [(s, 3, 3) for s in range(3)] +
+                         [(s, 5, 2) for s in range(2)])
+def test_path_tube_variants(solver, seed, dof, delta):
+    """Joint steps of 2 and 3 per waypoint and tube radii 1..6: the compile-time and
+    run-time step variants of the bit-parallel search, blocked frames with edge 3..11,
+    and the byte path (edge 13) against the oracle."""
+    say("path variants", seed, dof, delta)
+    W = 4
+    arm, sc, rng = tiny_case(100 + seed, dof, 3000, nbox=4, n=24)
+    pf = oracle.pose_fn_for(arm, sc)
+    start, _, _ = synth.first_valid_pose(rng, arm, pf, batch=256)
+    _, target = synth.walk_target(rng, arm, start, W, delta, pf)
+    occ = oracle.raster(sc)
+    scene = solver.scene(sc)
+    for r0, r1 in ((1, 2), (3, 4), (5, 5), (6, 6)):
+        st, path = solver.path(scene, arm, start, target, W, delta, tube_r0=r0, tube_r1=r1)
+        rst, rpath, _ = oracle.plan_path(arm, occ, start, target, W, delta, r0=r0, r1=r1)
+        assert st == rst, (r0, r1, st, rst)
+        if st == msc.OK:
+            assert np.array_equal(path, rpath), (r0, r1, path, rpath)
+
+
 def test_path_zero_waypoints(solver):
     arm, sc, rng = tiny_case(2, 3, 3000)
     pf = oracle.pose_fn_for(arm, sc)
