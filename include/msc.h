@@ -98,12 +98,21 @@ typedef struct {
     int32_t tube_r1;       /* relaxed tube radius after a failure (default 2) */
     int32_t reach_retries; /* reach poses tried by msc_path, in canonical order (default 4) */
     uint32_t flags;        /* MSC_CAPTURE_SETS | MSC_NO_PRUNE */
+    /* Approach cone of the last segment (the cone at the target in Fig 3): only final
+     * orientations (ia, ie) whose direction d = (cos el cos az, cos el sin az, sin el),
+     * az = ia * step, el = ie * step, satisfies d . a >= cos(half) - 1e-9, where a is the
+     * direction of (approach_az_cdeg, approach_el_cdeg), are offered to the backward
+     * pathway.  Evaluated on the host in FP64.  approach_half_cdeg < 0 (the default)
+     * disables the cone; 0..18000 is the half-angle in centidegrees. */
+    int32_t approach_az_cdeg;
+    int32_t approach_el_cdeg;
+    int32_t approach_half_cdeg;
 } msc_opts;
 
 typedef struct msc_ctx msc_ctx;
 typedef struct msc_scene msc_scene;
 
-/* Fill *opts with the defaults {-1, 1, 2, 4, 0}. */
+/* Fill *opts with the defaults {-1, 1, 2, 4, 0, 0, 0, -1} (no approach cone). */
 void msc_opts_default(msc_opts* opts);
 
 /* Create a context on HIP device `device` that enqueues on `hip_stream` (a hipStream_t,

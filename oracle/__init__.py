@@ -47,7 +47,8 @@ class _Arm(ctypes.Structure):
                 ("base", ctypes.c_int32 * 3), ("ia0", ctypes.c_int32), ("ie0", ctypes.c_int32),
                 ("type", ctypes.c_int32 * 16), ("len", ctypes.c_int32 * 16),
                 ("lo", ctypes.c_int32 * 16), ("hi", ctypes.c_int32 * 16),
-                ("ref", ctypes.c_int32 * 16)]
+                ("ref", ctypes.c_int32 * 16),
+                ("app_az_cdeg", ctypes.c_int32), ("app_el_cdeg", ctypes.c_int32), ("app_half_cdeg", ctypes.c_int32)]
 
 
 _lib = None
@@ -94,8 +95,9 @@ def _ptr(a: np.ndarray, ct):
 
 
 def make_arm(arm, lo: Optional[Sequence[int]] = None, hi: Optional[Sequence[int]] = None,
-             ref: Optional[Sequence[int]] = None) -> _Arm:
-    """Oracle arm from a duck-typed arm; lo/hi/ref override the limits (steps)."""
+             ref: Optional[Sequence[int]] = None, approach=None) -> _Arm:
+    """Oracle arm from a duck-typed arm; lo/hi/ref override the limits (steps);
+    approach = (az_cdeg, el_cdeg, half_cdeg) restricts the last segment's direction."""
     n = len(arm.types)
     step = arm.step_cdeg
     a = _Arm()
@@ -112,6 +114,7 @@ def make_arm(arm, lo: Optional[Sequence[int]] = None, hi: Optional[Sequence[int]
         a.lo[k] = int(lo[k]) if lo is not None else int(arm.lo_cdeg[k] // step)
         a.hi[k] = int(hi[k]) if hi is not None else int(arm.hi_cdeg[k] // step)
         a.ref[k] = int(ref[k]) if ref is not None else 0
+    a.app_az_cdeg, a.app_el_cdeg, a.app_half_cdeg = (0, 0, -1) if approach is None else (int(v) for v in approach)
     return a
 
 
@@ -213,11 +216,11 @@ class ReachResult:
 
 
 def reach(arm, occ: np.ndarray, target: Sequence[int], m: Optional[int] = None, want: int = 1,
-          lo=None, hi=None, ref=None, prune: bool = True, keep_sets: bool = True) -> ReachResult:
+          lo=None, hi=None, ref=None, prune: bool = True, keep_sets: bool = True, approach=None) -> ReachResult:
     """Staged forward/backward search with exact per-stage de-duplication; returns
     the first ``want`` solutions in the canonical order and (optionally) every set.
     Keys: (voxel (z*N+y)*N+x) << 16 | ia << 8 | ie."""
-    a = make_arm(arm, lo, hi, ref)
+    a = make_arm(arm, lo, hi, ref, approach)
     n = a.n
     if m is None:
         m = (n + 1) // 2
@@ -255,10 +258,10 @@ def reach(arm, occ: np.ndarray, target: Sequence[int], m: Optional[int] = None, 
         L.orc_free(h)
 
 
-def brute_sets(arm, occ, target, kf: int, kb: int, prune: bool = True, lo=None, hi=None):
+def brute_sets(arm, occ, target, kf: int, kb: int, prune: bool = True, lo=None, hi=None, approach=None):
     """Per-stage sets by exhaustive enumeration of prefixes (forward, stages 0..kf)
     and suffixes (backward, stages kb..n).  Tiny arms only."""
-    a = make_arm(arm, lo, hi)
+    a = make_arm(arm, lo, hi, approach=approach)
     occ = np.ascontiguousarray(occ, np.uint8)
     t = np.ascontiguousarray(np.asarray(target, np.int32))
     L = lib()
@@ -377,7 +380,7 @@ def tube_search(arm, occ, start, goal, W: int, delta: int, r: int, lim_lo, lim_h
 
 
 def plan_path(arm, occ, start, target, W: int, delta: int, r0: int = 1, r1: int = 2, retries: int = 4,
-              m: Optional[int] = None):
+              m: Optional[int] = None, approach=None):
     """Reach pose + path.  The reach search runs with every joint limited to
     start +- W*delta and the canonical order centred on the start pose; then the
     tube search from each of the first ``retries`` reach poses with tube radius r0,
@@ -393,7 +396,8 @@ def plan_path(arm, occ, start, target, W: int, delta: int, r0: int = 1, r1: int 
         return E_ARG, None, None
     wlo = np.maximum(lim_lo, start - W * delta)
     whi = np.minimum(lim_hi, start + W * delta)
-    res = reach(arm, occ, target, m=m, want=retries, lo=wlo, hi=whi, ref=start, keep_sets=False)
+    res = reach(arm, occ, target, m=m, want=retries, lo=wlo, hi=whi, ref=start, keep_sets=False,
+                approach=approach)
     if res.status != OK:
         return NO_REACH, None, res
     for q in res.sols:

@@ -51,11 +51,36 @@ struct orc_arm {
     int32_t lo[16];      // joint lower limit in steps (inclusive)
     int32_t hi[16];      // joint upper limit in steps (inclusive)
     int32_t ref[16];     // reference angle for the canonical order, in steps
+    // Approach cone of the last segment (Fig 3, the cone at the target): final
+    // orientations whose direction lies within app_half_cdeg of the direction of
+    // (app_az_cdeg, app_el_cdeg); app_half_cdeg < 0: no cone.
+    int32_t app_az_cdeg, app_el_cdeg, app_half_cdeg;
 };
 
 }  // extern "C"
 
 namespace {
+
+// Direction of orientation (az, el) given in degrees: (cos el cos az, cos el sin az, sin el).
+void unit_dir(double az_deg, double el_deg, double d[3]) {
+    const double az = az_deg * M_PI / 180.0, el = el_deg * M_PI / 180.0;
+    d[0] = std::cos(el) * std::cos(az);
+    d[1] = std::cos(el) * std::sin(az);
+    d[2] = std::sin(el);
+}
+
+// Is the final orientation (ia, ie) inside the arm's approach cone?  The angle to the
+// axis is at most the half-angle when the dot product of the unit directions is at
+// least its cosine; a band of 1e-9 keeps a boundary case inside whatever the rounding.
+bool in_cone(const orc_arm& A, int ia, int ie) {
+    if (A.app_half_cdeg < 0) return true;
+    double a[3], d[3];
+    unit_dir(A.app_az_cdeg / 100.0, A.app_el_cdeg / 100.0, a);
+    const double step = 360.0 / A.na;
+    unit_dir(ia * step, ie * step, d);
+    const double dot = a[0] * d[0] + a[1] * d[1] + a[2] * d[2];
+    return dot >= std::cos(A.app_half_cdeg / 100.0 * M_PI / 180.0) - 1e-9;
+}
 
 const double kPi = 3.14159265358979323846;
 
@@ -414,7 +439,7 @@ void solve(const Problem& P, int m, int want, Result& R) {
     // at its last segment ends on the target.
     for (int ia = 0; ia < A.na; ++ia)
         for (int ie = 0; ie < A.na; ++ie)
-            if (!P.prune || P.orient[n][(size_t)ia * A.na + ie])
+            if ((!P.prune || P.orient[n][(size_t)ia * A.na + ie]) && in_cone(A, ia, ie))
                 R.B[n].push_back(make_key(N, t[0], t[1], t[2], ia, ie));
     sort_unique(R.B[n]);
     for (int k = n; k > m; --k) R.B[k - 1] = backward_stage(P, R.B[k], k);
@@ -718,7 +743,7 @@ int orc_brute_sets(const orc_arm* arm, int32_t N, const uint8_t* occ, const int3
     int64_t t[3] = {target[0], target[1], target[2]};
     for (int ia = 0; ia < A.na; ++ia)
         for (int ie = 0; ie < A.na; ++ie)
-            if (!prune || P.orient[A.n][(size_t)ia * A.na + ie])
+            if ((!prune || P.orient[A.n][(size_t)ia * A.na + ie]) && in_cone(A, ia, ie))
                 brute_backward(*g_brute, A.n, t, ia, ie, kb);
     for (auto& v : g_brute->F) sort_unique(v);
     for (auto& v : g_brute->B) sort_unique(v);

@@ -77,11 +77,12 @@ hipError_t launch_orient(const OrientArgs& a, uint64_t* rows_ie, uint64_t* rows_
 // flag / seq: see k_publish (flag may be null)
 hipError_t launch_publish(const unsigned long long* src, unsigned long long* dst, int n, unsigned long long* flag,
                           unsigned long long seq, hipStream_t st);
-// seeds: also write their states to `list` (capacity 1, resp. na^2) and count them
+// seeds: also write their states to `list` (capacity 1, resp. na^2) and count them;
+// cone: approach-cone rows of the final orientation (may be null)
 hipError_t launch_seed_fwd(SetView s, GridView g, int x, int y, int z, int ia, int ie, uint64_t* list,
                            unsigned long long* counter, hipStream_t st);
 hipError_t launch_seed_bwd(SetView s, GridView g, int x, int y, int z, const uint64_t* rows_ie, int prune,
-                           uint64_t* list, unsigned long long* counter, hipStream_t st);
+                           const uint64_t* cone, uint64_t* list, unsigned long long* counter, hipStream_t st);
 hipError_t launch_expand_fwd(const uint64_t* in, uint64_t count, SetView out, GridView g, JointView j,
                              int tx, int ty, int tz, long long r2, unsigned long long* counter,
                              unsigned long long* overflow, hipStream_t st);

@@ -499,8 +499,10 @@ __global__ void k_seed_fwd(SetView s, GridView g, int x, int y, int z, int ia, i
     }
 }
 
+// rows_ie: reachable final orientations (used when prune); cone: the approach cone's
+// final orientations (null: no cone); both as [ia][4 words of ie bits].
 __global__ void k_seed_bwd(SetView s, GridView g, int x, int y, int z, const uint64_t* rows_ie, int prune,
-                           uint64_t* list, unsigned long long* counter) {
+                           const uint64_t* cone, uint64_t* list, unsigned long long* counter) {
     const int na = s.na;
     const bool free_cell = cell_free(g, x, y, z);
     const int lane = threadIdx.x & 63;
@@ -513,6 +515,7 @@ __global__ void k_seed_bwd(SetView s, GridView g, int x, int y, int z, const uin
             ia = o / na;
             ie = o % na;
             ok = !prune || ((rows_ie[ia * 4 + (ie >> 6)] >> (ie & 63)) & 1ull);
+            ok = ok && (!cone || ((cone[ia * 4 + (ie >> 6)] >> (ie & 63)) & 1ull));
             ok = ok && set_insert(s, x, y, z, ia, ie) > 0;
         }
         const uint64_t bal = __ballot(ok);
@@ -530,9 +533,9 @@ hipError_t launch_seed_fwd(SetView s, GridView g, int x, int y, int z, int ia, i
 }
 
 hipError_t launch_seed_bwd(SetView s, GridView g, int x, int y, int z, const uint64_t* rows_ie, int prune,
-                           uint64_t* list, unsigned long long* counter, hipStream_t st) {
+                           const uint64_t* cone, uint64_t* list, unsigned long long* counter, hipStream_t st) {
     hipLaunchKernelGGL(k_seed_bwd, dim3(grid_for((uint64_t)s.na * s.na)), dim3(kBlock), 0, st, s, g, x, y, z,
-                       rows_ie, prune, list, counter);
+                       rows_ie, prune, cone, list, counter);
     return hipGetLastError();
 }
 

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstdarg>
 #include <cstdio>
@@ -294,7 +295,36 @@ struct Plan {
     int target[3];
     int prune;
     int split;   // -1 adaptive
+    int app_az, app_el, app_half;   // approach cone of the last segment (centidegrees; half < 0: none)
 };
+
+msc_status set_approach(Lane* c, const msc_opts& o, Plan& p) {
+    if (o.approach_half_cdeg > 18000) return fail(c, MSC_E_ARG, "approach half-angle above 18000 cdeg");
+    p.app_az = o.approach_az_cdeg;
+    p.app_el = o.approach_el_cdeg;
+    p.app_half = o.approach_half_cdeg < 0 ? -1 : o.approach_half_cdeg;
+    return MSC_OK;
+}
+
+// Final orientations inside the approach cone, as rows of na bits per azimuth index
+// (word ia * 4 + ie / 64, bit ie % 64): d(ia, ie) . a >= cos(half) - 1e-9 in FP64.
+void approach_rows(const Plan& p, uint64_t* rows) {
+    constexpr double kPi = 3.14159265358979323846;
+    const double deg = kPi / 180.0;
+    const double az = p.app_az / 100.0 * deg, el = p.app_el / 100.0 * deg;
+    const double ax = std::cos(el) * std::cos(az), ay = std::cos(el) * std::sin(az), azz = std::sin(el);
+    const double lim = std::cos(p.app_half / 100.0 * deg) - 1e-9;
+    const double step = 360.0 / p.na;
+    std::memset(rows, 0, sizeof(uint64_t) * 4 * (size_t)p.na);
+    for (int ia = 0; ia < p.na; ++ia) {
+        const double a = ia * step * deg;
+        for (int ie = 0; ie < p.na; ++ie) {
+            const double e = ie * step * deg;
+            const double dot = std::cos(e) * std::cos(a) * ax + std::cos(e) * std::sin(a) * ay + std::sin(e) * azz;
+            if (dot >= lim) rows[(size_t)ia * 4 + (ie >> 6)] |= 1ull << (ie & 63);
+        }
+    }
+}
 
 msc_status check_arm(Lane* c, const msc_arm* arm, int grid_n) {
     if (!arm) return fail(c, MSC_E_ARG, "arm is NULL");
@@ -339,6 +369,8 @@ void make_plan(const msc_arm* arm, const int32_t* target, Plan& p) {
     for (int i = 0; i < 3; ++i) p.target[i] = target ? target[i] : 0;
     p.prune = 1;
     p.split = -1;
+    p.app_az = p.app_el = 0;
+    p.app_half = -1;
 }
 
 msc_status get_table(Lane* c, int na, int S, int L, TableEntry* out) {
@@ -564,8 +596,15 @@ msc_status run_reach(Lane* c, const msc_scene* sc, const Plan& p, int want, bool
         LAUNCH(MSC_K_SEED, 0, 0,
                launch_seed_fwd(F[0].view, g, p.base[0], p.base[1], p.base[2], p.ia0, p.ie0, (uint64_t*)l0, ctr,
                                c->stream));
+        const uint64_t* cone = nullptr;
+        if (p.app_half >= 0) {
+            void *hc, *dc;
+            MSC_TRY(host_area(c, sizeof(uint64_t) * 4 * (size_t)na, &hc, &dc));
+            approach_rows(p, (uint64_t*)hc);
+            cone = (const uint64_t*)dc;
+        }
         LAUNCH(MSC_K_SEED, n, 0,
-               launch_seed_bwd(B[n].view, g, p.target[0], p.target[1], p.target[2], rows_for(n, 0), p.prune,
+               launch_seed_bwd(B[n].view, g, p.target[0], p.target[1], p.target[2], rows_for(n, 0), p.prune, cone,
                                (uint64_t*)ln, ctr2, c->stream));
         MSC_TRY(publish_and_wait(c, ctr, 2));
         const volatile unsigned long long* h = (const volatile unsigned long long*)(c->staging + kStagingBytes - 64);
@@ -980,6 +1019,7 @@ msc_status reach_on(Lane* c, const msc_scene* sc, const msc_arm* arm, const int3
     make_plan(arm, target, p);
     p.prune = (o.flags & MSC_NO_PRUNE) ? 0 : 1;
     p.split = o.split_m;
+    MSC_TRY(set_approach(c, o, p));
     ReachOut r;
     msc_status st = run_reach(c, sc, p, 1, (o.flags & MSC_CAPTURE_SETS) != 0, r);
     if (st != MSC_OK) return st;
@@ -1009,6 +1049,7 @@ msc_status path_on(Lane* c, const msc_scene* sc, const msc_arm* arm, const int32
     make_plan(arm, target, p);
     p.prune = (o.flags & MSC_NO_PRUNE) ? 0 : 1;
     p.split = o.split_m;
+    MSC_TRY(set_approach(c, o, p));
     const int n = p.n;
     const int delta = max_delta_cdeg / arm->step_cdeg;
     int start[kMaxDof];
@@ -1165,6 +1206,9 @@ void msc_opts_default(msc_opts* o) {
     o->tube_r1 = 2;
     o->reach_retries = 4;
     o->flags = 0;
+    o->approach_az_cdeg = 0;
+    o->approach_el_cdeg = 0;
+    o->approach_half_cdeg = -1;
 }
 
 msc_status msc_ctx_create(int device, void* hip_stream, void* dev_workspace, uint64_t ws_bytes, msc_ctx** out) {

@@ -63,7 +63,9 @@ class MscQuery(ctypes.Structure):
 
 class MscOpts(ctypes.Structure):
     _fields_ = [("split_m", ctypes.c_int32), ("tube_r0", ctypes.c_int32), ("tube_r1", ctypes.c_int32),
-                ("reach_retries", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+                ("reach_retries", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("approach_az_cdeg", ctypes.c_int32), ("approach_el_cdeg", ctypes.c_int32),
+                ("approach_half_cdeg", ctypes.c_int32)]
 
 
 class MscStats(ctypes.Structure):
@@ -149,9 +151,12 @@ def make_arm(arm) -> MscArm:
     return a
 
 
-def make_opts(split_m: int = -1, tube_r0: int = 1, tube_r1: int = 2, retries: int = 4, flags: int = 0) -> MscOpts:
+def make_opts(split_m: int = -1, tube_r0: int = 1, tube_r1: int = 2, retries: int = 4, flags: int = 0,
+              approach=None) -> MscOpts:
+    """approach: None, or (az_cdeg, el_cdeg, half_cdeg) of the last segment's approach cone."""
     o = MscOpts()
     o.split_m, o.tube_r0, o.tube_r1, o.reach_retries, o.flags = split_m, tube_r0, tube_r1, retries, flags
+    o.approach_az_cdeg, o.approach_el_cdeg, o.approach_half_cdeg = (0, 0, -1) if approach is None else approach
     return o
 
 
@@ -282,11 +287,11 @@ class Solver:
 
     # -- solving ------------------------------------------------------------
     def reach(self, scene: Scene, arm, target: Sequence[int], split_m: int = -1,
-              flags: int = 0) -> Tuple[int, Optional[np.ndarray]]:
+              flags: int = 0, approach=None) -> Tuple[int, Optional[np.ndarray]]:
         a = make_arm(arm)
         t = np.ascontiguousarray(np.asarray(target, np.int32))
         out = np.zeros(a.dof, np.int32)
-        o = make_opts(split_m=split_m, flags=flags)
+        o = make_opts(split_m=split_m, flags=flags, approach=approach)
         rc = self.lib.msc_reach(self.ctx, scene.handle, ctypes.byref(a), _ptr(t, ctypes.c_int32), ctypes.byref(o),
                                 _ptr(out, ctypes.c_int32))
         self._check(rc, "msc_reach")
@@ -294,12 +299,12 @@ class Solver:
 
     def path(self, scene: Scene, arm, start: Sequence[int], target: Sequence[int], waypoints: int, delta: int,
              split_m: int = -1, tube_r0: int = 1, tube_r1: int = 2, retries: int = 4,
-             flags: int = 0) -> Tuple[int, Optional[np.ndarray]]:
+             flags: int = 0, approach=None) -> Tuple[int, Optional[np.ndarray]]:
         a = make_arm(arm)
         s = np.ascontiguousarray(np.asarray(start, np.int32) * a.step_cdeg)
         t = np.ascontiguousarray(np.asarray(target, np.int32))
         out = np.zeros((waypoints + 1) * a.dof, np.int32)
-        o = make_opts(split_m, tube_r0, tube_r1, retries, flags)
+        o = make_opts(split_m, tube_r0, tube_r1, retries, flags, approach)
         rc = self.lib.msc_path(self.ctx, scene.handle, ctypes.byref(a), _ptr(s, ctypes.c_int32),
                                _ptr(t, ctypes.c_int32), int(waypoints), int(delta) * a.step_cdeg, ctypes.byref(o),
                                _ptr(out, ctypes.c_int32))

@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts_match_header_sizes():
     # msc_arm: 3 + 3 + 2 + 4*16 int32 = 72 * 4 bytes; msc_opts: 5 * 4 bytes
     assert ctypes.sizeof(msc.MscArm) == 4 * (3 + 3 + 2 + 4 * 16)
-    assert ctypes.sizeof(msc.MscOpts) == 20
+    assert ctypes.sizeof(msc.MscOpts) == 32   # 5 fields + the approach cone (3)
     assert ctypes.sizeof(msc.MscBox) == 24 and ctypes.sizeof(msc.MscSphere) == 16
 
 

@@ -78,10 +78,10 @@ def pick_target(arm, occ, rng, n, reachable=True):
     return tuple(int(v) for v in ends[i])
 
 
-def compare_reach(solver, scene, arm, occ, target, m, prune=True, lo=None, hi=None, ref=None):
+def compare_reach(solver, scene, arm, occ, target, m, prune=True, lo=None, hi=None, ref=None, approach=None):
     flags = msc.CAPTURE_SETS | (0 if prune else msc.NO_PRUNE)
-    st, pose = solver.reach(scene, arm, target, split_m=m, flags=flags)
-    ref_res = oracle.reach(arm, occ, target, m=m, prune=prune)
+    st, pose = solver.reach(scene, arm, target, split_m=m, flags=flags, approach=approach)
+    ref_res = oracle.reach(arm, occ, target, m=m, prune=prune, approach=approach)
     assert st == ref_res.status, (st, ref_res.status)
     if st == msc.OK:
         assert np.array_equal(pose, ref_res.pose), (pose, ref_res.pose)
@@ -270,6 +270,46 @@ def test_path_tube_variants(solver, seed, dof, delta):
         assert st == rst, (r0, r1, st, rst)
         if st == msc.OK:
             assert np.array_equal(path, rpath), (r0, r1, path, rpath)
+
+
+# ---------------------------------------------------------------------------
+# Approach cone of the last segment
+# ---------------------------------------------------------------------------
+
+def final_direction_cdeg(arm, q):
+    ia = arm.az0_cdeg // arm.step_cdeg + sum(int(v) for v, t in zip(q, arm.types) if t == 0)
+    ie = arm.el0_cdeg // arm.step_cdeg + sum(int(v) for v, t in zip(q, arm.types) if t == 1)
+    return (ia % arm.na) * arm.step_cdeg, (ie % arm.na) * arm.step_cdeg
+
+
+@pytest.mark.parametrize("seed,dof,step", [(s, 4, 4500) for s in range(3)] + [(s, 5, 3000) for s in range(3)])
+def test_cone_reach_sets(solver, seed, dof, step):
+    """Every stage set, the join and the canonical pose with an approach cone centred on
+    the final direction of a solution (half-angles 0, 45 and 100 deg)."""
+    say("cone reach", seed, dof, step)
+    arm, sc, rng = tiny_case(seed, dof, step)
+    occ = oracle.raster(sc)
+    scene = solver.scene(sc)
+    target = pick_target(arm, occ, rng, sc.n)
+    cnt, sols = oracle.brute_solutions(arm, occ, target, cap=64)
+    az, el = final_direction_cdeg(arm, sols[0]) if cnt else (0, 9000)
+    for half in (0, 4500, 10000):
+        for m in (0, dof // 2, dof):
+            compare_reach(solver, scene, arm, occ, target, m, approach=(az, el, half))
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_cone_path(solver, seed):
+    say("cone path", seed)
+    arm, sc, start, target = path_case(seed, 4, 3000, 24, 4)
+    occ = oracle.raster(sc)
+    scene = solver.scene(sc)
+    for approach in ((0, 9000, 9000), (9000, 0, 6000), (18000, 4500, 3000)):
+        st, path = solver.path(scene, arm, start, target, 4, 1, approach=approach)
+        rst, rpath, _ = oracle.plan_path(arm, occ, start, target, 4, 1, approach=approach)
+        assert st == rst, (approach, st, rst)
+        if st == msc.OK:
+            assert np.array_equal(path, rpath)
 
 
 def test_path_zero_waypoints(solver):

@@ -237,3 +237,86 @@ def test_orientation_reachability():
             for e in el:
                 expect[a, e] = True
         assert np.array_equal(O[k + 1], expect)
+
+
+# ---------------------------------------------------------------------------
+# Approach cone of the last segment (Fig 3: the cone at the target)
+# ---------------------------------------------------------------------------
+
+def final_orientation(arm, q):
+    """(ia, ie) after the chain: yaw joints add to the azimuth index, pitch joints to
+    the elevation index (R1), from the initial orientation."""
+    na = arm.na
+    ia = arm.az0_cdeg // arm.step_cdeg + sum(int(v) for v, t in zip(q, arm.types) if t == 0)
+    ie = arm.el0_cdeg // arm.step_cdeg + sum(int(v) for v, t in zip(q, arm.types) if t == 1)
+    return ia % na, ie % na
+
+
+def cone_members(na, az_cdeg, el_cdeg, half_cdeg):
+    """Orientations whose direction is within half of the axis (FP64, 1e-9 band)."""
+    a = np.deg2rad([az_cdeg / 100.0, el_cdeg / 100.0])
+    axis = np.array([np.cos(a[1]) * np.cos(a[0]), np.cos(a[1]) * np.sin(a[0]), np.sin(a[1])])
+    idx = np.arange(na)
+    az, el = np.meshgrid(np.deg2rad(idx * 360.0 / na), np.deg2rad(idx * 360.0 / na), indexing="ij")
+    d = np.stack([np.cos(el) * np.cos(az), np.cos(el) * np.sin(az), np.sin(el)], -1)
+    return (d @ axis) >= np.cos(np.deg2rad(half_cdeg / 100.0)) - 1e-9
+
+
+def seed_orientations(arm, occ, target, approach):
+    """Orientations of the unpruned backward seed set B_n at the target."""
+    sets = oracle.brute_sets(arm, occ, target, 0, arm.dof, prune=False, approach=approach)
+    _, _, _, ia, ie = oracle.key_fields(sets[("B", arm.dof)], occ.shape[0])
+    return set(zip(ia.tolist(), ie.tolist()))
+
+
+def test_cone_seed_closed_forms():
+    """Half-angle 90 deg about straight up keeps the elevations 0..180 deg (sin el >= 0):
+    (na/2 + 1) * na orientations; half-angle 0 about a direction keeps exactly the two
+    (azimuth, elevation) pairs of the torus that name it; 180 deg keeps everything."""
+    arm, scene, rng = tiny_case(1, 3, 3000)
+    occ = np.zeros_like(oracle.raster(scene))
+    na = arm.na
+    t = (scene.n // 2, scene.n // 2, scene.n // 2)
+    up = seed_orientations(arm, occ, t, (0, 9000, 9000))
+    assert up == {(ia, ie) for ia in range(na) for ie in range(na // 2 + 1)}
+    assert len(up) == (na // 2 + 1) * na
+    one = seed_orientations(arm, occ, t, (3000, 3000, 0))   # az 30, el 30 deg: na = 12 bins of 30 deg
+    assert one == {(1, 1), (1 + na // 2, na // 2 - 1)}
+    assert len(seed_orientations(arm, occ, t, (4500, -2000, 18000))) == na * na
+
+
+@pytest.mark.parametrize("seed,dof,step", [(s, 4, 4500) for s in range(4)] + [(s, 5, 3000) for s in range(4)])
+def test_cone_solutions_match_filtered_brute_force(seed, dof, step):
+    """With a cone, the canonical poses are the brute-force solutions whose final
+    orientation lies in the cone, in the canonical order, at every split.  The cone is
+    centred on the final direction of one solution (so it keeps at least that one)."""
+    arm, scene, rng = tiny_case(seed, dof, step)
+    occ = oracle.raster(scene)
+    target = pick_target(arm, scene, rng, occ)
+    cnt, sols = oracle.brute_solutions(arm, occ, target, cap=1 << 16)
+    if cnt:
+        ia, ie = final_orientation(arm, sols[int(rng.integers(cnt))])
+        approach = (ia * arm.step_cdeg, ie * arm.step_cdeg, 4500)
+    else:
+        approach = (0, 9000, 4500)
+    inside = cone_members(arm.na, *approach)
+    kept = [q for q in sols[:cnt] if inside[final_orientation(arm, q)]]
+    for m in range(arm.dof + 1):
+        res = oracle.reach(arm, occ, target, m=m, want=len(kept) + 1, approach=approach)
+        if not kept:
+            assert res.status == oracle.NO_REACH
+            continue
+        assert res.status == oracle.OK
+        assert np.array_equal(res.sols, np.asarray(kept, np.int32).reshape(-1, arm.dof)), m
+
+
+def test_full_cone_is_no_cone():
+    arm, scene, rng = tiny_case(4, 5, 4500)
+    occ = oracle.raster(scene)
+    target = pick_target(arm, scene, rng, occ)
+    a = oracle.reach(arm, occ, target, want=8)
+    b = oracle.reach(arm, occ, target, want=8, approach=(12300, 4500, 18000))
+    assert a.status == b.status
+    assert np.array_equal(a.sols, b.sols)
+    for key in a.sets:
+        assert np.array_equal(a.sets[key], b.sets[key])
