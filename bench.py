@@ -87,13 +87,14 @@ def expansion_bytes(solver, msc, n, na, stats):
     return out
 
 
-def cpu_baseline(queries, split):
+def cpu_baseline(queries, split, approach=None):
     import oracle
 
     q = queries[0]
     t0 = time.perf_counter()
     occ = oracle.raster(q.scene)
-    st, path, _ = oracle.plan_path(q.arm, occ, q.start, q.target, q.waypoints, q.max_delta, m=split)
+    st, path, _ = oracle.plan_path(q.arm, occ, q.start, q.target, q.waypoints, q.max_delta, m=split,
+                                   approach=approach)
     dt = time.perf_counter() - t0
     return {"value": 1.0 / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
             "sample": "1 query (scene seed 0): raster + windowed reach (split %d) + tube path, single thread, "
@@ -359,6 +360,8 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=100)
     ap.add_argument("--workspace-gb", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cone", type=int, nargs=3, metavar=("AZ_CDEG", "EL_CDEG", "HALF_CDEG"),
+                    help="approach cone of the last segment for every query (a variant workload)")
     ap.add_argument("--plain-only", action="store_true",
                     help="stop after the plain phase (the run profiled for profiles/expand_trace_c2.md)")
     ap.add_argument("--trace-summary", nargs=2, metavar=("KERNEL_TRACE_CSV", "BENCH_JSON"),
@@ -388,6 +391,7 @@ def main():
     from paper_1906_10678_amd import msc, synth
 
     solver = msc.Solver(0, workspace_bytes=args.workspace_gb << 30)
+    cone = tuple(args.cone) if args.cone else None
     print("preparing %d queries" % args.queries, file=sys.stderr, flush=True)
     queries = [synth.query_c2(s, solver.pose_fn_for) for s in range(args.queries)]
     arm = queries[0].arm
@@ -397,7 +401,8 @@ def main():
     alg, splits = [], []
     for q in queries:
         scene = solver.scene(q.scene)
-        st, _ = solver.path(scene, q.arm, q.start, q.target, q.waypoints, q.max_delta, flags=msc.CAPTURE_SETS)
+        st, _ = solver.path(scene, q.arm, q.start, q.target, q.waypoints, q.max_delta, flags=msc.CAPTURE_SETS,
+                            approach=cone)
         stats = solver.stats()
         splits.append(stats["split_m"])
         alg.append(expansion_bytes(solver, msc, n, na, stats))
@@ -410,7 +415,8 @@ def main():
     def plain_step(i):
         q = queries[i % len(queries)]
         scene = solver.scene(q.scene)
-        st, path = solver.path(scene, q.arm, q.start, q.target, q.waypoints, q.max_delta, flags=msc.PROFILE)
+        st, path = solver.path(scene, q.arm, q.start, q.target, q.waypoints, q.max_delta, flags=msc.PROFILE,
+                               approach=cone)
         if st < 0:
             raise RuntimeError("query %d: error status %d" % (i % len(queries), st))
         statuses[i % len(queries)] = st
@@ -470,7 +476,7 @@ def main():
                 scenes[key] = solver.scene(q.scene)
             specs.append(msc.QuerySpec(scenes[key], q.arm, q.target, start=q.start, waypoints=q.waypoints,
                                        delta=q.max_delta))
-        res = solver.batch(specs)
+        res = solver.batch(specs, approach=cone)
         for j, (st, _, _) in enumerate(res):
             qi = (b * args.batch + j) % len(queries)
             if st != statuses[qi]:
@@ -525,12 +531,13 @@ def main():
                    "batch": args.batch, "lanes": lanes, "lane_sweep": {str(k): round(v, 1) for k, v in sweep.items()},
                    "queries": len(queries), "grid": n, "dof": arm.dof, "waypoints": queries[0].waypoints,
                    "splits": splits, "statuses": [statuses[i] for i in range(len(queries))],
+                   "approach_cone_cdeg": list(cone) if cone else None,
                    "p_latency": "per query, from batch start to its completion"},
         "plain": plain,
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(queries, splits[0])
+        result["cpu_baseline"] = cpu_baseline(queries, splits[0], cone)
     print(json.dumps(result), flush=True)
 
 

@@ -355,12 +355,12 @@ class Solver:
     def lane_bytes(self) -> int:
         return int(self.lib.msc_lane_bytes(self.ctx))
 
-    def batch(self, specs, split_m: int = -1, flags: int = 0):
+    def batch(self, specs, split_m: int = -1, flags: int = 0, approach=None):
         """Solve QuerySpecs with msc_batch; returns their results."""
         arr = (MscQuery * max(1, len(specs)))()
         for i, sp in enumerate(specs):
             arr[i] = sp.c
-        o = make_opts(split_m=split_m, flags=flags)
+        o = make_opts(split_m=split_m, flags=flags, approach=approach)
         self._check(self.lib.msc_batch(self.ctx, arr, len(specs), ctypes.byref(o)), "msc_batch")
         for i, sp in enumerate(specs):
             sp.c.status = arr[i].status
@@ -370,8 +370,8 @@ class Solver:
     def query_bytes(self, spec: QuerySpec) -> int:
         return int(self.lib.msc_query_bytes(ctypes.byref(spec.c)))
 
-    def server_start(self, split_m: int = -1, flags: int = 0):
-        o = make_opts(split_m=split_m, flags=flags)
+    def server_start(self, split_m: int = -1, flags: int = 0, approach=None):
+        o = make_opts(split_m=split_m, flags=flags, approach=approach)
         self._check(self.lib.msc_server_start(self.ctx, ctypes.byref(o)), "msc_server_start")
         self._inflight = {}
 
