@@ -280,6 +280,67 @@ def trace_summary(args):
     print("wrote", TRACE_PROFILE, flush=True)
 
 
+def bench_c2serve(args):
+    """The 8-DOF reach + path queries arriving as a Poisson stream, served by the server
+    with one lane (one query at a time: the plain form) and with several lanes (queries
+    overlap on the device): served/s and p50/p99 latency from submission to completion
+    at each offered rate."""
+    from paper_1906_10678_amd import msc, synth
+
+    solver = msc.Solver(0, workspace_bytes=args.workspace_gb << 30)
+    queries = [synth.query_c2(s, solver.pose_fn_for) for s in range(args.queries)]
+    scenes = [solver.scene(q.scene) for q in queries]
+    rng = np.random.default_rng(7)
+    out_rows = []
+    for lanes in (1, args.lanes if args.lanes > 0 else 8):
+        solver.set_lanes(lanes)
+        solver.server_start()
+        try:
+            for rate in args.serve_rates:
+                gaps = rng.exponential(1.0 / rate, size=int(rate * args.serve_seconds * 1.2) + 8)
+                t_arr = np.cumsum(gaps)
+                t_arr = t_arr[t_arr < args.serve_seconds]
+                pending, lat, sts = [], [], []
+                t0 = time.perf_counter()
+                i = 0
+                while i < len(t_arr) or pending:
+                    now = time.perf_counter() - t0
+                    while i < len(t_arr) and t_arr[i] <= now:
+                        q = queries[i % len(queries)]
+                        spec = msc.QuerySpec(scenes[i % len(queries)], q.arm, q.target, start=q.start,
+                                             waypoints=q.waypoints, delta=q.max_delta)
+                        pending.append((solver.submit(spec), spec))
+                        i += 1
+                    still = []
+                    for t, spec in pending:
+                        if solver.poll(t):
+                            st, _, ms = spec.result()
+                            lat.append(ms)
+                            sts.append(st)
+                        else:
+                            still.append((t, spec))
+                    pending = still
+                    if i < len(t_arr) and not pending:
+                        time.sleep(max(0.0, min(0.001, t_arr[i] - (time.perf_counter() - t0))))
+                wall = time.perf_counter() - t0
+                lat = np.array(lat)
+                row = {"lanes": lanes, "offered_per_s": rate, "served": len(lat),
+                       "served_per_s": round(len(lat) / wall, 1),
+                       "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                       "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                       "statuses": {str(k): sts.count(k) for k in sorted(set(sts))}}
+                out_rows.append(row)
+                print(json.dumps(row), file=sys.stderr, flush=True)
+        finally:
+            solver.server_stop()
+    solver.set_lanes(0)
+    print(json.dumps({"metric": "8-DOF reach+path served/s and p50/p99 ms under Poisson arrivals",
+                      "seconds_per_rate": args.serve_seconds, "rows": out_rows,
+                      "config": {"workload": "the 16 8-DOF reach + 16-waypoint path queries of the benchmark, "
+                                             "Poisson arrivals, latency from submission to completion; one lane "
+                                             "= one query at a time"}}), flush=True)
+
+
 def bench_c3(args):
     """Batched reach poses: 64 scenes (128^3 or 256^3, 10..60 boxes), 8 queries each, DOF
     5..8 unwindowed (+-170 deg in 5 deg steps); targets are ends of random poses, so
@@ -345,8 +406,11 @@ def bench_c5(args):
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
-    ap.add_argument("--workload", choices=["c2", "c3", "c5"], default="c2",
-                    help="c2: 8-DOF reach + path (default); c3: batched reach; c5: serving")
+    ap.add_argument("--workload", choices=["c2", "c2serve", "c3", "c5"], default="c2",
+                    help="c2: 8-DOF reach + path (default); c2serve: the same queries served under Poisson "
+                         "arrivals, one lane vs several; c3: batched reach; c5: serving with moving obstacles")
+    ap.add_argument("--serve-rates", type=float, nargs="+", default=[200.0, 400.0, 600.0, 900.0])
+    ap.add_argument("--serve-seconds", type=float, default=4.0)
     ap.add_argument("--c3-scenes", type=int, default=64)
     ap.add_argument("--c5-rates", type=float, nargs="+", default=[200.0, 500.0, 1000.0, 2000.0])
     ap.add_argument("--c5-seconds", type=float, default=10.0)
@@ -381,6 +445,8 @@ def main():
         sys.exit(2)
     if args.traffic_run:
         return traffic_run(args)
+    if args.workload == "c2serve":
+        return bench_c2serve(args)
     if args.workload == "c3":
         return bench_c3(args)
     if args.workload == "c5":
