@@ -382,6 +382,44 @@ def bench_c3(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_c4(args):
+    """Batched paths at full size: 8 scenes of 512^3 (40 boxes + 16 spheres, dilation 4),
+    32 plans each, 8-DOF chain with doubled segment lengths, 2.5 deg steps (144 bins),
+    8..64 waypoints of at most one step per joint.  All 256 plans in msc_batch calls over
+    worker lanes that split a large workspace (memory per plan reaches tens of GB)."""
+    import torch
+
+    from paper_1906_10678_amd import msc, synth
+
+    solver = msc.Solver(0, workspace_bytes=args.workspace_gb << 30)
+    qs = synth.queries_c4(solver.pose_fn_for, scenes=args.c4_scenes, per_scene=32)
+    print("c4: %d plans" % len(qs), file=sys.stderr, flush=True)
+    scenes = {}
+    specs = []
+    for q in qs:
+        key = q.seed[:2]
+        if key not in scenes:
+            scenes[key] = solver.scene(q.scene)
+        specs.append(msc.QuerySpec(scenes[key], q.arm, q.target, start=q.start, waypoints=q.waypoints,
+                                   delta=q.max_delta))
+    lanes = args.lanes if args.lanes > 0 else 4
+    solver.set_lanes(lanes)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = solver.batch(specs)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sts = [r[0] for r in res]
+    lat = np.array([r[2] for r in res])
+    out = {"metric": "batched 8-DOF path plans/sec (512^3, 2.5 deg)", "value": round(len(qs) / wall, 3),
+           "unit": "plans/s", "seconds": round(wall, 3), "lanes": lanes, "plans": len(qs),
+           "workspace_gb": args.workspace_gb, "statuses": {str(k): sts.count(k) for k in sorted(set(sts))},
+           "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+           "config": {"workload": "batched paths: 8 scenes 512^3 (40 boxes + 16 spheres, dilation 4), 32 plans "
+                                  "each, 8-DOF doubled lengths, 2.5 deg, 8..64 waypoints"}}
+    print(json.dumps(out), flush=True)
+
+
 def bench_c5(args):
     """Serving with dynamic obstacles: Poisson arrivals, 70% reach / 30% path, moving
     boxes re-rasterised every 10 ms tick, midcourse replanning; p50/p99 per class."""
@@ -406,9 +444,11 @@ def bench_c5(args):
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
-    ap.add_argument("--workload", choices=["c2", "c2serve", "c3", "c5"], default="c2",
+    ap.add_argument("--workload", choices=["c2", "c2serve", "c3", "c4", "c5"], default="c2",
                     help="c2: 8-DOF reach + path (default); c2serve: the same queries served under Poisson "
-                         "arrivals, one lane vs several; c3: batched reach; c5: serving with moving obstacles")
+                         "arrivals, one lane vs several; c3: batched reach; c4: batched paths at 512^3; "
+                         "c5: serving with moving obstacles")
+    ap.add_argument("--c4-scenes", type=int, default=8)
     ap.add_argument("--serve-rates", type=float, nargs="+", default=[200.0, 400.0, 600.0, 900.0])
     ap.add_argument("--serve-seconds", type=float, default=4.0)
     ap.add_argument("--c3-scenes", type=int, default=64)
@@ -449,6 +489,8 @@ def main():
         return bench_c2serve(args)
     if args.workload == "c3":
         return bench_c3(args)
+    if args.workload == "c4":
+        return bench_c4(args)
     if args.workload == "c5":
         return bench_c5(args)
 
