@@ -219,7 +219,9 @@ typedef struct {
     int32_t split_m;                     /* split actually used */
     int32_t dof;
     int64_t fwd_count[MSC_MAX_DOF + 1];  /* |F_k|, k = 0..split_m */
-    int64_t bwd_count[MSC_MAX_DOF + 1];  /* |B_k|, k = split_m..dof */
+    int64_t bwd_count[MSC_MAX_DOF + 1];  /* |B_k|, k = split_m..dof; -2 for the set the meet probes
+                                            when it was built without a count (split >= 1 and no
+                                            MSC_CAPTURE_SETS) */
     int64_t join_count;                  /* |C_m|; -1 when C_m was not built (split >= 1 without MSC_CAPTURE_SETS) */
     int32_t fwd_dense[MSC_MAX_DOF + 1];  /* 1 if F_k used a dense bitset, 0 if a hash set */
     int32_t bwd_dense[MSC_MAX_DOF + 1];

@@ -140,6 +140,7 @@ struct TubeBlk {
     uint32_t Bq, nblk;         // cells per block (B^q), blocks per frame (B^no)
     uint64_t nw;               // words per frame
     size_t lds;                // dynamic LDS bytes
+    int frames_lds;            // 1: the W + 1 validity and reach frames are kept in LDS
 };
 TubeBlk tube_blk_plan(const TubeArgs& a);
 hipError_t launch_tube_bits(const TubeArgs& a, const TubeBlk& t, uint64_t* vbits, uint64_t* rbits, int32_t* path,

@@ -208,7 +208,7 @@ __device__ void block_add(unsigned long long v, unsigned long long* dst) {
     if (threadIdx.x == 0) {
         unsigned long long t = 0;
         for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += part[w];
-        if (t) atomicAdd(dst, t);
+        if (t && dst) atomicAdd(dst, t);
     }
 }
 
@@ -606,7 +606,7 @@ hipError_t launch_expand_fwd(const uint64_t* in, uint64_t count, SetView out, Gr
 // outputs whose fastest orientation axis is the joint's axis: the run is set with at
 // most a few masked atomicOr (other outputs: k_expand_bwd_set).
 // ---------------------------------------------------------------------------
-template <int NP>
+template <int NP, bool COUNT>
 __global__ void __launch_bounds__(kBlock) k_expand_bwd(const uint64_t* __restrict__ in, uint64_t count,
                                                        SetView out, GridView g, JointView j, int bx, int by,
                                                        int bz, long long r2, const uint64_t* __restrict__ orows,
@@ -668,18 +668,26 @@ __global__ void __launch_bounds__(kBlock) k_expand_bwd(const uint64_t* __restric
         // a row of na bits spans at most NP words (NP is fixed per launch from na); only
         // non-empty parts are sent, and all of them are in flight before the first result
         // is used (the empty asm statements keep the uses out of the conditional sends)
-        uint64_t old[NP];
+        if constexpr (COUNT) {
+            uint64_t old[NP];
 #pragma unroll
-        for (int w = 0; w < NP; ++w) {
-            old[w] = ~0ull;
-            if (part[w]) old[w] = atomicOr((unsigned long long*)&out.words[word0 + w], (unsigned long long)part[w]);
+            for (int w = 0; w < NP; ++w) {
+                old[w] = ~0ull;
+                if (part[w])
+                    old[w] = atomicOr((unsigned long long*)&out.words[word0 + w], (unsigned long long)part[w]);
+            }
+#pragma unroll
+            for (int w = 0; w < NP; ++w) asm volatile("" : "+v"(old[w]));
+#pragma unroll
+            for (int w = 0; w < NP; ++w) added += __popcll(part[w] & ~old[w]);
+        } else {
+            // no count wanted: the atomics return nothing and the wave does not wait
+#pragma unroll
+            for (int w = 0; w < NP; ++w)
+                if (part[w]) atomicOr((unsigned long long*)&out.words[word0 + w], (unsigned long long)part[w]);
         }
-#pragma unroll
-        for (int w = 0; w < NP; ++w) asm volatile("" : "+v"(old[w]));
-#pragma unroll
-        for (int w = 0; w < NP; ++w) added += __popcll(part[w] & ~old[w]);
     }
-    block_add(added, counter);
+    if constexpr (COUNT) block_add(added, counter);
     if (ovf) atomicAdd(overflow, ovf);
 }
 
@@ -729,6 +737,24 @@ __global__ void __launch_bounds__(kBlock) k_expand_bwd_set(const uint64_t* __res
     if (ovf) atomicAdd(overflow, ovf);
 }
 
+template <bool COUNT>
+void launch_bwd_dense(int np, dim3 grid, hipStream_t st, const uint64_t* in, uint64_t count, SetView out,
+                      GridView g, JointView j, int bx, int by, int bz, long long r2, const uint64_t* orows,
+                      unsigned long long* counter, unsigned long long* overflow) {
+    if (np == 2)
+        hipLaunchKernelGGL((k_expand_bwd<2, COUNT>), grid, dim3(kBlock), 0, st, in, count, out, g, j, bx, by, bz, r2,
+                           orows, counter, overflow);
+    else if (np == 3)
+        hipLaunchKernelGGL((k_expand_bwd<3, COUNT>), grid, dim3(kBlock), 0, st, in, count, out, g, j, bx, by, bz, r2,
+                           orows, counter, overflow);
+    else if (np == 4)
+        hipLaunchKernelGGL((k_expand_bwd<4, COUNT>), grid, dim3(kBlock), 0, st, in, count, out, g, j, bx, by, bz, r2,
+                           orows, counter, overflow);
+    else
+        hipLaunchKernelGGL((k_expand_bwd<5, COUNT>), grid, dim3(kBlock), 0, st, in, count, out, g, j, bx, by, bz, r2,
+                           orows, counter, overflow);
+}
+
 hipError_t launch_expand_bwd(const uint64_t* in, uint64_t count, SetView out, GridView g, JointView j,
                              int bx, int by, int bz, long long r2, const uint64_t* orows,
                              unsigned long long* counter, unsigned long long* overflow, hipStream_t st) {
@@ -737,18 +763,10 @@ hipError_t launch_expand_bwd(const uint64_t* in, uint64_t count, SetView out, Gr
     if (run_dense) {
         const int np = ((out.na + 63) >> 6) + 1;   // words a row of na bits can touch
         const dim3 grid(grid_for(count));
-        if (np == 2)
-            hipLaunchKernelGGL(k_expand_bwd<2>, grid, dim3(kBlock), 0, st, in, count, out, g, j, bx, by, bz, r2, orows,
-                               counter, overflow);
-        else if (np == 3)
-            hipLaunchKernelGGL(k_expand_bwd<3>, grid, dim3(kBlock), 0, st, in, count, out, g, j, bx, by, bz, r2, orows,
-                               counter, overflow);
-        else if (np == 4)
-            hipLaunchKernelGGL(k_expand_bwd<4>, grid, dim3(kBlock), 0, st, in, count, out, g, j, bx, by, bz, r2, orows,
-                               counter, overflow);
+        if (counter)
+            launch_bwd_dense<true>(np, grid, st, in, count, out, g, j, bx, by, bz, r2, orows, counter, overflow);
         else
-            hipLaunchKernelGGL(k_expand_bwd<5>, grid, dim3(kBlock), 0, st, in, count, out, g, j, bx, by, bz, r2, orows,
-                               counter, overflow);
+            launch_bwd_dense<false>(np, grid, st, in, count, out, g, j, bx, by, bz, r2, orows, counter, overflow);
     } else {
         const int lg = group_log2_for(count, j.hi - j.lo + 1);
         hipLaunchKernelGGL(k_expand_bwd_set, dim3(grid_for(count << lg)), dim3(kBlock), 0, st, in, count, out, g, j,
@@ -1120,7 +1138,9 @@ hipError_t launch_dmark(const uint64_t* flist, uint64_t count, SetView fprev, Se
                         JointView j, unsigned long long* counter, int tx, int ty, int tz, long long r2,
                         hipStream_t st) {
     if (count == 0) return hipSuccess;
-    const int lg = group_log2_for(count, j.hi - j.lo + 1);
+    // at most 8 lanes per state: a lane tries several angles (measured faster than a
+    // wave per state, whose lanes each try one)
+    const int lg = std::min(group_log2_for(count, j.hi - j.lo + 1), 3);
     hipLaunchKernelGGL(k_dmark, dim3(grid_for(count << lg)), dim3(kBlock), 0, st, flist, count, fprev, fnext, g, j,
                        counter, lg, tx, ty, tz, r2);
     return hipGetLastError();
@@ -1707,6 +1727,13 @@ TubeBlk tube_blk_plan(const TubeArgs& a) {
     t.nw = nblk * (uint64_t)t.b;
     const size_t bytes = 2 * t.nw * 8 + align8(nblk * (uint64_t)t.no) + align8(nblk);
     t.lds = bytes <= kBlkLdsMax ? bytes : 0;
+    // small frames: every validity and reach frame stays in LDS, so no waypoint waits
+    // on a global memory round trip
+    const size_t frames = 2 * (size_t)(a.W + 1) * t.nw * 8;
+    if (t.lds && bytes + frames <= kBlkLdsMax) {
+        t.frames_lds = 1;
+        t.lds = bytes + frames;
+    }
     return t;
 }
 
@@ -1737,7 +1764,7 @@ __device__ __forceinline__ void shl128(uint64_t x0, uint64_t x1, int s, uint64_t
     }
 }
 
-template <int DL>
+template <int DL, bool FL>
 __global__ void __launch_bounds__(kBlkThreads) k_tube_blk(TubeArgs a, TubeBlk tb, const uint64_t* vbits,
                                                           uint64_t* rbits, int32_t* path, int32_t* status) {
     extern __shared__ uint64_t sm[];
@@ -1745,9 +1772,12 @@ __global__ void __launch_bounds__(kBlkThreads) k_tube_blk(TubeArgs a, TubeBlk tb
     const int no = tb.no, q = tb.q, b = tb.b;
     const uint32_t nblk = tb.nblk, Bq = tb.Bq;
     const int nw = (int)tb.nw;
+    const size_t nfw = FL ? (size_t)(a.W + 1) * nw : 0;            // words of the LDS frames
     uint64_t* fa = sm;
     uint64_t* fb = sm + nw;
-    uint8_t* dig = reinterpret_cast<uint8_t*>(sm + 2 * nw);       // [block][outer joint]
+    const uint64_t* V = FL ? sm + 2 * nw : vbits;                  // validity frames
+    uint64_t* R = FL ? sm + 2 * nw + nfw : rbits;                  // reach frames
+    uint8_t* dig = reinterpret_cast<uint8_t*>(sm + 2 * nw + 2 * nfw);  // [block][outer joint]
     uint8_t* l1o = dig + align8((size_t)nblk * no);                // outer L1 distance per block
     __shared__ uint32_t sblk[kMaxDof], scell[kMaxDof];
     __shared__ unsigned long long pge[kBlkPatterns * 2];           // [inner joint][v <= B][word]
@@ -1755,6 +1785,13 @@ __global__ void __launch_bounds__(kBlkThreads) k_tube_blk(TubeArgs a, TubeBlk tb
     __shared__ int shw[kMaxDof], dlo[kMaxDof], dhi[kMaxDof], flo[kMaxDof], qcur[kMaxDof];
     __shared__ unsigned long long best_part[kBlkThreads / 64];
     __shared__ int fail;
+    __shared__ int gstart[kMaxDof], gdiff[kMaxDof];     // the guide's ends, read once
+    // guide_at from the LDS copy (the argument block is not re-read in the serial loops)
+    auto sguide = [&](int w, int k) {
+        const int num = w * gdiff[k];
+        const uint32_t mag = (2u * (uint32_t)(num < 0 ? -num : num) + (uint32_t)a.W) / (2u * (uint32_t)a.W);
+        return gstart[k] + (num < 0 ? -(int)mag : (int)mag);
+    };
     const int tid = threadIdx.x;
     const int nthr = (int)blockDim.x;    // a multiple of 64, fewer for small frames
     if (tid == 0) {
@@ -1769,6 +1806,10 @@ __global__ void __launch_bounds__(kBlkThreads) k_tube_blk(TubeArgs a, TubeBlk tb
             st *= (uint32_t)B;
         }
         fail = 0;
+    }
+    if (tid < n) {
+        gstart[tid] = a.start[tid];
+        gdiff[tid] = a.goal[tid] - a.start[tid];
     }
     __syncthreads();
     // inner patterns, one thread per inner cell c: its bit goes into "digit of inner joint
@@ -1798,89 +1839,98 @@ __global__ void __launch_bounds__(kBlkThreads) k_tube_blk(TubeArgs a, TubeBlk tb
         }
         l1o[u] = (uint8_t)d1;
     }
+    if constexpr (FL) {
+        for (size_t i = tid; i < nfw; i += nthr) sm[2 * nw + i] = vbits[i];
+        __syncthreads();
+    }
     for (int i = tid; i < nw; i += nthr) {
-        fa[i] = vbits[i];
-        rbits[i] = vbits[i];
+        fa[i] = V[i];
+        R[i] = V[i];
     }
     __syncthreads();
-    // Forward: R_w = valid_w AND the delta-dilation of R_{w-1}, one joint at a time.
+    // Forward: R_w = valid_w AND the delta-dilation of R_{w-1}.  The dilation is a
+    // product over joints, so its order is free: the outer joints move whole blocks (one
+    // pass each, through LDS), then each thread dilates its own blocks along the inner
+    // joints in registers and applies the validity frame.
     uint64_t* src = fa;
     uint64_t* dst = fb;
     for (int w = 1; w <= a.W; ++w) {
-        if (tid < n) shw[tid] = guide_at(a, w, tid) - guide_at(a, w - 1, tid);
+        if (tid < n) shw[tid] = sguide(w, tid) - sguide(w - 1, tid);
         __syncthreads();
-        for (int k = 0; k < n; ++k) {
+        for (int k = 0; k < no; ++k) {
             const int sh = shw[k];
-            if (k < no) {
-                // outer joint: whole blocks move by t * S blocks
-                const int S = (int)sblk[k];
-                for (uint32_t u = tid; u < nblk; u += nthr) {
-                    const int d = dig[(size_t)u * no + k];
-                    uint64_t a0 = 0, a1 = 0;
-                    auto take = [&](int e) {
-                        const int t = sh + e;
-                        if (d + t < 0 || d + t >= B) return;
-                        const size_t from = ((size_t)u + (ptrdiff_t)t * S) * (size_t)b;
-                        a0 |= src[from];
-                        if (b == 2) a1 |= src[from + 1];
-                    };
-                    if constexpr (DL > 0) {
+            // outer joint: whole blocks move by t * S blocks
+            const int S = (int)sblk[k];
+            for (uint32_t u = tid; u < nblk; u += nthr) {
+                const int d = dig[(size_t)u * no + k];
+                uint64_t a0 = 0, a1 = 0;
+                auto take = [&](int e) {
+                    const int t = sh + e;
+                    if (d + t < 0 || d + t >= B) return;
+                    const size_t from = ((size_t)u + (ptrdiff_t)t * S) * (size_t)b;
+                    a0 |= src[from];
+                    if (b == 2) a1 |= src[from + 1];
+                };
+                if constexpr (DL > 0) {
 #pragma unroll
-                        for (int e = -DL; e <= DL; ++e) take(e);
-                    } else {
-                        for (int e = -dl; e <= dl; ++e) take(e);
-                    }
-                    dst[(size_t)u * b] = a0;
-                    if (b == 2) dst[(size_t)u * b + 1] = a1;
+                    for (int e = -DL; e <= DL; ++e) take(e);
+                } else {
+                    for (int e = -dl; e <= dl; ++e) take(e);
                 }
-            } else {
-                // inner joint: a shift by t * s cells inside every block
-                const int ki = k - no;
-                const int s1 = (int)scell[k];
-                const bool last = k == n - 1;
-                for (uint32_t u = tid; u < nblk; u += nthr) {
-                    const size_t i0 = (size_t)u * b;
-                    const uint64_t x0 = src[i0], x1 = b == 2 ? src[i0 + 1] : 0ull;
-                    uint64_t a0 = 0, a1 = 0;
-                    auto take = [&](int e) {
-                        const int t = sh + e;
-                        const int vlo = t < 0 ? -t : 0;
-                        const int vend = t > 0 ? B - t : B;        // exclusive
-                        if (vlo >= vend) return;
-                        const int lo_i = (ki * (B + 1) + vlo) * 2, hi_i = (ki * (B + 1) + vend) * 2;
-                        const uint64_t m0 = pge[lo_i] & ~pge[hi_i], m1 = pge[lo_i + 1] & ~pge[hi_i + 1];
-                        uint64_t y0, y1;
-                        if (t >= 0)
-                            shr128(x0, x1, t * s1, y0, y1);
-                        else
-                            shl128(x0, x1, -t * s1, y0, y1);
-                        a0 |= y0 & m0;
-                        a1 |= y1 & m1;
-                    };
-                    if constexpr (DL > 0) {
-#pragma unroll
-                        for (int e = -DL; e <= DL; ++e) take(e);
-                    } else {
-                        for (int e = -dl; e <= dl; ++e) take(e);
-                    }
-                    if (last) {
-                        const size_t g0 = (size_t)w * nw + i0;
-                        a0 &= vbits[g0];
-                        rbits[g0] = a0;
-                        if (b == 2) {
-                            a1 &= vbits[g0 + 1];
-                            rbits[g0 + 1] = a1;
-                        }
-                    }
-                    dst[i0] = a0;
-                    if (b == 2) dst[i0 + 1] = a1;
-                }
+                dst[(size_t)u * b] = a0;
+                if (b == 2) dst[(size_t)u * b + 1] = a1;
             }
             __syncthreads();
             uint64_t* tmp = src;
             src = dst;
             dst = tmp;
         }
+        // inner joints: shifts by t * s cells inside the block, in registers
+        for (uint32_t u = tid; u < nblk; u += nthr) {
+            const size_t i0 = (size_t)u * b;
+            uint64_t x0 = src[i0], x1 = b == 2 ? src[i0 + 1] : 0ull;
+            for (int ki = 0; ki < q; ++ki) {
+                const int sh = shw[no + ki];
+                const int s1 = (int)scell[no + ki];
+                uint64_t a0 = 0, a1 = 0;
+                auto take = [&](int e) {
+                    const int t = sh + e;
+                    const int vlo = t < 0 ? -t : 0;
+                    const int vend = t > 0 ? B - t : B;        // exclusive
+                    if (vlo >= vend) return;
+                    const int lo_i = (ki * (B + 1) + vlo) * 2, hi_i = (ki * (B + 1) + vend) * 2;
+                    const uint64_t m0 = pge[lo_i] & ~pge[hi_i], m1 = pge[lo_i + 1] & ~pge[hi_i + 1];
+                    uint64_t y0, y1;
+                    if (t >= 0)
+                        shr128(x0, x1, t * s1, y0, y1);
+                    else
+                        shl128(x0, x1, -t * s1, y0, y1);
+                    a0 |= y0 & m0;
+                    a1 |= y1 & m1;
+                };
+                if constexpr (DL > 0) {
+#pragma unroll
+                    for (int e = -DL; e <= DL; ++e) take(e);
+                } else {
+                    for (int e = -dl; e <= dl; ++e) take(e);
+                }
+                x0 = a0;
+                x1 = a1;
+            }
+            const size_t g0 = (size_t)w * nw + i0;
+            x0 &= V[g0];
+            R[g0] = x0;
+            dst[i0] = x0;
+            if (b == 2) {
+                x1 &= V[g0 + 1];
+                R[g0 + 1] = x1;
+                dst[i0 + 1] = x1;
+            }
+        }
+        __syncthreads();
+        uint64_t* tmp = src;
+        src = dst;
+        dst = tmp;
     }
     // the goal: every digit = r
     {
@@ -1894,15 +1944,15 @@ __global__ void __launch_bounds__(kBlkThreads) k_tube_blk(TubeArgs a, TubeBlk tb
         }
     }
     if (tid < n) {
-        qcur[tid] = a.goal[tid];
-        path[a.W * n + tid] = a.goal[tid];
+        qcur[tid] = gstart[tid] + gdiff[tid];
+        path[a.W * n + tid] = qcur[tid];
     }
     // Backward choice: among the reachable cells of frame w-1 whose digits lie within
     // delta of the current pose, the smallest L1 distance to the guide, ties by the
     // smallest cell (u Bq + v orders poses lexicographically).
     for (int w = a.W; w >= 1; --w) {
         if (tid < n) {
-            const int f = guide_at(a, w - 1, tid) - r;
+            const int f = sguide(w - 1, tid) - r;
             const int lo = qcur[tid] - dl - f, hi = qcur[tid] + dl - f;
             flo[tid] = f;
             dlo[tid] = lo < 0 ? 0 : lo;
@@ -1921,7 +1971,7 @@ __global__ void __launch_bounds__(kBlkThreads) k_tube_blk(TubeArgs a, TubeBlk tb
             ib0 &= pge[lo_i] & ~pge[hi_i];
             ib1 &= pge[lo_i + 1] & ~pge[hi_i + 1];
         }
-        const uint64_t* R = rbits + (size_t)(w - 1) * nw;
+        const uint64_t* Rw = R + (size_t)(w - 1) * nw;
         unsigned long long best = ~0ull;
         if (ib0 | ib1) {
             for (uint32_t u = tid; u < nblk; u += nthr) {
@@ -1931,8 +1981,8 @@ __global__ void __launch_bounds__(kBlkThreads) k_tube_blk(TubeArgs a, TubeBlk tb
                     in = in && d >= dlo[k] && d <= dhi[k];
                 }
                 if (!in) continue;
-                const uint64_t m0 = R[(size_t)u * b] & ib0;
-                const uint64_t m1 = b == 2 ? (R[(size_t)u * b + 1] & ib1) : 0ull;
+                const uint64_t m0 = Rw[(size_t)u * b] & ib0;
+                const uint64_t m1 = b == 2 ? (Rw[(size_t)u * b + 1] & ib1) : 0ull;
                 if (!(m0 | m1)) continue;
                 const unsigned long long lo1 = l1o[u];
                 for (int l = 0; l <= q * r; ++l) {
@@ -1973,20 +2023,27 @@ __global__ void __launch_bounds__(kBlkThreads) k_tube_blk(TubeArgs a, TubeBlk tb
     if (tid == 0) *status = fail ? 0 : 1;
 }
 
-template <int DL>
+template <int DL, bool FL>
 hipError_t launch_tube_blk_dl(const TubeArgs& a, const TubeBlk& t, const uint64_t* vbits, uint64_t* rbits,
                               int32_t* path, int32_t* status, hipStream_t st) {
     static std::once_flag once;
     static hipError_t attr = hipSuccess;
     std::call_once(once, [] {
-        attr = hipFuncSetAttribute((const void*)k_tube_blk<DL>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        attr = hipFuncSetAttribute((const void*)k_tube_blk<DL, FL>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)kBlkLdsMax);
     });
     if (attr != hipSuccess) return attr;
     // threads: one per block of the frame, rounded to waves (barriers of idle waves cost)
     const uint32_t threads = std::min<uint32_t>(kBlkThreads, std::max<uint32_t>(64u, (t.nblk + 63u) & ~63u));
-    hipLaunchKernelGGL(k_tube_blk<DL>, dim3(1), dim3(threads), t.lds, st, a, t, vbits, rbits, path, status);
+    hipLaunchKernelGGL((k_tube_blk<DL, FL>), dim3(1), dim3(threads), t.lds, st, a, t, vbits, rbits, path, status);
     return hipGetLastError();
+}
+
+template <int DL>
+hipError_t launch_tube_blk_dl(const TubeArgs& a, const TubeBlk& t, const uint64_t* vbits, uint64_t* rbits,
+                              int32_t* path, int32_t* status, hipStream_t st) {
+    if (t.frames_lds) return launch_tube_blk_dl<DL, true>(a, t, vbits, rbits, path, status, st);
+    return launch_tube_blk_dl<DL, false>(a, t, vbits, rbits, path, status, st);
 }
 
 hipError_t launch_tube_bits(const TubeArgs& a, const TubeBlk& t, uint64_t* vbits, uint64_t* rbits, int32_t* path,

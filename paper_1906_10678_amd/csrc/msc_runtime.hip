@@ -45,6 +45,7 @@ struct StageSet {
     uint64_t count = 0;
     bool listed = false;
     bool used = false;
+    bool counted = true;   // false: built without a member count (count is meaningless)
 };
 
 }  // namespace
@@ -705,16 +706,25 @@ msc_status run_reach(Lane* c, const msc_scene* sc, const Plan& p, int want, bool
             int64_t rb = 0;
             for (int j = 0; j < k - 1; ++j) rb += R[j];
             long long r2 = p.prune ? (long long)(rb * rb) : -1;
-            unsigned long long* ctr = take_counter(c);
-            if (!ctr) return fail(c, MSC_E_CAPACITY, "out of counters");
+            // The set the meet probes needs no member count (an empty one simply meets
+            // nothing): it is built without one, and without a host round trip, unless
+            // the sets are captured.
+            const bool last = p.split == 0 ? k - 1 == 0 : k - 1 - kf == 1;
+            const bool count = capture || !last;
+            unsigned long long* ctr = count ? take_counter(c) : nullptr;
+            if (count && !ctr) return fail(c, MSC_E_CAPACITY, "out of counters");
             LAUNCH(MSC_K_EXPAND_BWD, k - 1, (int64_t)B[kb].count,
                    launch_expand_bwd(B[kb].list, B[kb].count, B[k - 1].view, g, jv[k - 1], p.base[0], p.base[1],
                                      p.base[2], r2, rows_for(k - 1, yaw), ctr, ovf, c->stream));
-            const int rec = c->last_rec;
-            MSC_TRY(read_counter(c, ctr, &B[k - 1].count));
-            prof_out(c, rec, (int64_t)B[k - 1].count);
             kb = k - 1;
-            empty = B[k - 1].count == 0;
+            if (count) {
+                const int rec = c->last_rec;
+                MSC_TRY(read_counter(c, ctr, &B[k - 1].count));
+                prof_out(c, rec, (int64_t)B[k - 1].count);
+                empty = B[k - 1].count == 0;
+            } else {
+                B[k - 1].counted = false;
+            }
         }
     }
     MSC_TRY(check_overflow(c, ovf, "a stage set"));
@@ -722,7 +732,7 @@ msc_status run_reach(Lane* c, const msc_scene* sc, const Plan& p, int want, bool
     c->stats.split_m = m;
     for (int k = 0; k <= n; ++k) {
         c->stats.fwd_count[k] = F[k].used ? (int64_t)F[k].count : -1;
-        c->stats.bwd_count[k] = B[k].used ? (int64_t)B[k].count : -1;
+        c->stats.bwd_count[k] = !B[k].used ? -1 : B[k].counted ? (int64_t)B[k].count : -2;
         c->stats.fwd_dense[k] = F[k].used && F[k].view.kind == kDense;
         c->stats.bwd_dense[k] = B[k].used && B[k].view.kind == kDense;
     }
