@@ -444,6 +444,8 @@ def bench_c5(args):
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--arm", choices=["chain", "gms"], default="chain",
+                    help="gms: the same workload with the paper's arm model, two DOF per segment (a variant)")
     ap.add_argument("--workload", choices=["c2", "c2serve", "c3", "c4", "c5"], default="c2",
                     help="c2: 8-DOF reach + path (default); c2serve: the same queries served under Poisson "
                          "arrivals, one lane vs several; c3: batched reach; c4: batched paths at 512^3; "
@@ -501,7 +503,8 @@ def main():
     solver = msc.Solver(0, workspace_bytes=args.workspace_gb << 30)
     cone = tuple(args.cone) if args.cone else None
     print("preparing %d queries" % args.queries, file=sys.stderr, flush=True)
-    queries = [synth.query_c2(s, solver.pose_fn_for) for s in range(args.queries)]
+    gen = synth.query_gms if args.arm == "gms" else synth.query_c2
+    queries = [gen(s, solver.pose_fn_for) for s in range(args.queries)]
     arm = queries[0].arm
     n, na = queries[0].scene.n, arm.na
 
@@ -618,7 +621,7 @@ def main():
     qlat = np.array(qlat)
 
     result = {
-        "metric": "8-DOF reach+path solves/sec",
+        "metric": "8-DOF reach+path solves/sec" + (" (4 segments x 2 DOF)" if args.arm == "gms" else ""),
         "value": round(args.steps * args.batch / wall, 3),
         "unit": "solves/s",
         "n_gpus": 1,
@@ -640,6 +643,8 @@ def main():
                    "queries": len(queries), "grid": n, "dof": arm.dof, "waypoints": queries[0].waypoints,
                    "splits": splits, "statuses": [statuses[i] for i in range(len(queries))],
                    "approach_cone_cdeg": list(cone) if cone else None,
+                   "arm": ("two DOF per segment: (yaw, length 0) + (pitch, length L), L = 60, 50, 40, 25 voxels"
+                           if args.arm == "gms" else "alternating yaw/pitch chain"),
                    "p_latency": "per query, from batch start to its completion"},
         "plain": plain,
         "roofline": roofline,

@@ -104,6 +104,26 @@ def arm_c2() -> Arm:
     return arm_chain(8, C2_LENS, 500, 17000, (128, 128, 0))
 
 
+# The paper's own arm model gives every segment two degrees of freedom at its proximal
+# end (azimuth and elevation, "Joint Angular Velocities"); eight DOF = four segments
+# ("The selection process for an 8DOF arm").  Here a segment is a zero-length yaw link
+# followed by the pitch joint that carries it.  Lengths: the 8-DOF chain's, summed in
+# pairs.
+GMS_LENS = [60, 50, 40, 25]
+
+
+def arm_gms(lens: Sequence[int] = GMS_LENS, step_cdeg: int = 500, limit_cdeg: int = 17000,
+            base: Tuple[int, int, int] = (128, 128, 0)) -> Arm:
+    """Two joints per segment: (yaw, length 0) then (pitch, length L), symmetric limits."""
+    types, L = [], []
+    for l in lens:
+        types += [YAW, PITCH]
+        L += [0, int(l)]
+    k = len(types)
+    return Arm(types=types, lens=L, lo_cdeg=[-limit_cdeg] * k, hi_cdeg=[limit_cdeg] * k,
+               step_cdeg=step_cdeg, base=base)
+
+
 def scaled_lens(n: int, dof: int) -> List[int]:
     """Prefix of the 8-DOF chain with lengths scaled by n/256, halves rounded up."""
     return [int(np.floor(l * n / 256 + 0.5)) for l in C2_LENS[:dof]]
@@ -174,6 +194,14 @@ def scene_c2(seed: int = 0) -> Scene:
     arm = arm_c2()
     return random_scene(rng_for(2, seed, 0), 256, 2, 32, (5, 40), 8, (4, 20),
                         base=arm.base, column=arm.lens[0])
+
+
+def scene_gms(seed: int = 0) -> Scene:
+    """The 256^3 scenes of the 8-DOF chain (boxes, spheres, dilation 2), with the column
+    above the base kept clear to the first segment's length."""
+    arm = arm_gms()
+    return random_scene(rng_for(6, seed, 0), 256, 2, 32, (5, 40), 8, (4, 20),
+                        base=arm.base, column=max(arm.lens))
 
 
 # --------------------------------------------------------------------------
@@ -256,6 +284,18 @@ def query_c2(seed: int, pose_fn_for: Callable[[Arm, Scene], PoseFn], waypoints: 
     _, end = walk_target(rng_for(2, seed, 2), arm, start, waypoints, delta, pf)
     return Query(arm=arm, scene=scene, target=tuple(int(v) for v in end), start=start,
                  waypoints=waypoints, max_delta=delta, seed=(2, seed))
+
+
+def query_gms(seed: int, pose_fn_for: Callable[[Arm, Scene], PoseFn], waypoints: int = 16,
+              delta: int = 1) -> Query:
+    """Reach + path query of the two-DOF-per-segment arm, drawn like the 8-DOF chain's:
+    random valid start, target at the end of a feasible 16-move walk."""
+    arm, scene = arm_gms(), scene_gms(seed)
+    pf = pose_fn_for(arm, scene)
+    start, _, _ = first_valid_pose(rng_for(6, seed, 1), arm, pf)
+    _, end = walk_target(rng_for(6, seed, 2), arm, start, waypoints, delta, pf)
+    return Query(arm=arm, scene=scene, target=tuple(int(v) for v in end), start=start,
+                 waypoints=waypoints, max_delta=delta, seed=(6, seed))
 
 
 # --------------------------------------------------------------------------

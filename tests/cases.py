@@ -51,3 +51,26 @@ def tiny_case(seed: int, dof: int = 3, step_cdeg: int = 3000, n: int = 20, nbox:
 def arm_fields(arm) -> dict:
     return dict(types=list(arm.types), lens=list(arm.lens), lo=list(arm.lo_cdeg), hi=list(arm.hi_cdeg),
                 step=arm.step_cdeg, base=tuple(arm.base))
+
+
+def tiny_gms_arm(rng: np.random.Generator, segments: int, step_cdeg: int = 3000, n: int = 20) -> synth.Arm:
+    """The paper's arm model at tiny size: each segment a zero-length yaw link followed by
+    a pitch joint carrying the segment (2 DOF per segment), random windows."""
+    lens = [int(v) for v in rng.integers(2, 6, size=segments)]
+    arm = synth.arm_gms(lens, step_cdeg, 18000, (n // 2, n // 2, 0))
+    na = 36000 // step_cdeg
+    lo, hi = [], []
+    for k in range(arm.dof):
+        span = int(rng.integers(max(1, na // 4), na // 2 + 1))
+        lo.append(-span * step_cdeg)
+        hi.append(int(rng.integers(span // 2, span + 1)) * step_cdeg)
+    arm.lo_cdeg, arm.hi_cdeg = lo, hi
+    return arm
+
+
+def tiny_gms_case(seed: int, segments: int = 2, step_cdeg: int = 3000, n: int = 20, nbox: int = 3,
+                  dilate: int = 0, nsph: int = 1):
+    rng = synth.rng_for(906, seed)
+    arm = tiny_gms_arm(rng, segments, step_cdeg, n)
+    scene = tiny_scene(rng, n, nbox, dilate, nsph, base=arm.base, column=max(arm.lens))
+    return arm, scene, rng
