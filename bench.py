@@ -420,6 +420,52 @@ def bench_c4(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_refine(args):
+    """Exact end points (msc_refine) of 2^20 discrete poses of the two-DOF-per-segment arm,
+    each with a target point inside its end voxel: whole-call rate (host arrays in and
+    out) and the kernel's own time from its HIP events; the oracle on a sample."""
+    import torch
+
+    from paper_1906_10678_amd import msc, synth
+
+    solver = msc.Solver(0, workspace_bytes=args.workspace_gb << 30)
+    arm = synth.arm_gms()
+    count = 1 << 20
+    rng = synth.rng_for(912, 0)
+    q = synth.candidate_poses(rng, arm, count)
+    empty = synth.Scene(n=512, dilate=0, boxes=np.zeros((0, 6), np.int32), spheres=np.zeros((0, 4), np.int32))
+    scene = solver.scene(empty)
+    _, ends = solver.pose_check(scene, arm, q)
+    targets = ends.astype(np.float64) + rng.uniform(-0.5, 0.5, size=(count, 3))
+    solver.refine(arm, q[:4096], targets[:4096])
+    torch.cuda.synchronize()
+    walls, kern = [], []
+    for _ in range(max(1, args.steps)):
+        t0 = time.perf_counter()
+        ang, st = solver.refine(arm, q, targets)
+        walls.append(time.perf_counter() - t0)
+        kern.append(sum(r[4] for r in solver.timings() if r[0] == "refine"))
+    wall, kms = float(np.median(walls)), float(np.median(kern))
+    # FP64 bytes per pose: 8 int32 angles + 3 doubles in, 8 doubles + 1 int32 out
+    bytes_per_pose = arm.dof * 4 + 24 + arm.dof * 8 + 4
+    out = {"metric": "exact end points/sec (two-DOF-per-segment arm, FP64)", "value": round(count / wall, 1),
+           "unit": "poses/s", "poses": count, "refined": int((st == 0).sum()),
+           "kernel_ms": round(kms, 4), "kernel_poses_per_s": round(count / (kms * 1e-3), 1),
+           "kernel_GBps": round(count * bytes_per_pose / (kms * 1e-3) / 1e9, 2),
+           "config": {"workload": "2^20 uniform poses of the 4 x 2-DOF arm, targets uniform in the end voxel; "
+                                  "value includes the host-device copies"}}
+    if not args.no_cpu_baseline:
+        import oracle
+        k = 2000
+        t0 = time.perf_counter()
+        for i in range(k):
+            oracle.refine(arm, q[i], targets[i])
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(k / dt, 1), "unit": "poses/s", "cores": 1, "kind": "oracle",
+                               "sample": "first %d poses, single thread" % k}
+    print(json.dumps(out), flush=True)
+
+
 def bench_c5(args):
     """Serving with dynamic obstacles: Poisson arrivals, 70% reach / 30% path, moving
     boxes re-rasterised every 10 ms tick, midcourse replanning; p50/p99 per class."""
@@ -446,7 +492,7 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--arm", choices=["chain", "gms"], default="chain",
                     help="gms: the same workload with the paper's arm model, two DOF per segment (a variant)")
-    ap.add_argument("--workload", choices=["c2", "c2serve", "c3", "c4", "c5"], default="c2",
+    ap.add_argument("--workload", choices=["c2", "c2serve", "c3", "c4", "c5", "refine"], default="c2",
                     help="c2: 8-DOF reach + path (default); c2serve: the same queries served under Poisson "
                          "arrivals, one lane vs several; c3: batched reach; c4: batched paths at 512^3; "
                          "c5: serving with moving obstacles")
@@ -493,6 +539,8 @@ def main():
         return bench_c3(args)
     if args.workload == "c4":
         return bench_c4(args)
+    if args.workload == "refine":
+        return bench_refine(args)
     if args.workload == "c5":
         return bench_c5(args)
 

@@ -168,6 +168,29 @@ msc_status msc_pose_check(msc_ctx* ctx, const msc_scene* scene, const msc_arm* a
                           const int32_t* poses_cdeg, int64_t count, uint8_t* valid_out,
                           int32_t* end_out);
 
+/* Exact end point of discrete poses ("Exact IK solution with discretized segment
+ * mappings"), FP64 on the GPU.  The arm's last two segments must each have two DOF:
+ * joints dof-4 .. dof-1 are a zero-length link, a link of the other kind (length L3 > 0),
+ * a zero-length link, a link of the other kind (length L4 > 0); else MSC_E_ARG.  For
+ * pose i (poses_cdeg[i*dof..], multiples of the step) and exact target point
+ * targets[i*3..] (voxel units, voxel centres at integer coordinates): the first dof-4
+ * joints keep their discrete angles; P = the continuous end of those segments; the
+ * joint J between the last two segments becomes the point with |J - P| = L3 and
+ * |target - J| = L4 in the plane through P, the target and the discrete pose's joint,
+ * on that joint's side (the closing point nearest to it; if the discrete joint lies on
+ * the line P-target, the plane through u x e, e the axis least aligned with u, is
+ * taken).  angles_out[i*dof..] receives every joint's angle in degrees: discrete ones,
+ * then the continuous increments of the last four joints (each yaw adds to the
+ * azimuth, each pitch to the elevation), unwrapped next to the discrete values.
+ * status_out[i] = 0 when refined, 1 when |target - P| is 0 or outside [|L3 - L4|,
+ * L3 + L4] (the discrete angles are written).  Joint limits and obstacles are not
+ * re-checked: the exact pose stays in the plane of the cleared discrete one.  All
+ * arrays are host memory owned by the caller; count may be 0.  The kernel time of each
+ * launch (up to 2^20 poses) is left for msc_get_timings. */
+msc_status msc_refine(msc_ctx* ctx, const msc_arm* arm, const int32_t* poses_cdeg,
+                      const double* targets, int64_t count, double* angles_out,
+                      int32_t* status_out);
+
 /* Worker lanes for msc_batch and the server.  The workspace, minus a region for the
  * shared segment tables, is split into 1 + nworkers equal windows: one for this
  * context's own calls, one per worker lane.  Each worker lane has its own HIP stream
@@ -236,7 +259,7 @@ msc_status msc_get_stats(msc_ctx* ctx, msc_stats* out);
 typedef enum {
     MSC_K_FILL = 0, MSC_K_TABLES, MSC_K_RASTER, MSC_K_ORIENT, MSC_K_SEED, MSC_K_EXPAND_FWD,
     MSC_K_EXPAND_BWD, MSC_K_COMPACT, MSC_K_JOIN, MSC_K_DMARK, MSC_K_DFS, MSC_K_POSE,
-    MSC_K_TUBE_VALID, MSC_K_TUBE_SOLVE, MSC_K_COUNT
+    MSC_K_TUBE_VALID, MSC_K_TUBE_SOLVE, MSC_K_REFINE, MSC_K_COUNT
 } msc_kernel;
 typedef struct {
     int32_t kernel;     /* msc_kernel */

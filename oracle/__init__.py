@@ -425,3 +425,104 @@ def key_fields(keys: np.ndarray, n: int):
     ia = ((keys >> np.uint64(8)) & np.uint64(0xff)).astype(np.int64)
     v = (keys >> np.uint64(16)).astype(np.int64)
     return v % n, (v // n) % n, v // (n * n), ia, ie
+
+
+# --------------------------------------------------------------------------
+# Exact end point for a discrete pose ("Exact IK solution with discretized segment
+# mappings").  Plain FP64 with the math module, one pose at a time.
+# --------------------------------------------------------------------------
+
+YAW = 0
+
+
+def _unit(az_deg: float, el_deg: float) -> np.ndarray:
+    """Direction of a segment at global azimuth / elevation (degrees)."""
+    a, e = np.radians(az_deg), np.radians(el_deg)
+    return np.array([np.cos(e) * np.cos(a), np.cos(e) * np.sin(a), np.sin(e)])
+
+
+def _wrap180(x: float) -> float:
+    """x modulo 360 in (-180, 180]."""
+    y = x % 360.0
+    return y - 360.0 if y > 180.0 else y
+
+
+def _angles_near(s: np.ndarray, ref_az: float, ref_el: float) -> Tuple[float, float]:
+    """(az, el) of vector s, of its two names on the (az, el) torus -- (az, el) and
+    (az + 180, 180 - el) point the same way -- the one nearer (ref_az, ref_el), unwrapped
+    next to it.  A vertical s keeps ref_az."""
+    L = float(np.linalg.norm(s))
+    el = float(np.degrees(np.arcsin(np.clip(s[2] / L, -1.0, 1.0))))
+    if np.hypot(s[0], s[1]) <= 1e-12 * L:
+        az = ref_az
+    else:
+        az = float(np.degrees(np.arctan2(s[1], s[0])))
+    best = None
+    for a, e in ((az, el), (az + 180.0, 180.0 - el)):
+        da, de = _wrap180(a - ref_az), _wrap180(e - ref_el)
+        cost = abs(da) + abs(de)
+        if best is None or cost < best[0]:
+            best = (cost, ref_az + da, ref_el + de)
+    return best[1], best[2]
+
+
+def refine_ok_arm(arm) -> bool:
+    """The last two segments each have two DOF: joints dof-4..dof-1 are a zero-length
+    link, a link of the other kind, a zero-length link, a link of the other kind."""
+    n = len(arm.types)
+    if n < 4:
+        return False
+    t, L = list(arm.types), list(arm.lens)
+    return (L[n - 4] == 0 and L[n - 2] == 0 and t[n - 4] != t[n - 3] and t[n - 2] != t[n - 1]
+            and L[n - 3] > 0 and L[n - 1] > 0)
+
+
+def refine(arm, q: Sequence[int], target: Sequence[float]) -> Tuple[int, np.ndarray]:
+    """(status, joint angles in degrees).  The first dof-4 joints keep their discrete
+    angles; the last two segments are recomputed so that the chain ends on `target`:
+    P = end of the fixed part (continuous FK), Jd = the discrete pose's joint between
+    the last two segments, J = the point at distance L3 from P and L4 from the target in
+    the plane (P, target, Jd) on Jd's side; status 1 (discrete angles returned) when no
+    such triangle exists."""
+    n = len(arm.types)
+    assert refine_ok_arm(arm)
+    step = arm.step_cdeg / 100.0
+    az, el = arm.az0_cdeg / 100.0, arm.el0_cdeg / 100.0
+    dirs = []
+    for k in range(n):
+        if arm.types[k] == YAW:
+            az += q[k] * step
+        else:
+            el += q[k] * step
+        dirs.append((az, el))
+    disc = np.array([q[k] * step for k in range(n)], dtype=np.float64)
+    P = np.array(arm.base, dtype=np.float64)
+    for k in range(n - 4):
+        P = P + arm.lens[k] * _unit(*dirs[k])
+    L3, L4 = float(arm.lens[n - 3]), float(arm.lens[n - 1])
+    Jd = P + L3 * _unit(*dirs[n - 3])
+    T = np.asarray(target, dtype=np.float64)
+    v = T - P
+    d = float(np.linalg.norm(v))
+    if d == 0.0 or d > L3 + L4 or d < abs(L3 - L4):
+        return NO_REACH, disc
+    u = v / d
+    a = (L3 * L3 - L4 * L4 + d * d) / (2.0 * d)
+    h = float(np.sqrt(max(L3 * L3 - a * a, 0.0)))
+    rel = Jd - P
+    w = rel - np.dot(rel, u) * u
+    if np.linalg.norm(w) <= 1e-9 * L3:
+        i = int(np.argmin(np.abs(u)))
+        e = np.zeros(3)
+        e[i] = 1.0
+        w = np.cross(u, e)
+    w = w / np.linalg.norm(w)
+    J = P + a * u + h * w
+    az3, el3 = _angles_near(J - P, *dirs[n - 3])
+    az4, el4 = _angles_near(T - J, *dirs[n - 1])
+    prev = dirs[n - 5] if n >= 5 else (arm.az0_cdeg / 100.0, arm.el0_cdeg / 100.0)
+    out = disc.copy()
+    for k0, (pa, pe), (na_, ne) in ((n - 4, prev, (az3, el3)), (n - 2, (az3, el3), (az4, el4))):
+        for k in (k0, k0 + 1):
+            out[k] = (na_ - pa) if arm.types[k] == YAW else (ne - pe)
+    return OK, out

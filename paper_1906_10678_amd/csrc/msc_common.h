@@ -123,6 +123,16 @@ struct PoseArgs {
 hipError_t launch_pose_check(const PoseArgs& a, const int32_t* q, int64_t count, uint8_t* valid,
                              int32_t* ends, hipStream_t st);
 
+// Exact end point of discrete poses (FP64): angles in degrees, lengths in voxels.
+struct RefineArgs {
+    int n;
+    int type[kMaxDof];
+    double len[kMaxDof];
+    double base[3], az0, el0, step;
+};
+hipError_t launch_refine(const RefineArgs& a, const int32_t* q_steps, const double* targets, int64_t count,
+                         double* angles, int32_t* status, hipStream_t st);
+
 struct TubeArgs {
     JointView joints[kMaxDof];
     GridView g;

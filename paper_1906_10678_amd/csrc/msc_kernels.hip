@@ -1147,6 +1147,136 @@ hipError_t launch_dmark(const uint64_t* flist, uint64_t count, SetView fprev, Se
 }
 
 // ---------------------------------------------------------------------------
+// Exact end point ("Exact IK solution with discretized segment mappings"): the last two
+// segments of a discrete pose, each with two DOF, are recomputed in FP64 so that the
+// chain ends on the exact target.  P = end of the fixed first segments, J = the joint
+// between the last two: |J - P| = L3, |T - J| = L4, in the plane of P, T and the
+// discrete joint, on its side (the closing point nearest to it).  One thread per pose.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void unit_dir(double az, double el, double& x, double& y, double& z) {
+    constexpr double kRad = 3.14159265358979323846 / 180.0;
+    const double a = az * kRad, e = el * kRad;
+    x = cos(e) * cos(a);
+    y = cos(e) * sin(a);
+    z = sin(e);
+}
+
+__device__ __forceinline__ double wrap180(double x) {
+    double y = fmod(x, 360.0);
+    if (y < 0.0) y += 360.0;
+    return y > 180.0 ? y - 360.0 : y;
+}
+
+// (az, el) of s, as the name of its direction on the (az, el) torus -- (az, el) or
+// (az + 180, 180 - el) -- nearer (raz, rel), unwrapped next to it; vertical s keeps raz
+__device__ void angles_near(double sx, double sy, double sz, double raz, double rel, double& az, double& el) {
+    constexpr double kDeg = 180.0 / 3.14159265358979323846;
+    const double L = sqrt(sx * sx + sy * sy + sz * sz);
+    const double e0 = asin(fmin(fmax(sz / L, -1.0), 1.0)) * kDeg;
+    const double a0 = hypot(sx, sy) <= 1e-12 * L ? raz : atan2(sy, sx) * kDeg;
+    const double da0 = wrap180(a0 - raz), de0 = wrap180(e0 - rel);
+    const double da1 = wrap180(a0 + 180.0 - raz), de1 = wrap180(180.0 - e0 - rel);
+    if (fabs(da1) + fabs(de1) < fabs(da0) + fabs(de0)) {
+        az = raz + da1;
+        el = rel + de1;
+    } else {
+        az = raz + da0;
+        el = rel + de0;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_refine(RefineArgs a, const int32_t* __restrict__ q,
+                                                   const double* __restrict__ tgt, int64_t count,
+                                                   double* __restrict__ out, int32_t* __restrict__ status) {
+    const int n = a.n;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t* qi = q + i * n;
+        double* oi = out + i * n;
+        double az = a.az0, el = a.el0;
+        double px = a.base[0], py = a.base[1], pz = a.base[2];
+        double paz = a.az0, pel = a.el0, az3 = 0, el3 = 0, az4 = 0, el4 = 0;
+        for (int k = 0; k < n; ++k) {
+            const double inc = qi[k] * a.step;
+            oi[k] = inc;
+            if (a.type[k] == 0)
+                az += inc;
+            else
+                el += inc;
+            if (k < n - 4) {
+                double x, y, z;
+                unit_dir(az, el, x, y, z);
+                px = px + a.len[k] * x;
+                py = py + a.len[k] * y;
+                pz = pz + a.len[k] * z;
+            }
+            if (k == n - 5) {
+                paz = az;
+                pel = el;
+            }
+            if (k == n - 3) {
+                az3 = az;
+                el3 = el;
+            }
+            if (k == n - 1) {
+                az4 = az;
+                el4 = el;
+            }
+        }
+        const double L3 = a.len[n - 3], L4 = a.len[n - 1];
+        double jx, jy, jz;
+        unit_dir(az3, el3, jx, jy, jz);
+        jx = px + L3 * jx;
+        jy = py + L3 * jy;
+        jz = pz + L3 * jz;
+        const double tx = tgt[i * 3], ty = tgt[i * 3 + 1], tz = tgt[i * 3 + 2];
+        const double vx = tx - px, vy = ty - py, vz = tz - pz;
+        const double d = sqrt(vx * vx + vy * vy + vz * vz);
+        if (d == 0.0 || d > L3 + L4 || d < fabs(L3 - L4)) {
+            status[i] = 1;
+            continue;
+        }
+        const double ux = vx / d, uy = vy / d, uz = vz / d;
+        const double aa = (L3 * L3 - L4 * L4 + d * d) / (2.0 * d);
+        const double h = sqrt(fmax(L3 * L3 - aa * aa, 0.0));
+        const double rx = jx - px, ry = jy - py, rz = jz - pz;
+        const double ru = rx * ux + ry * uy + rz * uz;
+        double wx = rx - ru * ux, wy = ry - ru * uy, wz = rz - ru * uz;
+        if (sqrt(wx * wx + wy * wy + wz * wz) <= 1e-9 * L3) {
+            // the discrete joint is on the line: a fixed perpendicular, u x (the axis
+            // least aligned with u)
+            const double ax = fabs(ux), ay = fabs(uy), az_ = fabs(uz);
+            const int ix = (ax <= ay && ax <= az_) ? 0 : (ay <= az_ ? 1 : 2);
+            const double ex = ix == 0, ey = ix == 1, ez = ix == 2;
+            wx = uy * ez - uz * ey;
+            wy = uz * ex - ux * ez;
+            wz = ux * ey - uy * ex;
+        }
+        const double wn = sqrt(wx * wx + wy * wy + wz * wz);
+        wx /= wn;
+        wy /= wn;
+        wz /= wn;
+        const double Jx = px + aa * ux + h * wx, Jy = py + aa * uy + h * wy, Jz = pz + aa * uz + h * wz;
+        double a3, e3, a4, e4;
+        angles_near(Jx - px, Jy - py, Jz - pz, az3, el3, a3, e3);
+        angles_near(tx - Jx, ty - Jy, tz - Jz, az4, el4, a4, e4);
+        oi[n - 4] = a.type[n - 4] == 0 ? a3 - paz : e3 - pel;
+        oi[n - 3] = a.type[n - 3] == 0 ? a3 - paz : e3 - pel;
+        oi[n - 2] = a.type[n - 2] == 0 ? a4 - a3 : e4 - e3;
+        oi[n - 1] = a.type[n - 1] == 0 ? a4 - a3 : e4 - e3;
+        status[i] = 0;
+    }
+}
+
+hipError_t launch_refine(const RefineArgs& a, const int32_t* q_steps, const double* targets, int64_t count,
+                         double* angles, int32_t* status, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_refine, dim3(grid_for((uint64_t)count)), dim3(kBlock), 0, st, a, q_steps, targets, count,
+                       angles, status);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Reach poses (Step 3): depth-first walk from the root over the joint angles in the
 // canonical order (distance to the reference angle, then value), stepping only into
 // states that extend to a full solution (D_k on the forward side, B_k on the

@@ -1534,6 +1534,59 @@ msc_status msc_pose_check(msc_ctx* o, const msc_scene* sc, const msc_arm* arm, c
     return MSC_OK;
 }
 
+msc_status msc_refine(msc_ctx* o, const msc_arm* arm, const int32_t* poses_cdeg, const double* targets,
+                      int64_t count, double* angles_out, int32_t* status_out) {
+    if (!o) return MSC_E_ARG;
+    Lane* c = o->control;
+
+    MSC_TRY(check_arm(c, arm, 1 << 30));
+    const int n = arm->dof;
+    if (n < 4 || arm->len_vox[n - 4] != 0 || arm->len_vox[n - 2] != 0 || arm->len_vox[n - 3] <= 0 ||
+        arm->len_vox[n - 1] <= 0 || arm->type[n - 4] == arm->type[n - 3] || arm->type[n - 2] == arm->type[n - 1])
+        return fail(c, MSC_E_ARG, "the last two segments must each be a zero-length link and a link of the other kind");
+    if (count < 0 || (count && (!poses_cdeg || !targets || !angles_out || !status_out)))
+        return fail(c, MSC_E_ARG, "bad pose arrays");
+    for (int64_t i = 0; i < count * n; ++i)
+        if (poses_cdeg[i] % arm->step_cdeg) return fail(c, MSC_E_ARG, "pose angle not a multiple of the step");
+    for (int64_t i = 0; i < count * 3; ++i)
+        if (!std::isfinite(targets[i])) return fail(c, MSC_E_ARG, "target not finite");
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, MSC_E_HIP, "hipSetDevice");
+    RefineArgs a{};
+    a.n = n;
+    for (int k = 0; k < n; ++k) {
+        a.type[k] = arm->type[k];
+        a.len[k] = (double)arm->len_vox[k];
+    }
+    for (int d = 0; d < 3; ++d) a.base[d] = (double)arm->base[d];
+    a.az0 = arm->az0_cdeg / 100.0;
+    a.el0 = arm->el0_cdeg / 100.0;
+    a.step = arm->step_cdeg / 100.0;
+    // the kernel time of every chunk is kept for msc_get_timings
+    prof_reset(c, MSC_PROFILE);
+    const int64_t chunk = 1 << 20;
+    std::vector<int32_t> q;
+    for (int64_t b = 0; b < count; b += chunk) {
+        begin_call(c);
+        const int64_t cnt = std::min(chunk, count - b);
+        q.assign(poses_cdeg + b * n, poses_cdeg + (b + cnt) * n);
+        for (auto& v : q) v /= arm->step_cdeg;
+        void *d_q, *d_t, *d_a, *d_s;
+        MSC_TRY(arena_alloc(c, (uint64_t)cnt * n * 4, &d_q));
+        MSC_TRY(arena_alloc(c, (uint64_t)cnt * 24, &d_t));
+        MSC_TRY(arena_alloc(c, (uint64_t)cnt * n * 8, &d_a));
+        MSC_TRY(arena_alloc(c, (uint64_t)cnt * 4, &d_s));
+        HIP_TRY(hipMemcpyAsync(d_q, q.data(), (size_t)cnt * n * 4, hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(hipMemcpyAsync(d_t, targets + b * 3, (size_t)cnt * 24, hipMemcpyHostToDevice, c->stream));
+        LAUNCH(MSC_K_REFINE, -1, cnt,
+               launch_refine(a, (const int32_t*)d_q, (const double*)d_t, cnt, (double*)d_a, (int32_t*)d_s, c->stream));
+        HIP_TRY(hipMemcpyAsync(angles_out + b * n, d_a, (size_t)cnt * n * 8, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipMemcpyAsync(status_out + b, d_s, (size_t)cnt * 4, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+    }
+    prof_finish(c);
+    return MSC_OK;
+}
+
 msc_status msc_get_stats(msc_ctx* o, msc_stats* out) {
     if (!o || !out) return MSC_E_ARG;
     *out = o->control->stats;

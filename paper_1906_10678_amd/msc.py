@@ -22,7 +22,7 @@ OK, NO_REACH, NO_PATH = 0, 1, 2
 E_ARG, E_NOMEM, E_HIP, E_CAPACITY, E_STATE = -1, -2, -3, -4, -5
 CAPTURE_SETS, NO_PRUNE, PROFILE = 1, 2, 4
 KERNELS = ["fill", "tables", "raster", "orient", "seed", "expand_fwd", "expand_bwd", "compact", "join", "dmark",
-           "dfs", "pose", "tube_valid", "tube_solve"]
+           "dfs", "pose", "tube_valid", "tube_solve", "refine"]
 SET_F, SET_B, SET_C, SET_D = 0, 1, 2, 3
 
 EXPORTS = [
@@ -30,7 +30,7 @@ EXPORTS = [
     "msc_scene_destroy", "msc_reach", "msc_path", "msc_pose_check", "msc_get_stats",
     "msc_debug_tables", "msc_debug_raster", "msc_debug_set", "msc_last_error", "msc_get_timings",
     "msc_ctx_set_lanes", "msc_lane_bytes", "msc_batch", "msc_query_bytes", "msc_server_start",
-    "msc_server_submit", "msc_server_poll", "msc_server_wait", "msc_server_stop",
+    "msc_server_submit", "msc_server_poll", "msc_server_wait", "msc_server_stop", "msc_refine",
 ]
 
 
@@ -102,6 +102,7 @@ def load_library(path: str = LIB_PATH):
     L.msc_path.argtypes = [c_void_p, c_void_p, P(MscArm), P(i32), P(i32), i32, i32, P(MscOpts), P(i32)]
     L.msc_pose_check.argtypes = [c_void_p, c_void_p, P(MscArm), P(i32), i64, P(ctypes.c_uint8), P(i32)]
     L.msc_get_stats.argtypes = [c_void_p, P(MscStats)]
+    L.msc_refine.argtypes = [c_void_p, P(MscArm), P(i32), P(ctypes.c_double), i64, P(ctypes.c_double), P(i32)]
     L.msc_debug_tables.argtypes = [c_void_p, P(MscArm), i32, P(i32), P(i32)]
     L.msc_debug_raster.argtypes = [c_void_p, c_void_p, P(ctypes.c_uint8)]
     L.msc_debug_set.argtypes = [c_void_p, i32, i32, P(u64), u64, P(u64)]
@@ -320,6 +321,21 @@ class Solver:
                                      _ptr(valid, ctypes.c_uint8), _ptr(ends, ctypes.c_int32))
         self._check(rc, "msc_pose_check")
         return valid.astype(bool), ends.astype(np.int64)
+
+    def refine(self, arm, q, targets) -> Tuple[np.ndarray, np.ndarray]:
+        """Exact end points (msc_refine): q[count, dof] in steps, targets[count, 3] (voxel
+        units); returns (angles in degrees [count, dof], status [count])."""
+        a = make_arm(arm)
+        q = np.ascontiguousarray(np.asarray(q, np.int32).reshape(-1, a.dof) * a.step_cdeg)
+        t = np.ascontiguousarray(np.asarray(targets, np.float64).reshape(-1, 3))
+        if t.shape[0] != q.shape[0]:
+            raise ValueError("one target per pose")
+        ang = np.zeros(q.shape, np.float64)
+        st = np.zeros(q.shape[0], np.int32)
+        rc = self.lib.msc_refine(self.ctx, ctypes.byref(a), _ptr(q, ctypes.c_int32), _ptr(t, ctypes.c_double),
+                                 q.shape[0], _ptr(ang, ctypes.c_double), _ptr(st, ctypes.c_int32))
+        self._check(rc, "msc_refine")
+        return ang, st
 
     def pose_fn_for(self, arm, sc):
         """A synth-compatible pose function backed by the GPU library."""
