@@ -266,9 +266,27 @@ __global__ void k_fill16(uint64_t* p, uint64_t n, uint64_t v) {
         q[i] = vv;
     if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) p[n - 1] = v;
 }
+// The same with nontemporal stores, for sets far larger than the caches: the cleared
+// lines are not kept dirty in L2 / MALL ahead of the stage that scatters into the set
+// (measured: the backward stage and the meet run faster after it).
+typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+__global__ void k_fill16nt(uint64_t* p, uint64_t n, uint64_t v) {
+    const uint64_t pairs = n >> 1;
+    u64x2* q = reinterpret_cast<u64x2*>(p);
+    u64x2 vv;
+    vv.x = v;
+    vv.y = v;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < pairs;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        __builtin_nontemporal_store(vv, &q[i]);
+    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) p[n - 1] = v;
+}
+constexpr uint64_t kFillNtWords = (64ull << 20) / 8;
 hipError_t launch_fill(uint64_t* p, uint64_t n, uint64_t value, hipStream_t st) {
     if (n == 0) return hipSuccess;
-    if (((uintptr_t)p & 15) == 0 && n >= 2)
+    if (((uintptr_t)p & 15) == 0 && n >= kFillNtWords)
+        hipLaunchKernelGGL(k_fill16nt, dim3(grid_for(n >> 1, kBlock, 16384)), dim3(kBlock), 0, st, p, n, value);
+    else if (((uintptr_t)p & 15) == 0 && n >= 2)
         hipLaunchKernelGGL(k_fill16, dim3(grid_for(n >> 1, kBlock, 16384)), dim3(kBlock), 0, st, p, n, value);
     else
         hipLaunchKernelGGL(k_fill, dim3(grid_for(n, kBlock, 8192)), dim3(kBlock), 0, st, p, n, value);
