@@ -466,6 +466,64 @@ def bench_refine(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_replan(args):
+    """Midcourse replanning (msc_replan) on the 16 8-DOF queries: each with a reference
+    path, the straight 16-move line from the start toward a drawn pose of the window;
+    one replan per call, every reach pose of the first four tried and the path nearest
+    the reference kept."""
+    import torch
+
+    from paper_1906_10678_amd import msc, synth
+
+    solver = msc.Solver(0, workspace_bytes=args.workspace_gb << 30)
+    queries = [synth.query_c2(s, solver.pose_fn_for) for s in range(args.queries)]
+    refs = []
+    for i, q in enumerate(queries):
+        rng = synth.rng_for(916, i)
+        goal = np.asarray(q.start, np.int64) + rng.integers(-16, 17, size=q.arm.dof)
+        refs.append(np.rint(np.linspace(q.start, goal, q.waypoints + 1)).astype(np.int64))
+    scenes = [solver.scene(q.scene) for q in queries]
+    statuses, picks = {}, {}
+    for i, q in enumerate(queries):
+        st, _ = solver.replan(scenes[i], q.arm, q.start, q.target, q.waypoints, q.max_delta, refs[i])
+        statuses[i] = st
+        picks[i] = solver.stats()["reach_index"] if st == msc.OK else -1
+    torch.cuda.synchronize()
+    lat, kern = [], []
+    t0 = time.perf_counter()
+    for k in range(args.plain_steps):
+        i = k % len(queries)
+        q = queries[i]
+        ts = time.perf_counter()
+        st, _ = solver.replan(scenes[i], q.arm, q.start, q.target, q.waypoints, q.max_delta, refs[i],
+                              flags=msc.PROFILE)
+        lat.append(time.perf_counter() - ts)
+        kern.append(sum(r[4] for r in solver.timings()))
+        if st != statuses[i]:
+            raise RuntimeError("replan %d: status %d, first run %d" % (i, st, statuses[i]))
+    wall = time.perf_counter() - t0
+    lat = np.array(lat) * 1e3
+    out = {"metric": "8-DOF replans/sec (nearest of the first four reach poses' paths)",
+           "value": round(args.plain_steps / wall, 3), "unit": "replans/s",
+           "p50_ms": round(float(np.percentile(lat, 50)), 4), "p99_ms": round(float(np.percentile(lat, 99)), 4),
+           "gpu_ms_per_replan": round(float(np.mean(kern)), 4),
+           "statuses": [statuses[i] for i in range(len(queries))],
+           "chosen_reach_pose": [picks[i] for i in range(len(queries))],
+           "config": {"workload": "the 16 8-DOF reach + 16-waypoint path queries, each with a straight reference "
+                                  "path toward a drawn pose; one replan per call"}}
+    if args.cpu_replan:
+        # about two minutes of single-thread oracle work (radius-2 tube searches in numpy)
+        import oracle
+        q = queries[0]
+        t0 = time.perf_counter()
+        occ = oracle.raster(q.scene)
+        oracle.replan_path(q.arm, occ, q.start, q.target, q.waypoints, q.max_delta, refs[0])
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(1.0 / dt, 4), "unit": "replans/s", "cores": 1, "kind": "oracle",
+                               "sample": "query 0, single thread, %.1f s" % dt}
+    print(json.dumps(out), flush=True)
+
+
 def bench_c5(args):
     """Serving with dynamic obstacles: Poisson arrivals, 70% reach / 30% path, moving
     boxes re-rasterised every 10 ms tick, midcourse replanning; p50/p99 per class."""
@@ -492,7 +550,7 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--arm", choices=["chain", "gms"], default="chain",
                     help="gms: the same workload with the paper's arm model, two DOF per segment (a variant)")
-    ap.add_argument("--workload", choices=["c2", "c2serve", "c3", "c4", "c5", "refine"], default="c2",
+    ap.add_argument("--workload", choices=["c2", "c2serve", "c3", "c4", "c5", "refine", "replan"], default="c2",
                     help="c2: 8-DOF reach + path (default); c2serve: the same queries served under Poisson "
                          "arrivals, one lane vs several; c3: batched reach; c4: batched paths at 512^3; "
                          "c5: serving with moving obstacles")
@@ -510,6 +568,8 @@ def main():
     ap.add_argument("--lanes", type=int, default=0, help="worker lanes (0: pick the best of a short sweep)")
     ap.add_argument("--queries", type=int, default=16, help="distinct seeded queries")
     ap.add_argument("--plain-steps", type=int, default=100)
+    ap.add_argument("--cpu-replan", action="store_true",
+                    help="replan workload: also time the oracle on query 0 (about two minutes)")
     ap.add_argument("--workspace-gb", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cone", type=int, nargs=3, metavar=("AZ_CDEG", "EL_CDEG", "HALF_CDEG"),
@@ -541,6 +601,8 @@ def main():
         return bench_c4(args)
     if args.workload == "refine":
         return bench_refine(args)
+    if args.workload == "replan":
+        return bench_replan(args)
     if args.workload == "c5":
         return bench_c5(args)
 

@@ -160,6 +160,19 @@ msc_status msc_path(msc_ctx* ctx, const msc_scene* scene, const msc_arm* arm,
                     const int32_t* start_cdeg, const int32_t target[3], int32_t waypoints,
                     int32_t max_delta_cdeg, const msc_opts* opts, int32_t* path_out);
 
+/* Midcourse replanning ("Dynamic Obstacles": of the new paths, the one with the least
+ * mean distance to the original path).  Arguments and result as msc_path, plus
+ * ref_cdeg[(waypoints+1)*dof], the original path's rows to compare with (centidegrees,
+ * multiples of the step; row 0 need not equal the start).  Instead of the first path
+ * found, every one of the first reach_retries reach poses in the canonical order is
+ * tried (tube radius tube_r0, then tube_r1) and the path with the smallest sum over the
+ * waypoints of the L1 joint distance in steps to ref is returned; the earlier reach
+ * pose keeps a tie.  MSC_NO_PATH if no reach pose gives a path. */
+msc_status msc_replan(msc_ctx* ctx, const msc_scene* scene, const msc_arm* arm,
+                      const int32_t* start_cdeg, const int32_t target[3], int32_t waypoints,
+                      int32_t max_delta_cdeg, const int32_t* ref_cdeg, const msc_opts* opts,
+                      int32_t* path_out);
+
 /* Forward-kinematics replay of `count` poses (poses_cdeg[count*dof]) on the GPU:
  * valid_out[i] = 1 if the base is free and every segment sample is inside the grid
  * and free, else 0; end_out[i*3..] = end voxel of the chain (computed even when

@@ -411,6 +411,43 @@ def plan_path(arm, occ, start, target, W: int, delta: int, r0: int = 1, r1: int 
     return NO_PATH, None, res
 
 
+def replan_path(arm, occ, start, target, W: int, delta: int, ref_path, r0: int = 1, r1: int = 2,
+                retries: int = 4, m: Optional[int] = None, approach=None):
+    """Midcourse replanning ("Dynamic Obstacles"): among the paths of the first
+    ``retries`` reach poses (each with tube radius r0, then r1, as in plan_path), the
+    one whose mean distance to the original path ``ref_path`` [(W+1), dof] is smallest:
+    the sum over the W+1 waypoints of the L1 joint distance in steps; ties by the earlier
+    reach pose.  Returns (status, path or None, reach result)."""
+    start = np.asarray(start, np.int64)
+    ref_path = np.asarray(ref_path, np.int64).reshape(W + 1, -1)
+    lim_lo, lim_hi = arm_limits(arm)
+    if np.any(start < lim_lo) or np.any(start > lim_hi) or W < 0 or delta < 0:
+        return E_ARG, None, None
+    valid, _ = poses(arm, occ, start[None, :])
+    if not valid[0]:
+        return E_ARG, None, None
+    wlo = np.maximum(lim_lo, start - W * delta)
+    whi = np.minimum(lim_hi, start + W * delta)
+    res = reach(arm, occ, target, m=m, want=retries, lo=wlo, hi=whi, ref=start, keep_sets=False,
+                approach=approach)
+    if res.status != OK:
+        return NO_REACH, None, res
+    best, best_cost = None, None
+    for q in res.sols:
+        radii = [r0] if r1 == r0 else [r0, r1]
+        for r in radii:
+            p = start[None, :].astype(np.int32) if W == 0 else tube_search(arm, occ, start, q, W, delta, r,
+                                                                            lim_lo, lim_hi)
+            if p is not None:
+                cost = int(np.abs(np.asarray(p, np.int64) - ref_path).sum())
+                if best_cost is None or cost < best_cost:
+                    best, best_cost = p, cost
+                break
+    if best is None:
+        return NO_PATH, None, res
+    return OK, best, res
+
+
 def arm_limits(arm):
     step = arm.step_cdeg
     lo = np.array(arm.lo_cdeg, np.int64) // step

@@ -1037,9 +1037,12 @@ msc_status reach_on(Lane* c, const msc_scene* sc, const msc_arm* arm, const int3
     return MSC_OK;
 }
 
+// ref_cdeg (may be null): the original path, (waypoints + 1) * dof centidegrees.  With
+// it every one of the first reach_retries reach poses is tried and the path nearest
+// the original one is kept (replanning); without it the first path found is returned.
 msc_status path_on(Lane* c, const msc_scene* sc, const msc_arm* arm, const int32_t* start_cdeg,
                    const int32_t target[3], int32_t waypoints, int32_t max_delta_cdeg, const msc_opts* opts,
-                   int32_t* path_out) {
+                   int32_t* path_out, const int32_t* ref_cdeg = nullptr) {
 
     MSC_TRY(check_scene(c, sc));
     MSC_TRY(check_arm(c, arm, sc->n));
@@ -1068,6 +1071,14 @@ msc_status path_on(Lane* c, const msc_scene* sc, const msc_arm* arm, const int32
         start[k] = start_cdeg[k] / arm->step_cdeg;
         if (start[k] < p.lo[k] || start[k] > p.hi[k]) return fail(c, MSC_E_ARG, "start angle %d outside its limits", k);
     }
+    std::vector<int32_t> ref;
+    if (ref_cdeg) {
+        ref.assign(ref_cdeg, ref_cdeg + (size_t)(waypoints + 1) * n);
+        for (auto& v : ref) {
+            if (v % arm->step_cdeg) return fail(c, MSC_E_ARG, "reference path angle not a multiple of the step");
+            v /= arm->step_cdeg;
+        }
+    }
     uint8_t ok = 0;
     MSC_TRY(pose_check_steps(c, sc, p, start, 1, &ok, nullptr));
     if (!ok) return fail(c, MSC_E_ARG, "start pose is not clear of obstacles");
@@ -1089,6 +1100,8 @@ msc_status path_on(Lane* c, const msc_scene* sc, const msc_arm* arm, const int32
         for (int k = 0; k < n; ++k) path_out[k] = start[k] * arm->step_cdeg;
         return MSC_OK;
     }
+    std::vector<int32_t> best;
+    int64_t best_cost = -1;
     std::vector<JointView> jv;
     for (int k = 0; k < n; ++k) {
         p.lo[k] = lim_lo[k];
@@ -1161,12 +1174,29 @@ msc_status path_on(Lane* c, const msc_scene* sc, const msc_arm* arm, const int32
             c->stats.attempts++;
             if (ok2) {
                 std::memcpy(path.data(), h_path, path.size() * 4);
-                for (size_t j = 0; j < path.size(); ++j) path_out[j] = path[j] * arm->step_cdeg;
-                c->stats.tube_r = rad;
-                c->stats.reach_index = i;
-                return MSC_OK;
+                if (ref.empty()) {
+                    for (size_t j = 0; j < path.size(); ++j) path_out[j] = path[j] * arm->step_cdeg;
+                    c->stats.tube_r = rad;
+                    c->stats.reach_index = i;
+                    return MSC_OK;
+                }
+                // replanning: the sum over the waypoints of the L1 distance (steps) to the
+                // original path; the earlier reach pose keeps a tie
+                int64_t cost = 0;
+                for (size_t j = 0; j < path.size(); ++j) cost += std::abs((int64_t)path[j] - ref[j]);
+                if (best_cost < 0 || cost < best_cost) {
+                    best = path;
+                    best_cost = cost;
+                    c->stats.tube_r = rad;
+                    c->stats.reach_index = i;
+                }
+                break;
             }
         }
+    }
+    if (best_cost >= 0) {
+        for (size_t j = 0; j < best.size(); ++j) path_out[j] = best[j] * arm->step_cdeg;
+        return MSC_OK;
     }
     return MSC_NO_PATH;
 }
@@ -1357,6 +1387,18 @@ msc_status msc_path(msc_ctx* o, const msc_scene* sc, const msc_arm* arm, const i
     Lane* c = o->control;
     prof_reset(c, opts ? opts->flags : 0u);
     msc_status st = path_on(c, sc, arm, start_cdeg, target, waypoints, max_delta_cdeg, opts, path_out);
+    prof_finish(c);
+    return st;
+}
+
+msc_status msc_replan(msc_ctx* o, const msc_scene* sc, const msc_arm* arm, const int32_t* start_cdeg,
+                      const int32_t target[3], int32_t waypoints, int32_t max_delta_cdeg, const int32_t* ref_cdeg,
+                      const msc_opts* opts, int32_t* path_out) {
+    if (!o) return MSC_E_ARG;
+    Lane* c = o->control;
+    if (!ref_cdeg) return fail(c, MSC_E_ARG, "NULL reference path");
+    prof_reset(c, opts ? opts->flags : 0u);
+    msc_status st = path_on(c, sc, arm, start_cdeg, target, waypoints, max_delta_cdeg, opts, path_out, ref_cdeg);
     prof_finish(c);
     return st;
 }

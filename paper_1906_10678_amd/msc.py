@@ -30,7 +30,7 @@ EXPORTS = [
     "msc_scene_destroy", "msc_reach", "msc_path", "msc_pose_check", "msc_get_stats",
     "msc_debug_tables", "msc_debug_raster", "msc_debug_set", "msc_last_error", "msc_get_timings",
     "msc_ctx_set_lanes", "msc_lane_bytes", "msc_batch", "msc_query_bytes", "msc_server_start",
-    "msc_server_submit", "msc_server_poll", "msc_server_wait", "msc_server_stop", "msc_refine",
+    "msc_server_submit", "msc_server_poll", "msc_server_wait", "msc_server_stop", "msc_refine", "msc_replan",
 ]
 
 
@@ -101,6 +101,7 @@ def load_library(path: str = LIB_PATH):
     L.msc_reach.argtypes = [c_void_p, c_void_p, P(MscArm), P(i32), P(MscOpts), P(i32)]
     L.msc_path.argtypes = [c_void_p, c_void_p, P(MscArm), P(i32), P(i32), i32, i32, P(MscOpts), P(i32)]
     L.msc_pose_check.argtypes = [c_void_p, c_void_p, P(MscArm), P(i32), i64, P(ctypes.c_uint8), P(i32)]
+    L.msc_replan.argtypes = [c_void_p, c_void_p, P(MscArm), P(i32), P(i32), i32, i32, P(i32), P(MscOpts), P(i32)]
     L.msc_get_stats.argtypes = [c_void_p, P(MscStats)]
     L.msc_refine.argtypes = [c_void_p, P(MscArm), P(i32), P(ctypes.c_double), i64, P(ctypes.c_double), P(i32)]
     L.msc_debug_tables.argtypes = [c_void_p, P(MscArm), i32, P(i32), P(i32)]
@@ -310,6 +311,23 @@ class Solver:
                                _ptr(t, ctypes.c_int32), int(waypoints), int(delta) * a.step_cdeg, ctypes.byref(o),
                                _ptr(out, ctypes.c_int32))
         self._check(rc, "msc_path")
+        return rc, (out.reshape(waypoints + 1, a.dof) // a.step_cdeg if rc == OK else None)
+
+    def replan(self, scene: Scene, arm, start: Sequence[int], target: Sequence[int], waypoints: int, delta: int,
+               ref_path, split_m: int = -1, tube_r0: int = 1, tube_r1: int = 2, retries: int = 4,
+               flags: int = 0, approach=None) -> Tuple[int, Optional[np.ndarray]]:
+        """msc_replan: the path of the first `retries` reach poses nearest ref_path
+        [(waypoints+1), dof] (steps)."""
+        a = make_arm(arm)
+        s = np.ascontiguousarray(np.asarray(start, np.int32) * a.step_cdeg)
+        t = np.ascontiguousarray(np.asarray(target, np.int32))
+        ref = np.ascontiguousarray(np.asarray(ref_path, np.int32).reshape(waypoints + 1, a.dof) * a.step_cdeg)
+        out = np.zeros((waypoints + 1) * a.dof, np.int32)
+        o = make_opts(split_m, tube_r0, tube_r1, retries, flags, approach)
+        rc = self.lib.msc_replan(self.ctx, scene.handle, ctypes.byref(a), _ptr(s, ctypes.c_int32),
+                                 _ptr(t, ctypes.c_int32), int(waypoints), int(delta) * a.step_cdeg,
+                                 _ptr(ref, ctypes.c_int32), ctypes.byref(o), _ptr(out, ctypes.c_int32))
+        self._check(rc, "msc_replan")
         return rc, (out.reshape(waypoints + 1, a.dof) // a.step_cdeg if rc == OK else None)
 
     def pose_check(self, scene: Scene, arm, q) -> Tuple[np.ndarray, np.ndarray]:

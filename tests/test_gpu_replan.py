@@ -1,0 +1,52 @@
+"""GPU parity of midcourse replanning (msc_replan: the candidate path nearest the
+original one) with the oracle, through the C ABI: tiny chains with random reference
+paths, a reference equal to the first path (msc_path's answer comes back), and
+full-size 8-DOF queries with a straight reference toward a drawn pose."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1906_10678_amd import msc, synth
+
+from test_gpu_parity import say
+from test_oracle_replan import path_case
+
+
+def reference(rng, start, W, span):
+    goal = np.asarray(start, np.int64) + rng.integers(-span, span + 1, size=len(start))
+    return np.rint(np.linspace(start, goal, W + 1)).astype(np.int64)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("seed", range(12))
+def test_replan_tiny(solver, seed):
+    arm, sc, occ, start, target, W = path_case(seed, with_scene=True)
+    scene = solver.scene(sc)
+    rng = synth.rng_for(914, seed)
+    ref = reference(rng, start, W, 3)
+    say("replan tiny", seed)
+    st, path = solver.replan(scene, arm, start, target, W, 1, ref)
+    rst, rpath, _ = oracle.replan_path(arm, occ, start, target, W, 1, ref)
+    assert st == rst
+    if st == msc.OK:
+        assert np.array_equal(path, rpath)
+    st1, p1 = solver.path(scene, arm, start, target, W, 1)
+    if st1 == msc.OK:
+        st2, p2 = solver.replan(scene, arm, start, target, W, 1, p1)
+        assert st2 == msc.OK and np.array_equal(p2, p1)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("seed", [0, 3])
+def test_replan_full_size(solver, seed):
+    q = synth.query_c2(seed, solver.pose_fn_for)
+    scene = solver.scene(q.scene)
+    occ = oracle.raster(q.scene)
+    rng = synth.rng_for(915, seed)
+    ref = reference(rng, q.start, q.waypoints, 16)
+    say("replan c2", seed)
+    st, path = solver.replan(scene, q.arm, q.start, q.target, q.waypoints, q.max_delta, ref, split_m=6)
+    rst, rpath, _ = oracle.replan_path(q.arm, occ, q.start, q.target, q.waypoints, q.max_delta, ref, m=6)
+    assert st == rst
+    if st == msc.OK:
+        assert np.array_equal(path, rpath)
