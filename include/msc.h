@@ -227,6 +227,8 @@ typedef struct {
     int32_t* out;                /* reach: [dof]; path: [(waypoints+1)*dof] centidegrees */
     msc_status status;           /* written when the query completes */
     float latency_ms;            /* written: submission (server) or batch start to completion */
+    const int32_t* ref_cdeg;     /* path: NULL, or the original path's [(waypoints+1)*dof] rows:
+                                    the query is then solved as msc_replan */
 } msc_query;
 
 /* Batched execution: solve nq independent queries; every worker lane takes the next

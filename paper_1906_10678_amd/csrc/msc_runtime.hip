@@ -1208,7 +1208,8 @@ msc_status query_on(Lane* L, msc_query* q, const msc_opts* opts) {
     if (q->kind == 0)
         st = reach_on(L, q->scene, q->arm, q->target, opts, q->out);
     else if (q->kind == 1)
-        st = path_on(L, q->scene, q->arm, q->start_cdeg, q->target, q->waypoints, q->max_delta_cdeg, opts, q->out);
+        st = path_on(L, q->scene, q->arm, q->start_cdeg, q->target, q->waypoints, q->max_delta_cdeg, opts, q->out,
+                     q->ref_cdeg);
     else
         st = fail(L, MSC_E_ARG, "query kind %d", q->kind);
     prof_finish(L);

@@ -58,7 +58,8 @@ class MscQuery(ctypes.Structure):
     _fields_ = [("scene", ctypes.c_void_p), ("arm", ctypes.POINTER(MscArm)), ("kind", ctypes.c_int32),
                 ("target", ctypes.c_int32 * 3), ("start_cdeg", ctypes.POINTER(ctypes.c_int32)),
                 ("waypoints", ctypes.c_int32), ("max_delta_cdeg", ctypes.c_int32),
-                ("out", ctypes.POINTER(ctypes.c_int32)), ("status", ctypes.c_int), ("latency_ms", ctypes.c_float)]
+                ("out", ctypes.POINTER(ctypes.c_int32)), ("status", ctypes.c_int), ("latency_ms", ctypes.c_float),
+                ("ref_cdeg", ctypes.POINTER(ctypes.c_int32))]
 
 
 class MscOpts(ctypes.Structure):
@@ -166,7 +167,7 @@ class QuerySpec:
     """A reach (kind 0) or reach + path (kind 1) query for msc_batch / the server; owns
     the ctypes buffers until the query completes."""
 
-    def __init__(self, scene: "Scene", arm, target, start=None, waypoints: int = 0, delta: int = 0):
+    def __init__(self, scene: "Scene", arm, target, start=None, waypoints: int = 0, delta: int = 0, ref=None):
         self.scene = scene
         self.arm_c = make_arm(arm)
         self.dof = self.arm_c.dof
@@ -186,6 +187,10 @@ class QuerySpec:
         q.waypoints = self.waypoints
         q.max_delta_cdeg = int(delta) * self.step
         q.out = _ptr(self.out, ctypes.c_int32)
+        # replanning: the original path's rows (steps), kept alive with the query
+        self.ref = None if ref is None else np.ascontiguousarray(
+            np.asarray(ref, np.int32).reshape(self.waypoints + 1, self.dof) * self.step)
+        q.ref_cdeg = _ptr(self.ref, ctypes.c_int32) if self.ref is not None else None
         q.status = -100
         self.c = q
 

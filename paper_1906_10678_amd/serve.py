@@ -267,7 +267,9 @@ class ServingLoop:
             if not valid[0]:
                 continue  # the arm's current pose is hit: nothing to replan from
             remaining = W - done_wp
-            spec = msc.QuerySpec(scene, ex.arm, ex.target, start=current, waypoints=remaining, delta=1)
+            # the new path nearest the rest of the original one ("Dynamic Obstacles")
+            spec = msc.QuerySpec(scene, ex.arm, ex.target, start=current, waypoints=remaining, delta=1,
+                                 ref=ex.path[done_wp:])
             req = Request("replan", self.tick, spec)
             req.execute = Executing(path=None, target=ex.target, arm=ex.arm, scene_idx=ex.scene_idx,
                                     start_tick=0, replans=ex.replans + 1)

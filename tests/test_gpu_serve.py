@@ -17,6 +17,9 @@ def solve_alone(solver, spec):
     if spec.kind == 0:
         return solver.reach(spec.scene, arm, list(spec.c.target))
     start = np.asarray(spec.start) // spec.step
+    if spec.ref is not None:
+        return solver.replan(spec.scene, arm, start, list(spec.c.target), spec.waypoints,
+                             spec.c.max_delta_cdeg // spec.step, spec.ref // spec.step)
     return solver.path(spec.scene, arm, start, list(spec.c.target), spec.waypoints, spec.c.max_delta_cdeg // spec.step)
 
 
