@@ -219,7 +219,8 @@ uint64_t msc_lane_bytes(msc_ctx* ctx);
 typedef struct {
     const msc_scene* scene;
     const msc_arm* arm;
-    int32_t kind;                /* 0 = reach pose (msc_reach), 1 = reach + path (msc_path) */
+    int32_t kind;                /* 0 = reach pose (msc_reach), 1 = reach + path (msc_path, or
+                                    msc_replan when ref_cdeg is set) */
     int32_t target[3];
     const int32_t* start_cdeg;   /* path: [dof] start pose */
     int32_t waypoints;           /* path: moves W */

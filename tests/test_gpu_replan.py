@@ -50,3 +50,25 @@ def test_replan_full_size(solver, seed):
     assert st == rst
     if st == msc.OK:
         assert np.array_equal(path, rpath)
+
+
+@pytest.mark.gpu
+def test_batched_replans_equal_alone(solver):
+    """Queries that carry an original path, solved by msc_batch over worker lanes, give
+    msc_replan's answers."""
+    specs, alone = [], []
+    for seed in range(8):
+        arm, sc, occ, start, target, W = path_case(seed, with_scene=True)
+        scene = solver.scene(sc)
+        ref = reference(synth.rng_for(917, seed), start, W, 3)
+        specs.append(msc.QuerySpec(scene, arm, target, start=start, waypoints=W, delta=1, ref=ref))
+        alone.append(solver.replan(scene, arm, start, target, W, 1, ref))
+    solver.set_lanes(3)
+    try:
+        res = solver.batch(specs)
+    finally:
+        solver.set_lanes(0)
+    for (st, path, _), (ast, apath) in zip(res, alone):
+        assert st == ast
+        if st == msc.OK:
+            assert np.array_equal(path, apath)
