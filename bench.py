@@ -17,7 +17,9 @@ Two phases:
 algorithmic bytes / kernel time summed over the expansion launches of the plain timed
 region; algorithmic bytes per launch = 8 * (non-zero 64-bit words of the input set +
 of the output set + occupancy words of the active box) in the layout
-[orientation][z][y][x/64], from captured stage sets of the same queries.
+[orientation][z][y][x/64], from captured stage sets of the same queries.  Also
+`copy_GBps` (a 1 GiB device-to-device copy timed in the same run, reads + writes: the
+achievable ceiling) and `frac_of_copy` = achieved / copy_GBps.
 `cpu_baseline` times the CPU oracle on one query of the same workload.
 """
 from __future__ import annotations
@@ -673,7 +675,8 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": measured_traffic(),
                 "kernel": "expand (k_expand_fwd + k_expand_bwd)", "launches": cnt,
                 "avg_launch_us": round(1e3 * ms_sum / max(cnt, 1), 2),
-                "alg_bytes_per_launch": round(b_sum / max(cnt, 1))}
+                "alg_bytes_per_launch": round(b_sum / max(cnt, 1)),
+                "alg_bytes_max_launch": int(max(v for a in alg for v in a.values()))}
     plain_lat = np.array(lat) * 1e3
     plain = {"solves_per_s": round(args.plain_steps / plain_wall, 3),
              "p50_ms": round(float(np.percentile(plain_lat, 50)), 4),
@@ -685,6 +688,21 @@ def main():
         print(json.dumps({"plain": plain, "roofline": roofline, "queries": len(queries), "splits": splits}),
               flush=True)
         return
+
+    # achievable HBM bandwidth on this device: a 1 GiB device-to-device copy (read + write)
+    src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * (1 << 30) / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    roofline["copy_GBps"] = round(copy_gbs, 1)
+    roofline["frac_of_copy"] = round(roofline["achieved"] / copy_gbs, 5)
 
     # ---- batched: each step rasterises the scenes of a batch and solves it with msc_batch
     def batch_step(b):
