@@ -178,6 +178,121 @@ def traffic_run(args):
     print("traffic run done", json.dumps(out), flush=True)
 
 
+C4_STAGES_PROFILE = os.path.join(ROOT, "profiles", "c4_big_stages.md")
+
+
+def c4_stages_run(args):
+    """The program of the big-stage measurement: six full-size batched-path plans (512^3,
+    2.5 deg, doubled lengths), each solved once to warm up, a 1 GiB device copy (the
+    counter calibration), then each solved once more with HIP-event times per launch."""
+    import torch
+
+    from paper_1906_10678_amd import msc, synth
+
+    solver = msc.Solver(0, workspace_bytes=args.workspace_gb << 30)
+    qs = synth.queries_c4(solver.pose_fn_for, scenes=1, per_scene=6)
+    scenes = [solver.scene(q.scene) for q in qs]
+    for q, sc in zip(qs, scenes):
+        solver.path(sc, q.arm, q.start, q.target, q.waypoints, q.max_delta)
+    torch.cuda.synchronize()
+    x = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    plans = []
+    for q, sc in zip(qs, scenes):
+        st, _ = solver.path(sc, q.arm, q.start, q.target, q.waypoints, q.max_delta, flags=msc.PROFILE)
+        stats = solver.stats()
+        plans.append({"status": st, "split": stats["split_m"], "fwd": stats["fwd_count"], "bwd": stats["bwd_count"],
+                      "recs": [list(r) for r in solver.timings()]})
+    torch.cuda.synchronize()
+    os.makedirs(os.path.dirname(args.c4_stages_run) or ".", exist_ok=True)
+    with open(args.c4_stages_run, "w") as f:
+        json.dump({"copy_bytes": 1 << 30, "plans": plans}, f)
+    print("c4 stages run done", len(plans), flush=True)
+
+
+def c4_stages_summary(args):
+    """HBM bytes (two counter passes) against HIP-event time (a run of the same program
+    outside the profiler) of the two kernels that dominate the full-size plans: the
+    backward stage into the set the meet probes, and the meet."""
+    import csv
+
+    fetch_csv, write_csv, times_json = args.c4_stages_summary
+    times = json.load(open(times_json))
+
+    def rows_after_copies(path, counter):
+        rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
+        rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+        copies = [r for r in rows if "copyBuffer" in r["Kernel_Name"]]
+        last = max(int(r["Dispatch_Id"]) for r in copies)
+        cal = [float(r["Counter_Value"]) for r in copies if int(r["Dispatch_Id"]) > last - 3]
+        factor = (times["copy_bytes"] / 1024.0) / (sum(cal) / len(cal))
+        return factor, [r for r in rows if int(r["Dispatch_Id"]) > last]
+
+    ff, frows = rows_after_copies(fetch_csv, "FETCH_SIZE")
+    wf, wrows = rows_after_copies(write_csv, "WRITE_SIZE")
+    def per_plan(rows):
+        """Per plan (the dispatches up to its meet): the last backward expansion (the
+        stage into B_m, dense or hashed) and the meet."""
+        out, last_bwd = [], None
+        for r in rows:
+            name = r["Kernel_Name"].split("(")[0]
+            if "k_expand_bwd" in name:
+                last_bwd = r
+            elif "k_meet" in name:
+                out.append((last_bwd, r))
+                last_bwd = None
+        return out
+
+    fp, wp = per_plan(frows), per_plan(wrows)
+    lines = ["# Full-size plans: HBM traffic of the two dominant kernels", "",
+             "Six plans of the batched-path workload (512^3 grid, 8-DOF chain with doubled lengths, 2.5 deg), "
+             "each solved once with HIP-event times per launch; HBM bytes from two rocprofv3 counter passes "
+             "over the same program, scaled by a 1 GiB device copy (FETCH x %.4f, WRITE x %.4f).  Per plan, "
+             "the backward stage into the set the meet probes (its last backward expansion) and the meet."
+             % (ff, wf), "",
+             "```",
+             "python -u bench.py --c4-stages-run gpurun_out/c4_times.json --workspace-gb 200",
+             "timeout -s KILL 240 rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/c4_fetch -o run "
+             "-- python -u bench.py --c4-stages-run gpurun_out/c4_pmc.json --workspace-gb 200",
+             "timeout -s KILL 240 rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/c4_write -o run "
+             "-- python -u bench.py --c4-stages-run gpurun_out/c4_pmc.json --workspace-gb 200",
+             "python bench.py --c4-stages-summary gpurun_out/c4_fetch/run_counter_collection.csv "
+             "gpurun_out/c4_write/run_counter_collection.csv gpurun_out/c4_times.json",
+             "```", "",
+             "| plan | kernel | input states | HBM read MB | HBM write MB | ms (events) | HBM GB/s | of 8 TB/s |",
+             "|---|---|---|---|---|---|---|---|"]
+    tot = {"bwd": [0.0, 0.0], "meet": [0.0, 0.0]}
+    for i, p in enumerate(times["plans"][:len(fp)]):
+        bwd_recs = [r for r in p["recs"] if r[0] == "expand_bwd"]
+        meet_recs = [r for r in p["recs"] if r[0] == "join"]
+        pairs = [("bwd", bwd_recs[-1] if bwd_recs else None, fp[i][0], wp[i][0]),
+                 ("meet", meet_recs[-1] if meet_recs else None, fp[i][1], wp[i][1])]
+        for kind, rec, f, w in pairs:
+            if rec is None or f is None or w is None:
+                continue
+            rb = float(f["Counter_Value"]) * ff * 1024
+            wb = float(w["Counter_Value"]) * wf * 1024
+            ms = rec[4]
+            tot[kind][0] += rb + wb
+            tot[kind][1] += ms
+            lines.append("| %d | %s | %d | %.1f | %.1f | %.3f | %.0f | %.3f |" % (
+                i, f["Kernel_Name"].split("(")[0], rec[2], rb / 1e6, wb / 1e6, ms,
+                (rb + wb) / (ms * 1e-3) / 1e9, (rb + wb) / (ms * 1e-3) / 8e12))
+    for kind, label in (("bwd", "backward stage into B_m"), ("meet", "meet")):
+        b, ms = tot[kind]
+        if ms > 0:
+            lines.append("| all | %s | | | | %.3f | %.0f | %.3f |" % (label, ms, b / (ms * 1e-3) / 1e9,
+                                                                    b / (ms * 1e-3) / 8e12))
+    lines += ["", "- kernel sources sha256: `%s`" % kernel_source_hash(), ""]
+    with open(C4_STAGES_PROFILE, "w") as f:
+        f.write("\n".join(lines))
+    print("wrote", C4_STAGES_PROFILE, flush=True)
+
+
 def traffic_summary(args):
     """Writes the expansion-traffic summary from the two counter CSVs of the traffic run."""
     import csv
@@ -550,6 +665,10 @@ def bench_c5(args):
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--c4-stages-run", metavar="OUT_JSON",
+                    help="run the program of the full-size big-stage measurement (see profiles/c4_big_stages.md)")
+    ap.add_argument("--c4-stages-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "TIMES_JSON"),
+                    help="write profiles/c4_big_stages.md")
     ap.add_argument("--arm", choices=["chain", "gms"], default="chain",
                     help="gms: the same workload with the paper's arm model, two DOF per segment (a variant)")
     ap.add_argument("--workload", choices=["c2", "c2serve", "c3", "c4", "c5", "refine", "replan"], default="c2",
@@ -590,11 +709,15 @@ def main():
         return traffic_summary(args)
     if args.trace_summary:
         return trace_summary(args)
+    if args.c4_stages_summary:
+        return c4_stages_summary(args)
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the solver has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
     if args.traffic_run:
         return traffic_run(args)
+    if args.c4_stages_run:
+        return c4_stages_run(args)
     if args.workload == "c2serve":
         return bench_c2serve(args)
     if args.workload == "c3":
