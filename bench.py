@@ -19,7 +19,9 @@ region; algorithmic bytes per launch = 8 * (non-zero 64-bit words of the input s
 of the output set + occupancy words of the active box) in the layout
 [orientation][z][y][x/64], from captured stage sets of the same queries.  Also
 `copy_GBps` (a 1 GiB device-to-device copy timed in the same run, reads + writes: the
-achievable ceiling) and `frac_of_copy` = achieved / copy_GBps.
+achievable ceiling), `frac_of_copy` = achieved / copy_GBps, and `full_size_hbm`: the HBM
+rate of the meet and of the backward stage into B_m on full-size plans, read from the
+committed counter summary (profiles/c4_big_stages.md) while the kernel sources match.
 `cpu_baseline` times the CPU oracle on one query of the same workload.
 """
 from __future__ import annotations
@@ -137,6 +139,26 @@ def measured_traffic():
         return float(fields["HBM bytes per expansion launch"])
     except (KeyError, ValueError):
         return None
+
+
+def full_size_stages():
+    """HBM rate of the two dominant kernels on full-size plans, from the committed
+    counter summary (profiles/c4_big_stages.md), or None when it is missing or was taken
+    on other kernel sources."""
+    try:
+        with open(C4_STAGES_PROFILE) as f:
+            text = f.read()
+    except OSError:
+        return None
+    if "kernel sources sha256: `%s`" % kernel_source_hash() not in text:
+        return None
+    out = {}
+    for line in text.splitlines():
+        cells = [c.strip() for c in line.strip("|").split("|")]
+        if len(cells) == 8 and cells[0] == "all":
+            key = "meet" if cells[1] == "meet" else "backward_into_B_m"
+            out[key] = {"hbm_GBps": float(cells[6]), "frac": float(cells[7])}
+    return out or None
 
 
 def traffic_run(args):
@@ -826,6 +848,8 @@ def main():
     del src, dst
     roofline["copy_GBps"] = round(copy_gbs, 1)
     roofline["frac_of_copy"] = round(roofline["achieved"] / copy_gbs, 5)
+    # the kernels on full-size plans, where the sets stream from HBM (counter summary)
+    roofline["full_size_hbm"] = full_size_stages()
 
     # ---- batched: each step rasterises the scenes of a batch and solves it with msc_batch
     def batch_step(b):
