@@ -49,3 +49,34 @@ def test_host_only_entry_points():
     # a NULL context is rejected without touching the device
     assert lib.msc_reach(None, None, None, None, None, None) == msc.E_ARG
     assert lib.msc_last_error(None) == b"NULL context"
+
+
+def test_ctypes_layouts_match_a_c_compiler(tmp_path):
+    """Every struct of include/msc.h has the same size and field offsets in the binding
+    as a C compiler gives it (gcc on the header itself)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"msc_arm": msc.MscArm, "msc_box": msc.MscBox, "msc_sphere": msc.MscSphere,
+               "msc_opts": msc.MscOpts, "msc_query": msc.MscQuery, "msc_stats": msc.MscStats,
+               "msc_timing": msc.MscTiming}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "msc.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for fname, _ in py._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, fname, cname, fname))
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = {}
+    for line in subprocess.check_output([str(exe)]).decode().splitlines():
+        a, b, v = line.split()
+        got[(a, b)] = int(v)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
