@@ -1,0 +1,54 @@
+"""Full-size batched-path plans (512^3 grid, 8-DOF chain with doubled lengths, 2.5 deg
+steps) against stored oracle answers, through the C ABI: the plans of scene 0 with at
+most 20 waypoints (the oracle's time grows steeply with the window)."""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1906_10678_amd import msc, synth
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.join(HERE, "golden"))
+from make_c2_paths import fingerprint  # noqa: E402
+
+GOLDEN_PATH = os.path.join(HERE, "golden", "c4_paths.json")
+
+
+def _golden():
+    if not os.path.exists(GOLDEN_PATH):
+        return {"rows": [], "plans": 0}
+    with open(GOLDEN_PATH) as f:
+        return json.load(f)
+
+
+@pytest.mark.gpu
+def test_c4_full_size_paths_match_oracle(solver):
+    g = _golden()
+    assert g["rows"], "no stored answers: run tests/golden/make_c4_paths.py"
+    qs = synth.queries_c4(solver.pose_fn_for, scenes=1, per_scene=g["plans"])
+    scenes = {}
+    for row in g["rows"]:
+        q = qs[row["plan"]]
+        print("c4 golden plan", row["plan"], "waypoints", q.waypoints, flush=True)
+        assert fingerprint(q) == row["fingerprint"], "stored answers are stale: rerun tests/golden/make_c4_paths.py"
+        key = q.seed[:2]
+        if key not in scenes:
+            scenes[key] = solver.scene(q.scene)
+        st, path = solver.path(scenes[key], q.arm, q.start, q.target, q.waypoints, q.max_delta)
+        assert st == row["status"], (row["plan"], st, row["status"])
+        if st == msc.OK:
+            assert np.array_equal(path, np.asarray(row["path"], np.int32)), row["plan"]
+
+
+def test_c4_golden_file_is_consistent():
+    g = _golden()
+    for r in g["rows"]:
+        assert r["waypoints"] <= g["max_waypoints"]
+        assert r["status"] in (0, 1, 2)
+        if r["status"] == 0:
+            p = np.asarray(r["path"])
+            assert p.shape == (r["waypoints"] + 1, 8)
+            assert np.abs(np.diff(p, axis=0)).max() <= 1
