@@ -1,0 +1,59 @@
+"""Full-size batched reach (128^3 / 256^3 grids, unwindowed joints, 5 deg steps) against
+stored oracle answers, through msc_batch over worker lanes: the queries of scenes 0..15
+whose arm has at most 6 DOF (the oracle's time grows steeply with the DOF)."""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1906_10678_amd import msc, synth
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.join(HERE, "golden"))
+from make_c2_paths import fingerprint  # noqa: E402
+
+GOLDEN_PATH = os.path.join(HERE, "golden", "c3_reach.json")
+
+
+def _golden():
+    if not os.path.exists(GOLDEN_PATH):
+        return {"rows": []}
+    with open(GOLDEN_PATH) as f:
+        return json.load(f)
+
+
+@pytest.mark.gpu
+def test_c3_full_size_batch_matches_oracle(solver):
+    g = _golden()
+    assert g["rows"], "no stored answers: run tests/golden/make_c3_reach.py"
+    qs = synth.queries_c3(solver.pose_fn_for, scenes=g["scenes"], per_scene=g["per_scene"])
+    scenes, specs, rows = {}, [], []
+    for row in g["rows"]:
+        q = qs[row["query"]]
+        assert fingerprint(q) == row["fingerprint"], "stored answers are stale: rerun tests/golden/make_c3_reach.py"
+        key = q.seed[:2]
+        if key not in scenes:
+            scenes[key] = solver.scene(q.scene)
+        specs.append(msc.QuerySpec(scenes[key], q.arm, q.target))
+        rows.append(row)
+    print("c3 golden: %d queries" % len(specs), flush=True)
+    solver.set_lanes(4)
+    try:
+        res = solver.batch(specs)
+    finally:
+        solver.set_lanes(0)
+    for row, (st, pose, _) in zip(rows, res):
+        assert st == row["status"], (row["query"], st, row["status"])
+        if st == msc.OK:
+            assert np.array_equal(pose, np.asarray(row["pose"], np.int32)), row["query"]
+
+
+def test_c3_golden_file_is_consistent():
+    g = _golden()
+    for r in g["rows"]:
+        assert r["dof"] <= g["max_dof"] and r["n"] in (128, 256)
+        assert r["status"] in (0, 1)
+        if r["status"] == 0:
+            assert len(r["pose"]) == r["dof"]
