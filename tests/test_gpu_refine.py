@@ -81,3 +81,14 @@ def test_refine_full_size_reach_pose(solver):
 def test_refine_rejects_arms_without_two_dof_segments(solver):
     with pytest.raises(msc.MscError):
         solver.refine(synth.arm_c2(), np.zeros((1, 8), np.int32), np.zeros((1, 3)))
+
+
+@pytest.mark.gpu
+def test_refine_rejects_non_finite_targets(solver):
+    arm = synth.arm_gms()
+    q = np.zeros((2, arm.dof), np.int32)
+    t = np.array([[10.0, 10.0, 10.0], [np.nan, 0.0, 0.0]])
+    with pytest.raises(msc.MscError):
+        solver.refine(arm, q, t)
+    ang, st = solver.refine(arm, q[:1], t[:1])
+    assert ang.shape == (1, arm.dof)

@@ -2,6 +2,8 @@
 original one) with the oracle, through the C ABI: tiny chains with random reference
 paths, a reference equal to the first path (msc_path's answer comes back), and
 full-size 8-DOF queries with a straight reference toward a drawn pose."""
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -72,3 +74,29 @@ def test_batched_replans_equal_alone(solver):
         assert st == ast
         if st == msc.OK:
             assert np.array_equal(path, apath)
+
+
+@pytest.mark.gpu
+def test_replan_argument_errors(solver):
+    arm, sc, occ, start, target, W = path_case(0, with_scene=True)
+    scene = solver.scene(sc)
+    ref = np.repeat(np.asarray(start, np.int64)[None, :], W + 1, axis=0)
+    a = msc.make_arm(arm)
+    s = np.ascontiguousarray(np.asarray(start, np.int32) * a.step_cdeg)
+    t = np.ascontiguousarray(np.asarray(target, np.int32))
+    out = np.zeros((W + 1) * a.dof, np.int32)
+    bad = np.ascontiguousarray(ref.astype(np.int32) * a.step_cdeg + 1)   # not a multiple of the step
+    o = msc.make_opts()
+
+    def P(x):
+        return x.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+    rc = solver.lib.msc_replan(solver.ctx, scene.handle, ctypes.byref(a), P(s), P(t), W, a.step_cdeg, P(bad),
+                               ctypes.byref(o), P(out))
+    assert rc == msc.E_ARG
+    rc = solver.lib.msc_replan(solver.ctx, scene.handle, ctypes.byref(a), P(s), P(t), W, a.step_cdeg, None,
+                               ctypes.byref(o), P(out))
+    assert rc == msc.E_ARG
+    # a valid call still works after the rejected ones
+    st, _ = solver.replan(scene, arm, start, target, W, 1, ref)
+    assert st in (msc.OK, msc.NO_REACH, msc.NO_PATH)
