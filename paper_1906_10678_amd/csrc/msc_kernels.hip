@@ -442,16 +442,33 @@ __global__ void k_orient(OrientArgs oa, uint64_t* rows_ie, uint64_t* rows_ia) {
         A[t] = (t == ia0);
         E[t] = (t == ie0);
     }
+    if (tid < 4) {
+        Abits[tid] = (ia0 >> 6) == tid ? 1ull << (ia0 & 63) : 0ull;
+        Ebits[tid] = (ie0 >> 6) == tid ? 1ull << (ie0 & 63) : 0ull;
+    }
     __syncthreads();
     for (int k = 0; k <= n; ++k) {
         if (k > 0) {
             const bool yaw = oa.type[k - 1] == 0;
             const int lo = oa.lo[k - 1], hi = oa.hi[k - 1];
             uint8_t* S = yaw ? A : E;
+            const uint64_t* Sb = yaw ? Abits : Ebits;     // S as bits (gathered below for k - 1)
+            // t is reached iff S holds a value in the circular interval t - hi .. t - lo:
+            // one masked AND of the bit rows per value (no loop over the window)
             for (int t = tid; t < na; t += blockDim.x) {
-                uint8_t any = 0;
-                for (int a = lo; a <= hi && !any; ++a) any = S[wrap_na(t - a, na)];
-                T[t] = any;
+                uint64_t m[4] = {0, 0, 0, 0};
+                if (hi - lo + 1 >= na) {
+                    mask_range(m, 0, na - 1);
+                } else {
+                    const int s0 = wrap_na(t - hi, na), e0 = s0 + (hi - lo);
+                    if (e0 < na) {
+                        mask_range(m, s0, e0);
+                    } else {
+                        mask_range(m, s0, na - 1);
+                        mask_range(m, 0, e0 - na);
+                    }
+                }
+                T[t] = ((m[0] & Sb[0]) | (m[1] & Sb[1]) | (m[2] & Sb[2]) | (m[3] & Sb[3])) != 0;
             }
             __syncthreads();
             for (int t = tid; t < na; t += blockDim.x) S[t] = T[t];
@@ -1309,6 +1326,7 @@ __global__ void __launch_bounds__(kDfsThreads) k_dfs(DfsArgs a) {
     __shared__ int olen[kMaxDof];
     __shared__ uint64_t state[kMaxDof + 1];
     __shared__ uint64_t cmask[kMaxDof][4];
+    __shared__ uint64_t nextk[kMaxDof][kMaxNa];   // the state each accepted candidate leads to
     __shared__ int pick[kMaxDof];
     __shared__ int depth, nsol, done, need_eval;
     __shared__ long long steps;
@@ -1363,6 +1381,7 @@ __global__ void __launch_bounds__(kDfsThreads) k_dfs(DfsArgs a) {
                     const bool mem = set_member(a.sets[d + 1], key);
                     const bool clear = segment_clear_all(a.g, J, o, x, y, z);
                     ok = mem && clear;
+                    if (ok) nextk[d][c] = key;
                 }
                 const unsigned long long b = __ballot(ok);
                 if (tid == 0) cmask[d][c0 >> 6] = b;
@@ -1408,17 +1427,8 @@ __global__ void __launch_bounds__(kDfsThreads) k_dfs(DfsArgs a) {
                     --depth;
                     continue;
                 }
-                const JointView J = a.joints[depth];
-                int av = order[depth][j];
-                pick[depth] = av;
-                int x, y, z, ia, ie;
-                unpack_key(state[depth], x, y, z, ia, ie);
-                if (J.type == 0)
-                    ia = wrap_na(ia + av, na);
-                else
-                    ie = wrap_na(ie + av, na);
-                short4 dd = J.off[ia * na + ie];
-                state[depth + 1] = pack_key(x + dd.x, y + dd.y, z + dd.z, ia, ie);
+                pick[depth] = order[depth][j];
+                state[depth + 1] = nextk[depth][j];
                 ++depth;
                 if (depth < a.n) {
                     need_eval = 1;
