@@ -1483,11 +1483,65 @@ __global__ void k_pose_check(PoseArgs a, const int32_t* q, int64_t count, uint8_
     }
 }
 
+// The same for a few poses, one wave per pose: lane k takes segment k.  Its orientation
+// is the sum of the joint steps before it, its start the prefix sum of the earlier end
+// offsets (a scan over the lanes), so the segments are tested together instead of one
+// after another.
+__global__ void __launch_bounds__(64) k_pose_check_wave(PoseArgs a, const int32_t* q, int64_t count,
+                                                        uint8_t* valid, int32_t* ends) {
+    const int lane = threadIdx.x;
+    const int64_t i = blockIdx.x;
+    if (i >= count) return;
+    const int32_t* qi = q + i * a.n;
+    const bool live = lane < a.n;
+    int o = 0, dx = 0, dy = 0, dz = 0;
+    if (live) {
+        int ia = a.ia0, ie = a.ie0;
+        for (int k = 0; k <= lane; ++k) {
+            if (a.joints[k].type == 0)
+                ia = wrap_na(ia + qi[k], a.na);
+            else
+                ie = wrap_na(ie + qi[k], a.na);
+        }
+        o = ia * a.na + ie;
+        const short4 d = a.joints[lane].off[o];
+        dx = d.x;
+        dy = d.y;
+        dz = d.z;
+    }
+    // inclusive scan of the offsets over the lanes; the segment starts at the exclusive sum
+    int sx = dx, sy = dy, sz = dz;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int tx = __shfl_up(sx, off, 64), ty = __shfl_up(sy, off, 64), tz = __shfl_up(sz, off, 64);
+        if (lane >= off) {
+            sx += tx;
+            sy += ty;
+            sz += tz;
+        }
+    }
+    const int x = a.bx + sx - dx, y = a.by + sy - dy, z = a.bz + sz - dz;
+    bool ok = true;
+    if (live) ok = segment_clear_all(a.g, a.joints[lane], o, x, y, z);
+    if (lane == 0) ok = ok && cell_free(a.g, a.bx, a.by, a.bz);
+    const bool all = __ballot(!ok) == 0;
+    if (lane == a.n - 1) {
+        valid[i] = all ? 1 : 0;
+        if (ends) {
+            ends[i * 3] = a.bx + sx;
+            ends[i * 3 + 1] = a.by + sy;
+            ends[i * 3 + 2] = a.bz + sz;
+        }
+    }
+}
+
 hipError_t launch_pose_check(const PoseArgs& a, const int32_t* q, int64_t count, uint8_t* valid, int32_t* ends,
                              hipStream_t st) {
     if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pose_check, dim3(grid_for((uint64_t)count)), dim3(kBlock), 0, st, a, q, count, valid,
-                       ends);
+    if (count <= 64 && a.n >= 1)
+        hipLaunchKernelGGL(k_pose_check_wave, dim3((uint32_t)count), dim3(64), 0, st, a, q, count, valid, ends);
+    else
+        hipLaunchKernelGGL(k_pose_check, dim3(grid_for((uint64_t)count)), dim3(kBlock), 0, st, a, q, count, valid,
+                           ends);
     return hipGetLastError();
 }
 
