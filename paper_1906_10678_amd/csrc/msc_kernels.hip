@@ -551,6 +551,20 @@ __global__ void k_seed_bwd(SetView s, GridView g, int x, int y, int z, const uin
             ie = o % na;
             ok = !prune || ((rows_ie[ia * 4 + (ie >> 6)] >> (ie & 63)) & 1ull);
             ok = ok && (!cone || ((cone[ia * 4 + (ie >> 6)] >> (ie & 63)) & 1ull));
+        }
+        // a dense set whose orientation index is ia * na + ie, with word-aligned voxel
+        // blocks: the wave's 64 orientations are the 64 bits of one word, set by one atomic
+        uint64_t bit0 = 0;
+        const bool one_word = s.kind == kDense && !s.fast_ia && ((na * na) & 63) == 0 &&
+                              dense_bit(s, x, y, z, o0 / na, o0 % na, bit0) && (bit0 & 63) == 0;
+        if (one_word) {
+            const uint64_t want = __ballot(ok);
+            uint64_t added = 0;
+            if (lane == 0 && want)
+                added = want & ~(uint64_t)atomicOr((unsigned long long*)&s.words[bit0 >> 6], (unsigned long long)want);
+            added = __shfl(added, 0, 64);
+            ok = (added >> lane) & 1ull;
+        } else {
             ok = ok && set_insert(s, x, y, z, ia, ie) > 0;
         }
         const uint64_t bal = __ballot(ok);
