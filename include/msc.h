@@ -126,7 +126,8 @@ msc_status msc_ctx_destroy(msc_ctx* ctx);
 /* Device bytes needed by the occupancy grid of an n^3 scene. */
 uint64_t msc_scene_bytes(int32_t n);
 
-/* Rasterise a scene into the caller's device buffer dev_grid (msc_scene_bytes(n) bytes):
+/* Rasterise a scene into the caller's device buffer dev_grid (msc_scene_bytes(n) bytes,
+ * or msc_scene_bytes_dynamic(n, ticks) for a scene with moving obstacles):
  * a voxel is blocked when it lies within Euclidean distance dilate_r of a box or within
  * r + dilate_r of a sphere centre ("The representations of the arm and obstacles":
  * obstacles masked in a voxel array, dilated for thickness and clearance).  Voxels
@@ -136,6 +137,24 @@ msc_status msc_scene_create(msc_ctx* ctx, int32_t n, int32_t dilate_r, const msc
                             int32_t nbox, const msc_sphere* spheres, int32_t nsph, void* dev_grid,
                             uint64_t grid_bytes, msc_scene** out);
 msc_status msc_scene_destroy(msc_scene* scene);
+
+/* Moving obstacles ("Dynamic Obstacles": obstacles detected while the arm moves, the
+ * voxel mask updated as they move).  A scene whose grid buffer holds
+ * msc_scene_bytes_dynamic(n, ticks) bytes (ticks in 1..64) keeps its static grid and
+ * up to `ticks` grids of recent logical ticks; returns 0 for bad arguments. */
+uint64_t msc_scene_bytes_dynamic(int32_t n, int32_t ticks);
+
+/* The scene's grid for logical tick `tick`: the static obstacles of msc_scene_create
+ * plus the boxes[nbox] of this tick, dilated by the same radius, written into a grid
+ * of a tick that no query is using (the oldest such; the current grid only when no other
+ * is free), asynchronously on the context's stream.  The new grid becomes the scene's current grid: msc_reach / msc_path /
+ * msc_pose_check / msc_debug_raster calls made afterwards see it, and so do queries
+ * submitted to the server afterwards (msc_server_submit binds a query to the grid of
+ * its submission tick, so its result does not depend on later ticks or on the other
+ * queries in flight).  Errors: E_NOMEM if the buffer holds no grids of ticks,
+ * E_CAPACITY if every grid of a tick is still in use, E_ARG for a box extent < 1.
+ * Called from the thread that owns the context. */
+msc_status msc_scene_set_dynamic(msc_scene* scene, const msc_box* boxes, int32_t nbox, int64_t tick);
 
 /* Reach pose ("The procedure for IK solution", Steps 1-3).  Writes the first pose of
  * the canonical order into angles_out[dof] (centidegrees): joint tuples ordered
@@ -230,6 +249,15 @@ typedef struct {
     float latency_ms;            /* written: submission (server) or batch start to completion */
     const int32_t* ref_cdeg;     /* path: NULL, or the original path's [(waypoints+1)*dof] rows:
                                     the query is then solved as msc_replan */
+    int64_t tick;                /* written: the logical tick of the scene grid the query was
+                                    solved on (0 for a scene without moving obstacles) */
+    int32_t execute_ticks;       /* server path queries: > 0 = once solved, the path executes on
+                                    the server's logical clock, waypoint w reached w*execute_ticks
+                                    ticks after it completed, and msc_server_step re-validates its
+                                    remaining waypoints; 0 = not executed */
+    int32_t replan_depth;        /* written by the server: 0 for a submitted query, 1 + that of the
+                                    path it replaces for a replan issued by msc_server_step */
+    char error[128];             /* written: the message when status < 0, else "" */
 } msc_query;
 
 /* Batched execution: solve nq independent queries; every worker lane takes the next
@@ -249,9 +277,39 @@ uint64_t msc_query_bytes(const msc_query* q);
  * the server is not running.  poll sets *done = 1 once q->status is written. */
 msc_status msc_server_start(msc_ctx* ctx, const msc_opts* opts);
 msc_status msc_server_submit(msc_ctx* ctx, msc_query* q, uint64_t* ticket);
+/* *done = 1 once (and only the first time) the ticket's query has completed; E_STATE for
+ * a ticket that was never issued or whose completion was already reported. */
 msc_status msc_server_poll(msc_ctx* ctx, uint64_t ticket, int32_t* done);
+/* Blocks until the ticket's query has completed; E_STATE as for msc_server_poll. */
 msc_status msc_server_wait(msc_ctx* ctx, uint64_t ticket);
 msc_status msc_server_stop(msc_ctx* ctx);
+
+/* One logical tick of the server ("Dynamic Obstacles": a moving obstacle that will block
+ * a waypoint ahead of the moving arm triggers a new path for the rest of the way, from
+ * the current pose, with the least distance to the original path).  Call it after the
+ * scenes' msc_scene_set_dynamic for the same tick.  For every path executing on the
+ * server (msc_query.execute_ticks): the waypoint w reached at this tick is
+ * (tick - completion tick) / execute_ticks; a path past its last waypoint is finished;
+ * otherwise its waypoints w..W are re-validated on the scene's current grid (sampled
+ * segment points free and in the grid, as msc_pose_check).  If they are all clear the
+ * path goes on; if waypoint w itself is blocked the path stops (no pose to replan
+ * from); else a replan (msc_replan semantics: start = waypoint w, W - w waypoints, the
+ * same target, reference = waypoints w..W) is queued ahead of submitted queries and,
+ * once solved, executes in its place.  The tick must not decrease.  report may be NULL. */
+typedef struct {
+    int32_t executing;      /* paths executing after the step */
+    int32_t finished;       /* paths that passed their last waypoint */
+    int32_t stopped;        /* paths whose current pose is blocked */
+    int32_t replans;        /* replans queued */
+    int64_t poses_checked;  /* waypoints re-validated */
+} msc_step_report;
+msc_status msc_server_step(msc_ctx* ctx, int64_t tick, msc_step_report* report);
+
+/* Copies up to cap completed replans issued by msc_server_step into out (oldest first)
+ * and sets *count.  Their pointers (arm, start_cdeg, out, ref_cdeg) point to storage the
+ * server keeps until the next msc_server_take_replans or msc_server_stop; status,
+ * tick, latency_ms (from the step that issued it) and replan_depth are filled. */
+msc_status msc_server_take_replans(msc_ctx* ctx, msc_query* out, int32_t cap, int32_t* count);
 
 /* Statistics of the last msc_reach / msc_path call on this context. */
 typedef struct {

@@ -68,6 +68,15 @@ hipError_t launch_tables(int na, int S, int L, short4* off, short4* sweep, unsig
                          hipStream_t st);
 hipError_t launch_raster(uint64_t* occ, int n, int wpr, int r, const int32_t* boxes, int nbox,
                          const int32_t* spheres, int nsph, hipStream_t st);
+// Moving boxes of one tick, passed by value: (lo x, y, z, ext x, y, z) per box.
+constexpr int kDynBoxes = 16;
+struct DynBoxes {
+    int32_t b[kDynBoxes * 6];
+    int count;
+};
+// dst = src | dilated boxes (src may equal dst).
+hipError_t launch_raster_dyn(uint64_t* dst, const uint64_t* src, int n, int wpr, int r, const DynBoxes& db,
+                             hipStream_t st);
 struct OrientArgs {
     int n, na, ia0, ie0;
     int type[kMaxDof], lo[kMaxDof], hi[kMaxDof];

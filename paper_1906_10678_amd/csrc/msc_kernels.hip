@@ -425,6 +425,42 @@ hipError_t launch_raster(uint64_t* occ, int n, int wpr, int r, const int32_t* bo
     return hipGetLastError();
 }
 
+// Grid of one tick with moving boxes ("Dynamic Obstacles"): dst = src OR the boxes of
+// `db` dilated by r, word by word (the same row spans as k_raster).  src is the static
+// grid (its bits past the grid edge are already set), or dst itself when a further
+// launch adds more boxes.  The boxes travel in the kernel arguments, so the call needs
+// no staging memory.
+__global__ void k_raster_dyn(uint64_t* dst, const uint64_t* src, int n, int wpr, int r, DynBoxes db) {
+    const uint64_t total = (uint64_t)n * n * wpr;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < total;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const int xw = (int)(i % wpr);
+        const uint64_t row = i / wpr;
+        const long long y = (long long)(row % n), z = (long long)(row / n);
+        const long long x0 = 64ll * xw;
+        uint64_t bits = src[i];
+        for (int b = 0; b < db.count; ++b) {
+            const int32_t* B = db.b + 6 * b;
+            const long long ylo = B[1], yhi = (long long)B[1] + B[4] - 1;
+            const long long zlo = B[2], zhi = (long long)B[2] + B[5] - 1;
+            const long long dy = y < ylo ? ylo - y : (y > yhi ? y - yhi : 0);
+            const long long dz = z < zlo ? zlo - z : (z > zhi ? z - zhi : 0);
+            const long long rem = (long long)r * r - dy * dy - dz * dz;
+            if (rem < 0) continue;
+            const long long w = isqrt_floor(rem);
+            bits |= span_bits((long long)B[0] - w, (long long)B[0] + B[3] - 1 + w, x0);
+        }
+        dst[i] = bits;
+    }
+}
+
+hipError_t launch_raster_dyn(uint64_t* dst, const uint64_t* src, int n, int wpr, int r, const DynBoxes& db,
+                             hipStream_t st) {
+    const uint64_t total = (uint64_t)n * n * wpr;
+    hipLaunchKernelGGL(k_raster_dyn, dim3(grid_for(total)), dim3(kBlock), 0, st, dst, src, n, wpr, r, db);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Orientation reachability O_k (k = 0..n): orientations the chain can have after k
 // joints, positions ignored.  Yaw joints move only the azimuth index and pitch joints

@@ -14,7 +14,9 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <memory>
 #include <mutex>
+#include <set>
 #include <string>
 #include <thread>
 #include <tuple>
@@ -32,6 +34,7 @@ namespace {
 constexpr uint64_t kAlign = 256;
 constexpr size_t kStagingBytes = 1 << 20;
 constexpr int kCounters = 512;
+constexpr int kMaxTickGrids = 64;   // grids of ticks per scene
 
 struct TableEntry {
     short4* off;
@@ -95,12 +98,31 @@ struct msc_ctx {
     ServerState* server = nullptr;
 };
 
+// Grids of ticks of a scene with moving obstacles.  Slot 0 holds the static obstacles;
+// slots 1.. hold the grids of recent ticks, each with the number of queries solving on
+// it and an event recorded after it was written.  A slot is rewritten only when no
+// query uses it.
+struct GridSlot {
+    uint64_t* grid = nullptr;
+    int64_t tick = 0;
+    int refs = 0;
+    hipEvent_t ready = nullptr;
+};
+struct SceneDyn {
+    std::mutex mu;
+    std::vector<GridSlot> slot;
+    int cur = 0;
+};
+
+// The solver reads only ctx .. bytes; a shallow copy with another grid and tick is how
+// a query is solved on the grid of its tick.
 struct msc_scene {
     msc_ctx* ctx = nullptr;
     int64_t tick = 0;
     int n = 0, wpr = 0, dilate = 0;
-    uint64_t* grid = nullptr;
+    uint64_t* grid = nullptr;   // the grid of the current tick
     uint64_t bytes = 0;
+    SceneDyn* dyn = nullptr;    // null when the buffer holds only the static grid
 };
 
 namespace {
@@ -405,6 +427,43 @@ msc_status get_table(Lane* c, int na, int S, int L, TableEntry* out) {
 }
 
 GridView grid_view(const msc_scene* s) { return GridView{s->grid, s->n, s->wpr}; }
+
+// A query's hold on the grid of its scene's current tick.
+struct Binding {
+    SceneDyn* dyn = nullptr;
+    int slot = -1;
+    msc_scene view{};           // the scene with the bound grid and tick
+    hipEvent_t ready = nullptr; // wait for it on a stream other than the one that wrote the grid
+};
+
+Binding bind_scene(const msc_scene* s) {
+    Binding b;
+    if (!s) return b;
+    if (!s->dyn) {
+        b.view = *s;
+    } else {
+        // msc_scene_set_dynamic changes grid and tick under the same lock
+        std::lock_guard<std::mutex> lock(s->dyn->mu);
+        b.view = *s;
+        b.dyn = s->dyn;
+        b.slot = s->dyn->cur;
+        GridSlot& g = s->dyn->slot[b.slot];
+        ++g.refs;
+        b.view.grid = g.grid;
+        b.view.tick = g.tick;
+        b.ready = g.ready;
+    }
+    return b;
+}
+
+void unbind_scene(Binding& b) {
+    if (b.dyn && b.slot >= 0) {
+        std::lock_guard<std::mutex> lock(b.dyn->mu);
+        --b.dyn->slot[b.slot].refs;
+    }
+    b.dyn = nullptr;
+    b.slot = -1;
+}
 
 // Voxel box of the states after k segments: within sum_{j<=k} R_j of the base and
 // sum_{j>k} R_j of the target (the pruning radii), clipped to the grid.
@@ -1201,19 +1260,32 @@ msc_status path_on(Lane* c, const msc_scene* sc, const msc_arm* arm, const int32
     return MSC_NO_PATH;
 }
 
-msc_status query_on(Lane* L, msc_query* q, const msc_opts* opts) {
-    if (!q->scene || !q->arm || !q->out) return fail(L, MSC_E_ARG, "query with a NULL scene, arm or output");
-    prof_reset(L, opts ? opts->flags : 0u);
+// Solves q on lane L against the grid held by binding b, writes q->status, q->tick and
+// q->error, and releases the binding.
+void query_on(Lane* L, msc_query* q, const msc_opts* opts, Binding& b) {
     msc_status st;
-    if (q->kind == 0)
-        st = reach_on(L, q->scene, q->arm, q->target, opts, q->out);
-    else if (q->kind == 1)
-        st = path_on(L, q->scene, q->arm, q->start_cdeg, q->target, q->waypoints, q->max_delta_cdeg, opts, q->out,
-                     q->ref_cdeg);
-    else
-        st = fail(L, MSC_E_ARG, "query kind %d", q->kind);
-    prof_finish(L);
-    return st;
+    L->err.clear();
+    if (!q->scene || !q->arm || !q->out) {
+        st = fail(L, MSC_E_ARG, "query with a NULL scene, arm or output");
+    } else {
+        prof_reset(L, opts ? opts->flags : 0u);
+        if (b.ready && L->stream != L->owner->stream) (void)hipStreamWaitEvent(L->stream, b.ready, 0);
+        const msc_scene* sc = &b.view;
+        if (q->kind == 0)
+            st = reach_on(L, sc, q->arm, q->target, opts, q->out);
+        else if (q->kind == 1)
+            st = path_on(L, sc, q->arm, q->start_cdeg, q->target, q->waypoints, q->max_delta_cdeg, opts, q->out,
+                         q->ref_cdeg);
+        else
+            st = fail(L, MSC_E_ARG, "query kind %d", q->kind);
+        prof_finish(L);
+    }
+    // a call that failed part-way may leave kernels in flight that read the grid
+    if (st < 0) (void)hipStreamSynchronize(L->stream);
+    q->status = st;
+    q->tick = b.view.tick;
+    std::snprintf(q->error, sizeof q->error, "%s", st < 0 ? L->err.c_str() : "");
+    unbind_scene(b);
 }
 
 double now_ms() {
@@ -1223,20 +1295,120 @@ double now_ms() {
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// Server state: a FIFO of submitted queries served by one host thread per worker lane.
+// Server state: a queue of submitted queries served by one host thread per worker
+// lane, the server's logical clock and the paths executing on it ("Dynamic
+// Obstacles": an arm in motion along a computed path, replanned midcourse when a
+// moving obstacle will block a waypoint ahead of it).
 // ---------------------------------------------------------------------------
+namespace {
+
+// A path executing on the logical clock: waypoint w is reached at start_tick + w * tpw.
+struct Exec {
+    const msc_scene* scene = nullptr;
+    msc_arm arm{};
+    std::vector<int32_t> rows;   // (W + 1) * dof centidegrees
+    int W = 0;
+    int32_t target[3] = {0, 0, 0};
+    int32_t max_delta_cdeg = 0;
+    int64_t start_tick = 0;
+    int32_t tpw = 0;
+    int32_t depth = 0;           // replans that led to this path
+};
+
+// A replan issued by msc_server_step: its query record and the arrays it points to.
+struct ReplanRec {
+    msc_query q{};
+    msc_arm arm{};
+    std::vector<int32_t> start, ref, out;
+    double issued_ms = 0.0;
+};
+
+struct Job {
+    uint64_t ticket = 0;
+    msc_query* q = nullptr;
+    Binding bind;
+    ReplanRec* rec = nullptr;    // set for a replan issued by the server
+};
+
+}  // namespace
+
 struct ServerState {
     std::mutex mu;
     std::condition_variable cv;
-    std::deque<std::pair<uint64_t, msc_query*>> queue;
-    std::map<uint64_t, double> submitted;   // ticket -> submission time (ms)
-    std::map<uint64_t, int> done;            // ticket -> 1 once finished
+    std::deque<Job> queue;
+    std::map<uint64_t, double> submitted;   // ticket -> submission time (ms), until finished
+    std::set<uint64_t> done;                 // finished, not yet reported by poll / wait
     std::condition_variable done_cv;
     std::vector<std::thread> threads;
     msc_opts opts{};
     bool stop = false;
     uint64_t next_ticket = 1;
+    int64_t tick = 0;
+    std::vector<Exec> executing;
+    std::map<uint64_t, std::unique_ptr<ReplanRec>> replans;   // issued replans, by ticket
+    std::vector<uint64_t> replans_done;                        // finished, not yet taken
+    std::vector<std::unique_ptr<ReplanRec>> taken;             // returned by the last take
 };
+
+namespace {
+
+// Validity of the remaining waypoints of executing paths on the grids of the current
+// tick: one pose-check launch per (path), reading its rows from the control lane's
+// mapped staging memory and writing its verdicts there; the launches of as many paths
+// as fit the staging buffer run back to back, then one wait.
+msc_status revalidate(Lane* c, const std::vector<Exec>& ex, const std::vector<std::pair<size_t, int>>& live,
+                      std::vector<std::vector<uint8_t>>& valid) {
+    valid.assign(live.size(), {});
+    struct Pending {
+        size_t item;
+        uint8_t* host;
+        int rows;
+    };
+    std::vector<Pending> pend;
+    begin_call(c);
+    auto flush = [&]() -> msc_status {
+        if (pend.empty()) return MSC_OK;
+        MSC_TRY(sync_lane(c));
+        for (const Pending& p : pend) valid[p.item].assign(p.host, p.host + p.rows);
+        pend.clear();
+        begin_call(c);
+        return MSC_OK;
+    };
+    for (size_t i = 0; i < live.size(); ++i) {
+        const Exec& e = ex[live[i].first];
+        const int d = live[i].second;
+        const int n = e.arm.dof;
+        const int rows = e.W - d + 1;
+        const size_t qbytes = (size_t)rows * n * 4;
+        if (qbytes + (size_t)rows + 1024 > kStagingBytes / 2)
+            return fail(c, MSC_E_CAPACITY, "executing path of %d waypoints too long to re-validate", e.W);
+        if (c->staging_used + qbytes + (size_t)rows + 1024 > kStagingBytes - 4096) MSC_TRY(flush());
+        Plan p;
+        make_plan(&e.arm, nullptr, p);
+        std::vector<JointView> jv;
+        MSC_TRY(joint_views(c, p, jv));
+        void *hq, *dq, *hv, *dv;
+        MSC_TRY(host_area(c, qbytes, &hq, &dq));
+        MSC_TRY(host_area(c, (size_t)rows, &hv, &dv));
+        int32_t* qs = (int32_t*)hq;
+        for (size_t j = 0; j < (size_t)rows * n; ++j) qs[j] = e.rows[(size_t)d * n + j] / e.arm.step_cdeg;
+        PoseArgs a{};
+        for (int k = 0; k < n; ++k) a.joints[k] = jv[k];
+        a.g = grid_view(e.scene);
+        a.n = n;
+        a.na = p.na;
+        a.bx = p.base[0];
+        a.by = p.base[1];
+        a.bz = p.base[2];
+        a.ia0 = p.ia0;
+        a.ie0 = p.ie0;
+        LAUNCH(MSC_K_POSE, -1, rows, launch_pose_check(a, (const int32_t*)dq, rows, (uint8_t*)dv, nullptr, c->stream));
+        pend.push_back({i, (uint8_t*)hv, rows});
+    }
+    return flush();
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -1361,13 +1533,86 @@ msc_status msc_scene_create(msc_ctx* o, int32_t n, int32_t dilate_r, const msc_b
         delete s;
         return fail(c, MSC_E_HIP, "raster: %s", hipGetErrorString(e));
     }
+    // room for grids of ticks: slot 0 keeps the static grid, the others take
+    // msc_scene_set_dynamic
+    const uint64_t one = msc_scene_bytes(n);
+    const uint64_t slots = std::min<uint64_t>(grid_bytes / one, (uint64_t)kMaxTickGrids + 1);
+    if (slots >= 2) {
+        s->dyn = new (std::nothrow) SceneDyn();
+        if (!s->dyn) {
+            delete s;
+            return fail(c, MSC_E_NOMEM, "host allocation");
+        }
+        s->dyn->slot.resize(slots);
+        for (uint64_t i = 0; i < slots; ++i) {
+            GridSlot& g = s->dyn->slot[i];
+            g.grid = (uint64_t*)((char*)dev_grid + i * one);
+            if (i > 0 && hipEventCreateWithFlags(&g.ready, hipEventDisableTiming) != hipSuccess) {
+                msc_scene_destroy(s);
+                return fail(c, MSC_E_HIP, "hipEventCreateWithFlags");
+            }
+        }
+        s->dyn->cur = 0;
+    }
     *out = s;
     return MSC_OK;
 }
 
 msc_status msc_scene_destroy(msc_scene* s) {
     if (!s) return MSC_E_ARG;
+    if (s->dyn) {
+        for (GridSlot& g : s->dyn->slot)
+            if (g.ready) (void)hipEventDestroy(g.ready);
+        delete s->dyn;
+    }
     delete s;
+    return MSC_OK;
+}
+
+uint64_t msc_scene_bytes_dynamic(int32_t n, int32_t ticks) {
+    if (n <= 0 || ticks < 1 || ticks > kMaxTickGrids) return 0;
+    return msc_scene_bytes(n) * (uint64_t)(ticks + 1);
+}
+
+msc_status msc_scene_set_dynamic(msc_scene* s, const msc_box* boxes, int32_t nbox, int64_t tick) {
+    if (!s) return MSC_E_ARG;
+    msc_ctx* o = s->ctx;
+    Lane* c = o->control;
+    if (nbox < 0 || (nbox && !boxes)) return fail(c, MSC_E_ARG, "bad moving-box array");
+    for (int i = 0; i < nbox; ++i)
+        for (int a = 0; a < 3; ++a)
+            if (boxes[i].ext[a] < 1) return fail(c, MSC_E_ARG, "moving box %d has an extent < 1", i);
+    if (!s->dyn) return fail(c, MSC_E_NOMEM, "the scene buffer holds no grids of ticks (msc_scene_bytes_dynamic)");
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, MSC_E_HIP, "hipSetDevice");
+    SceneDyn* d = s->dyn;
+    std::lock_guard<std::mutex> lock(d->mu);
+    // the oldest slot no query uses; the current one only when it is the last free one
+    // (calls that read it without a binding run on this stream and have returned)
+    int pick = -1;
+    for (int i = 1; i < (int)d->slot.size(); ++i) {
+        if (i == d->cur || d->slot[i].refs > 0) continue;
+        if (pick < 0 || d->slot[i].tick < d->slot[pick].tick) pick = i;
+    }
+    if (pick < 0 && d->cur > 0 && d->slot[d->cur].refs == 0) pick = d->cur;
+    if (pick < 0) return fail(c, MSC_E_CAPACITY, "every grid of a tick is in use by queries");
+    GridSlot& g = d->slot[pick];
+    const uint64_t* src = d->slot[0].grid;
+    for (int b0 = 0; b0 == 0 || b0 < nbox; b0 += kDynBoxes) {
+        DynBoxes db{};
+        db.count = std::min(kDynBoxes, nbox - b0);
+        for (int i = 0; i < db.count; ++i)
+            for (int a = 0; a < 3; ++a) {
+                db.b[i * 6 + a] = boxes[b0 + i].lo[a];
+                db.b[i * 6 + 3 + a] = boxes[b0 + i].ext[a];
+            }
+        HIP_TRY(launch_raster_dyn(g.grid, src, s->n, s->wpr, s->dilate, db, c->stream));
+        src = g.grid;
+    }
+    HIP_TRY(hipEventRecord(g.ready, c->stream));
+    g.tick = tick;
+    d->cur = pick;
+    s->grid = g.grid;
+    s->tick = tick;
     return MSC_OK;
 }
 
@@ -1419,7 +1664,8 @@ msc_status msc_batch(msc_ctx* o, msc_query* q, int32_t nq, const msc_opts* opts)
     const double t0 = now_ms();
     if (o->workers.empty()) {
         for (int32_t i = 0; i < nq; ++i) {
-            q[i].status = query_on(o->control, &q[i], opts);
+            Binding b = bind_scene(q[i].scene);
+            query_on(o->control, &q[i], opts, b);
             q[i].latency_ms = (float)(now_ms() - t0);
         }
         return MSC_OK;
@@ -1430,7 +1676,8 @@ msc_status msc_batch(msc_ctx* o, msc_query* q, int32_t nq, const msc_opts* opts)
         threads.emplace_back([&, L]() {
             (void)hipSetDevice(o->device);
             for (int32_t i = next.fetch_add(1); i < nq; i = next.fetch_add(1)) {
-                q[i].status = query_on(L, &q[i], opts);
+                Binding b = bind_scene(q[i].scene);
+                query_on(L, &q[i], opts, b);
                 q[i].latency_ms = (float)(now_ms() - t0);
             }
         });
@@ -1466,21 +1713,43 @@ static void server_worker(msc_ctx* o, Lane* L) {
     (void)hipSetDevice(o->device);
     ServerState* S = o->server;
     while (true) {
-        std::pair<uint64_t, msc_query*> job;
+        Job job;
         {
             std::unique_lock<std::mutex> lock(S->mu);
             S->cv.wait(lock, [&] { return S->stop || !S->queue.empty(); });
             if (S->queue.empty()) return;  // stop requested and nothing left
-            job = S->queue.front();
+            job = std::move(S->queue.front());
             S->queue.pop_front();
         }
-        msc_query* q = job.second;
-        q->status = query_on(L, q, &S->opts);
+        msc_query* q = job.q;
+        query_on(L, q, &S->opts, job.bind);
+        const double t = now_ms();
         {
             std::lock_guard<std::mutex> lock(S->mu);
-            q->latency_ms = (float)(now_ms() - S->submitted[job.first]);
-            S->submitted.erase(job.first);
-            S->done[job.first] = 1;
+            if (job.rec) {
+                q->latency_ms = (float)(t - job.rec->issued_ms);
+                S->replans_done.push_back(job.ticket);
+            } else {
+                q->latency_ms = (float)(t - S->submitted[job.ticket]);
+            }
+            // a solved path that is to be executed starts at the current tick
+            if (q->kind == 1 && q->execute_ticks > 0 && q->status == MSC_OK) {
+                Exec e;
+                e.scene = q->scene;
+                e.arm = *q->arm;
+                e.W = q->waypoints;
+                e.rows.assign(q->out, q->out + (size_t)(q->waypoints + 1) * q->arm->dof);
+                for (int i = 0; i < 3; ++i) e.target[i] = q->target[i];
+                e.max_delta_cdeg = q->max_delta_cdeg;
+                e.start_tick = S->tick;
+                e.tpw = q->execute_ticks;
+                e.depth = q->replan_depth;
+                S->executing.push_back(std::move(e));
+            }
+            if (!job.rec) {
+                S->submitted.erase(job.ticket);
+                S->done.insert(job.ticket);
+            }
         }
         S->done_cv.notify_all();
     }
@@ -1503,13 +1772,19 @@ msc_status msc_server_submit(msc_ctx* o, msc_query* q, uint64_t* ticket) {
     if (!o || !q || !ticket) return MSC_E_ARG;
     ServerState* S = o->server;
     if (!S) return ctx_fail(o, MSC_E_STATE, "the server is not running");
+    if (q->execute_ticks < 0) return ctx_fail(o, MSC_E_ARG, "execute_ticks < 0");
     // admission by memory: a query must fit one lane window
     if (msc_query_bytes(q) > o->control->hi) return ctx_fail(o, MSC_E_NOMEM, "query exceeds a lane window");
+    q->replan_depth = 0;
+    Job job;
+    job.q = q;
+    job.bind = bind_scene(q->scene);   // the grid of the scene's current tick
     {
         std::lock_guard<std::mutex> lock(S->mu);
-        *ticket = S->next_ticket++;
-        S->submitted[*ticket] = now_ms();
-        S->queue.emplace_back(*ticket, q);
+        job.ticket = S->next_ticket++;
+        *ticket = job.ticket;
+        S->submitted[job.ticket] = now_ms();
+        S->queue.push_back(std::move(job));
     }
     S->cv.notify_one();
     return MSC_OK;
@@ -1521,8 +1796,13 @@ msc_status msc_server_poll(msc_ctx* o, uint64_t ticket, int32_t* done) {
     if (!S) return ctx_fail(o, MSC_E_STATE, "the server is not running");
     std::lock_guard<std::mutex> lock(S->mu);
     auto it = S->done.find(ticket);
-    *done = it != S->done.end() ? 1 : 0;
-    if (*done) S->done.erase(it);
+    if (it != S->done.end()) {
+        S->done.erase(it);
+        *done = 1;
+        return MSC_OK;
+    }
+    if (!S->submitted.count(ticket)) return ctx_fail(o, MSC_E_STATE, "unknown ticket, or its completion was already reported");
+    *done = 0;
     return MSC_OK;
 }
 
@@ -1531,8 +1811,129 @@ msc_status msc_server_wait(msc_ctx* o, uint64_t ticket) {
     ServerState* S = o->server;
     if (!S) return ctx_fail(o, MSC_E_STATE, "the server is not running");
     std::unique_lock<std::mutex> lock(S->mu);
+    if (!S->done.count(ticket) && !S->submitted.count(ticket))
+        return ctx_fail(o, MSC_E_STATE, "unknown ticket, or its completion was already reported");
     S->done_cv.wait(lock, [&] { return S->done.count(ticket) > 0; });
     S->done.erase(ticket);
+    return MSC_OK;
+}
+
+msc_status msc_server_step(msc_ctx* o, int64_t tick, msc_step_report* report) {
+    if (!o) return MSC_E_ARG;
+    ServerState* S = o->server;
+    if (!S) return ctx_fail(o, MSC_E_STATE, "the server is not running");
+    Lane* c = o->control;
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, MSC_E_HIP, "hipSetDevice");
+    std::vector<Exec> ex;
+    {
+        std::lock_guard<std::mutex> lock(S->mu);
+        if (tick < S->tick) return ctx_fail(o, MSC_E_ARG, "the logical clock does not go backward");
+        S->tick = tick;
+        ex.swap(S->executing);
+    }
+    msc_step_report r{};
+    // (path, waypoint reached at this tick) of the paths still moving
+    std::vector<std::pair<size_t, int>> live;
+    for (size_t i = 0; i < ex.size(); ++i) {
+        const int64_t w = tick > ex[i].start_tick ? (tick - ex[i].start_tick) / ex[i].tpw : 0;
+        if (w >= ex[i].W) {
+            ++r.finished;
+            continue;
+        }
+        live.emplace_back(i, (int)w);
+    }
+    std::vector<std::vector<uint8_t>> valid;
+    prof_reset(c, 0u);
+    msc_status st = revalidate(c, ex, live, valid);
+    if (st != MSC_OK) {
+        // keep the paths for the next step
+        std::lock_guard<std::mutex> lock(S->mu);
+        for (auto& e : ex) S->executing.push_back(std::move(e));
+        o->err = c->err;
+        return st;
+    }
+    std::vector<Exec> keep;
+    std::vector<Job> jobs;
+    std::vector<std::unique_ptr<ReplanRec>> recs;
+    for (size_t i = 0; i < live.size(); ++i) {
+        Exec& e = ex[live[i].first];
+        const int d = live[i].second;
+        const std::vector<uint8_t>& v = valid[i];
+        r.poses_checked += (int64_t)v.size();
+        bool all = true;
+        for (uint8_t b : v) all = all && b;
+        if (all) {
+            keep.push_back(std::move(e));
+            continue;
+        }
+        if (!v[0]) {
+            // the arm's current pose is hit: there is no pose to replan from
+            ++r.stopped;
+            continue;
+        }
+        // the rest of the path, replanned from the current pose to the same target and
+        // kept nearest the rest of the original path; it executes when it is solved
+        const int n = e.arm.dof;
+        const int W2 = e.W - d;
+        auto rec = std::make_unique<ReplanRec>();
+        rec->arm = e.arm;
+        rec->start.assign(e.rows.begin() + (size_t)d * n, e.rows.begin() + (size_t)(d + 1) * n);
+        rec->ref.assign(e.rows.begin() + (size_t)d * n, e.rows.end());
+        rec->out.assign((size_t)(W2 + 1) * n, 0);
+        msc_query& q = rec->q;
+        q.scene = e.scene;
+        q.arm = &rec->arm;
+        q.kind = 1;
+        for (int k = 0; k < 3; ++k) q.target[k] = e.target[k];
+        q.start_cdeg = rec->start.data();
+        q.waypoints = W2;
+        q.max_delta_cdeg = e.max_delta_cdeg;
+        q.out = rec->out.data();
+        q.status = MSC_E_STATE;
+        q.ref_cdeg = rec->ref.data();
+        q.execute_ticks = e.tpw;
+        q.replan_depth = e.depth + 1;
+        rec->issued_ms = now_ms();
+        Job job;
+        job.q = &rec->q;
+        job.rec = rec.get();
+        job.bind = bind_scene(e.scene);
+        jobs.push_back(std::move(job));
+        recs.push_back(std::move(rec));
+        ++r.replans;
+    }
+    {
+        std::lock_guard<std::mutex> lock(S->mu);
+        for (auto& e : keep) S->executing.push_back(std::move(e));
+        // replans go ahead of new requests: the arm is already moving
+        for (size_t j = jobs.size(); j-- > 0;) {
+            jobs[j].ticket = S->next_ticket++;
+            S->replans[jobs[j].ticket] = std::move(recs[j]);
+            S->queue.push_front(std::move(jobs[j]));
+        }
+        r.executing = (int32_t)S->executing.size();
+    }
+    if (r.replans) S->cv.notify_all();
+    if (report) *report = r;
+    return MSC_OK;
+}
+
+msc_status msc_server_take_replans(msc_ctx* o, msc_query* out, int32_t cap, int32_t* count) {
+    if (!o || !count || cap < 0 || (cap && !out)) return MSC_E_ARG;
+    ServerState* S = o->server;
+    if (!S) return ctx_fail(o, MSC_E_STATE, "the server is not running");
+    std::lock_guard<std::mutex> lock(S->mu);
+    S->taken.clear();
+    int32_t k = 0;
+    size_t i = 0;
+    for (; i < S->replans_done.size() && k < cap; ++i, ++k) {
+        auto it = S->replans.find(S->replans_done[i]);
+        out[k] = it->second->q;
+        S->taken.push_back(std::move(it->second));
+        S->replans.erase(it);
+    }
+    S->replans_done.erase(S->replans_done.begin(), S->replans_done.begin() + (ptrdiff_t)i);
+    *count = k;
     return MSC_OK;
 }
 

@@ -31,6 +31,7 @@ EXPORTS = [
     "msc_debug_tables", "msc_debug_raster", "msc_debug_set", "msc_last_error", "msc_get_timings",
     "msc_ctx_set_lanes", "msc_lane_bytes", "msc_batch", "msc_query_bytes", "msc_server_start",
     "msc_server_submit", "msc_server_poll", "msc_server_wait", "msc_server_stop", "msc_refine", "msc_replan",
+    "msc_scene_bytes_dynamic", "msc_scene_set_dynamic", "msc_server_step", "msc_server_take_replans",
 ]
 
 
@@ -59,7 +60,13 @@ class MscQuery(ctypes.Structure):
                 ("target", ctypes.c_int32 * 3), ("start_cdeg", ctypes.POINTER(ctypes.c_int32)),
                 ("waypoints", ctypes.c_int32), ("max_delta_cdeg", ctypes.c_int32),
                 ("out", ctypes.POINTER(ctypes.c_int32)), ("status", ctypes.c_int), ("latency_ms", ctypes.c_float),
-                ("ref_cdeg", ctypes.POINTER(ctypes.c_int32))]
+                ("ref_cdeg", ctypes.POINTER(ctypes.c_int32)), ("tick", ctypes.c_int64),
+                ("execute_ticks", ctypes.c_int32), ("replan_depth", ctypes.c_int32), ("error", ctypes.c_char * 128)]
+
+
+class MscStepReport(ctypes.Structure):
+    _fields_ = [("executing", ctypes.c_int32), ("finished", ctypes.c_int32), ("stopped", ctypes.c_int32),
+                ("replans", ctypes.c_int32), ("poses_checked", ctypes.c_int64)]
 
 
 class MscOpts(ctypes.Structure):
@@ -120,11 +127,16 @@ def load_library(path: str = LIB_PATH):
     L.msc_server_poll.argtypes = [c_void_p, u64, P(i32)]
     L.msc_server_wait.argtypes = [c_void_p, u64]
     L.msc_server_stop.argtypes = [c_void_p]
+    L.msc_scene_bytes_dynamic.argtypes = [i32, i32]
+    L.msc_scene_bytes_dynamic.restype = u64
+    L.msc_scene_set_dynamic.argtypes = [c_void_p, P(MscBox), i32, i64]
+    L.msc_server_step.argtypes = [c_void_p, i64, P(MscStepReport)]
+    L.msc_server_take_replans.argtypes = [c_void_p, P(MscQuery), i32, P(i32)]
     L.msc_last_error.argtypes = [c_void_p]
     L.msc_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
         if name not in ("msc_opts_default", "msc_scene_bytes", "msc_last_error", "msc_lane_bytes",
-                        "msc_query_bytes"):
+                        "msc_query_bytes", "msc_scene_bytes_dynamic"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -167,7 +179,8 @@ class QuerySpec:
     """A reach (kind 0) or reach + path (kind 1) query for msc_batch / the server; owns
     the ctypes buffers until the query completes."""
 
-    def __init__(self, scene: "Scene", arm, target, start=None, waypoints: int = 0, delta: int = 0, ref=None):
+    def __init__(self, scene: "Scene", arm, target, start=None, waypoints: int = 0, delta: int = 0, ref=None,
+                 execute_ticks: int = 0):
         self.scene = scene
         self.arm_c = make_arm(arm)
         self.dof = self.arm_c.dof
@@ -191,8 +204,18 @@ class QuerySpec:
         self.ref = None if ref is None else np.ascontiguousarray(
             np.asarray(ref, np.int32).reshape(self.waypoints + 1, self.dof) * self.step)
         q.ref_cdeg = _ptr(self.ref, ctypes.c_int32) if self.ref is not None else None
+        q.execute_ticks = int(execute_ticks)
         q.status = -100
         self.c = q
+
+    @property
+    def tick(self) -> int:
+        """The logical tick of the scene grid the query was solved on."""
+        return int(self.c.tick)
+
+    @property
+    def error(self) -> str:
+        return self.c.error.decode()
 
     def result(self):
         """(status, joint values in steps: [dof] for reach, [(W+1), dof] for path, latency ms)."""
@@ -270,9 +293,13 @@ class Solver:
         return rc
 
     # -- scenes -------------------------------------------------------------
-    def scene(self, sc) -> Scene:
+    def scene(self, sc, ticks: int = 0) -> Scene:
+        """A scene's grid on the device; ticks > 0 leaves room for that many grids of
+        logical ticks with moving obstacles (set_dynamic)."""
         n = int(sc.n)
-        nbytes = int(self.lib.msc_scene_bytes(n))
+        nbytes = int(self.lib.msc_scene_bytes_dynamic(n, ticks) if ticks > 0 else self.lib.msc_scene_bytes(n))
+        if nbytes == 0:
+            raise MscError(E_ARG, "bad grid size or tick count")
         grid = self.torch.empty(nbytes, dtype=self.torch.uint8, device=self.dev)
         boxes = np.asarray(sc.boxes, np.int32).reshape(-1, 6)
         sph = np.asarray(sc.spheres, np.int32).reshape(-1, 4)
@@ -291,6 +318,17 @@ class Solver:
                                        ctypes.c_void_p(grid.data_ptr()), nbytes, ctypes.byref(h))
         self._check(rc, "msc_scene_create")
         return Scene(self, h, grid, n)
+
+    def set_dynamic(self, scene: Scene, boxes, tick: int):
+        """msc_scene_set_dynamic: the scene's grid of `tick` = static obstacles + boxes
+        (k, 6) int (lo x, y, z, extent x, y, z), dilated like the static ones."""
+        boxes = np.asarray(boxes, np.int32).reshape(-1, 6)
+        B = (MscBox * max(1, len(boxes)))()
+        for i, b in enumerate(boxes):
+            for a in range(3):
+                B[i].lo[a] = int(b[a])
+                B[i].ext[a] = int(b[3 + a])
+        self._check(self.lib.msc_scene_set_dynamic(scene.handle, B, len(boxes), int(tick)), "msc_scene_set_dynamic")
 
     # -- solving ------------------------------------------------------------
     def reach(self, scene: Scene, arm, target: Sequence[int], split_m: int = -1,
@@ -404,6 +442,8 @@ class Solver:
         for i, sp in enumerate(specs):
             sp.c.status = arr[i].status
             sp.c.latency_ms = arr[i].latency_ms
+            sp.c.tick = arr[i].tick
+            sp.c.error = arr[i].error
         return [sp.result() for sp in specs]
 
     def query_bytes(self, spec: QuerySpec) -> int:
@@ -433,6 +473,34 @@ class Solver:
 
     def server_stop(self):
         self._check(self.lib.msc_server_stop(self.ctx), "msc_server_stop")
+
+    def server_step(self, tick: int) -> dict:
+        """msc_server_step: re-validate executing paths at `tick`, queue replans."""
+        r = MscStepReport()
+        self._check(self.lib.msc_server_step(self.ctx, int(tick), ctypes.byref(r)), "msc_server_step")
+        return dict(executing=r.executing, finished=r.finished, stopped=r.stopped, replans=r.replans,
+                    poses_checked=r.poses_checked)
+
+    def take_replans(self) -> list:
+        """Completed replans issued by server_step, as dicts (joint values in steps)."""
+        if getattr(self, "_replan_buf", None) is None:
+            self._replan_buf = (MscQuery * 256)()
+        buf, cap = self._replan_buf, 256
+        cnt = ctypes.c_int32()
+        self._check(self.lib.msc_server_take_replans(self.ctx, buf, cap, ctypes.byref(cnt)), "msc_server_take_replans")
+        out = []
+        for q in buf[:cnt.value]:
+            a = q.arm.contents
+            n, step, W = a.dof, a.step_cdeg, q.waypoints
+            rows = lambda p, k: np.ctypeslib.as_array(p, shape=(k * n,)).reshape(k, n) // step  # noqa: E731
+            out.append(dict(status=q.status, tick=int(q.tick), latency_ms=float(q.latency_ms), depth=q.replan_depth,
+                            scene=q.scene, dof=n, step=step, arm_types=list(a.type[:n]), arm_lens=list(a.len_vox[:n]),
+                            lo_cdeg=list(a.lo_cdeg[:n]), hi_cdeg=list(a.hi_cdeg[:n]), base=tuple(a.base),
+                            target=tuple(q.target), waypoints=W, delta=q.max_delta_cdeg // step,
+                            start=rows(q.start_cdeg, 1)[0].copy(), ref=rows(q.ref_cdeg, W + 1).copy(),
+                            path=rows(q.out, W + 1).copy() if q.status == OK else None,
+                            error=q.error.decode()))
+        return out
 
     # -- debug --------------------------------------------------------------
     def debug_tables(self, arm, stage: int):

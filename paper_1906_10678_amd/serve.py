@@ -1,33 +1,36 @@
 """Serving loop with dynamic obstacles and midcourse replanning ("Dynamic Obstacles").
 
-A real-time loop of logical ticks (10 ms each):
+A real-time loop of logical ticks (10 ms each).  The library does the work of a tick;
+this module only draws the workload and drives the clock:
 
 * every tick, each scene's moving boxes advance (constant velocity in 1/1024-voxel
-  fixed point, reflected at the walls) and the scene is rasterised again into a new
-  device grid (static + moving obstacles): the grid of that tick;
+  fixed point, reflected at the walls) and ``msc_scene_set_dynamic`` writes the
+  scene's grid of that tick (static + moving obstacles) into one of the scene's
+  resident grids of recent ticks, asynchronously;
+* ``msc_server_step`` then re-validates, on the library's side, the remaining
+  waypoints of every path executing on the server's logical clock (one waypoint every
+  ``ticks_per_waypoint`` ticks: the paper's arm traverses a waypoint in about 83 ms)
+  and queues a replan of the rest of a path from its current pose when a waypoint
+  ahead collides;
 * requests arrive as a Poisson process (70% reach pose, 30% reach + path) and are
-  submitted to the library's server (continuous batching over worker lanes), each
-  against the grid of its arrival tick, so its result does not depend on what else is
-  in flight.  Their start poses and targets are drawn before the loop against the
-  static obstacles; at their tick a moving box may block the start (E_ARG) or the
-  target (NO_REACH), which are served outcomes like any other;
-* a finished path starts to execute: the arm advances one waypoint every
-  `ticks_per_waypoint` ticks ("each waypoint ... traversed in approximately 83 msec");
-  at every tick its remaining waypoints are re-validated on the GPU against the
-  current grid, and if one collides the remaining part is replanned from the current
-  pose to the same target (the paper's midcourse replanning);
-* latency of every request (submission to completion, wall clock) is recorded per
-  class: reach, path, replan.
+  submitted to the library's server (continuous batching over worker lanes); each is
+  bound to the grid of its submission tick, so its result does not depend on what else
+  is in flight.  Start poses and targets are drawn before the loop against the static
+  obstacles; at their tick a moving box may block the start (E_ARG) or the target
+  (NO_REACH), which are served outcomes like any other.  Solved paths execute on the
+  server;
+* latency of every request (submission to completion, measured by the library) is
+  recorded per class: reach, path, and the replans the server issued.
 
-Random draws come from `synth`; kinematics, rasterisation and search all run in the
-library.  A request that finds no answer (NO_REACH / NO_PATH: the target is blocked
-at that tick) still counts as served.
+Random draws come from `synth`; kinematics, rasterisation, re-validation and search
+all run in the library.
 """
 from __future__ import annotations
 
+import ctypes
 import time
 from dataclasses import dataclass, field
-from typing import Dict, List, Optional, Tuple
+from typing import Callable, Dict, List, Optional, Tuple
 
 import numpy as np
 
@@ -37,64 +40,61 @@ FIX = 1024  # fixed-point scale of moving-box positions
 
 
 @dataclass
-class MovingBox:
-    pos: np.ndarray     # lo corner, fixed point (int64, x FIX)
-    vel: np.ndarray     # fixed point per tick
-    ext: np.ndarray     # integer extent
+class Movers:
+    """The moving boxes of one scene: lo corners in fixed point, velocities per tick,
+    integer extents."""
+    pos: np.ndarray     # (k, 3) int64, x FIX
+    vel: np.ndarray     # (k, 3) int64, x FIX per tick
+    ext: np.ndarray     # (k, 3) int64
 
     def step(self, n: int):
         hi_lim = (n - self.ext) * FIX
-        self.pos = self.pos + self.vel
-        for a in range(3):
-            if self.pos[a] < 0:
-                self.pos[a] = -self.pos[a]
-                self.vel[a] = -self.vel[a]
-            elif self.pos[a] > hi_lim[a]:
-                self.pos[a] = 2 * hi_lim[a] - self.pos[a]
-                self.vel[a] = -self.vel[a]
+        p = self.pos + self.vel
+        lo_hit = p < 0
+        hi_hit = p > hi_lim
+        p = np.where(lo_hit, -p, p)
+        p = np.where(hi_hit, 2 * hi_lim - p, p)
+        self.vel = np.where(lo_hit | hi_hit, -self.vel, self.vel)
+        self.pos = p
 
-    def box(self) -> np.ndarray:
-        return np.concatenate([self.pos // FIX, self.ext]).astype(np.int32)
+    def boxes(self) -> np.ndarray:
+        """(k, 6) int32: lo corner then extent, as msc_box."""
+        return np.ascontiguousarray(np.concatenate([self.pos // FIX, self.ext], axis=1).astype(np.int32))
 
 
 @dataclass
 class DynScene:
     static: synth.Scene
-    movers: List[MovingBox]
+    movers: Movers
 
-    def at_tick(self) -> synth.Scene:
-        boxes = np.concatenate([self.static.boxes] + [m.box()[None, :] for m in self.movers]) \
-            if self.movers else self.static.boxes
-        return synth.Scene(n=self.static.n, dilate=self.static.dilate, boxes=boxes, spheres=self.static.spheres)
+    def at(self, boxes: np.ndarray) -> synth.Scene:
+        """The scene with the given moving boxes added to the static ones."""
+        return synth.Scene(n=self.static.n, dilate=self.static.dilate,
+                           boxes=np.concatenate([self.static.boxes, boxes]) if len(boxes) else self.static.boxes,
+                           spheres=self.static.spheres)
 
 
-def make_dyn_scene(seed: int, n: int = 256) -> DynScene:
+def make_dyn_scene(seed: int, n: int = 256, column: int = 30) -> DynScene:
     """C2-style static obstacles plus 1..8 moving boxes (edges 10..30 voxels, speed
-    0.5..3 voxels per tick in a uniform direction)."""
-    arm = synth.arm_c2()
-    static = synth.random_scene(synth.rng_for(5, seed, 0), n, 2, 32, (5, 40), 8, (4, 20), base=arm.base,
-                                column=arm.lens[0])
+    0.5..3 voxels per tick in a uniform direction), sizes scaled by n / 256."""
+    f = n / 256
+    base = (n // 2, n // 2, 0)
+    static = synth.random_scene(synth.rng_for(5, seed, 0), n, int(round(2 * f)), 32,
+                                (max(1, int(round(5 * f))), max(1, int(round(40 * f)))), 8,
+                                (max(1, int(round(4 * f))), max(1, int(round(20 * f)))), base=base, column=column)
     rng = synth.rng_for(5, seed, 1)
-    movers = []
-    for _ in range(int(rng.integers(1, 9))):
-        ext = rng.integers(10, 31, size=3)
-        lo = np.array([rng.integers(0, n - e + 1) for e in ext], np.int64) * FIX
+    k = int(rng.integers(1, 9))
+    pos, vel, ext = [], [], []
+    for _ in range(k):
+        e = np.minimum(rng.integers(max(1, int(round(10 * f))), max(1, int(round(30 * f))) + 1, size=3), n)
+        lo = np.array([rng.integers(0, n - v + 1) for v in e], np.int64) * FIX
         d = rng.normal(size=3)
         d /= np.linalg.norm(d)
-        speed = rng.uniform(0.5, 3.0)
-        vel = np.round(d * speed * FIX).astype(np.int64)
-        movers.append(MovingBox(pos=lo, vel=vel, ext=ext.astype(np.int64)))
-    return DynScene(static=static, movers=movers)
-
-
-@dataclass
-class Executing:
-    path: np.ndarray           # (W+1, dof) steps
-    target: Tuple[int, int, int]
-    arm: synth.Arm
-    scene_idx: int
-    start_tick: int
-    replans: int = 0
+        speed = rng.uniform(0.5, 3.0) * f
+        pos.append(lo)
+        vel.append(np.round(d * speed * FIX).astype(np.int64))
+        ext.append(e.astype(np.int64))
+    return DynScene(static=static, movers=Movers(np.array(pos), np.array(vel), np.array(ext)))
 
 
 @dataclass
@@ -107,22 +107,31 @@ class Template:
     waypoints: int = 0
 
 
-def draw_templates(solver: msc.Solver, dyn: List["DynScene"], count: int, seed: int, path_frac: float = 0.3):
-    """Request templates against the static obstacles: DOF 6..8 prefixes of the 8-DOF
-    chain; reach targets are ends of valid poses; path targets ends of feasible walks of
-    8..32 moves of one step (5 deg)."""
+def c5_arm(dof: int, n: int = 256) -> synth.Arm:
+    """The serving workload's arms: DOF-long prefixes of the 8-DOF chain, 5 deg steps."""
+    lens = synth.C2_LENS if n == 256 else synth.scaled_lens(n, 8)
+    return synth.arm_chain(dof, lens, 500, 17000, (n // 2, n // 2, 0))
+
+
+def draw_templates(solver: msc.Solver, dyn: List[DynScene], count: int, seed: int, path_frac: float = 0.3,
+                   dof_range: Tuple[int, int] = (6, 8), w_range: Tuple[int, int] = (8, 32),
+                   arm_for: Optional[Callable[[int], synth.Arm]] = None):
+    """Request templates against the static obstacles: arms of DOF in dof_range; reach
+    targets are ends of valid poses; path targets ends of feasible walks of w_range
+    moves of one step."""
     rng = synth.rng_for(7, seed)
+    n = dyn[0].static.n
+    arm_for = arm_for or (lambda d: c5_arm(d, n))
     statics = [solver.scene(d.static) for d in dyn]
-    base = synth.arm_c2().base
     out = []
     for _ in range(count):
         si = int(rng.integers(0, len(dyn)))
-        dof = int(rng.integers(6, 9))
-        arm = synth.arm_chain(dof, synth.C2_LENS, 500, 17000, base)
+        dof = int(rng.integers(dof_range[0], dof_range[1] + 1))
+        arm = arm_for(dof)
         pf = lambda q, sc=statics[si], a=arm: solver.pose_check(sc, a, q)  # noqa: E731
         if rng.random() < path_frac:
             start, _, _ = synth.first_valid_pose(rng, arm, pf, batch=512)
-            W = int(rng.integers(8, 33))
+            W = int(rng.integers(w_range[0], w_range[1] + 1))
             _, target = synth.walk_target(rng, arm, start, W, 1, pf, redraws=2)
             out.append(Template("path", si, arm, tuple(int(v) for v in target), start, W))
         else:
@@ -133,12 +142,10 @@ def draw_templates(solver: msc.Solver, dyn: List["DynScene"], count: int, seed: 
 
 @dataclass
 class Request:
-    kind: str                  # reach / path / replan
-    tick: int
+    kind: str                  # reach / path
     spec: msc.QuerySpec
     ticket: int = 0
-    submitted: float = 0.0
-    execute: Optional[Executing] = None
+    scene_idx: int = 0
 
 
 @dataclass
@@ -149,13 +156,28 @@ class ServeReport:
     submitted: int = 0
     wall_s: float = 0.0
     ticks: int = 0
+    late_ticks: int = 0        # ticks started more than one tick late (the loop fell behind)
+    stale_ticks: int = 0       # ticks whose grid could not be written (every grid of a tick in use)
     replans: int = 0
-    done_log: List[tuple] = field(default_factory=list)   # (kind, tick, status, result, spec)
+    stopped: int = 0
+    unserved: int = 0          # requests or replans still in flight when the drain timed out
+    tick_ms: List[float] = field(default_factory=list)   # host time spent in each tick's work
+    done_log: List[tuple] = field(default_factory=list)   # (kind, scene_idx, tick, status, result, spec)
+    replan_log: List[dict] = field(default_factory=list)
+
+    def count(self, kind: str, st: int):
+        self.statuses.setdefault(kind, {})
+        self.statuses[kind][st] = self.statuses[kind].get(st, 0) + 1
 
     def summary(self) -> dict:
         out = {"served": self.served, "submitted": self.submitted, "wall_s": round(self.wall_s, 3),
                "solves_per_s": round(self.served / max(self.wall_s, 1e-9), 2), "ticks": self.ticks,
-               "replans": self.replans}
+               "late_ticks": self.late_ticks, "stale_ticks": self.stale_ticks, "replans": self.replans,
+               "stopped": self.stopped}
+        if self.tick_ms:
+            t = np.array(self.tick_ms)
+            out["tick_work_ms"] = {"p50": round(float(np.percentile(t, 50)), 3),
+                                   "p99": round(float(np.percentile(t, 99)), 3)}
         for k, v in self.latencies.items():
             if v:
                 a = np.array(v)
@@ -168,48 +190,65 @@ class ServeReport:
 class ServingLoop:
     def __init__(self, solver: msc.Solver, nscenes: int = 16, seed: int = 0, rate: float = 500.0,
                  tick_ms: float = 10.0, path_frac: float = 0.3, ticks_per_waypoint: int = 8,
-                 keep_log: bool = False, templates: int = 2000):
+                 keep_log: bool = False, templates: int = 2000, n: int = 256,
+                 dof_range: Tuple[int, int] = (6, 8), w_range: Tuple[int, int] = (8, 32),
+                 arm_for: Optional[Callable[[int], synth.Arm]] = None, tick_grids: int = 24):
         self.solver = solver
         self.rng = synth.rng_for(6, seed)
-        self.dyn = [make_dyn_scene(seed * 1000 + i) for i in range(nscenes)]
-        self.templates = draw_templates(solver, self.dyn, templates, seed, path_frac)
+        column = (arm_for(dof_range[1]) if arm_for else c5_arm(dof_range[1], n)).lens[0]
+        self.dyn = [make_dyn_scene(seed * 1000 + i, n, column) for i in range(nscenes)]
+        self.templates = draw_templates(solver, self.dyn, templates, seed, path_frac, dof_range, w_range, arm_for)
+        self.scenes = [solver.scene(d.static, ticks=tick_grids) for d in self.dyn]
         self.next_template = 0
         self.rate = rate
         self.tick_ms = tick_ms
-        self.path_frac = path_frac
         self.tpw = ticks_per_waypoint
         self.keep_log = keep_log
         self.tick = 0
-        self.grids: Dict[int, List[msc.Scene]] = {}
         self.pending: List[Request] = []
-        self.executing: List[Executing] = []
         self.report = ServeReport()
+        self.mover_log: Dict[int, List[np.ndarray]] = {}   # tick -> moving boxes per scene (keep_log)
+        self.replans_inflight = 0
 
     # -- scenes -----------------------------------------------------------------
     def advance_tick(self):
+        """Move the boxes, write every scene's grid of this tick, then let the server
+        re-validate the executing paths on them."""
         if self.tick > 0:
             for d in self.dyn:
-                for m in d.movers:
-                    m.step(d.static.n)
-        self.grids[self.tick] = [self.solver.scene(d.at_tick()) for d in self.dyn]
-        # grids of old ticks are kept alive by the requests that reference them
-        for t in [t for t in self.grids if t < self.tick]:
-            del self.grids[t]
+                d.movers.step(d.static.n)
+        boxes = [d.movers.boxes() for d in self.dyn]
+        if self.keep_log:
+            self.mover_log[self.tick] = boxes
+        lib = self.solver.lib
+        for sc, b in zip(self.scenes, boxes):
+            rc = lib.msc_scene_set_dynamic(sc.handle, b.ctypes.data_as(ctypes.POINTER(msc.MscBox)), len(b),
+                                           self.tick)
+            if rc == msc.E_CAPACITY:
+                self.report.stale_ticks += 1   # queries keep solving on the previous grid
+            else:
+                self.solver._check(rc, "msc_scene_set_dynamic")
+        rep = self.solver.server_step(self.tick)
+        self.report.replans += rep["replans"]
+        self.report.stopped += rep["stopped"]
+        self.replans_inflight += rep["replans"]
+
+    def scene_at(self, scene_idx: int, tick: int) -> synth.Scene:
+        """The obstacles of a scene at a logical tick (needs keep_log)."""
+        return self.dyn[scene_idx].at(self.mover_log[tick][scene_idx])
 
     # -- requests ---------------------------------------------------------------
     def draw_request(self) -> Request:
         tp = self.templates[self.next_template % len(self.templates)]
         self.next_template += 1
-        scene = self.grids[self.tick][tp.scene_idx]
+        scene = self.scenes[tp.scene_idx]
         if tp.kind == "path":
-            spec = msc.QuerySpec(scene, tp.arm, tp.target, start=tp.start, waypoints=tp.waypoints, delta=1)
-            req = Request("path", self.tick, spec)
-            req.execute = Executing(path=None, target=tp.target, arm=tp.arm, scene_idx=tp.scene_idx, start_tick=0)
-            return req
-        return Request("reach", self.tick, msc.QuerySpec(scene, tp.arm, tp.target))
+            spec = msc.QuerySpec(scene, tp.arm, tp.target, start=tp.start, waypoints=tp.waypoints, delta=1,
+                                 execute_ticks=self.tpw)
+            return Request("path", spec, scene_idx=tp.scene_idx)
+        return Request("reach", msc.QuerySpec(scene, tp.arm, tp.target), scene_idx=tp.scene_idx)
 
     def submit(self, req: Request):
-        req.submitted = time.perf_counter()
         req.ticket = self.solver.submit(req.spec)
         self.pending.append(req)
         self.report.submitted += 1
@@ -222,63 +261,22 @@ class ServingLoop:
                 continue
             st, res, lat = req.spec.result()
             self.report.latencies[req.kind].append(lat)
-            self.report.statuses.setdefault(req.kind, {})
-            self.report.statuses[req.kind][st] = self.report.statuses[req.kind].get(st, 0) + 1
+            self.report.count(req.kind, st)
             self.report.served += 1
             if self.keep_log:
-                self.report.done_log.append((req.kind, req.tick, st, res, req.spec))
-            if req.kind in ("path", "replan") and st == msc.OK and req.execute is not None:
-                ex = req.execute
-                ex.path = res
-                ex.start_tick = self.tick
-                self.executing.append(ex)
+                self.report.done_log.append((req.kind, req.scene_idx, req.spec.tick, st, res, req.spec))
         self.pending = still
-
-    def revalidate(self):
-        """Re-check the remaining waypoints of executing paths against this tick's grid
-        (one GPU pose check per scene and arm); replan the rest of a path whose remaining
-        waypoints collide."""
-        live = []
-        for ex in self.executing:
-            done_wp = (self.tick - ex.start_tick) // self.tpw
-            if done_wp < ex.path.shape[0] - 1:
-                live.append((ex, done_wp))
-        groups: Dict[Tuple[int, int], List[Tuple[Executing, int]]] = {}
-        for ex, d in live:
-            groups.setdefault((ex.scene_idx, ex.arm.dof), []).append((ex, d))
-        verdict = {}
-        for (si, dof), items in groups.items():
-            rows = np.concatenate([ex.path[d:] for ex, d in items])
-            valid, _ = self.solver.pose_check(self.grids[self.tick][si], items[0][0].arm, rows)
-            o = 0
-            for ex, d in items:
-                k = ex.path.shape[0] - d
-                verdict[id(ex)] = valid[o:o + k]
-                o += k
-        keep = []
-        for ex, done_wp in live:
-            W = ex.path.shape[0] - 1
-            valid = verdict[id(ex)]
-            scene = self.grids[self.tick][ex.scene_idx]
-            if valid.all():
-                keep.append(ex)
-                continue
-            current = ex.path[done_wp]
-            if not valid[0]:
-                continue  # the arm's current pose is hit: nothing to replan from
-            remaining = W - done_wp
-            # the new path nearest the rest of the original one ("Dynamic Obstacles")
-            spec = msc.QuerySpec(scene, ex.arm, ex.target, start=current, waypoints=remaining, delta=1,
-                                 ref=ex.path[done_wp:])
-            req = Request("replan", self.tick, spec)
-            req.execute = Executing(path=None, target=ex.target, arm=ex.arm, scene_idx=ex.scene_idx,
-                                    start_tick=0, replans=ex.replans + 1)
-            self.submit(req)
-            self.report.replans += 1
-        self.executing = keep
+        for r in self.solver.take_replans():
+            self.replans_inflight -= 1
+            self.report.latencies["replan"].append(r["latency_ms"])
+            self.report.count("replan", r["status"])
+            self.report.served += 1
+            if self.keep_log:
+                r["scene_idx"] = next(i for i, sc in enumerate(self.scenes) if sc.handle.value == r["scene"])
+                self.report.replan_log.append(r)
 
     # -- loop -------------------------------------------------------------------
-    def run(self, seconds: float, warmup_s: float = 1.0) -> ServeReport:
+    def run(self, seconds: float, warmup_s: float = 1.0, drain_s: float = 30.0) -> ServeReport:
         self.solver.server_start()
         try:
             t_begin = time.perf_counter()
@@ -290,26 +288,32 @@ class ServingLoop:
                 now = time.perf_counter()
                 if not measuring and now >= measuring_from:
                     measuring = True
-                    self.report = ServeReport()
+                    self.report = ServeReport(done_log=self.report.done_log if self.keep_log else [],
+                                              replan_log=self.report.replan_log if self.keep_log else [])
                     measure_t0 = now
                 if now >= t_end:
                     break
                 if now >= next_tick_at:
+                    if now - next_tick_at > self.tick_ms / 1e3:
+                        self.report.late_ticks += 1
                     self.advance_tick()
                     arrivals = int(self.rng.poisson(self.rate * self.tick_ms / 1e3))
                     for _ in range(arrivals):
                         self.submit(self.draw_request())
-                    self.revalidate()
                     self.tick += 1
                     self.report.ticks += 1
+                    self.report.tick_ms.append((time.perf_counter() - now) * 1e3)
                     next_tick_at += self.tick_ms / 1e3
                 self.collect()
                 time.sleep(0.0002)
-            # drain
-            while self.pending:
+            # drain what is in flight (the clock stops with the measured window, so no
+            # further replans are issued)
+            t_drain = time.perf_counter()
+            while (self.pending or self.replans_inflight > 0) and time.perf_counter() - t_drain < drain_s:
                 self.collect()
                 time.sleep(0.0005)
             self.report.wall_s = time.perf_counter() - measure_t0
+            self.report.unserved = len(self.pending) + self.replans_inflight
         finally:
             self.solver.server_stop()
         return self.report
