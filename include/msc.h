@@ -223,6 +223,24 @@ msc_status msc_refine(msc_ctx* ctx, const msc_arm* arm, const int32_t* poses_cde
                       const double* targets, int64_t count, double* angles_out,
                       int32_t* status_out);
 
+/* msc_refine for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).  Same arguments,
+ * checks and results as msc_refine (bit-identical angles and statuses), but the device
+ * staging of poses, targets, angles and statuses lives in a fixed buffer of
+ * MSC_REFINE_STATIC_BYTES that the library holds on each device until the process ends,
+ * not in the context's workspace: the call allocates nothing.  At most
+ * msc_refine_static_max(dof) poses per call (about 33 000 at 8 DOF); a larger count
+ * returns MSC_E_CAPACITY with a message and writes nothing.  Every context on a device
+ * shares that device's buffer and the buffer keeps the last call's contents (every output
+ * is rewritten by each call): calls that overlap on one device, from different contexts or
+ * threads, race and must be serialised by the caller.  Not profiled (msc_get_timings). */
+#define MSC_REFINE_STATIC_BYTES (4u << 20)
+msc_status msc_refine_static(msc_ctx* ctx, const msc_arm* arm, const int32_t* poses_cdeg,
+                             const double* targets, int64_t count, double* angles_out,
+                             int32_t* status_out);
+/* Largest count msc_refine_static takes for an arm of `dof` joints (0 for a bad dof). */
+int64_t msc_refine_static_max(int32_t dof);
+
 /* Worker lanes for msc_batch and the server.  The workspace, minus a region for the
  * shared segment tables, is split into 1 + nworkers equal windows: one for this
  * context's own calls, one per worker lane.  Each worker lane has its own HIP stream

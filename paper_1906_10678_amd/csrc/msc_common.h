@@ -135,6 +135,7 @@ hipError_t launch_pose_check(const PoseArgs& a, const int32_t* q, int64_t count,
 // Exact end point of discrete poses (FP64): angles in degrees, lengths in voxels.
 struct RefineArgs {
     int n;
+    int q_div;                 // pose values are divided by this first (1: already in steps)
     int type[kMaxDof];
     double len[kMaxDof];
     double base[3], az0, el0, step;

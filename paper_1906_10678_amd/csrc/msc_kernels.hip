@@ -1282,7 +1282,7 @@ __global__ void __launch_bounds__(kBlock) k_refine(RefineArgs a, const int32_t* 
         double px = a.base[0], py = a.base[1], pz = a.base[2];
         double paz = a.az0, pel = a.el0, az3 = 0, el3 = 0, az4 = 0, el4 = 0;
         for (int k = 0; k < n; ++k) {
-            const double inc = qi[k] * a.step;
+            const double inc = (qi[k] / a.q_div) * a.step;
             oi[k] = inc;
             if (a.type[k] == 0)
                 az += inc;

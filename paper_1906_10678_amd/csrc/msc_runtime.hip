@@ -29,6 +29,38 @@ using namespace msc;
 
 struct ServerState;
 
+// Device staging of msc_refine_static: a fixed buffer in the library's code object, so
+// that call needs no device allocation.  Each device holds its own copy until the
+// process ends; the host looks its address up once per device (static_scratch_init,
+// from msc_ctx_create) and uses only that address, never the symbol itself.
+static __device__ __align__(256) unsigned char scratch[MSC_REFINE_STATIC_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+// With `device` current: look up this device's copy of the buffer (once per device).
+hipError_t static_scratch_init(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = (char*)ptr;
+    return hipSuccess;
+}
+
+char* static_scratch(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
+
+}  // namespace
+
 namespace {
 
 constexpr uint64_t kAlign = 256;
@@ -133,7 +165,12 @@ msc_status fail(Lane* c, msc_status st, const char* fmt, ...) {
     va_start(ap, fmt);
     vsnprintf(buf, sizeof buf, fmt, ap);
     va_end(ap);
-    if (c) c->err = buf;
+    if (c) {
+        c->err = buf;
+        // the control lane's message is now the context's latest: drop an older one
+        // left by a context-level call (msc_last_error prefers that one)
+        if (c->owner && c == c->owner->control) c->owner->err.clear();
+    }
     return st;
 }
 
@@ -1429,6 +1466,7 @@ msc_status msc_ctx_create(int device, void* hip_stream, void* dev_workspace, uin
     if (ws_bytes < (64ull << 20)) return MSC_E_ARG;
     if ((uintptr_t)dev_workspace % kAlign) return MSC_E_ARG;
     if (hipSetDevice(device) != hipSuccess) return MSC_E_HIP;
+    if (static_scratch_init(device) != hipSuccess) return MSC_E_HIP;
     msc_ctx* o = new (std::nothrow) msc_ctx();
     if (!o) return MSC_E_NOMEM;
     o->device = device;
@@ -1978,11 +2016,13 @@ msc_status msc_pose_check(msc_ctx* o, const msc_scene* sc, const msc_arm* arm, c
     return MSC_OK;
 }
 
-msc_status msc_refine(msc_ctx* o, const msc_arm* arm, const int32_t* poses_cdeg, const double* targets,
-                      int64_t count, double* angles_out, int32_t* status_out) {
-    if (!o) return MSC_E_ARG;
-    Lane* c = o->control;
+}  // extern "C"
 
+namespace {
+
+// Argument checks of msc_refine / msc_refine_static and the kernel's view of the arm.
+msc_status refine_prepare(Lane* c, const msc_arm* arm, const int32_t* poses_cdeg, const double* targets,
+                          int64_t count, double* angles_out, int32_t* status_out, RefineArgs& a) {
     MSC_TRY(check_arm(c, arm, 1 << 30));
     const int n = arm->dof;
     if (n < 4 || arm->len_vox[n - 4] != 0 || arm->len_vox[n - 2] != 0 || arm->len_vox[n - 3] <= 0 ||
@@ -1994,9 +2034,9 @@ msc_status msc_refine(msc_ctx* o, const msc_arm* arm, const int32_t* poses_cdeg,
         if (poses_cdeg[i] % arm->step_cdeg) return fail(c, MSC_E_ARG, "pose angle not a multiple of the step");
     for (int64_t i = 0; i < count * 3; ++i)
         if (!std::isfinite(targets[i])) return fail(c, MSC_E_ARG, "target not finite");
-    if (hipSetDevice(c->device) != hipSuccess) return fail(c, MSC_E_HIP, "hipSetDevice");
-    RefineArgs a{};
+    a = RefineArgs{};
     a.n = n;
+    a.q_div = 1;
     for (int k = 0; k < n; ++k) {
         a.type[k] = arm->type[k];
         a.len[k] = (double)arm->len_vox[k];
@@ -2005,6 +2045,29 @@ msc_status msc_refine(msc_ctx* o, const msc_arm* arm, const int32_t* poses_cdeg,
     a.az0 = arm->az0_cdeg / 100.0;
     a.el0 = arm->el0_cdeg / 100.0;
     a.step = arm->step_cdeg / 100.0;
+    return MSC_OK;
+}
+
+// Device bytes msc_refine_static needs for `count` poses of n joints: the poses, the
+// targets, the angles and the statuses, each region 256-byte aligned.
+uint64_t refine_static_bytes(int n, int64_t count) {
+    return align_up((uint64_t)count * n * 4) + align_up((uint64_t)count * 24) + align_up((uint64_t)count * n * 8) +
+           align_up((uint64_t)count * 4);
+}
+
+}  // namespace
+
+extern "C" {
+
+msc_status msc_refine(msc_ctx* o, const msc_arm* arm, const int32_t* poses_cdeg, const double* targets,
+                      int64_t count, double* angles_out, int32_t* status_out) {
+    if (!o) return MSC_E_ARG;
+    Lane* c = o->control;
+
+    RefineArgs a;
+    MSC_TRY(refine_prepare(c, arm, poses_cdeg, targets, count, angles_out, status_out, a));
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, MSC_E_HIP, "hipSetDevice");
+    const int n = a.n;
     // the kernel time of every chunk is kept for msc_get_timings
     prof_reset(c, MSC_PROFILE);
     const int64_t chunk = 1 << 20;
@@ -2028,6 +2091,53 @@ msc_status msc_refine(msc_ctx* o, const msc_arm* arm, const int32_t* poses_cdeg,
         HIP_TRY(hipStreamSynchronize(c->stream));
     }
     prof_finish(c);
+    return MSC_OK;
+}
+
+int64_t msc_refine_static_max(int32_t dof) {
+    if (dof < 1 || dof > MSC_MAX_DOF) return 0;
+    int64_t lo = 0, hi = (int64_t)(MSC_REFINE_STATIC_BYTES / 64);
+    while (lo < hi) {   // largest count whose regions fit the buffer
+        const int64_t mid = (lo + hi + 1) / 2;
+        if (refine_static_bytes(dof, mid) <= MSC_REFINE_STATIC_BYTES)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+msc_status msc_refine_static(msc_ctx* o, const msc_arm* arm, const int32_t* poses_cdeg, const double* targets,
+                             int64_t count, double* angles_out, int32_t* status_out) {
+    if (!o) return MSC_E_ARG;
+    Lane* c = o->control;
+
+    RefineArgs a;
+    MSC_TRY(refine_prepare(c, arm, poses_cdeg, targets, count, angles_out, status_out, a));
+    const int n = a.n;
+    if (count > msc_refine_static_max(n))
+        return fail(c, MSC_E_CAPACITY,
+                    "msc_refine_static: %lld poses of %d joints exceed its %llu-byte device buffer "
+                    "(at most %lld per call)",
+                    (long long)count, n, (unsigned long long)MSC_REFINE_STATIC_BYTES,
+                    (long long)msc_refine_static_max(n));
+    if (count == 0) return MSC_OK;
+    char* base = static_scratch(o->device);
+    if (!base) return fail(c, MSC_E_STATE, "msc_refine_static: no device buffer address for device %d", o->device);
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, MSC_E_HIP, "hipSetDevice");
+    // the kernel divides the centidegree values by the step itself: no host copy
+    a.q_div = arm->step_cdeg;
+    char* d_q = base;
+    char* d_t = d_q + align_up((uint64_t)count * n * 4);
+    char* d_a = d_t + align_up((uint64_t)count * 24);
+    char* d_s = d_a + align_up((uint64_t)count * n * 8);
+    HIP_TRY(hipMemcpyAsync(d_q, poses_cdeg, (size_t)count * n * 4, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(d_t, targets, (size_t)count * 24, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(launch_refine(a, (const int32_t*)d_q, (const double*)d_t, count, (double*)d_a, (int32_t*)d_s,
+                          c->stream));
+    HIP_TRY(hipMemcpyAsync(angles_out, d_a, (size_t)count * n * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(status_out, d_s, (size_t)count * 4, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
     return MSC_OK;
 }
 

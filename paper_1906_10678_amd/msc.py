@@ -32,6 +32,7 @@ EXPORTS = [
     "msc_ctx_set_lanes", "msc_lane_bytes", "msc_batch", "msc_query_bytes", "msc_server_start",
     "msc_server_submit", "msc_server_poll", "msc_server_wait", "msc_server_stop", "msc_refine", "msc_replan",
     "msc_scene_bytes_dynamic", "msc_scene_set_dynamic", "msc_server_step", "msc_server_take_replans",
+    "msc_refine_static", "msc_refine_static_max",
 ]
 
 
@@ -112,6 +113,9 @@ def load_library(path: str = LIB_PATH):
     L.msc_replan.argtypes = [c_void_p, c_void_p, P(MscArm), P(i32), P(i32), i32, i32, P(i32), P(MscOpts), P(i32)]
     L.msc_get_stats.argtypes = [c_void_p, P(MscStats)]
     L.msc_refine.argtypes = [c_void_p, P(MscArm), P(i32), P(ctypes.c_double), i64, P(ctypes.c_double), P(i32)]
+    L.msc_refine_static.argtypes = L.msc_refine.argtypes
+    L.msc_refine_static_max.argtypes = [i32]
+    L.msc_refine_static_max.restype = i64
     L.msc_debug_tables.argtypes = [c_void_p, P(MscArm), i32, P(i32), P(i32)]
     L.msc_debug_raster.argtypes = [c_void_p, c_void_p, P(ctypes.c_uint8)]
     L.msc_debug_set.argtypes = [c_void_p, i32, i32, P(u64), u64, P(u64)]
@@ -397,6 +401,25 @@ class Solver:
                                  q.shape[0], _ptr(ang, ctypes.c_double), _ptr(st, ctypes.c_int32))
         self._check(rc, "msc_refine")
         return ang, st
+
+    def refine_static(self, arm, q, targets) -> Tuple[np.ndarray, np.ndarray]:
+        """msc_refine_static: as refine(), with the device staging in the library's fixed
+        buffer (no workspace use); at most msc_refine_static_max(dof) poses."""
+        a = make_arm(arm)
+        q = np.ascontiguousarray(np.asarray(q, np.int32).reshape(-1, a.dof) * a.step_cdeg)
+        t = np.ascontiguousarray(np.asarray(targets, np.float64).reshape(-1, 3))
+        if t.shape[0] != q.shape[0]:
+            raise ValueError("one target per pose")
+        ang = np.zeros(q.shape, np.float64)
+        st = np.zeros(q.shape[0], np.int32)
+        rc = self.lib.msc_refine_static(self.ctx, ctypes.byref(a), _ptr(q, ctypes.c_int32),
+                                        _ptr(t, ctypes.c_double), q.shape[0], _ptr(ang, ctypes.c_double),
+                                        _ptr(st, ctypes.c_int32))
+        self._check(rc, "msc_refine_static")
+        return ang, st
+
+    def refine_static_max(self, dof: int) -> int:
+        return int(self.lib.msc_refine_static_max(dof))
 
     def pose_fn_for(self, arm, sc):
         """A synth-compatible pose function backed by the GPU library."""
