@@ -22,7 +22,8 @@ of the output set + occupancy words of the active box) in the layout
 achievable ceiling), `frac_of_copy` = achieved / copy_GBps, and `full_size_hbm`: the HBM
 rate of the meet and of the backward stage into B_m on full-size plans, read from the
 committed counter summary (profiles/c4_big_stages.md) while the kernel sources match.
-`cpu_baseline` times the CPU oracle on one query of the same workload.
+`cpu_baseline` times the CPU oracle on the host cores: all-core throughput over 16 queries of the
+same workload (one process per query), with the one-thread latency of query 0 beside it.
 """
 from __future__ import annotations
 
@@ -91,18 +92,44 @@ def expansion_bytes(solver, msc, n, na, stats):
     return out
 
 
-def cpu_baseline(queries, split, approach=None):
-    import oracle
+def query_record(q, split, approach=None) -> dict:
+    """A query as plain JSON for the oracle's timing child."""
+    a, sc = q.arm, q.scene
+    return {"arm": {"types": list(a.types), "lens": list(a.lens), "lo_cdeg": list(a.lo_cdeg),
+                    "hi_cdeg": list(a.hi_cdeg), "step_cdeg": a.step_cdeg, "base": list(a.base),
+                    "samples": a.samples, "az0_cdeg": a.az0_cdeg, "el0_cdeg": a.el0_cdeg},
+            "scene": {"n": sc.n, "dilate": sc.dilate, "boxes": np.asarray(sc.boxes).tolist(),
+                      "spheres": np.asarray(sc.spheres).tolist()},
+            "start": np.asarray(q.start).tolist(), "target": list(q.target), "waypoints": q.waypoints,
+            "max_delta": q.max_delta, "split": int(split), "approach": list(approach) if approach else None}
 
-    q = queries[0]
-    t0 = time.perf_counter()
-    occ = oracle.raster(q.scene)
-    st, path, _ = oracle.plan_path(q.arm, occ, q.start, q.target, q.waypoints, q.max_delta, m=split,
-                                   approach=approach)
-    dt = time.perf_counter() - t0
-    return {"value": 1.0 / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": "1 query (scene seed 0): raster + windowed reach (split %d) + tube path, single thread, "
-                      "%.1f s, status %d" % (split, dt, st)}
+
+def cpu_baseline(queries, splits, approach, procs, count):
+    """The oracle on the host cores, in a child process (a fresh interpreter that has not
+    touched the GPU): one query on one thread, then `count` queries over `procs` worker
+    processes.  value = the all-core throughput."""
+    import subprocess
+    import tempfile
+
+    procs = max(1, min(procs, len(os.sched_getaffinity(0))))
+    count = min(count, len(queries))
+    with tempfile.TemporaryDirectory() as tmp:
+        src, dst = os.path.join(tmp, "q.json"), os.path.join(tmp, "t.json")
+        with open(src, "w") as f:
+            json.dump([query_record(queries[i], splits[i], approach) for i in range(count)], f)
+        env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+        subprocess.run([sys.executable, "-m", "oracle.timing", src, dst, str(procs)], cwd=ROOT, env=env,
+                       check=True)
+        with open(dst) as f:
+            t = json.load(f)
+    return {"value": round(t["queries"] / t["throughput_wall_s"], 4), "unit": "solves/s", "cores": t["procs"],
+            "kind": "oracle",
+            "sample": "%d queries (scene seeds 0..%d) of the same workload, raster + windowed reach + tube path, "
+                      "one query per process over %d single-thread processes, %.1f s wall; statuses %s"
+                      % (t["queries"], t["queries"] - 1, t["procs"], t["throughput_wall_s"], t["statuses"]),
+            "latency_1_thread": {"value": round(1.0 / t["latency_s"], 4), "unit": "solves/s",
+                                 "seconds": round(t["latency_s"], 3), "query": 0, "status": t["latency_status"]},
+            "nproc": t["nproc"], "affinity_cpus": t["affinity"], "cpu_model": t["cpu_model"]}
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "expand_traffic_c2.md")
@@ -419,6 +446,42 @@ def trace_summary(args):
     print("wrote", TRACE_PROFILE, flush=True)
 
 
+def serve_poisson(solver, msc, queries, scenes, rate, seconds, rng):
+    """Queries submitted to the running server as a Poisson stream of the given rate for
+    `seconds`, cycling over `queries`; latency from submission to completion, measured by
+    the library.  Returns a row of served/s, p50/p99 and status counts."""
+    gaps = rng.exponential(1.0 / rate, size=int(rate * seconds * 1.2) + 8)
+    t_arr = np.cumsum(gaps)
+    t_arr = t_arr[t_arr < seconds]
+    pending, lat, sts = [], [], []
+    t0 = time.perf_counter()
+    i = 0
+    while i < len(t_arr) or pending:
+        now = time.perf_counter() - t0
+        while i < len(t_arr) and t_arr[i] <= now:
+            q = queries[i % len(queries)]
+            spec = msc.QuerySpec(scenes[i % len(queries)], q.arm, q.target, start=q.start,
+                                 waypoints=q.waypoints, delta=q.max_delta)
+            pending.append((solver.submit(spec), spec))
+            i += 1
+        still = []
+        for t, spec in pending:
+            if solver.poll(t):
+                st, _, ms = spec.result()
+                lat.append(ms)
+                sts.append(st)
+            else:
+                still.append((t, spec))
+        pending = still
+        if i < len(t_arr) and not pending:
+            time.sleep(max(0.0, min(0.001, t_arr[i] - (time.perf_counter() - t0))))
+    wall = time.perf_counter() - t0
+    lat = np.array(lat)
+    return {"offered_per_s": rate, "served": len(lat), "served_per_s": round(len(lat) / wall, 1),
+            "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "statuses": {str(k): sts.count(k) for k in sorted(set(sts))}}
+
+
 def bench_c2serve(args):
     """The 8-DOF reach + path queries arriving as a Poisson stream, served by the server
     with one lane (one query at a time: the plain form) and with several lanes (queries
@@ -436,38 +499,8 @@ def bench_c2serve(args):
         solver.server_start()
         try:
             for rate in args.serve_rates:
-                gaps = rng.exponential(1.0 / rate, size=int(rate * args.serve_seconds * 1.2) + 8)
-                t_arr = np.cumsum(gaps)
-                t_arr = t_arr[t_arr < args.serve_seconds]
-                pending, lat, sts = [], [], []
-                t0 = time.perf_counter()
-                i = 0
-                while i < len(t_arr) or pending:
-                    now = time.perf_counter() - t0
-                    while i < len(t_arr) and t_arr[i] <= now:
-                        q = queries[i % len(queries)]
-                        spec = msc.QuerySpec(scenes[i % len(queries)], q.arm, q.target, start=q.start,
-                                             waypoints=q.waypoints, delta=q.max_delta)
-                        pending.append((solver.submit(spec), spec))
-                        i += 1
-                    still = []
-                    for t, spec in pending:
-                        if solver.poll(t):
-                            st, _, ms = spec.result()
-                            lat.append(ms)
-                            sts.append(st)
-                        else:
-                            still.append((t, spec))
-                    pending = still
-                    if i < len(t_arr) and not pending:
-                        time.sleep(max(0.0, min(0.001, t_arr[i] - (time.perf_counter() - t0))))
-                wall = time.perf_counter() - t0
-                lat = np.array(lat)
-                row = {"lanes": lanes, "offered_per_s": rate, "served": len(lat),
-                       "served_per_s": round(len(lat) / wall, 1),
-                       "p50_ms": round(float(np.percentile(lat, 50)), 3),
-                       "p99_ms": round(float(np.percentile(lat, 99)), 3),
-                       "statuses": {str(k): sts.count(k) for k in sorted(set(sts))}}
+                row = {"lanes": lanes}
+                row.update(serve_poisson(solver, msc, queries, scenes, rate, args.serve_seconds, rng))
                 out_rows.append(row)
                 print(json.dumps(row), file=sys.stderr, flush=True)
         finally:
@@ -475,9 +508,9 @@ def bench_c2serve(args):
     solver.set_lanes(0)
     print(json.dumps({"metric": "8-DOF reach+path served/s and p50/p99 ms under Poisson arrivals",
                       "seconds_per_rate": args.serve_seconds, "rows": out_rows,
-                      "config": {"workload": "the 16 8-DOF reach + 16-waypoint path queries of the benchmark, "
+                      "config": {"workload": "the %d 8-DOF reach + 16-waypoint path queries of the benchmark, "
                                              "Poisson arrivals, latency from submission to completion; one lane "
-                                             "= one query at a time"}}), flush=True)
+                                             "= one query at a time" % len(queries)}}), flush=True)
 
 
 def bench_c3(args):
@@ -709,7 +742,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=2, help="untimed batches")
     ap.add_argument("--batch", type=int, default=64, help="queries per batch")
     ap.add_argument("--lanes", type=int, default=0, help="worker lanes (0: pick the best of a short sweep)")
-    ap.add_argument("--queries", type=int, default=16, help="distinct seeded queries")
+    ap.add_argument("--queries", type=int, default=64,
+                    help="distinct seeded queries (a batch holds no query twice while batch <= queries)")
+    ap.add_argument("--serve-rate", type=float, default=600.0,
+                    help="offered rate of the served phase of the bench line (Poisson arrivals)")
+    ap.add_argument("--serve-phase-seconds", type=float, default=3.0)
+    ap.add_argument("--cpu-procs", type=int, default=16, help="processes of the all-core oracle leg")
+    ap.add_argument("--cpu-queries", type=int, default=16, help="queries of the all-core oracle leg")
     ap.add_argument("--plain-steps", type=int, default=100)
     ap.add_argument("--cpu-replan", action="store_true",
                     help="replan workload: also time the oracle on query 0 (about two minutes)")
@@ -892,8 +931,24 @@ def main():
         qlat.extend(batch_step(b))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    solver.set_lanes(0)
     qlat = np.array(qlat)
+
+    # ---- served: the same queries as a Poisson stream through the server, one lane (one
+    # query at a time, the plain form) against the batch's lane count
+    served = {"offered_per_s": args.serve_rate, "seconds": args.serve_phase_seconds,
+              "p_latency": "per query, from submission to completion"}
+    scenes = [solver.scene(q.scene) for q in queries]
+    rng = np.random.default_rng(11)
+    for key, L in (("one_lane", 1), ("lanes_%d" % lanes, lanes)):
+        solver.set_lanes(L)
+        solver.server_start(approach=cone)
+        try:
+            served[key] = serve_poisson(solver, msc, queries, scenes, args.serve_rate, args.serve_phase_seconds,
+                                        rng)
+        finally:
+            solver.server_stop()
+        print("served", key, served[key], file=sys.stderr, flush=True)
+    solver.set_lanes(0)
 
     result = {
         "metric": "8-DOF reach+path solves/sec" + (" (4 segments x 2 DOF)" if args.arm == "gms" else ""),
@@ -922,10 +977,11 @@ def main():
                            if args.arm == "gms" else "alternating yaw/pitch chain"),
                    "p_latency": "per query, from batch start to its completion"},
         "plain": plain,
+        "served": served,
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(queries, splits[0], cone)
+        result["cpu_baseline"] = cpu_baseline(queries, splits, cone, args.cpu_procs, args.cpu_queries)
     print(json.dumps(result), flush=True)
 
 

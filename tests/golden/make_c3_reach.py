@@ -1,7 +1,8 @@
-"""Writes c3_reach.json: the oracle's answers to the full-size batched-reach queries of
-scenes 0..15 (128^3 / 256^3 grids, unwindowed joints, 5 deg steps) whose arm has at
-most 6 DOF (the oracle needs seconds for those, far longer for 7 and 8 DOF), with a
-fingerprint of each query's inputs.
+"""Writes c3_reach.json: the oracle's answers to full-size batched-reach queries of scenes
+0..15 (128^3 / 256^3 grids, unwindowed joints, 5 deg steps), with a fingerprint of each
+query's inputs: every query whose arm has at most 6 DOF (seconds each for the oracle),
+and the first HIGH_DOF_COUNT queries by index with 7 or 8 DOF (up to about 12 minutes
+and 12 GB each).
 
 Only the oracle computes these values.  Run from the repository root:
 python tests/golden/make_c3_reach.py
@@ -24,6 +25,8 @@ from paper_1906_10678_amd import synth  # noqa: E402
 SCENES = 16
 PER_SCENE = 8
 MAX_DOF = 6
+HIGH_DOF_COUNT = 12
+WORKERS = 3   # memory: the 8-DOF queries hold up to about 12 GB each
 
 
 def queries():
@@ -41,12 +44,15 @@ def solve(args):
 def main():
     oracle.build()
     qs = queries()
-    todo = [(i, q) for i, q in enumerate(qs) if q.arm.dof <= MAX_DOF]
-    with Pool(min(4, os.cpu_count() or 1)) as p:
-        rows = p.map(solve, todo)
+    # the long 7-8 DOF queries first, so they overlap with the rest
+    todo = [(i, q) for i, q in enumerate(qs) if q.arm.dof > MAX_DOF][:HIGH_DOF_COUNT]
+    todo += [(i, q) for i, q in enumerate(qs) if q.arm.dof <= MAX_DOF]
+    with Pool(min(WORKERS, os.cpu_count() or 1)) as p:
+        rows = sorted(p.map(solve, todo, chunksize=1), key=lambda r: r["query"])
     out = os.path.join(os.path.dirname(os.path.abspath(__file__)), "c3_reach.json")
     with open(out, "w") as f:
-        json.dump({"scenes": SCENES, "per_scene": PER_SCENE, "max_dof": MAX_DOF, "rows": rows}, f)
+        json.dump({"scenes": SCENES, "per_scene": PER_SCENE, "max_dof": MAX_DOF, "high_dof_count": HIGH_DOF_COUNT,
+                   "rows": rows}, f)
     print("wrote", out, len(rows), "queries", [r["status"] for r in rows])
 
 

@@ -7,7 +7,7 @@ candidates the one closest in configuration is taken.  Concretely: poses at
 waypoint w lie in a tube of radius r around the integer guide from the start to the
 reach pose, every move changes each joint by at most delta, and the backward choice
 is the L1-closest pose to the guide, ties broken by joint values.  The tube radius
-is relaxed after a failure ("the filter criteria be relaxed ... adaptively").
+is relaxed only after a failure (adaptive relaxation, "Filtering for smoothness").
 """
 import itertools
 from fractions import Fraction
