@@ -124,6 +124,14 @@ def arm_gms(lens: Sequence[int] = GMS_LENS, step_cdeg: int = 500, limit_cdeg: in
                step_cdeg=step_cdeg, base=base)
 
 
+def arm_virtual(lens: Sequence[int], step_cdeg: int = 500, limit_cdeg: int = 17000,
+                base: Tuple[int, int, int] = (0, 0, 0)) -> Arm:
+    """A virtual arm for paths between arbitrary poses ("Path between Arbitrary Poses"):
+    a few segments that can each point anywhere (two joints per segment, as arm_gms),
+    rooted where the path starts (the base is replaced by the caller)."""
+    return arm_gms(lens, step_cdeg, limit_cdeg, base)
+
+
 def scaled_lens(n: int, dof: int) -> List[int]:
     """Prefix of the 8-DOF chain with lengths scaled by n/256, halves rounded up."""
     return [int(np.floor(l * n / 256 + 0.5)) for l in C2_LENS[:dof]]
