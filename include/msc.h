@@ -192,6 +192,58 @@ msc_status msc_replan(msc_ctx* ctx, const msc_scene* scene, const msc_arm* arm,
                       int32_t max_delta_cdeg, const int32_t* ref_cdeg, const msc_opts* opts,
                       int32_t* path_out);
 
+/* Waypoint tracking of the workspace-guided paths.  At each waypoint the pose is chosen
+ * among the poses whose every joint is within max_delta_cdeg of the previous pose (and
+ * within the arm's limits), that are clear of obstacles (as msc_pose_check) and whose
+ * joint `tracked` (the end of the first `tracked` segments) lies within squared distance
+ * eps2_vox (voxels) of the waypoint: the smallest L1 joint change in steps, then the
+ * smallest squared distance, then the canonical order centred on the previous pose (per
+ * joint |change| then change, joint 1 first).  When there is none the box is widened to
+ * relaxed_delta_cdeg for that waypoint ("Filtering for smoothness": relaxed adaptively,
+ * after a failure); when that fails too, the next candidate solution is tried.
+ * Defaults (msc_track_default): tracked -1 (msc_guided_path: dof - 2, msc_pose_path: dof),
+ * max_delta one step, relaxed_delta two steps (-1 each), eps2_vox 9.  Requirements:
+ * 0 <= max_delta <= relaxed_delta, multiples of the step; (2 relaxed/step + 1)^dof < 2^42;
+ * eps2_vox in 0..1023. */
+typedef struct {
+    int32_t tracked;
+    int32_t max_delta_cdeg;
+    int32_t relaxed_delta_cdeg;
+    int32_t eps2_vox;
+} msc_track;
+void msc_track_default(msc_track* t);
+
+/* Reach-pose-guided path ("Path Planning", "Smooth sequence computation"): the reach
+ * search of msc_reach (unwindowed, canonical order centred on 0) gives up to
+ * opts->reach_retries reach poses; for each in turn, the tracked joint walks back along
+ * the pose's own collision sample points, of segments tracked .. 2 (each from its end
+ * to its start, segments of length 0 have none), to the end of segment 1 (the root of
+ * the moving part of the arm: segment 1 rises along the initial orientation and its
+ * joint only spins it), one waypoint per sample, each pose chosen from the previous one
+ * as described for msc_track.  The first reach pose whose walk completes gives the path:
+ * path_out receives its M + 1 rows in execution order (row 0 = the pose at the root
+ * waypoint, the last row = the reach pose), M = samples * (segments of nonzero length
+ * among 2..tracked), and *rows_out = M + 1.  path_out must hold
+ * (samples * (tracked - 1) + 1) * dof values.  MSC_NO_REACH as msc_reach; MSC_NO_PATH when
+ * no walk completes.  track may be NULL for the defaults. */
+msc_status msc_guided_path(msc_ctx* ctx, const msc_scene* scene, const msc_arm* arm, const int32_t target[3],
+                           const msc_track* track, const msc_opts* opts, int32_t* path_out, int32_t* rows_out);
+
+/* Path between arbitrary poses ("Path between Arbitrary Poses"): a virtual arm
+ * (virtual_arm; its base is replaced by the voxel of joint `tracked` of the start pose,
+ * its step must equal the arm's) reaches for the target with the search of msc_reach;
+ * for each of its first opts->reach_retries poses in turn, the real arm's tracked joint
+ * follows the virtual pose's collision sample points from its root outward (segments
+ * 1..V, s = 1..samples each; the last is the target), forward from the start pose, each
+ * pose chosen from the previous one as described for msc_track.  path_out receives the
+ * M + 1 rows (row 0 = the start pose), M = samples of the virtual arm * its segments of
+ * nonzero length, and *rows_out = M + 1; it must hold (virtual samples * virtual dof + 1)
+ * * dof values.  E_ARG if the start pose is not clear; MSC_NO_REACH if the virtual arm
+ * cannot reach the target; MSC_NO_PATH if no walk completes. */
+msc_status msc_pose_path(msc_ctx* ctx, const msc_scene* scene, const msc_arm* arm, const int32_t* start_cdeg,
+                         const int32_t target[3], const msc_arm* virtual_arm, const msc_track* track,
+                         const msc_opts* opts, int32_t* path_out, int32_t* rows_out);
+
 /* Forward-kinematics replay of `count` poses (poses_cdeg[count*dof]) on the GPU:
  * valid_out[i] = 1 if the base is free and every segment sample is inside the grid
  * and free, else 0; end_out[i*3..] = end voxel of the chain (computed even when
@@ -351,7 +403,7 @@ msc_status msc_get_stats(msc_ctx* ctx, msc_stats* out);
 typedef enum {
     MSC_K_FILL = 0, MSC_K_TABLES, MSC_K_RASTER, MSC_K_ORIENT, MSC_K_SEED, MSC_K_EXPAND_FWD,
     MSC_K_EXPAND_BWD, MSC_K_COMPACT, MSC_K_JOIN, MSC_K_DMARK, MSC_K_DFS, MSC_K_POSE,
-    MSC_K_TUBE_VALID, MSC_K_TUBE_SOLVE, MSC_K_REFINE, MSC_K_COUNT
+    MSC_K_TUBE_VALID, MSC_K_TUBE_SOLVE, MSC_K_REFINE, MSC_K_TRACK, MSC_K_COUNT
 } msc_kernel;
 typedef struct {
     int32_t kernel;     /* msc_kernel */

@@ -143,6 +143,31 @@ struct RefineArgs {
 hipError_t launch_refine(const RefineArgs& a, const int32_t* q_steps, const double* targets, int64_t count,
                          double* angles, int32_t* status, hipStream_t st);
 
+// Waypoint tracking of the workspace-guided paths ("Path Planning", "Smooth sequence
+// computation", "Filtering for smoothness", "Path between Arbitrary Poses").  One block
+// per query walks the waypoints of each candidate solution in turn.
+constexpr int kTrackMaxPoints = 1024;
+struct TrackArgs {
+    JointView joints[kMaxDof];   // the real arm (full limits)
+    JointView vjoints[kMaxDof];  // mode 1: the virtual arm
+    GridView g;
+    int n, na, bx, by, bz, ia0, ie0;
+    int len[kMaxDof];            // real segment lengths (reach-pose waypoints)
+    int lim_lo[kMaxDof], lim_hi[kMaxDof];
+    int tracked;                 // the joint that follows the waypoints (1..n)
+    int delta, delta2;           // joint box per waypoint, relaxed box after a failure (steps)
+    int eps2;                    // squared voxel tolerance at a waypoint
+    int mode;                    // 0: reach-pose-guided, backward; 1: virtual arm, forward from start
+    int vn, vbx, vby, vbz, via0, vie0;
+    int vlen[kMaxDof];
+    int start[kMaxDof];          // mode 1: the start pose
+    int nsol;                    // candidate solutions, tried in order
+    const int32_t* sols;         // nsol * (mode 0: n, mode 1: vn) joint values in steps
+    int32_t* rows;               // out: (M + 1) * n joint values in steps, in path order
+    int32_t* status;             // out: [0] rows written (0: none), [1] solution used, [2] waypoints
+};
+hipError_t launch_track(const TrackArgs& a, hipStream_t st);
+
 struct TubeArgs {
     JointView joints[kMaxDof];
     GridView g;

@@ -1596,6 +1596,217 @@ hipError_t launch_pose_check(const PoseArgs& a, const int32_t* q, int64_t count,
 }
 
 // ---------------------------------------------------------------------------
+// Waypoint tracking ("Smooth sequence computation", "Filtering for smoothness", "Path
+// between Arbitrary Poses").  One block per query, persistent over the waypoints of
+// every candidate solution.  At a waypoint the block scores the joint box of radius d
+// around the current pose: candidate c enumerates the box in the canonical order (digit
+// k of c in base 2d + 1, joint 1 most significant, digit r <-> change t in the order
+// 0, -1, +1, -2, +2, ...), so the order key is (L1 change, squared distance, c) and the
+// pose is the block's minimum key among the poses that are valid and within the
+// tolerance.  The tracked joint's distance is tested first; only candidates within the
+// tolerance replay the whole arm against the grid.
+// ---------------------------------------------------------------------------
+constexpr int kTrackThreads = 512;
+
+__device__ __forceinline__ int track_change(int r) { return r == 0 ? 0 : ((r & 1) ? -((r + 1) >> 1) : (r >> 1)); }
+
+// Minimum key over the box of radius d around q (all threads return it).
+__device__ unsigned long long track_best(const TrackArgs& a, const int* q, int d, int px, int py, int pz,
+                                         bool base_free, unsigned long long* red) {
+    const int n = a.n;
+    const int B = 2 * d + 1;
+    uint64_t total = 1;
+    for (int k = 0; k < n; ++k) total *= (uint64_t)B;
+    unsigned long long best = ~0ull;
+    for (uint64_t c = threadIdx.x; c < total && base_free; c += blockDim.x) {
+        int t[kMaxDof];
+        uint64_t rest = c;
+        bool inside = true;
+        int l1 = 0;
+        for (int k = n - 1; k >= 0; --k) {
+            const int r = (int)(rest % (uint64_t)B);
+            rest /= (uint64_t)B;
+            t[k] = track_change(r);
+            const int v = q[k] + t[k];
+            inside = inside && v >= a.lim_lo[k] && v <= a.lim_hi[k];
+            l1 += t[k] < 0 ? -t[k] : t[k];
+        }
+        if (!inside) continue;
+        // the tracked joint first: offsets only
+        int ia = a.ia0, ie = a.ie0, x = a.bx, y = a.by, z = a.bz;
+        for (int k = 0; k < a.tracked; ++k) {
+            if (a.joints[k].type == 0)
+                ia = wrap_na(ia + q[k] + t[k], a.na);
+            else
+                ie = wrap_na(ie + q[k] + t[k], a.na);
+            const short4 o = a.joints[k].off[ia * a.na + ie];
+            x += o.x;
+            y += o.y;
+            z += o.z;
+        }
+        const int dx = x - px, dy = y - py, dz = z - pz;
+        const int d2 = dx * dx + dy * dy + dz * dz;
+        if (d2 > a.eps2) continue;
+        const unsigned long long key =
+            ((unsigned long long)l1 << 52) | ((unsigned long long)d2 << 42) | (unsigned long long)c;
+        if (key >= best) continue;
+        // the whole arm against the grid
+        ia = a.ia0;
+        ie = a.ie0;
+        x = a.bx;
+        y = a.by;
+        z = a.bz;
+        bool clear = true;
+        for (int k = 0; k < n && clear; ++k) {
+            const JointView& J = a.joints[k];
+            if (J.type == 0)
+                ia = wrap_na(ia + q[k] + t[k], a.na);
+            else
+                ie = wrap_na(ie + q[k] + t[k], a.na);
+            const int o = ia * a.na + ie;
+            clear = segment_clear_all(a.g, J, o, x, y, z);
+            const short4 off = J.off[o];
+            x += off.x;
+            y += off.y;
+            z += off.z;
+        }
+        if (clear) best = key;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(best, off, 64);
+        best = o < best ? o : best;
+    }
+    __syncthreads();   // red may still be read by the previous call
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = best;
+    __syncthreads();
+    best = ~0ull;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) best = red[w] < best ? red[w] : best;
+    return best;
+}
+
+__device__ void track_body(const TrackArgs& a) {
+    __shared__ int pts[kTrackMaxPoints * 3];
+    __shared__ int qc[kMaxDof];
+    __shared__ int seg[kMaxDof * 4];   // orientation and start voxel of each segment
+    __shared__ unsigned long long red[kTrackThreads / 64];
+    __shared__ int npts;
+    const int n = a.n;
+    const bool base_free = cell_free(a.g, a.bx, a.by, a.bz);
+    if (threadIdx.x == 0) {
+        a.status[0] = 0;
+        a.status[1] = -1;
+        a.status[2] = 0;
+    }
+    for (int i = 0; i < a.nsol; ++i) {
+        const int vn = a.mode == 0 ? n : a.vn;
+        const int32_t* sol = a.sols + (size_t)i * vn;
+        if (threadIdx.x == 0) {
+            // the solution's sample points, in the order the path visits them
+            const JointView* J = a.mode == 0 ? a.joints : a.vjoints;
+            const int* len = a.mode == 0 ? a.len : a.vlen;
+            int ia = a.mode == 0 ? a.ia0 : a.via0, ie = a.mode == 0 ? a.ie0 : a.vie0;
+            int x = a.mode == 0 ? a.bx : a.vbx, y = a.mode == 0 ? a.by : a.vby, z = a.mode == 0 ? a.bz : a.vbz;
+            for (int k = 0; k < vn; ++k) {
+                if (J[k].type == 0)
+                    ia = wrap_na(ia + sol[k], a.na);
+                else
+                    ie = wrap_na(ie + sol[k], a.na);
+                const int o = ia * a.na + ie;
+                seg[4 * k] = o;
+                seg[4 * k + 1] = x;
+                seg[4 * k + 2] = y;
+                seg[4 * k + 3] = z;
+                const short4 off = J[k].off[o];
+                x += off.x;
+                y += off.y;
+                z += off.z;
+            }
+            int m = 0;
+            if (a.mode == 0) {
+                // segments tracked .. 2 from their ends back to their starts, then the end
+                // of segment 1; the first point (the tracked joint itself) is left out
+                bool first = true;
+                for (int k = a.tracked - 1; k >= 1; --k) {
+                    if (len[k] == 0) continue;
+                    const short4* sw = J[k].sweep + (size_t)seg[4 * k] * J[k].S;
+                    for (int s = J[k].S - 1; s >= 0; --s) {
+                        if (first) {
+                            first = false;
+                            continue;
+                        }
+                        pts[3 * m] = seg[4 * k + 1] + sw[s].x;
+                        pts[3 * m + 1] = seg[4 * k + 2] + sw[s].y;
+                        pts[3 * m + 2] = seg[4 * k + 3] + sw[s].z;
+                        ++m;
+                    }
+                }
+                if (!first) {
+                    pts[3 * m] = seg[4 * 1 + 1];
+                    pts[3 * m + 1] = seg[4 * 1 + 2];
+                    pts[3 * m + 2] = seg[4 * 1 + 3];
+                    ++m;
+                }
+            } else {
+                for (int k = 0; k < vn; ++k) {
+                    if (len[k] == 0) continue;
+                    const short4* sw = J[k].sweep + (size_t)seg[4 * k] * J[k].S;
+                    for (int s = 0; s < J[k].S; ++s) {
+                        pts[3 * m] = seg[4 * k + 1] + sw[s].x;
+                        pts[3 * m + 1] = seg[4 * k + 2] + sw[s].y;
+                        pts[3 * m + 2] = seg[4 * k + 3] + sw[s].z;
+                        ++m;
+                    }
+                }
+            }
+            npts = m;
+        }
+        if (threadIdx.x < n) qc[threadIdx.x] = a.mode == 0 ? sol[threadIdx.x] : a.start[threadIdx.x];
+        __syncthreads();
+        const int M = npts;
+        if (threadIdx.x < n) a.rows[(size_t)(a.mode == 0 ? M : 0) * n + threadIdx.x] = qc[threadIdx.x];
+        int w = 0;
+        for (; w < M; ++w) {
+            const int px = pts[3 * w], py = pts[3 * w + 1], pz = pts[3 * w + 2];
+            int d = a.delta;
+            unsigned long long best = track_best(a, qc, d, px, py, pz, base_free, red);
+            if (best == ~0ull && a.delta2 != a.delta) {
+                d = a.delta2;
+                best = track_best(a, qc, d, px, py, pz, base_free, red);
+            }
+            if (best == ~0ull) break;
+            __syncthreads();   // every thread has read qc
+            if (threadIdx.x == 0) {
+                uint64_t rest = best & ((1ull << 42) - 1);
+                const uint64_t B = (uint64_t)(2 * d + 1);
+                for (int k = n - 1; k >= 0; --k) {
+                    qc[k] += track_change((int)(rest % B));
+                    rest /= B;
+                }
+            }
+            __syncthreads();
+            const int row = a.mode == 0 ? M - 1 - w : w + 1;
+            if (threadIdx.x < n) a.rows[(size_t)row * n + threadIdx.x] = qc[threadIdx.x];
+        }
+        if (threadIdx.x == 0) a.status[2] = w;
+        if (w == M) {
+            if (threadIdx.x == 0) {
+                a.status[0] = M + 1;
+                a.status[1] = i;
+            }
+            return;
+        }
+        __syncthreads();   // pts and qc are rewritten for the next solution
+    }
+}
+
+__global__ void __launch_bounds__(kTrackThreads) k_track(TrackArgs a) { track_body(a); }
+
+hipError_t launch_track(const TrackArgs& a, hipStream_t st) {
+    hipLaunchKernelGGL(k_track, dim3(1), dim3(kTrackThreads), 0, st, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Tube path search ("Smooth sequence computation", "Filtering for smoothness").
 // Waypoint w has the frame g_w - r .. g_w + r per joint, g_w the guide
 // start + round_half_away(w*(goal - start)/W); cell digits are base 2r+1 with joint 0

@@ -1297,6 +1297,168 @@ msc_status path_on(Lane* c, const msc_scene* sc, const msc_arm* arm, const int32
     return MSC_NO_PATH;
 }
 
+// ---------------------------------------------------------------------------
+// Workspace-guided paths: candidate solutions from the reach search, then one block
+// walks the waypoints of each in turn (k_track).
+// ---------------------------------------------------------------------------
+msc_status track_params(Lane* c, const msc_arm* arm, const msc_track* tr, int default_tracked, TrackArgs& ta) {
+    msc_track t;
+    msc_track_default(&t);
+    if (tr) t = *tr;
+    const int step = arm->step_cdeg;
+    ta.tracked = t.tracked < 0 ? default_tracked : t.tracked;
+    if (ta.tracked < 1 || ta.tracked > arm->dof) return fail(c, MSC_E_ARG, "tracked joint outside 1..dof");
+    const int d = t.max_delta_cdeg < 0 ? step : t.max_delta_cdeg;
+    const int d2 = t.relaxed_delta_cdeg < 0 ? 2 * step : t.relaxed_delta_cdeg;
+    if (d % step || d2 % step || d < 0 || d2 < d)
+        return fail(c, MSC_E_ARG, "track deltas must be multiples of the step with 0 <= max <= relaxed");
+    ta.delta = d / step;
+    ta.delta2 = d2 / step;
+    double cells = std::pow(2.0 * ta.delta2 + 1.0, (double)arm->dof);
+    if (cells >= 4398046511104.0) return fail(c, MSC_E_ARG, "relaxed joint box has 2^42 poses or more");
+    if (t.eps2_vox < 0 || t.eps2_vox > 1023) return fail(c, MSC_E_ARG, "eps2_vox outside 0..1023");
+    ta.eps2 = t.eps2_vox;
+    return MSC_OK;
+}
+
+// Fills the real arm's part of ta (joint views, limits, base) from plan p.
+msc_status track_arm(Lane* c, const msc_scene* sc, const Plan& p, TrackArgs& ta) {
+    std::vector<JointView> jv;
+    MSC_TRY(joint_views(c, p, jv));
+    for (int k = 0; k < p.n; ++k) {
+        ta.joints[k] = jv[k];
+        ta.len[k] = p.len[k];
+        ta.lim_lo[k] = p.lo[k];
+        ta.lim_hi[k] = p.hi[k];
+    }
+    ta.g = grid_view(sc);
+    ta.n = p.n;
+    ta.na = p.na;
+    ta.bx = p.base[0];
+    ta.by = p.base[1];
+    ta.bz = p.base[2];
+    ta.ia0 = p.ia0;
+    ta.ie0 = p.ie0;
+    return MSC_OK;
+}
+
+// Runs k_track over the candidate solutions sols[nsol * width] and copies the rows.
+msc_status track_run(Lane* c, TrackArgs& ta, const std::vector<int32_t>& sols, int nsol, int width, int max_rows,
+                     int step_cdeg, int32_t* path_out, int32_t* rows_out) {
+    void *h_sols, *d_sols, *h_rows, *d_rows, *h_st, *d_st;
+    MSC_TRY(host_area(c, (size_t)nsol * width * 4, &h_sols, &d_sols));
+    MSC_TRY(host_area(c, (size_t)max_rows * ta.n * 4, &h_rows, &d_rows));
+    MSC_TRY(host_area(c, 16, &h_st, &d_st));
+    std::memcpy(h_sols, sols.data(), (size_t)nsol * width * 4);
+    ta.nsol = nsol;
+    ta.sols = (const int32_t*)d_sols;
+    ta.rows = (int32_t*)d_rows;
+    ta.status = (int32_t*)d_st;
+    LAUNCH(MSC_K_TRACK, -1, nsol, launch_track(ta, c->stream));
+    MSC_TRY(sync_lane(c));
+    const volatile int32_t* st = (const volatile int32_t*)h_st;
+    const int rows = st[0];
+    c->stats.attempts = st[1] < 0 ? nsol : st[1] + 1;
+    c->stats.reach_index = st[1];
+    if (rows <= 0) return MSC_NO_PATH;
+    if (rows > max_rows) return fail(c, MSC_E_CAPACITY, "tracked path longer than planned");
+    const int32_t* hr = (const int32_t*)h_rows;
+    for (size_t j = 0; j < (size_t)rows * ta.n; ++j) path_out[j] = hr[j] * step_cdeg;
+    *rows_out = rows;
+    return MSC_OK;
+}
+
+msc_status guided_on(Lane* c, const msc_scene* sc, const msc_arm* arm, const int32_t target[3], const msc_track* tr,
+                     const msc_opts* opts, int32_t* path_out, int32_t* rows_out) {
+    MSC_TRY(check_scene(c, sc));
+    MSC_TRY(check_arm(c, arm, sc->n));
+    if (!target || !path_out || !rows_out) return fail(c, MSC_E_ARG, "NULL target or output");
+    for (int i = 0; i < 3; ++i)
+        if (target[i] < 0 || target[i] >= sc->n) return fail(c, MSC_E_ARG, "target outside the grid");
+    msc_opts o = opts_or_default(opts);
+    if (o.split_m < -1 || o.split_m > arm->dof) return fail(c, MSC_E_ARG, "split_m outside -1..dof");
+    if (o.reach_retries < 1 || o.reach_retries > 64) return fail(c, MSC_E_ARG, "bad options");
+    TrackArgs ta{};
+    MSC_TRY(track_params(c, arm, tr, std::max(1, arm->dof - 2), ta));
+    const int max_rows = arm->samples * (ta.tracked - 1) + 1;
+    if (max_rows > kTrackMaxPoints) return fail(c, MSC_E_ARG, "more than %d waypoints", kTrackMaxPoints);
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, MSC_E_HIP, "hipSetDevice");
+    begin_call(c);
+    Plan p;
+    make_plan(arm, target, p);
+    p.prune = (o.flags & MSC_NO_PRUNE) ? 0 : 1;
+    p.split = o.split_m;
+    MSC_TRY(set_approach(c, o, p));
+    ReachOut r;
+    msc_status st = run_reach(c, sc, p, o.reach_retries, (o.flags & MSC_CAPTURE_SETS) != 0, r);
+    if (st != MSC_OK) return st;
+    MSC_TRY(track_arm(c, sc, p, ta));
+    ta.mode = 0;
+    return track_run(c, ta, r.sols, r.nsol, p.n, max_rows, arm->step_cdeg, path_out, rows_out);
+}
+
+msc_status pose_path_on(Lane* c, const msc_scene* sc, const msc_arm* arm, const int32_t* start_cdeg,
+                        const int32_t target[3], const msc_arm* varm, const msc_track* tr, const msc_opts* opts,
+                        int32_t* path_out, int32_t* rows_out) {
+    MSC_TRY(check_scene(c, sc));
+    MSC_TRY(check_arm(c, arm, sc->n));
+    if (!start_cdeg || !target || !varm || !path_out || !rows_out) return fail(c, MSC_E_ARG, "NULL argument");
+    for (int i = 0; i < 3; ++i)
+        if (target[i] < 0 || target[i] >= sc->n) return fail(c, MSC_E_ARG, "target outside the grid");
+    if (varm->step_cdeg != arm->step_cdeg) return fail(c, MSC_E_ARG, "the virtual arm's step differs from the arm's");
+    msc_opts o = opts_or_default(opts);
+    if (o.split_m < -1 || o.reach_retries < 1 || o.reach_retries > 64) return fail(c, MSC_E_ARG, "bad options");
+    TrackArgs ta{};
+    MSC_TRY(track_params(c, arm, tr, arm->dof, ta));
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, MSC_E_HIP, "hipSetDevice");
+    begin_call(c);
+    Plan p;
+    make_plan(arm, target, p);
+    int start[kMaxDof];
+    for (int k = 0; k < p.n; ++k) {
+        if (start_cdeg[k] % arm->step_cdeg) return fail(c, MSC_E_ARG, "start angle %d not a multiple of the step", k);
+        start[k] = start_cdeg[k] / arm->step_cdeg;
+        if (start[k] < p.lo[k] || start[k] > p.hi[k]) return fail(c, MSC_E_ARG, "start angle %d outside its limits", k);
+        ta.start[k] = start[k];
+    }
+    uint8_t ok = 0;
+    MSC_TRY(pose_check_steps(c, sc, p, start, 1, &ok, nullptr));
+    if (!ok) return fail(c, MSC_E_ARG, "start pose is not clear of obstacles");
+    // the virtual arm's root: joint `tracked` of the start pose
+    Plan ps = p;
+    ps.n = ta.tracked;
+    int32_t root[3];
+    MSC_TRY(pose_check_steps(c, sc, ps, start, 1, &ok, root));
+    msc_arm va = *varm;
+    for (int i = 0; i < 3; ++i) va.base[i] = root[i];
+    MSC_TRY(check_arm(c, &va, sc->n));
+    const int max_rows = va.samples * va.dof + 1;
+    if (max_rows > kTrackMaxPoints) return fail(c, MSC_E_ARG, "more than %d waypoints", kTrackMaxPoints);
+    begin_call(c);
+    Plan pv;
+    make_plan(&va, target, pv);
+    pv.prune = (o.flags & MSC_NO_PRUNE) ? 0 : 1;
+    pv.split = o.split_m > va.dof ? -1 : o.split_m;
+    ReachOut r;
+    msc_status st = run_reach(c, sc, pv, o.reach_retries, false, r);
+    if (st != MSC_OK) return st;
+    std::vector<JointView> vjv;
+    MSC_TRY(joint_views(c, pv, vjv));
+    for (int k = 0; k < pv.n; ++k) {
+        ta.vjoints[k] = vjv[k];
+        ta.vlen[k] = pv.len[k];
+    }
+    ta.vn = pv.n;
+    ta.vbx = pv.base[0];
+    ta.vby = pv.base[1];
+    ta.vbz = pv.base[2];
+    ta.via0 = pv.ia0;
+    ta.vie0 = pv.ie0;
+    MSC_TRY(track_arm(c, sc, p, ta));
+    ta.mode = 1;
+    return track_run(c, ta, r.sols, r.nsol, pv.n, max_rows, arm->step_cdeg, path_out, rows_out);
+}
+
 // Solves q on lane L against the grid held by binding b, writes q->status, q->tick and
 // q->error, and releases the binding.
 void query_on(Lane* L, msc_query* q, const msc_opts* opts, Binding& b) {
@@ -1683,6 +1845,35 @@ msc_status msc_replan(msc_ctx* o, const msc_scene* sc, const msc_arm* arm, const
     if (!ref_cdeg) return fail(c, MSC_E_ARG, "NULL reference path");
     prof_reset(c, opts ? opts->flags : 0u);
     msc_status st = path_on(c, sc, arm, start_cdeg, target, waypoints, max_delta_cdeg, opts, path_out, ref_cdeg);
+    prof_finish(c);
+    return st;
+}
+
+void msc_track_default(msc_track* t) {
+    if (!t) return;
+    t->tracked = -1;
+    t->max_delta_cdeg = -1;
+    t->relaxed_delta_cdeg = -1;
+    t->eps2_vox = 9;
+}
+
+msc_status msc_guided_path(msc_ctx* o, const msc_scene* sc, const msc_arm* arm, const int32_t target[3],
+                           const msc_track* track, const msc_opts* opts, int32_t* path_out, int32_t* rows_out) {
+    if (!o) return MSC_E_ARG;
+    Lane* c = o->control;
+    prof_reset(c, opts ? opts->flags : 0u);
+    msc_status st = guided_on(c, sc, arm, target, track, opts, path_out, rows_out);
+    prof_finish(c);
+    return st;
+}
+
+msc_status msc_pose_path(msc_ctx* o, const msc_scene* sc, const msc_arm* arm, const int32_t* start_cdeg,
+                         const int32_t target[3], const msc_arm* virtual_arm, const msc_track* track,
+                         const msc_opts* opts, int32_t* path_out, int32_t* rows_out) {
+    if (!o) return MSC_E_ARG;
+    Lane* c = o->control;
+    prof_reset(c, opts ? opts->flags : 0u);
+    msc_status st = pose_path_on(c, sc, arm, start_cdeg, target, virtual_arm, track, opts, path_out, rows_out);
     prof_finish(c);
     return st;
 }

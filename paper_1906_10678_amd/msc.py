@@ -22,7 +22,7 @@ OK, NO_REACH, NO_PATH = 0, 1, 2
 E_ARG, E_NOMEM, E_HIP, E_CAPACITY, E_STATE = -1, -2, -3, -4, -5
 CAPTURE_SETS, NO_PRUNE, PROFILE = 1, 2, 4
 KERNELS = ["fill", "tables", "raster", "orient", "seed", "expand_fwd", "expand_bwd", "compact", "join", "dmark",
-           "dfs", "pose", "tube_valid", "tube_solve", "refine"]
+           "dfs", "pose", "tube_valid", "tube_solve", "refine", "track"]
 SET_F, SET_B, SET_C, SET_D = 0, 1, 2, 3
 
 EXPORTS = [
@@ -32,7 +32,7 @@ EXPORTS = [
     "msc_ctx_set_lanes", "msc_lane_bytes", "msc_batch", "msc_query_bytes", "msc_server_start",
     "msc_server_submit", "msc_server_poll", "msc_server_wait", "msc_server_stop", "msc_refine", "msc_replan",
     "msc_scene_bytes_dynamic", "msc_scene_set_dynamic", "msc_server_step", "msc_server_take_replans",
-    "msc_refine_static", "msc_refine_static_max",
+    "msc_refine_static", "msc_refine_static_max", "msc_track_default", "msc_guided_path", "msc_pose_path",
 ]
 
 
@@ -41,6 +41,11 @@ class MscArm(ctypes.Structure):
                 ("base", ctypes.c_int32 * 3), ("az0_cdeg", ctypes.c_int32), ("el0_cdeg", ctypes.c_int32),
                 ("type", ctypes.c_int32 * MAX_DOF), ("len_vox", ctypes.c_int32 * MAX_DOF),
                 ("lo_cdeg", ctypes.c_int32 * MAX_DOF), ("hi_cdeg", ctypes.c_int32 * MAX_DOF)]
+
+
+class MscTrack(ctypes.Structure):
+    _fields_ = [("tracked", ctypes.c_int32), ("max_delta_cdeg", ctypes.c_int32),
+                ("relaxed_delta_cdeg", ctypes.c_int32), ("eps2_vox", ctypes.c_int32)]
 
 
 class MscBox(ctypes.Structure):
@@ -113,6 +118,11 @@ def load_library(path: str = LIB_PATH):
     L.msc_replan.argtypes = [c_void_p, c_void_p, P(MscArm), P(i32), P(i32), i32, i32, P(i32), P(MscOpts), P(i32)]
     L.msc_get_stats.argtypes = [c_void_p, P(MscStats)]
     L.msc_refine.argtypes = [c_void_p, P(MscArm), P(i32), P(ctypes.c_double), i64, P(ctypes.c_double), P(i32)]
+    L.msc_track_default.argtypes = [P(MscTrack)]
+    L.msc_track_default.restype = None
+    L.msc_guided_path.argtypes = [c_void_p, c_void_p, P(MscArm), P(i32), P(MscTrack), P(MscOpts), P(i32), P(i32)]
+    L.msc_pose_path.argtypes = [c_void_p, c_void_p, P(MscArm), P(i32), P(i32), P(MscArm), P(MscTrack), P(MscOpts),
+                                P(i32), P(i32)]
     L.msc_refine_static.argtypes = L.msc_refine.argtypes
     L.msc_refine_static_max.argtypes = [i32]
     L.msc_refine_static_max.restype = i64
@@ -140,7 +150,8 @@ def load_library(path: str = LIB_PATH):
     L.msc_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
         if name not in ("msc_opts_default", "msc_scene_bytes", "msc_last_error", "msc_lane_bytes",
-                        "msc_query_bytes", "msc_scene_bytes_dynamic"):
+                        "msc_query_bytes", "msc_scene_bytes_dynamic", "msc_refine_static_max",
+                        "msc_track_default"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -177,6 +188,16 @@ def make_opts(split_m: int = -1, tube_r0: int = 1, tube_r1: int = 2, retries: in
     o.split_m, o.tube_r0, o.tube_r1, o.reach_retries, o.flags = split_m, tube_r0, tube_r1, retries, flags
     o.approach_az_cdeg, o.approach_el_cdeg, o.approach_half_cdeg = (0, 0, -1) if approach is None else approach
     return o
+
+
+def make_track(a: "MscArm", tracked: int = -1, delta: int = -1, delta2: int = -1, eps2: int = 9) -> "MscTrack":
+    """delta / delta2 in steps (-1: the library's defaults)."""
+    t = MscTrack()
+    t.tracked = tracked
+    t.max_delta_cdeg = -1 if delta < 0 else delta * a.step_cdeg
+    t.relaxed_delta_cdeg = -1 if delta2 < 0 else delta2 * a.step_cdeg
+    t.eps2_vox = eps2
+    return t
 
 
 class QuerySpec:
@@ -359,6 +380,45 @@ class Solver:
                                _ptr(out, ctypes.c_int32))
         self._check(rc, "msc_path")
         return rc, (out.reshape(waypoints + 1, a.dof) // a.step_cdeg if rc == OK else None)
+
+    def guided_path(self, scene: Scene, arm, target: Sequence[int], tracked: int = -1, delta: int = -1,
+                    delta2: int = -1, eps2: int = 9, split_m: int = -1, retries: int = 4, flags: int = 0,
+                    approach=None) -> Tuple[int, Optional[np.ndarray]]:
+        """msc_guided_path: (status, rows[(M+1), dof] in steps, root waypoint pose first).
+        delta / delta2 in steps (-1: one and two steps)."""
+        a = make_arm(arm)
+        t = np.ascontiguousarray(np.asarray(target, np.int32))
+        tr = make_track(a, tracked, delta, delta2, eps2)
+        k = a.dof - 2 if tracked < 0 else tracked
+        out = np.zeros((a.samples * max(k - 1, 0) + 1) * a.dof, np.int32)
+        rows = ctypes.c_int32()
+        o = make_opts(split_m, 1, 2, retries, flags, approach)
+        rc = self.lib.msc_guided_path(self.ctx, scene.handle, ctypes.byref(a), _ptr(t, ctypes.c_int32),
+                                      ctypes.byref(tr), ctypes.byref(o), _ptr(out, ctypes.c_int32), ctypes.byref(rows))
+        self._check(rc, "msc_guided_path")
+        if rc != OK:
+            return rc, None
+        return rc, out[:rows.value * a.dof].reshape(rows.value, a.dof) // a.step_cdeg
+
+    def pose_path(self, scene: Scene, arm, start: Sequence[int], target: Sequence[int], virtual_arm,
+                  tracked: int = -1, delta: int = -1, delta2: int = -1, eps2: int = 9, split_m: int = -1,
+                  retries: int = 4, flags: int = 0) -> Tuple[int, Optional[np.ndarray]]:
+        """msc_pose_path: (status, rows[(M+1), dof] in steps, row 0 = start)."""
+        a = make_arm(arm)
+        va = make_arm(virtual_arm)
+        s = np.ascontiguousarray(np.asarray(start, np.int32) * a.step_cdeg)
+        t = np.ascontiguousarray(np.asarray(target, np.int32))
+        tr = make_track(a, tracked, delta, delta2, eps2)
+        out = np.zeros((va.samples * va.dof + 1) * a.dof, np.int32)
+        rows = ctypes.c_int32()
+        o = make_opts(split_m, 1, 2, retries, flags)
+        rc = self.lib.msc_pose_path(self.ctx, scene.handle, ctypes.byref(a), _ptr(s, ctypes.c_int32),
+                                    _ptr(t, ctypes.c_int32), ctypes.byref(va), ctypes.byref(tr), ctypes.byref(o),
+                                    _ptr(out, ctypes.c_int32), ctypes.byref(rows))
+        self._check(rc, "msc_pose_path")
+        if rc != OK:
+            return rc, None
+        return rc, out[:rows.value * a.dof].reshape(rows.value, a.dof) // a.step_cdeg
 
     def replan(self, scene: Scene, arm, start: Sequence[int], target: Sequence[int], waypoints: int, delta: int,
                ref_path, split_m: int = -1, tube_r0: int = 1, tube_r1: int = 2, retries: int = 4,

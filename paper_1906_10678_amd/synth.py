@@ -128,8 +128,9 @@ def arm_virtual(lens: Sequence[int], step_cdeg: int = 500, limit_cdeg: int = 170
                 base: Tuple[int, int, int] = (0, 0, 0)) -> Arm:
     """A virtual arm for paths between arbitrary poses ("Path between Arbitrary Poses"):
     a few segments that can each point anywhere (two joints per segment, as arm_gms),
-    rooted where the path starts (the base is replaced by the caller)."""
-    return arm_gms(lens, step_cdeg, limit_cdeg, base)
+    rooted where the path starts (the base is replaced by the caller).  The limits are
+    the largest multiple of the step within limit_cdeg."""
+    return arm_gms(lens, step_cdeg, (limit_cdeg // step_cdeg) * step_cdeg, base)
 
 
 def scaled_lens(n: int, dof: int) -> List[int]:

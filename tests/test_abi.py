@@ -61,7 +61,8 @@ def test_ctypes_layouts_match_a_c_compiler(tmp_path):
         pytest.skip("no C compiler")
     structs = {"msc_arm": msc.MscArm, "msc_box": msc.MscBox, "msc_sphere": msc.MscSphere,
                "msc_opts": msc.MscOpts, "msc_query": msc.MscQuery, "msc_stats": msc.MscStats,
-               "msc_timing": msc.MscTiming, "msc_step_report": msc.MscStepReport}
+               "msc_timing": msc.MscTiming, "msc_step_report": msc.MscStepReport,
+               "msc_track": msc.MscTrack}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "msc.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
