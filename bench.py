@@ -696,6 +696,96 @@ def bench_replan(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_guided(args):
+    """Workspace-guided paths on the 8-DOF workload's scenes: reach-pose-guided paths to
+    the queries' targets (--workload guided), or paths from their start poses to their
+    targets through a virtual arm of three 20-voxel segments (--workload posepath).  One
+    query per call (every launch timed with HIP events), then batches over worker lanes
+    with the tracking on each lane and fused into one launch per batch."""
+    import torch
+
+    from paper_1906_10678_amd import msc, synth
+
+    solver = msc.Solver(0, workspace_bytes=args.workspace_gb << 30)
+    nq = args.queries
+    queries = [synth.query_c2(s, solver.pose_fn_for) for s in range(nq)]
+    scenes = [solver.scene(q.scene) for q in queries]
+    varm = synth.arm_virtual([20, 20, 20])
+    kind = 2 if args.workload == "guided" else 3
+
+    def alone(i, flags=0):
+        q = queries[i]
+        if kind == 2:
+            return solver.guided_path(scenes[i], q.arm, q.target, flags=flags)
+        return solver.pose_path(scenes[i], q.arm, q.start, q.target, varm, flags=flags)
+
+    def spec(i):
+        q = queries[i]
+        if kind == 2:
+            return msc.QuerySpec(scenes[i], q.arm, q.target, kind=2)
+        return msc.QuerySpec(scenes[i], q.arm, q.target, start=q.start, kind=3, virtual_arm=varm)
+
+    first = [alone(i) for i in range(nq)]
+    statuses = [st for st, _ in first]
+    rows = [0 if r is None else len(r) for _, r in first]
+    torch.cuda.synchronize()
+    lat, per_kernel = [], {}
+    t0 = time.perf_counter()
+    for i in range(args.plain_steps):
+        ts = time.perf_counter()
+        st, _ = alone(i % nq, msc.PROFILE)
+        lat.append(time.perf_counter() - ts)
+        if st != statuses[i % nq]:
+            raise RuntimeError("query %d: status %d, first run %d" % (i % nq, st, statuses[i % nq]))
+        for kname, stage, nin, nout, ms in solver.timings():
+            t = per_kernel.setdefault(kname, [0.0, 0])
+            t[0] += ms
+            t[1] += 1
+    wall = time.perf_counter() - t0
+    lat = np.array(lat) * 1e3
+    plain = {"solves_per_s": round(args.plain_steps / wall, 3), "p50_ms": round(float(np.percentile(lat, 50)), 4),
+             "p99_ms": round(float(np.percentile(lat, 99)), 4),
+             "kernel_ms_per_query": {k: round(v[0] / args.plain_steps, 4) for k, v in sorted(per_kernel.items())}}
+    print("plain", plain, file=sys.stderr, flush=True)
+    lanes = args.lanes if args.lanes > 0 else 12
+    solver.set_lanes(lanes)
+    batched = {}
+    try:
+        for name, flags in (("per_lane", 0), ("fused", msc.FUSED_TRACK)):
+            def step():
+                specs = [spec(i) for i in range(nq)]
+                res = solver.batch(specs, flags=flags)
+                for i, (st, r, _) in enumerate(res):
+                    if st != statuses[i] or (st == msc.OK and not np.array_equal(r, first[i][1])):
+                        raise RuntimeError("batched query %d differs from alone" % i)
+                return [r[2] for r in res]
+            for _ in range(args.warmup):
+                step()
+            torch.cuda.synchronize()
+            ql = []
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                ql.extend(step())
+            torch.cuda.synchronize()
+            w = time.perf_counter() - t0
+            ql = np.array(ql)
+            batched[name] = {"solves_per_s": round(args.steps * nq / w, 3),
+                             "p50_ms": round(float(np.percentile(ql, 50)), 4),
+                             "p99_ms": round(float(np.percentile(ql, 99)), 4)}
+            print(name, batched[name], file=sys.stderr, flush=True)
+    finally:
+        solver.set_lanes(0)
+    what = ("reach-pose-guided paths (joint 6 of 8 walks the reach pose's samples back to the end of segment 1)"
+            if kind == 2 else "paths from the start pose through a virtual arm of three 20-voxel segments "
+                              "(end effector tracked)")
+    print(json.dumps({"metric": "8-DOF workspace-guided path solves/sec and p50/p99 ms", "workload": args.workload,
+                      "queries": nq, "statuses": statuses, "rows": rows, "plain": plain, "batched": batched,
+                      "lanes": lanes, "batch": nq,
+                      "config": {"workload": "%s; the 8-DOF path workload's scenes and targets (256^3, 5 deg), "
+                                             "filter one step, relaxed two, tolerance 3 voxels" % what}}),
+          flush=True)
+
+
 def bench_c5(args):
     """Serving with dynamic obstacles: Poisson arrivals, 70% reach / 30% path, moving
     boxes re-rasterised every 10 ms tick, midcourse replanning; p50/p99 per class."""
@@ -726,7 +816,8 @@ def main():
                     help="write profiles/c4_big_stages.md")
     ap.add_argument("--arm", choices=["chain", "gms"], default="chain",
                     help="gms: the same workload with the paper's arm model, two DOF per segment (a variant)")
-    ap.add_argument("--workload", choices=["c2", "c2serve", "c3", "c4", "c5", "refine", "replan"], default="c2",
+    ap.add_argument("--workload", choices=["c2", "c2serve", "c3", "c4", "c5", "refine", "replan", "guided",
+                                           "posepath"], default="c2",
                     help="c2: 8-DOF reach + path (default); c2serve: the same queries served under Poisson "
                          "arrivals, one lane vs several; c3: batched reach; c4: batched paths at 512^3; "
                          "c5: serving with moving obstacles")
@@ -791,6 +882,8 @@ def main():
         return bench_replan(args)
     if args.workload == "c5":
         return bench_c5(args)
+    if args.workload in ("guided", "posepath"):
+        return bench_guided(args)
 
     import torch
 

@@ -91,6 +91,8 @@ typedef struct { int32_t c[3], r; } msc_sphere;
 #define MSC_CAPTURE_SETS 1u /* keep every stage set for msc_debug_set */
 #define MSC_NO_PRUNE 2u     /* disable the distance / orientation pruning (tests) */
 #define MSC_PROFILE 4u      /* time every kernel launch of the call with HIP events */
+#define MSC_FUSED_TRACK 8u  /* msc_batch: the waypoint tracking of every kind 2 / 3 query runs in
+                               one launch after all their searches (one block per query) */
 
 typedef struct {
     int32_t split_m;       /* forward stages before the join: -1 = adaptive, else 0..dof */
@@ -309,12 +311,14 @@ typedef struct {
     const msc_scene* scene;
     const msc_arm* arm;
     int32_t kind;                /* 0 = reach pose (msc_reach), 1 = reach + path (msc_path, or
-                                    msc_replan when ref_cdeg is set) */
+                                    msc_replan when ref_cdeg is set), 2 = reach-pose-guided path
+                                    (msc_guided_path), 3 = path between poses (msc_pose_path) */
     int32_t target[3];
     const int32_t* start_cdeg;   /* path: [dof] start pose */
     int32_t waypoints;           /* path: moves W */
     int32_t max_delta_cdeg;      /* path: max joint change per move */
-    int32_t* out;                /* reach: [dof]; path: [(waypoints+1)*dof] centidegrees */
+    int32_t* out;                /* reach: [dof]; path: [(waypoints+1)*dof]; kinds 2, 3: as the
+                                    path_out of msc_guided_path / msc_pose_path (centidegrees) */
     msc_status status;           /* written when the query completes */
     float latency_ms;            /* written: submission (server) or batch start to completion */
     const int32_t* ref_cdeg;     /* path: NULL, or the original path's [(waypoints+1)*dof] rows:
@@ -328,12 +332,20 @@ typedef struct {
     int32_t replan_depth;        /* written by the server: 0 for a submitted query, 1 + that of the
                                     path it replaces for a replan issued by msc_server_step */
     char error[128];             /* written: the message when status < 0, else "" */
+    const msc_arm* virtual_arm;  /* kind 3: the virtual arm of msc_pose_path */
+    msc_track track;             /* kinds 2 and 3: tracking parameters (msc_track_default values) */
+    int32_t rows;                /* written: path rows of kinds 2 and 3 */
 } msc_query;
 
 /* Batched execution: solve nq independent queries; every worker lane takes the next
  * unsolved query when it finishes one (with no worker lanes, the context's own lane
- * solves them in order).  Results are those of msc_reach / msc_path for each query
- * alone.  Returns MSC_OK once every query ran; per-query results are in q[i].status. */
+ * solves them in order).  Results are those of msc_reach / msc_path / msc_guided_path /
+ * msc_pose_path for each query alone ("The procedure for IK solution": the searches of
+ * independent targets run in parallel).  With MSC_FUSED_TRACK in opts->flags the
+ * waypoint tracking of the kind 2 and 3 queries is deferred and run for all of them in
+ * one persistent launch on the context's stream, one block per query, once every search
+ * has finished (same results).  Returns MSC_OK once every query ran; per-query results
+ * are in q[i].status. */
 msc_status msc_batch(msc_ctx* ctx, msc_query* q, int32_t nq, const msc_opts* opts);
 
 /* Device-memory estimate of one query (bytes), used for admission. */

@@ -167,6 +167,8 @@ struct TrackArgs {
     int32_t* status;             // out: [0] rows written (0: none), [1] solution used, [2] waypoints
 };
 hipError_t launch_track(const TrackArgs& a, hipStream_t st);
+// args: device array of `count` argument blocks, one block per query
+hipError_t launch_track_batch(const TrackArgs* args, int count, hipStream_t st);
 
 struct TubeArgs {
     JointView joints[kMaxDof];

@@ -1610,35 +1610,39 @@ constexpr int kTrackThreads = 512;
 
 __device__ __forceinline__ int track_change(int r) { return r == 0 ? 0 : ((r & 1) ? -((r + 1) >> 1) : (r >> 1)); }
 
-// Minimum key over the box of radius d around q (all threads return it).
+// Minimum key over the box of radius d around q (all threads return it).  The box is
+// split at the tracked joint: a thread takes prefixes (the changes of joints
+// 1..tracked, the high digits of c), tests the tracked joint's distance and the prefix
+// segments once, and only then walks the suffixes (the remaining joints) of a prefix
+// that passed.
 __device__ unsigned long long track_best(const TrackArgs& a, const int* q, int d, int px, int py, int pz,
                                          bool base_free, unsigned long long* red) {
-    const int n = a.n;
-    const int B = 2 * d + 1;
-    uint64_t total = 1;
-    for (int k = 0; k < n; ++k) total *= (uint64_t)B;
+    const int n = a.n, tr = a.tracked;
+    const uint64_t B = (uint64_t)(2 * d + 1);
+    uint64_t total_p = 1, total_s = 1;
+    for (int k = 0; k < tr; ++k) total_p *= B;
+    for (int k = tr; k < n; ++k) total_s *= B;
     unsigned long long best = ~0ull;
-    for (uint64_t c = threadIdx.x; c < total && base_free; c += blockDim.x) {
-        int t[kMaxDof];
-        uint64_t rest = c;
+    for (uint64_t pi = threadIdx.x; pi < total_p && base_free; pi += blockDim.x) {
+        int tp[kMaxDof];
+        uint64_t rest = pi;
         bool inside = true;
-        int l1 = 0;
-        for (int k = n - 1; k >= 0; --k) {
-            const int r = (int)(rest % (uint64_t)B);
-            rest /= (uint64_t)B;
-            t[k] = track_change(r);
-            const int v = q[k] + t[k];
+        int l1p = 0;
+        for (int k = tr - 1; k >= 0; --k) {
+            tp[k] = track_change((int)(rest % B));
+            rest /= B;
+            const int v = q[k] + tp[k];
             inside = inside && v >= a.lim_lo[k] && v <= a.lim_hi[k];
-            l1 += t[k] < 0 ? -t[k] : t[k];
+            l1p += tp[k] < 0 ? -tp[k] : tp[k];
         }
         if (!inside) continue;
-        // the tracked joint first: offsets only
+        // the tracked joint: offsets only
         int ia = a.ia0, ie = a.ie0, x = a.bx, y = a.by, z = a.bz;
-        for (int k = 0; k < a.tracked; ++k) {
+        for (int k = 0; k < tr; ++k) {
             if (a.joints[k].type == 0)
-                ia = wrap_na(ia + q[k] + t[k], a.na);
+                ia = wrap_na(ia + q[k] + tp[k], a.na);
             else
-                ie = wrap_na(ie + q[k] + t[k], a.na);
+                ie = wrap_na(ie + q[k] + tp[k], a.na);
             const short4 o = a.joints[k].off[ia * a.na + ie];
             x += o.x;
             y += o.y;
@@ -1647,22 +1651,21 @@ __device__ unsigned long long track_best(const TrackArgs& a, const int* q, int d
         const int dx = x - px, dy = y - py, dz = z - pz;
         const int d2 = dx * dx + dy * dy + dz * dz;
         if (d2 > a.eps2) continue;
-        const unsigned long long key =
-            ((unsigned long long)l1 << 52) | ((unsigned long long)d2 << 42) | (unsigned long long)c;
-        if (key >= best) continue;
-        // the whole arm against the grid
+        const unsigned long long head = ((unsigned long long)d2 << 42) | (unsigned long long)(pi * total_s);
+        if (((unsigned long long)l1p << 52 | head) >= best) continue;   // no suffix can do better
+        // the prefix segments against the grid
         ia = a.ia0;
         ie = a.ie0;
         x = a.bx;
         y = a.by;
         z = a.bz;
         bool clear = true;
-        for (int k = 0; k < n && clear; ++k) {
+        for (int k = 0; k < tr && clear; ++k) {
             const JointView& J = a.joints[k];
             if (J.type == 0)
-                ia = wrap_na(ia + q[k] + t[k], a.na);
+                ia = wrap_na(ia + q[k] + tp[k], a.na);
             else
-                ie = wrap_na(ie + q[k] + t[k], a.na);
+                ie = wrap_na(ie + q[k] + tp[k], a.na);
             const int o = ia * a.na + ie;
             clear = segment_clear_all(a.g, J, o, x, y, z);
             const short4 off = J.off[o];
@@ -1670,7 +1673,40 @@ __device__ unsigned long long track_best(const TrackArgs& a, const int* q, int d
             y += off.y;
             z += off.z;
         }
-        if (clear) best = key;
+        if (!clear) continue;
+        // the suffixes, in canonical order
+        for (uint64_t si = 0; si < total_s; ++si) {
+            int ts[kMaxDof];
+            uint64_t r2 = si;
+            bool in2 = true;
+            int l1 = l1p;
+            for (int k = n - 1; k >= tr; --k) {
+                ts[k] = track_change((int)(r2 % B));
+                r2 /= B;
+                const int v = q[k] + ts[k];
+                in2 = in2 && v >= a.lim_lo[k] && v <= a.lim_hi[k];
+                l1 += ts[k] < 0 ? -ts[k] : ts[k];
+            }
+            if (!in2) continue;
+            const unsigned long long key = ((unsigned long long)l1 << 52) | (head + si);
+            if (key >= best) continue;
+            int sia = ia, sie = ie, sx = x, sy = y, sz = z;
+            bool ok = true;
+            for (int k = tr; k < n && ok; ++k) {
+                const JointView& J = a.joints[k];
+                if (J.type == 0)
+                    sia = wrap_na(sia + q[k] + ts[k], a.na);
+                else
+                    sie = wrap_na(sie + q[k] + ts[k], a.na);
+                const int o = sia * a.na + sie;
+                ok = segment_clear_all(a.g, J, o, sx, sy, sz);
+                const short4 off = J.off[o];
+                sx += off.x;
+                sy += off.y;
+                sz += off.z;
+            }
+            if (ok) best = key;
+        }
     }
     for (int off = 32; off > 0; off >>= 1) {
         const unsigned long long o = __shfl_xor(best, off, 64);
@@ -1801,8 +1837,24 @@ __device__ void track_body(const TrackArgs& a) {
 
 __global__ void __launch_bounds__(kTrackThreads) k_track(TrackArgs a) { track_body(a); }
 
+// Many queries in one launch: block b tracks query b, its arguments copied to LDS.
+__global__ void __launch_bounds__(kTrackThreads) k_track_batch(const TrackArgs* __restrict__ args) {
+    __shared__ TrackArgs a;
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(args + blockIdx.x);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(&a);
+    for (uint32_t i = threadIdx.x; i < sizeof(TrackArgs) / 4; i += blockDim.x) dst[i] = src[i];
+    __syncthreads();
+    track_body(a);
+}
+
 hipError_t launch_track(const TrackArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(k_track, dim3(1), dim3(kTrackThreads), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_track_batch(const TrackArgs* args, int count, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_track_batch, dim3((uint32_t)count), dim3(kTrackThreads), 0, st, args);
     return hipGetLastError();
 }
 

@@ -174,6 +174,13 @@ msc_status fail(Lane* c, msc_status st, const char* fmt, ...) {
     return st;
 }
 
+// Return any status other than MSC_OK (errors and "no answer" results alike).
+#define MSC_TRY_STATUS(expr)             \
+    do {                                 \
+        msc_status s_ = (expr);          \
+        if (s_ != MSC_OK) return s_;     \
+    } while (0)
+
 #define HIP_TRY(expr)                                                                        \
     do {                                                                                     \
         hipError_t e_ = (expr);                                                              \
@@ -1368,20 +1375,30 @@ msc_status track_run(Lane* c, TrackArgs& ta, const std::vector<int32_t>& sols, i
     return MSC_OK;
 }
 
-msc_status guided_on(Lane* c, const msc_scene* sc, const msc_arm* arm, const int32_t target[3], const msc_track* tr,
-                     const msc_opts* opts, int32_t* path_out, int32_t* rows_out) {
+// A tracking launch waiting for its query's search: the kernel arguments, the
+// candidate solutions and the output sizes.
+struct TrackJob {
+    TrackArgs ta{};
+    std::vector<int32_t> sols;
+    int nsol = 0, width = 0, max_rows = 0, step = 0;
+};
+
+// The reach search of a reach-pose-guided path; MSC_OK leaves the tracking in job.
+msc_status guided_prepare(Lane* c, const msc_scene* sc, const msc_arm* arm, const int32_t target[3],
+                          const msc_track* tr, const msc_opts* opts, TrackJob& job) {
     MSC_TRY(check_scene(c, sc));
     MSC_TRY(check_arm(c, arm, sc->n));
-    if (!target || !path_out || !rows_out) return fail(c, MSC_E_ARG, "NULL target or output");
+    if (!target) return fail(c, MSC_E_ARG, "NULL target");
     for (int i = 0; i < 3; ++i)
         if (target[i] < 0 || target[i] >= sc->n) return fail(c, MSC_E_ARG, "target outside the grid");
     msc_opts o = opts_or_default(opts);
     if (o.split_m < -1 || o.split_m > arm->dof) return fail(c, MSC_E_ARG, "split_m outside -1..dof");
     if (o.reach_retries < 1 || o.reach_retries > 64) return fail(c, MSC_E_ARG, "bad options");
-    TrackArgs ta{};
+    TrackArgs& ta = job.ta;
+    ta = TrackArgs{};
     MSC_TRY(track_params(c, arm, tr, std::max(1, arm->dof - 2), ta));
-    const int max_rows = arm->samples * (ta.tracked - 1) + 1;
-    if (max_rows > kTrackMaxPoints) return fail(c, MSC_E_ARG, "more than %d waypoints", kTrackMaxPoints);
+    job.max_rows = arm->samples * (ta.tracked - 1) + 1;
+    if (job.max_rows > kTrackMaxPoints) return fail(c, MSC_E_ARG, "more than %d waypoints", kTrackMaxPoints);
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, MSC_E_HIP, "hipSetDevice");
     begin_call(c);
     Plan p;
@@ -1394,21 +1411,27 @@ msc_status guided_on(Lane* c, const msc_scene* sc, const msc_arm* arm, const int
     if (st != MSC_OK) return st;
     MSC_TRY(track_arm(c, sc, p, ta));
     ta.mode = 0;
-    return track_run(c, ta, r.sols, r.nsol, p.n, max_rows, arm->step_cdeg, path_out, rows_out);
+    job.sols = std::move(r.sols);
+    job.nsol = r.nsol;
+    job.width = p.n;
+    job.step = arm->step_cdeg;
+    return MSC_OK;
 }
 
-msc_status pose_path_on(Lane* c, const msc_scene* sc, const msc_arm* arm, const int32_t* start_cdeg,
-                        const int32_t target[3], const msc_arm* varm, const msc_track* tr, const msc_opts* opts,
-                        int32_t* path_out, int32_t* rows_out) {
+// The virtual arm's reach search of a path between poses; MSC_OK leaves the tracking in job.
+msc_status pose_path_prepare(Lane* c, const msc_scene* sc, const msc_arm* arm, const int32_t* start_cdeg,
+                             const int32_t target[3], const msc_arm* varm, const msc_track* tr,
+                             const msc_opts* opts, TrackJob& job) {
     MSC_TRY(check_scene(c, sc));
     MSC_TRY(check_arm(c, arm, sc->n));
-    if (!start_cdeg || !target || !varm || !path_out || !rows_out) return fail(c, MSC_E_ARG, "NULL argument");
+    if (!start_cdeg || !target || !varm) return fail(c, MSC_E_ARG, "NULL argument");
     for (int i = 0; i < 3; ++i)
         if (target[i] < 0 || target[i] >= sc->n) return fail(c, MSC_E_ARG, "target outside the grid");
     if (varm->step_cdeg != arm->step_cdeg) return fail(c, MSC_E_ARG, "the virtual arm's step differs from the arm's");
     msc_opts o = opts_or_default(opts);
     if (o.split_m < -1 || o.reach_retries < 1 || o.reach_retries > 64) return fail(c, MSC_E_ARG, "bad options");
-    TrackArgs ta{};
+    TrackArgs& ta = job.ta;
+    ta = TrackArgs{};
     MSC_TRY(track_params(c, arm, tr, arm->dof, ta));
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, MSC_E_HIP, "hipSetDevice");
     begin_call(c);
@@ -1432,8 +1455,8 @@ msc_status pose_path_on(Lane* c, const msc_scene* sc, const msc_arm* arm, const 
     msc_arm va = *varm;
     for (int i = 0; i < 3; ++i) va.base[i] = root[i];
     MSC_TRY(check_arm(c, &va, sc->n));
-    const int max_rows = va.samples * va.dof + 1;
-    if (max_rows > kTrackMaxPoints) return fail(c, MSC_E_ARG, "more than %d waypoints", kTrackMaxPoints);
+    job.max_rows = va.samples * va.dof + 1;
+    if (job.max_rows > kTrackMaxPoints) return fail(c, MSC_E_ARG, "more than %d waypoints", kTrackMaxPoints);
     begin_call(c);
     Plan pv;
     make_plan(&va, target, pv);
@@ -1456,27 +1479,113 @@ msc_status pose_path_on(Lane* c, const msc_scene* sc, const msc_arm* arm, const 
     ta.vie0 = pv.ie0;
     MSC_TRY(track_arm(c, sc, p, ta));
     ta.mode = 1;
-    return track_run(c, ta, r.sols, r.nsol, pv.n, max_rows, arm->step_cdeg, path_out, rows_out);
+    job.sols = std::move(r.sols);
+    job.nsol = r.nsol;
+    job.width = pv.n;
+    job.step = arm->step_cdeg;
+    return MSC_OK;
+}
+
+msc_status guided_on(Lane* c, const msc_scene* sc, const msc_arm* arm, const int32_t target[3], const msc_track* tr,
+                     const msc_opts* opts, int32_t* path_out, int32_t* rows_out) {
+    if (!path_out || !rows_out) return fail(c, MSC_E_ARG, "NULL output");
+    TrackJob job;
+    MSC_TRY_STATUS(guided_prepare(c, sc, arm, target, tr, opts, job));
+    return track_run(c, job.ta, job.sols, job.nsol, job.width, job.max_rows, job.step, path_out, rows_out);
+}
+
+msc_status pose_path_on(Lane* c, const msc_scene* sc, const msc_arm* arm, const int32_t* start_cdeg,
+                        const int32_t target[3], const msc_arm* varm, const msc_track* tr, const msc_opts* opts,
+                        int32_t* path_out, int32_t* rows_out) {
+    if (!path_out || !rows_out) return fail(c, MSC_E_ARG, "NULL output");
+    TrackJob job;
+    MSC_TRY_STATUS(pose_path_prepare(c, sc, arm, start_cdeg, target, varm, tr, opts, job));
+    return track_run(c, job.ta, job.sols, job.nsol, job.width, job.max_rows, job.step, path_out, rows_out);
+}
+
+// Tracking launches deferred by a batch with MSC_FUSED_TRACK: all of them in one launch
+// on lane c (one block per query), then the rows of each into its query.
+msc_status run_fused_tracks(Lane* c, std::vector<std::pair<msc_query*, TrackJob*>>& jobs) {
+    constexpr size_t kChunk = 256;   // kernel arguments of a chunk fit the staging buffer
+    for (size_t b = 0; b < jobs.size(); b += kChunk) {
+        const size_t cnt = std::min(kChunk, jobs.size() - b);
+        begin_call(c);
+        std::vector<TrackArgs> args(cnt);
+        std::vector<void*> h_rows(cnt), h_st(cnt);
+        for (size_t j = 0; j < cnt; ++j) {
+            TrackJob& job = *jobs[b + j].second;
+            void *h_sols, *d_sols, *d_rows, *d_st;
+            MSC_TRY(host_area(c, (size_t)job.nsol * job.width * 4, &h_sols, &d_sols));
+            MSC_TRY(host_area(c, (size_t)job.max_rows * job.ta.n * 4, &h_rows[j], &d_rows));
+            MSC_TRY(host_area(c, 16, &h_st[j], &d_st));
+            std::memcpy(h_sols, job.sols.data(), (size_t)job.nsol * job.width * 4);
+            args[j] = job.ta;
+            args[j].nsol = job.nsol;
+            args[j].sols = (const int32_t*)d_sols;
+            args[j].rows = (int32_t*)d_rows;
+            args[j].status = (int32_t*)d_st;
+        }
+        void* d_args;
+        MSC_TRY(upload(c, args.data(), cnt * sizeof(TrackArgs), &d_args));
+        LAUNCH(MSC_K_TRACK, -1, (int64_t)cnt, launch_track_batch((const TrackArgs*)d_args, (int)cnt, c->stream));
+        MSC_TRY(sync_lane(c));
+        for (size_t j = 0; j < cnt; ++j) {
+            msc_query* q = jobs[b + j].first;
+            TrackJob& job = *jobs[b + j].second;
+            const volatile int32_t* st = (const volatile int32_t*)h_st[j];
+            const int rows = st[0];
+            if (rows <= 0) {
+                q->status = MSC_NO_PATH;
+                continue;
+            }
+            if (rows > job.max_rows) {
+                q->status = MSC_E_CAPACITY;
+                std::snprintf(q->error, sizeof q->error, "tracked path longer than planned");
+                continue;
+            }
+            const int32_t* hr = (const int32_t*)h_rows[j];
+            for (size_t i = 0; i < (size_t)rows * job.ta.n; ++i) q->out[i] = hr[i] * job.step;
+            q->rows = rows;
+            q->status = MSC_OK;
+        }
+    }
+    return MSC_OK;
 }
 
 // Solves q on lane L against the grid held by binding b, writes q->status, q->tick and
 // q->error, and releases the binding.
-void query_on(Lane* L, msc_query* q, const msc_opts* opts, Binding& b) {
+// deferred: a kind 2 / 3 query of a fused batch leaves its tracking in *deferred (and
+// keeps the binding) instead of running it; returns true when it did.
+bool query_on(Lane* L, msc_query* q, const msc_opts* opts, Binding& b, TrackJob* deferred = nullptr) {
     msc_status st;
     L->err.clear();
+    q->rows = 0;
     if (!q->scene || !q->arm || !q->out) {
         st = fail(L, MSC_E_ARG, "query with a NULL scene, arm or output");
     } else {
         prof_reset(L, opts ? opts->flags : 0u);
         if (b.ready && L->stream != L->owner->stream) (void)hipStreamWaitEvent(L->stream, b.ready, 0);
         const msc_scene* sc = &b.view;
-        if (q->kind == 0)
+        if (q->kind == 0) {
             st = reach_on(L, sc, q->arm, q->target, opts, q->out);
-        else if (q->kind == 1)
+        } else if (q->kind == 1) {
             st = path_on(L, sc, q->arm, q->start_cdeg, q->target, q->waypoints, q->max_delta_cdeg, opts, q->out,
                          q->ref_cdeg);
-        else
+        } else if (q->kind == 2 || q->kind == 3) {
+            TrackJob own;
+            TrackJob& job = deferred ? *deferred : own;
+            st = q->kind == 2 ? guided_prepare(L, sc, q->arm, q->target, &q->track, opts, job)
+                              : pose_path_prepare(L, sc, q->arm, q->start_cdeg, q->target, q->virtual_arm, &q->track,
+                                                  opts, job);
+            if (st == MSC_OK && deferred) {
+                prof_finish(L);
+                return true;
+            }
+            if (st == MSC_OK)
+                st = track_run(L, job.ta, job.sols, job.nsol, job.width, job.max_rows, job.step, q->out, &q->rows);
+        } else {
             st = fail(L, MSC_E_ARG, "query kind %d", q->kind);
+        }
         prof_finish(L);
     }
     // a call that failed part-way may leave kernels in flight that read the grid
@@ -1485,6 +1594,7 @@ void query_on(Lane* L, msc_query* q, const msc_opts* opts, Binding& b) {
     q->tick = b.view.tick;
     std::snprintf(q->error, sizeof q->error, "%s", st < 0 ? L->err.c_str() : "");
     unbind_scene(b);
+    return false;
 }
 
 double now_ms() {
@@ -1891,27 +2001,56 @@ msc_status msc_batch(msc_ctx* o, msc_query* q, int32_t nq, const msc_opts* opts)
     if (nq < 0 || (nq && !q)) return ctx_fail(o, MSC_E_ARG, "bad query array");
     if (o->server) return ctx_fail(o, MSC_E_STATE, "the server is running");
     const double t0 = now_ms();
-    if (o->workers.empty()) {
-        for (int32_t i = 0; i < nq; ++i) {
-            Binding b = bind_scene(q[i].scene);
-            query_on(o->control, &q[i], opts, b);
-            q[i].latency_ms = (float)(now_ms() - t0);
+    const bool fused = opts && (opts->flags & MSC_FUSED_TRACK);
+    std::vector<TrackJob> jobs(fused ? (size_t)nq : 0);
+    std::vector<Binding> held(fused ? (size_t)nq : 0);
+    std::vector<char> deferred(fused ? (size_t)nq : 0, 0);
+    auto one = [&](Lane* L, int32_t i) {
+        Binding b = bind_scene(q[i].scene);
+        const bool defer = fused && (q[i].kind == 2 || q[i].kind == 3);
+        if (query_on(L, &q[i], opts, b, defer ? &jobs[i] : nullptr)) {
+            held[i] = b;   // the grid stays bound until the fused launch has run
+            deferred[i] = 1;
+            return;
         }
-        return MSC_OK;
+        q[i].latency_ms = (float)(now_ms() - t0);
+    };
+    if (o->workers.empty()) {
+        for (int32_t i = 0; i < nq; ++i) one(o->control, i);
+    } else {
+        std::atomic<int32_t> next{0};
+        std::vector<std::thread> threads;
+        for (Lane* L : o->workers) {
+            threads.emplace_back([&, L]() {
+                (void)hipSetDevice(o->device);
+                for (int32_t i = next.fetch_add(1); i < nq; i = next.fetch_add(1)) one(L, i);
+            });
+        }
+        for (auto& t : threads) t.join();
     }
-    std::atomic<int32_t> next{0};
-    std::vector<std::thread> threads;
-    for (Lane* L : o->workers) {
-        threads.emplace_back([&, L]() {
-            (void)hipSetDevice(o->device);
-            for (int32_t i = next.fetch_add(1); i < nq; i = next.fetch_add(1)) {
-                Binding b = bind_scene(q[i].scene);
-                query_on(L, &q[i], opts, b);
-                q[i].latency_ms = (float)(now_ms() - t0);
-            }
-        });
+    if (!fused) return MSC_OK;
+    std::vector<std::pair<msc_query*, TrackJob*>> pending;
+    for (int32_t i = 0; i < nq; ++i)
+        if (deferred[i]) pending.emplace_back(&q[i], &jobs[i]);
+    if (pending.empty()) return MSC_OK;
+    Lane* c = o->control;
+    prof_reset(c, opts->flags);
+    // the searches ran on the worker streams: their grids and tables are complete once
+    // those streams are idle
+    for (Lane* L : o->workers) (void)hipStreamSynchronize(L->stream);
+    c->err.clear();
+    msc_status st = run_fused_tracks(c, pending);
+    prof_finish(c);
+    const double t1 = now_ms();
+    for (int32_t i = 0; i < nq; ++i) {
+        if (!deferred[i]) continue;
+        if (st != MSC_OK) {
+            q[i].status = st;
+            std::snprintf(q[i].error, sizeof q[i].error, "%s", c->err.c_str());
+        }
+        q[i].latency_ms = (float)(t1 - t0);
+        unbind_scene(held[i]);
     }
-    for (auto& t : threads) t.join();
     return MSC_OK;
 }
 

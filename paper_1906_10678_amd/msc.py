@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libmsc.so")
 MAX_DOF = 16
 OK, NO_REACH, NO_PATH = 0, 1, 2
 E_ARG, E_NOMEM, E_HIP, E_CAPACITY, E_STATE = -1, -2, -3, -4, -5
-CAPTURE_SETS, NO_PRUNE, PROFILE = 1, 2, 4
+CAPTURE_SETS, NO_PRUNE, PROFILE, FUSED_TRACK = 1, 2, 4, 8
 KERNELS = ["fill", "tables", "raster", "orient", "seed", "expand_fwd", "expand_bwd", "compact", "join", "dmark",
            "dfs", "pose", "tube_valid", "tube_solve", "refine", "track"]
 SET_F, SET_B, SET_C, SET_D = 0, 1, 2, 3
@@ -67,7 +67,8 @@ class MscQuery(ctypes.Structure):
                 ("waypoints", ctypes.c_int32), ("max_delta_cdeg", ctypes.c_int32),
                 ("out", ctypes.POINTER(ctypes.c_int32)), ("status", ctypes.c_int), ("latency_ms", ctypes.c_float),
                 ("ref_cdeg", ctypes.POINTER(ctypes.c_int32)), ("tick", ctypes.c_int64),
-                ("execute_ticks", ctypes.c_int32), ("replan_depth", ctypes.c_int32), ("error", ctypes.c_char * 128)]
+                ("execute_ticks", ctypes.c_int32), ("replan_depth", ctypes.c_int32), ("error", ctypes.c_char * 128),
+                ("virtual_arm", ctypes.POINTER(MscArm)), ("track", MscTrack), ("rows", ctypes.c_int32)]
 
 
 class MscStepReport(ctypes.Structure):
@@ -201,18 +202,29 @@ def make_track(a: "MscArm", tracked: int = -1, delta: int = -1, delta2: int = -1
 
 
 class QuerySpec:
-    """A reach (kind 0) or reach + path (kind 1) query for msc_batch / the server; owns
-    the ctypes buffers until the query completes."""
+    """A query for msc_batch / the server: reach (kind 0), reach + path (kind 1),
+    reach-pose-guided path (kind 2) or path between poses through a virtual arm (kind 3);
+    owns the ctypes buffers until the query completes.  track = (tracked, delta, delta2,
+    eps2) with deltas in steps (-1: defaults)."""
 
     def __init__(self, scene: "Scene", arm, target, start=None, waypoints: int = 0, delta: int = 0, ref=None,
-                 execute_ticks: int = 0):
+                 execute_ticks: int = 0, kind: Optional[int] = None, virtual_arm=None, track=(-1, -1, -1, 9)):
         self.scene = scene
         self.arm_c = make_arm(arm)
         self.dof = self.arm_c.dof
         self.step = self.arm_c.step_cdeg
-        self.kind = 0 if start is None else 1
+        self.kind = (0 if start is None else 1) if kind is None else int(kind)
         self.waypoints = int(waypoints)
-        rows = (self.waypoints + 1) if self.kind == 1 else 1
+        self.varm_c = make_arm(virtual_arm) if virtual_arm is not None else None
+        if self.kind == 1:
+            rows = self.waypoints + 1
+        elif self.kind == 2:
+            k = self.dof - 2 if track[0] < 0 else track[0]
+            rows = self.arm_c.samples * max(k - 1, 0) + 1
+        elif self.kind == 3:
+            rows = self.varm_c.samples * self.varm_c.dof + 1
+        else:
+            rows = 1
         self.out = np.zeros(rows * self.dof, np.int32)
         self.start = None if start is None else np.ascontiguousarray(np.asarray(start, np.int32) * self.step)
         q = MscQuery()
@@ -230,6 +242,8 @@ class QuerySpec:
             np.asarray(ref, np.int32).reshape(self.waypoints + 1, self.dof) * self.step)
         q.ref_cdeg = _ptr(self.ref, ctypes.c_int32) if self.ref is not None else None
         q.execute_ticks = int(execute_ticks)
+        q.virtual_arm = ctypes.pointer(self.varm_c) if self.varm_c is not None else None
+        q.track = make_track(self.arm_c, *track)
         q.status = -100
         self.c = q
 
@@ -248,7 +262,12 @@ class QuerySpec:
         if st != OK:
             return st, None, self.c.latency_ms
         v = self.out // self.step
-        return st, (v if self.kind == 0 else v.reshape(self.waypoints + 1, self.dof)), self.c.latency_ms
+        if self.kind == 0:
+            return st, v, self.c.latency_ms
+        if self.kind == 1:
+            return st, v.reshape(self.waypoints + 1, self.dof), self.c.latency_ms
+        r = self.c.rows
+        return st, v[:r * self.dof].reshape(r, self.dof), self.c.latency_ms
 
 
 class MscError(RuntimeError):
@@ -527,6 +546,7 @@ class Solver:
             sp.c.latency_ms = arr[i].latency_ms
             sp.c.tick = arr[i].tick
             sp.c.error = arr[i].error
+            sp.c.rows = arr[i].rows
         return [sp.result() for sp in specs]
 
     def query_bytes(self, spec: QuerySpec) -> int:

@@ -145,3 +145,42 @@ def test_track_argument_errors(solver):
         with pytest.raises(msc.MscError) as e:
             solver.pose_path(scene, arm, bad[~ok][0], end[0], synth.arm_virtual([3, 3], step_cdeg=arm.step_cdeg))
         assert e.value.status == msc.E_ARG
+
+
+def test_batched_guided_and_pose_paths_equal_alone(solver):
+    """Kinds 2 and 3 through msc_batch, mixed with plain reach queries, on 0 and 3
+    worker lanes, with the tracking per lane and fused into one launch: every result is
+    the query's alone (which the tests above compare with the oracle)."""
+    specs_alone = []
+    for seed in range(6):
+        dof = 3 + seed % 2
+        arm, sc, rng = tiny_case(seed, dof=dof)
+        arm = wide(arm)
+        occ = oracle.raster(sc)
+        scene = solver.scene(sc)
+        varm = synth.arm_virtual([3, 3], step_cdeg=arm.step_cdeg)
+        qs = valid_poses(arm, occ, rng, 3)
+        for a, b in zip(qs[:-1], qs[1:]):
+            _, end = oracle.poses(arm, occ, b[None])
+            st, rows = solver.guided_path(scene, arm, end[0], dof - 1, 1, 2, 4)
+            specs_alone.append((dict(scene=scene, arm=arm, target=end[0], kind=2, track=(dof - 1, 1, 2, 4)),
+                                (st, rows)))
+            st, rows = solver.pose_path(scene, arm, a, end[0], varm, dof, 1, 2, 4)
+            specs_alone.append((dict(scene=scene, arm=arm, target=end[0], start=a, kind=3, virtual_arm=varm,
+                                     track=(dof, 1, 2, 4)), (st, rows)))
+            st, pose = solver.reach(scene, arm, end[0])
+            specs_alone.append((dict(scene=scene, arm=arm, target=end[0]), (st, pose)))
+    assert any(a[1][0] == msc.OK for a in specs_alone if a[0].get("kind") == 2)
+    for lanes in (0, 3):
+        for flags in (0, msc.FUSED_TRACK):
+            say("batch guided lanes", lanes, "flags", flags)
+            solver.set_lanes(lanes)
+            try:
+                specs = [msc.QuerySpec(**kw) for kw, _ in specs_alone]
+                res = solver.batch(specs, flags=flags)
+            finally:
+                solver.set_lanes(0)
+            for (kw, (st, val)), (bst, bval, _) in zip(specs_alone, res):
+                assert bst == st, (kw.get("kind"), bst, st)
+                if st == msc.OK:
+                    assert np.array_equal(bval, val)
