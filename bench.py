@@ -31,6 +31,7 @@ import argparse
 import json
 import os
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -835,9 +836,14 @@ def main():
     ap.add_argument("--lanes", type=int, default=0, help="worker lanes (0: pick the best of a short sweep)")
     ap.add_argument("--queries", type=int, default=64,
                     help="distinct seeded queries (a batch holds no query twice while batch <= queries)")
+    ap.add_argument("--alg-queries", type=int, default=16,
+                    help="queries whose stage sets are captured for the algorithmic bytes of the roofline")
     ap.add_argument("--serve-rate", type=float, default=600.0,
                     help="offered rate of the served phase of the bench line (Poisson arrivals)")
     ap.add_argument("--serve-phase-seconds", type=float, default=3.0)
+    ap.add_argument("--autotune", metavar="CACHE", default=os.path.join(tempfile.gettempdir(), "msc_tune_c2.txt"),
+                    help="tune the set kernels' launch shapes on the first 16 queries before timing (msc_autotune), "
+                         "writing the choice to CACHE ('none': keep the default shapes)")
     ap.add_argument("--cpu-procs", type=int, default=16, help="processes of the all-core oracle leg")
     ap.add_argument("--cpu-queries", type=int, default=16, help="queries of the all-core oracle leg")
     ap.add_argument("--plain-steps", type=int, default=100)
@@ -893,20 +899,43 @@ def main():
     cone = tuple(args.cone) if args.cone else None
     print("preparing %d queries" % args.queries, file=sys.stderr, flush=True)
     gen = synth.query_gms if args.arm == "gms" else synth.query_c2
-    queries = [gen(s, solver.pose_fn_for) for s in range(args.queries)]
+    queries = []
+    for s in range(args.queries):
+        queries.append(gen(s, solver.pose_fn_for))
+        if (s + 1) % 16 == 0:
+            print("prepared %d queries" % (s + 1), file=sys.stderr, flush=True)
     arm = queries[0].arm
     n, na = queries[0].scene.n, arm.na
 
-    # Algorithmic bytes per expansion launch, from one captured run of each query.
+    # Algorithmic bytes per expansion launch, from one captured run of each of the first
+    # 16 queries (the roofline sums the launches of those queries).
     alg, splits = [], []
-    for q in queries:
+    for i, q in enumerate(queries):
         scene = solver.scene(q.scene)
+        if i >= args.alg_queries:
+            solver.path(scene, q.arm, q.start, q.target, q.waypoints, q.max_delta, approach=cone)
+            splits.append(solver.stats()["split_m"])
+            alg.append(None)
+            continue
         st, _ = solver.path(scene, q.arm, q.start, q.target, q.waypoints, q.max_delta, flags=msc.CAPTURE_SETS,
                             approach=cone)
         stats = solver.stats()
         splits.append(stats["split_m"])
         alg.append(expansion_bytes(solver, msc, n, na, stats))
+        if (i + 1) % 4 == 0:
+            print("captured %d queries" % (i + 1), file=sys.stderr, flush=True)
     print("captured stage sets; splits", splits, file=sys.stderr, flush=True)
+    tuned = None
+    if args.autotune and args.autotune != "none":
+        specs = []
+        for q in queries[:16]:
+            specs.append(msc.QuerySpec(solver.scene(q.scene), q.arm, q.target, start=q.start, waypoints=q.waypoints,
+                                       delta=q.max_delta))
+        ts = time.perf_counter()
+        entries = solver.autotune(specs, args.autotune, approach=cone)
+        tuned = {"entries": len(entries), "non_default": sum(1 for e in entries if e[2] != 0),
+                 "seconds": round(time.perf_counter() - ts, 2), "cache": args.autotune}
+        print("autotune", tuned, entries, file=sys.stderr, flush=True)
 
     # ---- plain: one query per call, every launch timed with HIP events --------------
     # A query answered NO_REACH / NO_PATH is a complete solve (every retry was run);
@@ -942,6 +971,8 @@ def main():
             t[1] += 1
     b_sum, ms_sum, cnt = 0.0, 0.0, 0
     for qi, recs in launches:
+        if alg[qi] is None:
+            continue
         for kname, stage, nin, nout, ms in recs:
             if kname in ("expand_fwd", "expand_bwd"):
                 b_sum += alg[qi][(kname, stage)]
@@ -953,7 +984,8 @@ def main():
                 "kernel": "expand (k_expand_fwd + k_expand_bwd)", "launches": cnt,
                 "avg_launch_us": round(1e3 * ms_sum / max(cnt, 1), 2),
                 "alg_bytes_per_launch": round(b_sum / max(cnt, 1)),
-                "alg_bytes_max_launch": int(max(v for a in alg for v in a.values()))}
+                "alg_bytes_max_launch": int(max(v for a in alg if a is not None for v in a.values())),
+                "alg_queries": sum(1 for a in alg if a is not None)}
     plain_lat = np.array(lat) * 1e3
     plain = {"solves_per_s": round(args.plain_steps / plain_wall, 3),
              "p50_ms": round(float(np.percentile(plain_lat, 50)), 4),
@@ -1068,7 +1100,8 @@ def main():
                    "approach_cone_cdeg": list(cone) if cone else None,
                    "arm": ("two DOF per segment: (yaw, length 0) + (pitch, length L), L = 60, 50, 40, 25 voxels"
                            if args.arm == "gms" else "alternating yaw/pitch chain"),
-                   "p_latency": "per query, from batch start to its completion"},
+                   "p_latency": "per query, from batch start to its completion",
+                   "autotune": tuned},
         "plain": plain,
         "served": served,
         "roofline": roofline,

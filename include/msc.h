@@ -348,6 +348,27 @@ typedef struct {
  * are in q[i].status. */
 msc_status msc_batch(msc_ctx* ctx, msc_query* q, int32_t nq, const msc_opts* opts);
 
+/* Autotuner of the launch shapes of the set kernels (forward and backward stage
+ * expansions, the meet, D marking): "The procedure for IK solution" notes that Steps
+ * 2A/2B can be parallelized in various ways; how work items map to threads (the grid
+ * cap, i.e. items per thread, and the number of lanes that share one state) is chosen
+ * here by measurement.  Every query of q[nq] is solved on the context's own lane once per
+ * shape variant to warm up and twice more with every launch timed (HIP events); for each
+ * (kernel, log2 of the launch's input states) seen, the variant with the least total time
+ * is kept in the context (the default shape where nothing was measured).  Results do not
+ * depend on the shapes (the sets are the same).  With cache_path (may be NULL) the choice
+ * is written there as text, for msc_tune_load.  The queries' outputs are written as by
+ * msc_batch.  E_STATE while the server runs; a query's error status is returned. */
+msc_status msc_autotune(msc_ctx* ctx, msc_query* q, int32_t nq, const msc_opts* opts, const char* cache_path);
+/* Loads a choice written by msc_autotune.  E_ARG for a file that is not one (or names
+ * shapes this library does not have), E_STATE if it was tuned on another GPU model; the
+ * context's choice is unchanged on error.  msc_ctx_create loads the file named by the
+ * environment variable MSC_TUNE_CACHE when it exists and fits. */
+msc_status msc_tune_load(msc_ctx* ctx, const char* cache_path);
+/* The context's choice: up to cap entries (kernel, size class, variant, grid cap, lanes
+ * change) into out[cap*5]; *count = number of entries. */
+msc_status msc_tune_entries(msc_ctx* ctx, int32_t* out, int32_t cap, int32_t* count);
+
 /* Device-memory estimate of one query (bytes), used for admission. */
 uint64_t msc_query_bytes(const msc_query* q);
 

@@ -62,6 +62,15 @@ __host__ __device__ inline uint64_t mix64(uint64_t v) {
     return v;
 }
 
+// Launch shape of the grid-stride set kernels, chosen by the autotuner: the grid cap
+// (blocks; more work items per thread below it) and a change of the number of lanes
+// that share one state (log2, added to the launch's own choice, clamped to 0..6).
+// Every shape gives the same sets: only the mapping of work to threads changes.
+struct Shape {
+    uint32_t max_blocks = 16384;
+    int lg_bias = 0;
+};
+
 // Launch wrappers (msc_kernels.hip).  All enqueue on `st`.
 hipError_t launch_fill(uint64_t* p, uint64_t n, uint64_t value, hipStream_t st);
 hipError_t launch_tables(int na, int S, int L, short4* off, short4* sweep, unsigned int* maxn2,
@@ -94,11 +103,11 @@ hipError_t launch_seed_bwd(SetView s, GridView g, int x, int y, int z, const uin
                            const uint64_t* cone, uint64_t* list, unsigned long long* counter, hipStream_t st);
 hipError_t launch_expand_fwd(const uint64_t* in, uint64_t count, SetView out, GridView g, JointView j,
                              int tx, int ty, int tz, long long r2, unsigned long long* counter,
-                             unsigned long long* overflow, hipStream_t st);
+                             unsigned long long* overflow, hipStream_t st, Shape sh = Shape{});
 hipError_t launch_expand_bwd(const uint64_t* in, uint64_t count, SetView out, GridView g, JointView j,
                              int bx, int by, int bz, long long r2, const uint64_t* orows,
                              unsigned long long* counter, unsigned long long* overflow,
-                             hipStream_t st);
+                             hipStream_t st, Shape sh = Shape{});
 hipError_t launch_compact(SetView s, uint64_t* list, uint64_t cap, unsigned long long* counter,
                           unsigned long long* overflow, hipStream_t st);
 hipError_t launch_join(const uint64_t* flist, uint64_t count, SetView f, SetView b,
@@ -107,10 +116,11 @@ constexpr int kMeetInsert = 0, kMeetCount = 1, kMeetMark = 2;
 // (tx, ty, tz), r2: the target and the squared forward pruning radius of stage m (r2 < 0: none)
 hipError_t launch_meet(const uint64_t* flist, uint64_t count, SetView fprev, SetView b, SetView c, GridView g,
                        JointView j, int mode, unsigned long long* c_count, unsigned long long* kept_count,
-                       unsigned long long* overflow, int tx, int ty, int tz, long long r2, hipStream_t st);
+                       unsigned long long* overflow, int tx, int ty, int tz, long long r2, hipStream_t st,
+                       Shape sh = Shape{});
 hipError_t launch_dmark(const uint64_t* flist, uint64_t count, SetView fprev, SetView fnext, GridView g,
                         JointView j, unsigned long long* counter, int tx, int ty, int tz, long long r2,
-                        hipStream_t st);
+                        hipStream_t st, Shape sh = Shape{});
 
 struct DfsArgs {
     SetView sets[kMaxDof + 1];  // sets[k] = D_k for k <= m, B_k for k > m (k = 0..n)

@@ -674,11 +674,11 @@ __global__ void __launch_bounds__(kBlock) k_expand_fwd(const uint64_t* __restric
 
 hipError_t launch_expand_fwd(const uint64_t* in, uint64_t count, SetView out, GridView g, JointView j,
                              int tx, int ty, int tz, long long r2, unsigned long long* counter,
-                             unsigned long long* overflow, hipStream_t st) {
+                             unsigned long long* overflow, hipStream_t st, Shape sh) {
     uint64_t work = count * (uint64_t)(j.hi - j.lo + 1);
     if (work == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_expand_fwd, dim3(grid_for(work)), dim3(kBlock), 0, st, in, count, out, g, j, tx, ty, tz,
-                       r2, counter, overflow);
+    hipLaunchKernelGGL(k_expand_fwd, dim3(grid_for(work, kBlock, sh.max_blocks)), dim3(kBlock), 0, st, in, count,
+                       out, g, j, tx, ty, tz, r2, counter, overflow);
     return hipGetLastError();
 }
 
@@ -842,20 +842,20 @@ void launch_bwd_dense(int np, dim3 grid, hipStream_t st, const uint64_t* in, uin
 
 hipError_t launch_expand_bwd(const uint64_t* in, uint64_t count, SetView out, GridView g, JointView j,
                              int bx, int by, int bz, long long r2, const uint64_t* orows,
-                             unsigned long long* counter, unsigned long long* overflow, hipStream_t st) {
+                             unsigned long long* counter, unsigned long long* overflow, hipStream_t st, Shape sh) {
     if (count == 0) return hipSuccess;
     const bool run_dense = out.kind == kDense && ((out.fast_ia != 0) == (j.type == 0));
     if (run_dense) {
         const int np = ((out.na + 63) >> 6) + 1;   // words a row of na bits can touch
-        const dim3 grid(grid_for(count));
+        const dim3 grid(grid_for(count, kBlock, sh.max_blocks));
         if (counter)
             launch_bwd_dense<true>(np, grid, st, in, count, out, g, j, bx, by, bz, r2, orows, counter, overflow);
         else
             launch_bwd_dense<false>(np, grid, st, in, count, out, g, j, bx, by, bz, r2, orows, counter, overflow);
     } else {
-        const int lg = group_log2_for(count, j.hi - j.lo + 1);
-        hipLaunchKernelGGL(k_expand_bwd_set, dim3(grid_for(count << lg)), dim3(kBlock), 0, st, in, count, out, g, j,
-                           bx, by, bz, r2, orows, counter, overflow, lg);
+        const int lg = std::clamp(group_log2_for(count, j.hi - j.lo + 1) + sh.lg_bias, 0, 6);
+        hipLaunchKernelGGL(k_expand_bwd_set, dim3(grid_for(count << lg, kBlock, sh.max_blocks)), dim3(kBlock), 0, st,
+                           in, count, out, g, j, bx, by, bz, r2, orows, counter, overflow, lg);
     }
     return hipGetLastError();
 }
@@ -1156,11 +1156,12 @@ __global__ void __launch_bounds__(kBlock) k_meet(const uint64_t* __restrict__ fl
 
 hipError_t launch_meet(const uint64_t* flist, uint64_t count, SetView fprev, SetView b, SetView c, GridView g,
                        JointView j, int mode, unsigned long long* c_count, unsigned long long* kept_count,
-                       unsigned long long* overflow, int tx, int ty, int tz, long long r2, hipStream_t st) {
+                       unsigned long long* overflow, int tx, int ty, int tz, long long r2, hipStream_t st,
+                       Shape sh) {
     if (count == 0) return hipSuccess;
-    const int lg = group_log2_for(count, j.hi - j.lo + 1);
-    hipLaunchKernelGGL(k_meet, dim3(grid_for(count << lg)), dim3(kBlock), 0, st, flist, count, fprev, b, c, g, j,
-                       mode, c_count, kept_count, overflow, lg, tx, ty, tz, r2);
+    const int lg = std::clamp(group_log2_for(count, j.hi - j.lo + 1) + sh.lg_bias, 0, 6);
+    hipLaunchKernelGGL(k_meet, dim3(grid_for(count << lg, kBlock, sh.max_blocks)), dim3(kBlock), 0, st, flist, count,
+                       fprev, b, c, g, j, mode, c_count, kept_count, overflow, lg, tx, ty, tz, r2);
     return hipGetLastError();
 }
 
@@ -1221,13 +1222,13 @@ __global__ void __launch_bounds__(kBlock) k_dmark(const uint64_t* __restrict__ f
 
 hipError_t launch_dmark(const uint64_t* flist, uint64_t count, SetView fprev, SetView fnext, GridView g,
                         JointView j, unsigned long long* counter, int tx, int ty, int tz, long long r2,
-                        hipStream_t st) {
+                        hipStream_t st, Shape sh) {
     if (count == 0) return hipSuccess;
     // at most 8 lanes per state: a lane tries several angles (measured faster than a
     // wave per state, whose lanes each try one)
-    const int lg = std::min(group_log2_for(count, j.hi - j.lo + 1), 3);
-    hipLaunchKernelGGL(k_dmark, dim3(grid_for(count << lg)), dim3(kBlock), 0, st, flist, count, fprev, fnext, g, j,
-                       counter, lg, tx, ty, tz, r2);
+    const int lg = std::clamp(std::min(group_log2_for(count, j.hi - j.lo + 1), 3) + sh.lg_bias, 0, 6);
+    hipLaunchKernelGGL(k_dmark, dim3(grid_for(count << lg, kBlock, sh.max_blocks)), dim3(kBlock), 0, st, flist, count,
+                       fprev, fnext, g, j, counter, lg, tx, ty, tz, r2);
     return hipGetLastError();
 }
 

@@ -11,6 +11,7 @@
 #include <condition_variable>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -128,6 +129,12 @@ struct msc_ctx {
     std::vector<Lane*> workers;
     std::string err;
     ServerState* server = nullptr;
+    // launch shapes chosen by msc_autotune: variant per (kernel, log2 of the input
+    // states); -1 = the default shape.  tune_force >= 0 makes every tunable launch use
+    // that variant (while the tuner measures it).
+    int8_t tune[MSC_K_COUNT][64];
+    int tune_force = -1;
+    msc_ctx() { std::memset(tune, -1, sizeof tune); }
 };
 
 // Grids of ticks of a scene with moving obstacles.  Slot 0 holds the static obstacles;
@@ -246,6 +253,28 @@ void prof_reset(Lane* c, uint32_t flags) {
         HIP_TRY(expr);                                      \
         prof_end(c, pi_);                                   \
     } while (0)
+
+// Launch-shape variants the autotuner chooses from (variant 0 is the default).
+constexpr Shape kShapes[] = {{16384, 0}, {4096, 0}, {65536, 0}, {16384, -1}, {16384, 1}, {1024, 0},
+                             {512, 0},   {2048, 0}, {1024, -1}, {1024, 1}};
+constexpr int kNumShapes = (int)(sizeof kShapes / sizeof kShapes[0]);
+
+bool tunable(int kernel) {
+    return kernel == MSC_K_EXPAND_FWD || kernel == MSC_K_EXPAND_BWD || kernel == MSC_K_JOIN || kernel == MSC_K_DMARK;
+}
+
+int size_class(uint64_t count) {
+    int b = 0;
+    while (b < 63 && (count >> (b + 1))) ++b;
+    return b;
+}
+
+Shape shape_for(Lane* c, int kernel, uint64_t count) {
+    const msc_ctx* o = c->owner;
+    if (o->tune_force >= 0) return kShapes[o->tune_force];
+    const int v = o->tune[kernel][size_class(count)];
+    return v >= 0 && v < kNumShapes ? kShapes[v] : kShapes[0];
+}
 
 msc_status arena_alloc(Lane* c, uint64_t bytes, void** out) {
     uint64_t b = align_up(bytes ? bytes : 1);
@@ -735,7 +764,7 @@ msc_status run_reach(Lane* c, const msc_scene* sc, const Plan& p, int want, bool
         if (!ctr) return fail(c, MSC_E_CAPACITY, "out of counters");
         LAUNCH(MSC_K_EXPAND_FWD, k, (int64_t)F[k - 1].count,
                launch_expand_fwd(F[k - 1].list, F[k - 1].count, out.view, g, jv[k - 1], p.target[0], p.target[1],
-                                 p.target[2], r2, ctr, ovf, c->stream));
+                                 p.target[2], r2, ctr, ovf, c->stream, shape_for(c, MSC_K_EXPAND_FWD, F[k - 1].count)));
         const int rec = c->last_rec;
         MSC_TRY(read_counter(c, ctr, &out.count));
         prof_out(c, rec, (int64_t)out.count);
@@ -818,7 +847,7 @@ msc_status run_reach(Lane* c, const msc_scene* sc, const Plan& p, int want, bool
             if (count && !ctr) return fail(c, MSC_E_CAPACITY, "out of counters");
             LAUNCH(MSC_K_EXPAND_BWD, k - 1, (int64_t)B[kb].count,
                    launch_expand_bwd(B[kb].list, B[kb].count, B[k - 1].view, g, jv[k - 1], p.base[0], p.base[1],
-                                     p.base[2], r2, rows_for(k - 1, yaw), ctr, ovf, c->stream));
+                                     p.base[2], r2, rows_for(k - 1, yaw), ctr, ovf, c->stream, shape_for(c, MSC_K_EXPAND_BWD, B[kb].count)));
             kb = k - 1;
             if (count) {
                 const int rec = c->last_rec;
@@ -877,7 +906,7 @@ msc_status run_reach(Lane* c, const msc_scene* sc, const Plan& p, int want, bool
             if (!hc || !kc) return fail(c, MSC_E_CAPACITY, "out of counters");
             LAUNCH(MSC_K_JOIN, m, (int64_t)F[m - 1].count,
                    launch_meet(F[m - 1].list, F[m - 1].count, F[m - 1].view, B[m].view, B[m].view, g, jv[m - 1],
-                               kMeetMark, hc, kc, ovf, p.target[0], p.target[1], p.target[2], meet_r2, c->stream));
+                               kMeetMark, hc, kc, ovf, p.target[0], p.target[1], p.target[2], meet_r2, c->stream, shape_for(c, MSC_K_JOIN, F[m - 1].count)));
             const int jrec = c->last_rec;
             MSC_TRY(read_counter(c, kc, &joined));
             prof_out(c, jrec, (int64_t)joined);
@@ -932,7 +961,7 @@ msc_status run_reach(Lane* c, const msc_scene* sc, const Plan& p, int want, bool
         const long long dr2 = p.prune ? (long long)(rt_k * rt_k) : -1;
         LAUNCH(MSC_K_DMARK, k - 1, (int64_t)F[k - 1].count,
                launch_dmark(F[k - 1].list, F[k - 1].count, F[k - 1].view, F[k].view, g, jv[k - 1], dc, p.target[0],
-                            p.target[1], p.target[2], dr2, c->stream));
+                            p.target[1], p.target[2], dr2, c->stream, shape_for(c, MSC_K_DMARK, F[k - 1].count)));
         if (capture) MSC_TRY(capture_set(c, F[k - 1], N, 3, k - 1));
     }
 
@@ -1754,6 +1783,15 @@ msc_status msc_ctx_create(int device, void* hip_stream, void* dev_workspace, uin
         delete o;
         return st;
     }
+    // a tuning cache named by the environment, when it exists and fits this GPU
+    const char* cache = std::getenv("MSC_TUNE_CACHE");
+    if (cache && *cache) {
+        if (FILE* f = std::fopen(cache, "r")) {
+            std::fclose(f);
+            (void)msc_tune_load(o, cache);
+            o->err.clear();
+        }
+    }
     *out = o;
     return MSC_OK;
 }
@@ -2051,6 +2089,130 @@ msc_status msc_batch(msc_ctx* o, msc_query* q, int32_t nq, const msc_opts* opts)
         q[i].latency_ms = (float)(t1 - t0);
         unbind_scene(held[i]);
     }
+    return MSC_OK;
+}
+
+msc_status msc_autotune(msc_ctx* o, msc_query* q, int32_t nq, const msc_opts* opts, const char* cache_path) {
+    if (!o) return MSC_E_ARG;
+    if (nq <= 0 || !q) return ctx_fail(o, MSC_E_ARG, "no queries to tune on");
+    if (o->server) return ctx_fail(o, MSC_E_STATE, "the server is running");
+    Lane* c = o->control;
+    msc_opts po = opts_or_default(opts);
+    po.flags = (po.flags | MSC_PROFILE) & ~(MSC_CAPTURE_SETS | MSC_FUSED_TRACK);
+    const size_t cells = (size_t)MSC_K_COUNT * 64;
+    std::vector<double> sum(cells * kNumShapes, 0.0);
+    std::vector<int> cnt(cells * kNumShapes, 0);
+    constexpr int kReps = 3;   // the first solve of each variant warms up
+    for (int v = 0; v < kNumShapes; ++v) {
+        o->tune_force = v;
+        for (int rep = 0; rep < kReps; ++rep) {
+            for (int32_t i = 0; i < nq; ++i) {
+                Binding b = bind_scene(q[i].scene);
+                query_on(c, &q[i], &po, b);
+                if (q[i].status < 0) {
+                    o->tune_force = -1;
+                    o->err = q[i].error;
+                    return q[i].status;
+                }
+                if (rep == 0) continue;
+                for (const msc_timing& r : c->recs) {
+                    if (!tunable(r.kernel) || r.ms < 0) continue;
+                    const size_t cell = (size_t)r.kernel * 64 + size_class((uint64_t)std::max<int64_t>(r.in_count, 0));
+                    sum[cell * kNumShapes + v] += r.ms;
+                    cnt[cell * kNumShapes + v] += 1;
+                }
+            }
+        }
+    }
+    o->tune_force = -1;
+    std::memset(o->tune, -1, sizeof o->tune);
+    for (size_t cell = 0; cell < cells; ++cell) {
+        const int n0 = cnt[cell * kNumShapes];
+        if (n0 == 0) continue;
+        int best = 0;
+        bool same = true;
+        for (int v = 1; v < kNumShapes; ++v) {
+            same = same && cnt[cell * kNumShapes + v] == n0;
+            if (sum[cell * kNumShapes + v] < sum[cell * kNumShapes + best]) best = v;
+        }
+        if (same) o->tune[cell / 64][cell % 64] = (int8_t)best;
+    }
+    if (!cache_path) return MSC_OK;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, o->device) != hipSuccess) return ctx_fail(o, MSC_E_HIP, "device properties");
+    FILE* f = std::fopen(cache_path, "w");
+    if (!f) return ctx_fail(o, MSC_E_ARG, "cannot write the tuning cache");
+    std::fprintf(f, "msc-tune 1\ndevice %s\n", prop.gcnArchName);
+    for (int k = 0; k < MSC_K_COUNT; ++k)
+        for (int cl = 0; cl < 64; ++cl)
+            if (o->tune[k][cl] >= 0) {
+                const Shape& sh = kShapes[o->tune[k][cl]];
+                std::fprintf(f, "entry %d %d %d %u %d\n", k, cl, (int)o->tune[k][cl], sh.max_blocks, sh.lg_bias);
+            }
+    const bool ok = std::fclose(f) == 0;
+    return ok ? MSC_OK : ctx_fail(o, MSC_E_ARG, "cannot write the tuning cache");
+}
+
+msc_status msc_tune_load(msc_ctx* o, const char* cache_path) {
+    if (!o || !cache_path) return MSC_E_ARG;
+    if (o->server) return ctx_fail(o, MSC_E_STATE, "the server is running");
+    FILE* f = std::fopen(cache_path, "r");
+    if (!f) return ctx_fail(o, MSC_E_ARG, "cannot read the tuning cache");
+    char line[512];
+    int8_t tune[MSC_K_COUNT][64];
+    std::memset(tune, -1, sizeof tune);
+    msc_status st = MSC_OK;
+    int lineno = 0;
+    bool device_ok = false;
+    hipDeviceProp_t prop;
+    const bool have_prop = hipGetDeviceProperties(&prop, o->device) == hipSuccess;
+    while (st == MSC_OK && std::fgets(line, sizeof line, f)) {
+        ++lineno;
+        char dev[256];
+        int k, cl, v, bias;
+        unsigned mb;
+        if (lineno == 1) {
+            if (std::strncmp(line, "msc-tune 1", 10) != 0) st = ctx_fail(o, MSC_E_ARG, "not a tuning cache");
+        } else if (lineno == 2) {
+            if (std::sscanf(line, "device %255s", dev) != 1) {
+                st = ctx_fail(o, MSC_E_ARG, "tuning cache without a device line");
+            } else {
+                device_ok = have_prop && std::strcmp(dev, prop.gcnArchName) == 0;
+                if (!device_ok) st = ctx_fail(o, MSC_E_STATE, "tuning cache of another GPU model");
+            }
+        } else if (std::sscanf(line, "entry %d %d %d %u %d", &k, &cl, &v, &mb, &bias) == 5) {
+            if (k < 0 || k >= MSC_K_COUNT || !tunable(k) || cl < 0 || cl >= 64 || v < 0 || v >= kNumShapes ||
+                kShapes[v].max_blocks != mb || kShapes[v].lg_bias != bias)
+                st = ctx_fail(o, MSC_E_ARG, "tuning cache entry this library does not have");
+            else
+                tune[k][cl] = (int8_t)v;
+        } else {
+            st = ctx_fail(o, MSC_E_ARG, "malformed tuning cache line");
+        }
+    }
+    std::fclose(f);
+    if (st == MSC_OK && !device_ok) st = ctx_fail(o, MSC_E_ARG, "tuning cache without a device line");
+    if (st == MSC_OK) std::memcpy(o->tune, tune, sizeof tune);
+    return st;
+}
+
+msc_status msc_tune_entries(msc_ctx* o, int32_t* out, int32_t cap, int32_t* count) {
+    if (!o || !count || cap < 0 || (cap && !out)) return MSC_E_ARG;
+    int32_t n = 0;
+    for (int k = 0; k < MSC_K_COUNT; ++k)
+        for (int cl = 0; cl < 64; ++cl)
+            if (o->tune[k][cl] >= 0) {
+                if (n < cap) {
+                    const int v = o->tune[k][cl];
+                    out[5 * n] = k;
+                    out[5 * n + 1] = cl;
+                    out[5 * n + 2] = v;
+                    out[5 * n + 3] = (int32_t)kShapes[v].max_blocks;
+                    out[5 * n + 4] = kShapes[v].lg_bias;
+                }
+                ++n;
+            }
+    *count = n;
     return MSC_OK;
 }
 

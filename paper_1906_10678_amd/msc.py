@@ -33,6 +33,7 @@ EXPORTS = [
     "msc_server_submit", "msc_server_poll", "msc_server_wait", "msc_server_stop", "msc_refine", "msc_replan",
     "msc_scene_bytes_dynamic", "msc_scene_set_dynamic", "msc_server_step", "msc_server_take_replans",
     "msc_refine_static", "msc_refine_static_max", "msc_track_default", "msc_guided_path", "msc_pose_path",
+    "msc_autotune", "msc_tune_load", "msc_tune_entries",
 ]
 
 
@@ -124,6 +125,9 @@ def load_library(path: str = LIB_PATH):
     L.msc_guided_path.argtypes = [c_void_p, c_void_p, P(MscArm), P(i32), P(MscTrack), P(MscOpts), P(i32), P(i32)]
     L.msc_pose_path.argtypes = [c_void_p, c_void_p, P(MscArm), P(i32), P(i32), P(MscArm), P(MscTrack), P(MscOpts),
                                 P(i32), P(i32)]
+    L.msc_autotune.argtypes = [c_void_p, P(MscQuery), i32, P(MscOpts), ctypes.c_char_p]
+    L.msc_tune_load.argtypes = [c_void_p, ctypes.c_char_p]
+    L.msc_tune_entries.argtypes = [c_void_p, P(i32), i32, P(i32)]
     L.msc_refine_static.argtypes = L.msc_refine.argtypes
     L.msc_refine_static_max.argtypes = [i32]
     L.msc_refine_static_max.restype = i64
@@ -548,6 +552,28 @@ class Solver:
             sp.c.error = arr[i].error
             sp.c.rows = arr[i].rows
         return [sp.result() for sp in specs]
+
+    def autotune(self, specs, cache_path: Optional[str] = None, split_m: int = -1, approach=None):
+        """msc_autotune over QuerySpecs (solved on the context's own lane); returns the
+        chosen entries (kernel name, size class, variant, grid cap, lanes change)."""
+        arr = (MscQuery * max(1, len(specs)))()
+        for i, sp in enumerate(specs):
+            arr[i] = sp.c
+        o = make_opts(split_m=split_m, approach=approach)
+        path = cache_path.encode() if cache_path else None
+        self._check(self.lib.msc_autotune(self.ctx, arr, len(specs), ctypes.byref(o), path), "msc_autotune")
+        return self.tune_entries()
+
+    def tune_load(self, cache_path: str):
+        self._check(self.lib.msc_tune_load(self.ctx, cache_path.encode()), "msc_tune_load")
+
+    def tune_entries(self):
+        cnt = ctypes.c_int32()
+        self._check(self.lib.msc_tune_entries(self.ctx, None, 0, ctypes.byref(cnt)), "msc_tune_entries")
+        buf = np.zeros(max(1, cnt.value) * 5, np.int32)
+        self._check(self.lib.msc_tune_entries(self.ctx, _ptr(buf, ctypes.c_int32), cnt.value, ctypes.byref(cnt)),
+                    "msc_tune_entries")
+        return [(KERNELS[r[0]], int(r[1]), int(r[2]), int(r[3]), int(r[4])) for r in buf[:cnt.value * 5].reshape(-1, 5)]
 
     def query_bytes(self, spec: QuerySpec) -> int:
         return int(self.lib.msc_query_bytes(ctypes.byref(spec.c)))
