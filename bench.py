@@ -19,9 +19,10 @@ region; algorithmic bytes per launch = 8 * (non-zero 64-bit words of the input s
 of the output set + occupancy words of the active box) in the layout
 [orientation][z][y][x/64], from captured stage sets of the same queries.  Also
 `copy_GBps` (a 1 GiB device-to-device copy timed in the same run, reads + writes: the
-achievable ceiling), `frac_of_copy` = achieved / copy_GBps, and `full_size_hbm`: the HBM
-rate of the meet and of the backward stage into B_m on full-size plans, read from the
-committed counter summary (profiles/c4_big_stages.md) while the kernel sources match.
+achievable ceiling), `frac_of_copy` = achieved / copy_GBps, and `large_stages`: the
+algorithmic rate of the expansion launches above 256 MB (beyond the cache) on full-size
+plans, read from the committed summary (profiles/c4_big_stages.md) while the kernel
+sources match.
 `cpu_baseline` times the CPU oracle on the host cores: all-core throughput over 16 queries of the
 same workload (one process per query), with the one-thread latency of query 0 beside it.
 """
@@ -170,9 +171,9 @@ def measured_traffic():
 
 
 def full_size_stages():
-    """HBM rate of the two dominant kernels on full-size plans, from the committed
-    counter summary (profiles/c4_big_stages.md), or None when it is missing or was taken
-    on other kernel sources."""
+    """Algorithmic rate of the expansion launches beyond the cache on full-size plans, from
+    the committed summary (profiles/c4_big_stages.md), or None when it is missing or was
+    taken on other kernel sources."""
     try:
         with open(C4_STAGES_PROFILE) as f:
             text = f.read()
@@ -180,13 +181,12 @@ def full_size_stages():
         return None
     if "kernel sources sha256: `%s`" % kernel_source_hash() not in text:
         return None
-    out = {}
     for line in text.splitlines():
-        cells = [c.strip() for c in line.strip("|").split("|")]
-        if len(cells) == 8 and cells[0] == "all":
-            key = "meet" if cells[1] == "meet" else "backward_into_B_m"
-            out[key] = {"hbm_GBps": float(cells[6]), "frac": float(cells[7])}
-    return out or None
+        if line.startswith("- large stages: "):
+            parts = line[len("- large stages: "):].split(", ")
+            return {"launches": int(parts[0].split()[0]), "alg_GBps": float(parts[1].split()[0]),
+                    "frac": float(parts[2].split()[1]), "source": "profiles/c4_big_stages.md"}
+    return None
 
 
 def traffic_run(args):
@@ -232,9 +232,11 @@ C4_STAGES_PROFILE = os.path.join(ROOT, "profiles", "c4_big_stages.md")
 
 
 def c4_stages_run(args):
-    """The program of the big-stage measurement: six full-size batched-path plans (512^3,
-    2.5 deg, doubled lengths), each solved once to warm up, a 1 GiB device copy (the
-    counter calibration), then each solved once more with HIP-event times per launch."""
+    """The program of the full-size stage measurement: six batched-path plans (512^3, 2.5
+    deg, doubled lengths), each solved once to warm up, a 1 GiB device copy (the counter
+    calibration), then each solved once with HIP-event times per launch (the dispatches
+    the counter passes are read on), then once more with MSC_COUNT_SETS for the member
+    counts and the non-zero words of every stage's output."""
     import torch
 
     from paper_1906_10678_amd import msc, synth
@@ -255,8 +257,19 @@ def c4_stages_run(args):
     for q, sc in zip(qs, scenes):
         st, _ = solver.path(sc, q.arm, q.start, q.target, q.waypoints, q.max_delta, flags=msc.PROFILE)
         stats = solver.stats()
-        plans.append({"status": st, "split": stats["split_m"], "fwd": stats["fwd_count"], "bwd": stats["bwd_count"],
+        plans.append({"status": st, "split": stats["split_m"], "waypoints": q.waypoints,
                       "recs": [list(r) for r in solver.timings()]})
+        print("c4 stages: plan timed", len(plans), flush=True)
+    torch.cuda.synchronize()
+    for p, q, sc in zip(plans, qs, scenes):
+        st, _ = solver.path(sc, q.arm, q.start, q.target, q.waypoints, q.max_delta,
+                            flags=msc.PROFILE | msc.COUNT_SETS)
+        recs = solver.timings()
+        words = solver.timing_words()
+        if [r[0] for r in recs] != [r[0] for r in p["recs"]]:
+            raise RuntimeError("the counting run launched other kernels")
+        p["out_count"] = [int(r[3]) for r in recs]
+        p["out_words"] = words
     torch.cuda.synchronize()
     os.makedirs(os.path.dirname(args.c4_stages_run) or ".", exist_ok=True)
     with open(args.c4_stages_run, "w") as f:
@@ -265,79 +278,117 @@ def c4_stages_run(args):
 
 
 def c4_stages_summary(args):
-    """HBM bytes (two counter passes) against HIP-event time (a run of the same program
-    outside the profiler) of the two kernels that dominate the full-size plans: the
-    backward stage into the set the meet probes, and the meet."""
+    """Per expansion launch of the six full-size plans: algorithmic bytes (8 x (input
+    states read from the list + non-zero words of the output structure)), HBM bytes (two
+    counter passes), the L2 hit rate (a TCC_HIT / TCC_MISS pass) and the HIP-event time of
+    a run outside the profiler; the ones above 256 MB algorithmic (beyond the MALL) in a
+    table with totals, and the meet's HBM rate."""
     import csv
 
-    fetch_csv, write_csv, times_json = args.c4_stages_summary
+    fetch_csv, write_csv, tcc_csv, times_json = args.c4_stages_summary
     times = json.load(open(times_json))
+    kinds = {"expand_fwd": "k_expand_fwd", "expand_bwd": "k_expand_bwd", "join": "k_"}
 
-    def rows_after_copies(path, counter):
-        rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
-        rows.sort(key=lambda r: int(r["Dispatch_Id"]))
-        copies = [r for r in rows if "copyBuffer" in r["Kernel_Name"]]
-        last = max(int(r["Dispatch_Id"]) for r in copies)
-        cal = [float(r["Counter_Value"]) for r in copies if int(r["Dispatch_Id"]) > last - 3]
-        factor = (times["copy_bytes"] / 1024.0) / (sum(cal) / len(cal))
-        return factor, [r for r in rows if int(r["Dispatch_Id"]) > last]
+    def dispatches(path, counters):
+        """Counter values of the timed runs' dispatches after the calibration copies:
+        [(kernel name, {counter: value})] in dispatch order."""
+        by_id = {}
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] in counters:
+                d = by_id.setdefault(int(r["Dispatch_Id"]), [r["Kernel_Name"], {}])
+                d[1][r["Counter_Name"]] = d[1].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        ids = sorted(by_id)
+        copies = [i for i in ids if "copyBuffer" in by_id[i][0]]
+        last = max(copies)
+        cal = [by_id[i][1] for i in copies if i > last - 3]
+        return cal, [by_id[i] for i in ids if i > last]
 
-    ff, frows = rows_after_copies(fetch_csv, "FETCH_SIZE")
-    wf, wrows = rows_after_copies(write_csv, "WRITE_SIZE")
-    def per_plan(rows):
-        """Per plan (the dispatches up to its meet): the last backward expansion (the
-        stage into B_m, dense or hashed) and the meet."""
-        out, last_bwd = [], None
-        for r in rows:
-            name = r["Kernel_Name"].split("(")[0]
-            if "k_expand_bwd" in name:
-                last_bwd = r
-            elif "k_meet" in name:
-                out.append((last_bwd, r))
-                last_bwd = None
-        return out
+    def set_kernels(rows):
+        return [(name, v) for name, v in rows
+                if "k_expand_fwd" in name or "k_expand_bwd" in name or "k_meet" in name or "k_join" in name]
 
-    fp, wp = per_plan(frows), per_plan(wrows)
-    lines = ["# Full-size plans: HBM traffic of the two dominant kernels", "",
-             "Six plans of the batched-path workload (512^3 grid, 8-DOF chain with doubled lengths, 2.5 deg), "
-             "each solved once with HIP-event times per launch; HBM bytes from two rocprofv3 counter passes "
-             "over the same program, scaled by a 1 GiB device copy (FETCH x %.4f, WRITE x %.4f).  Per plan, "
-             "the backward stage into the set the meet probes (its last backward expansion) and the meet."
-             % (ff, wf), "",
+    fcal, frows = dispatches(fetch_csv, {"FETCH_SIZE"})
+    wcal, wrows = dispatches(write_csv, {"WRITE_SIZE"})
+    _, trows = dispatches(tcc_csv, {"TCC_HIT_sum", "TCC_MISS_sum"})
+    ff = (times["copy_bytes"] / 1024.0) / (sum(c["FETCH_SIZE"] for c in fcal) / len(fcal))
+    wf = (times["copy_bytes"] / 1024.0) / (sum(c["WRITE_SIZE"] for c in wcal) / len(wcal))
+    frows, wrows, trows = set_kernels(frows), set_kernels(wrows), set_kernels(trows)
+    launches = []
+    for i, p in enumerate(times["plans"]):
+        for j, r in enumerate(p["recs"]):
+            if r[0] in ("expand_fwd", "expand_bwd", "join"):
+                launches.append((i, j, r, p["out_words"][j], p["out_count"][j]))
+    n = min(len(launches), len(frows), len(wrows), len(trows))
+    big, meets, all_exp = [], [], [0.0, 0.0, 0]
+    for (i, j, r, words, outc), (fname, fv), (_, wv), (_, tv) in zip(launches[:n], frows, wrows, trows):
+        kname = fname.split("(")[0]
+        if r[0] == "join" and "k_meet" not in kname and "k_join" not in kname:
+            raise RuntimeError("dispatch order does not match the launch records")
+        hbm = fv["FETCH_SIZE"] * ff * 1024 + wv["WRITE_SIZE"] * wf * 1024
+        hit = tv.get("TCC_HIT_sum", 0.0)
+        miss = tv.get("TCC_MISS_sum", 0.0)
+        l2 = hit / (hit + miss) if hit + miss > 0 else float("nan")
+        ms = r[4]
+        if r[0] == "join":
+            meets.append((i, kname, r[2], hbm, l2, ms))
+            continue
+        alg = 8.0 * (r[2] + max(words, 0))
+        all_exp[0] += alg
+        all_exp[1] += ms
+        all_exp[2] += 1
+        if alg > 256e6:
+            big.append((i, kname, r[1], r[2], words, alg, hbm, l2, ms))
+    lines = ["# Full-size plans: expansion stages beyond the cache, against the HBM roofline", "",
+             "Six plans of the batched-path workload (512^3 grid, 8-DOF chain with doubled lengths, 2.5 deg).  "
+             "Per expansion launch: algorithmic bytes = 8 x (input states, read from the compacted list, + "
+             "non-zero 64-bit words of the output set's structure, counted on the device after the launch in a "
+             "second solve with MSC_COUNT_SETS); HBM bytes from FETCH_SIZE and WRITE_SIZE passes scaled by a "
+             "1 GiB device copy (x %.4f, x %.4f); L2 hit rate = TCC_HIT / (TCC_HIT + TCC_MISS) from a third "
+             "pass; time from HIP events of the timed solve.  The table lists the launches above 256 MB "
+             "algorithmic (larger than the MALL), where the 50%% target is judged." % (ff, wf), "",
              "```",
              "python -u bench.py --c4-stages-run gpurun_out/c4_times.json --workspace-gb 200",
-             "timeout -s KILL 240 rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/c4_fetch -o run "
+             "timeout -s KILL 300 rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/c4_fetch -o run "
              "-- python -u bench.py --c4-stages-run gpurun_out/c4_pmc.json --workspace-gb 200",
-             "timeout -s KILL 240 rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/c4_write -o run "
+             "timeout -s KILL 300 rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/c4_write -o run "
              "-- python -u bench.py --c4-stages-run gpurun_out/c4_pmc.json --workspace-gb 200",
+             "timeout -s KILL 300 rocprofv3 --pmc TCC_HIT_sum TCC_MISS_sum --output-format csv -d gpurun_out/c4_tcc "
+             "-o run -- python -u bench.py --c4-stages-run gpurun_out/c4_pmc.json --workspace-gb 200",
              "python bench.py --c4-stages-summary gpurun_out/c4_fetch/run_counter_collection.csv "
-             "gpurun_out/c4_write/run_counter_collection.csv gpurun_out/c4_times.json",
+             "gpurun_out/c4_write/run_counter_collection.csv gpurun_out/c4_tcc/run_counter_collection.csv "
+             "gpurun_out/c4_times.json",
              "```", "",
-             "| plan | kernel | input states | HBM read MB | HBM write MB | ms (events) | HBM GB/s | of 8 TB/s |",
-             "|---|---|---|---|---|---|---|---|"]
-    tot = {"bwd": [0.0, 0.0], "meet": [0.0, 0.0]}
-    for i, p in enumerate(times["plans"][:len(fp)]):
-        bwd_recs = [r for r in p["recs"] if r[0] == "expand_bwd"]
-        meet_recs = [r for r in p["recs"] if r[0] == "join"]
-        pairs = [("bwd", bwd_recs[-1] if bwd_recs else None, fp[i][0], wp[i][0]),
-                 ("meet", meet_recs[-1] if meet_recs else None, fp[i][1], wp[i][1])]
-        for kind, rec, f, w in pairs:
-            if rec is None or f is None or w is None:
-                continue
-            rb = float(f["Counter_Value"]) * ff * 1024
-            wb = float(w["Counter_Value"]) * wf * 1024
-            ms = rec[4]
-            tot[kind][0] += rb + wb
-            tot[kind][1] += ms
-            lines.append("| %d | %s | %d | %.1f | %.1f | %.3f | %.0f | %.3f |" % (
-                i, f["Kernel_Name"].split("(")[0], rec[2], rb / 1e6, wb / 1e6, ms,
-                (rb + wb) / (ms * 1e-3) / 1e9, (rb + wb) / (ms * 1e-3) / 8e12))
-    for kind, label in (("bwd", "backward stage into B_m"), ("meet", "meet")):
-        b, ms = tot[kind]
-        if ms > 0:
-            lines.append("| all | %s | | | | %.3f | %.0f | %.3f |" % (label, ms, b / (ms * 1e-3) / 1e9,
-                                                                    b / (ms * 1e-3) / 8e12))
-    lines += ["", "- kernel sources sha256: `%s`" % kernel_source_hash(), ""]
+             "| plan | kernel | stage | input states | output words | algorithmic MB | HBM MB | HBM / alg | L2 hit | ms | alg GB/s | of 8 TB/s |",
+             "|---|---|---|---|---|---|---|---|---|---|---|---|"]
+    ta = th = tm = 0.0
+    for i, kname, stage, nin, words, alg, hbm, l2, ms in big:
+        ta += alg
+        th += hbm
+        tm += ms
+        lines.append("| %d | %s | %d | %d | %d | %.1f | %.1f | %.2f | %.3f | %.3f | %.0f | %.3f |" % (
+            i, kname, stage, nin, words, alg / 1e6, hbm / 1e6, hbm / alg, l2, ms, alg / (ms * 1e-3) / 1e9,
+            alg / (ms * 1e-3) / 8e12))
+    if tm > 0:
+        lines.append("| all | %d launches | | | | %.1f | %.1f | %.2f | | %.3f | %.0f | %.3f |" % (
+            len(big), ta / 1e6, th / 1e6, th / ta, tm, ta / (tm * 1e-3) / 1e9, ta / (tm * 1e-3) / 8e12))
+    lines += ["", "Every expansion launch of the six plans: %d launches, %.1f MB algorithmic in %.3f ms, "
+              "%.0f GB/s (%.3f of 8 TB/s)." % (all_exp[2], all_exp[0] / 1e6, all_exp[1],
+                                              all_exp[0] / (all_exp[1] * 1e-3) / 1e9 if all_exp[1] else 0,
+                                              all_exp[0] / (all_exp[1] * 1e-3) / 8e12 if all_exp[1] else 0), "",
+              "The meet (random membership probes into the set of the last backward stage):", "",
+              "| plan | input states | HBM MB | L2 hit | ms | HBM GB/s | of 8 TB/s |", "|---|---|---|---|---|---|---|"]
+    mh = mm = 0.0
+    for i, kname, nin, hbm, l2, ms in meets:
+        mh += hbm
+        mm += ms
+        lines.append("| %d | %d | %.1f | %.3f | %.3f | %.0f | %.3f |" % (
+            i, nin, hbm / 1e6, l2, ms, hbm / (ms * 1e-3) / 1e9, hbm / (ms * 1e-3) / 8e12))
+    if mm > 0:
+        lines.append("| all | | %.1f | | %.3f | %.0f | %.3f |" % (mh / 1e6, mm, mh / (mm * 1e-3) / 1e9,
+                                                                 mh / (mm * 1e-3) / 8e12))
+    lines += ["", "- large stages: %d launches, %.0f GB/s algorithmic, frac %.4f" % (
+        len(big), ta / (tm * 1e-3) / 1e9 if tm else 0, ta / (tm * 1e-3) / 8e12 if tm else 0),
+        "- kernel sources sha256: `%s`" % kernel_source_hash(), ""]
     with open(C4_STAGES_PROFILE, "w") as f:
         f.write("\n".join(lines))
     print("wrote", C4_STAGES_PROFILE, flush=True)
@@ -588,6 +639,7 @@ def bench_c4(args):
            "unit": "plans/s", "seconds": round(wall, 3), "lanes": lanes, "plans": len(qs),
            "workspace_gb": args.workspace_gb, "statuses": {str(k): sts.count(k) for k in sorted(set(sts))},
            "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+           "no_path_plans": [[i, qs[i].waypoints] for i, st in enumerate(sts) if st == msc.NO_PATH],
            "config": {"workload": "batched paths: 8 scenes 512^3 (40 boxes + 16 spheres, dilation 4), 32 plans "
                                   "each, 8-DOF doubled lengths, 2.5 deg, 8..64 waypoints"}}
     print(json.dumps(out), flush=True)
@@ -813,7 +865,7 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--c4-stages-run", metavar="OUT_JSON",
                     help="run the program of the full-size big-stage measurement (see profiles/c4_big_stages.md)")
-    ap.add_argument("--c4-stages-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "TIMES_JSON"),
+    ap.add_argument("--c4-stages-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "TCC_CSV", "TIMES_JSON"),
                     help="write profiles/c4_big_stages.md")
     ap.add_argument("--arm", choices=["chain", "gms"], default="chain",
                     help="gms: the same workload with the paper's arm model, two DOF per segment (a variant)")
@@ -1013,7 +1065,7 @@ def main():
     roofline["copy_GBps"] = round(copy_gbs, 1)
     roofline["frac_of_copy"] = round(roofline["achieved"] / copy_gbs, 5)
     # the kernels on full-size plans, where the sets stream from HBM (counter summary)
-    roofline["full_size_hbm"] = full_size_stages()
+    roofline["large_stages"] = full_size_stages()
 
     # ---- batched: each step rasterises the scenes of a batch and solves it with msc_batch
     def batch_step(b):

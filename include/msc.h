@@ -93,6 +93,9 @@ typedef struct { int32_t c[3], r; } msc_sphere;
 #define MSC_PROFILE 4u      /* time every kernel launch of the call with HIP events */
 #define MSC_FUSED_TRACK 8u  /* msc_batch: the waypoint tracking of every kind 2 / 3 query runs in
                                one launch after all their searches (one block per query) */
+#define MSC_COUNT_SETS 16u  /* measurement: every stage set gets a member count (also the one the
+                               meet probes) and, with MSC_PROFILE, each expansion's record its
+                               output's non-zero words (extra kernels, outside the timed launches) */
 
 typedef struct {
     int32_t split_m;       /* forward stages before the join: -1 = adaptive, else 0..dof */
@@ -444,6 +447,9 @@ typedef struct {
     int64_t in_count;   /* input states (expansions, compaction, join, marking), else 0 */
     int64_t out_count;  /* new states (expansions), survivors (join, marking), else 0 */
     float ms;           /* event-to-event duration */
+    int64_t out_words;  /* expansions with MSC_COUNT_SETS: non-zero 64-bit words of the output set's
+                           structure (dense words; hash slots holding a member) after the launch;
+                           else -1 */
 } msc_timing;
 /* Copy up to cap records into out and set *count to the number recorded. */
 msc_status msc_get_timings(msc_ctx* ctx, msc_timing* out, int32_t cap, int32_t* count);

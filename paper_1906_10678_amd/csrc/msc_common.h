@@ -108,6 +108,8 @@ hipError_t launch_expand_bwd(const uint64_t* in, uint64_t count, SetView out, Gr
                              int bx, int by, int bz, long long r2, const uint64_t* orows,
                              unsigned long long* counter, unsigned long long* overflow,
                              hipStream_t st, Shape sh = Shape{});
+// Adds the non-zero words of s (dense: words != 0; hash: slots holding a member) to *counter.
+hipError_t launch_count_words(SetView s, unsigned long long* counter, hipStream_t st);
 hipError_t launch_compact(SetView s, uint64_t* list, uint64_t cap, unsigned long long* counter,
                           unsigned long long* overflow, hipStream_t st);
 hipError_t launch_join(const uint64_t* flist, uint64_t count, SetView f, SetView b,

@@ -1045,6 +1045,22 @@ __global__ void __launch_bounds__(kBlock) k_compact(SetView s, uint64_t* list, u
     }
 }
 
+// Measurement: non-zero words of a set's structure (one grid-stride pass).
+__global__ void __launch_bounds__(kBlock) k_count_words(SetView s, unsigned long long* counter) {
+    unsigned long long n = 0;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < s.cap; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t w = s.words[i];
+        n += s.kind == kDense ? (w != 0) : (w != kEmpty && !(w & kDead));
+    }
+    block_add(n, counter);
+}
+
+hipError_t launch_count_words(SetView s, unsigned long long* counter, hipStream_t st) {
+    if (s.cap == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_count_words, dim3(grid_for(s.cap, kBlock, 8192)), dim3(kBlock), 0, st, s, counter);
+    return hipGetLastError();
+}
+
 hipError_t launch_compact(SetView s, uint64_t* list, uint64_t cap, unsigned long long* counter,
                           unsigned long long* overflow, hipStream_t st) {
     uint64_t tiles = (s.cap + (uint64_t)kBlock * kCompactWords - 1) / ((uint64_t)kBlock * kCompactWords);

@@ -219,6 +219,7 @@ int prof_begin(Lane* c, int kernel, int stage, int64_t in) {
     t.in_count = in;
     t.out_count = 0;
     t.ms = -1.0f;
+    t.out_words = -1;
     c->recs.push_back(t);
     c->last_rec = (int)idx;
     return (int)idx;
@@ -230,6 +231,10 @@ void prof_end(Lane* c, int idx) {
 
 void prof_out(Lane* c, int idx, int64_t out) {
     if (idx >= 0 && idx < (int)c->recs.size()) c->recs[idx].out_count = out;
+}
+
+void prof_words(Lane* c, int idx, int64_t words) {
+    if (idx >= 0 && idx < (int)c->recs.size()) c->recs[idx].out_words = words;
 }
 
 void prof_finish(Lane* c) {
@@ -390,6 +395,7 @@ struct Plan {
     int type[kMaxDof], len[kMaxDof], lo[kMaxDof], hi[kMaxDof], ref[kMaxDof];
     int target[3];
     int prune;
+    int count_sets;   // MSC_COUNT_SETS: member counts and output words of every stage
     int split;   // -1 adaptive
     int app_az, app_el, app_half;   // approach cone of the last segment (centidegrees; half < 0: none)
 };
@@ -464,6 +470,7 @@ void make_plan(const msc_arm* arm, const int32_t* target, Plan& p) {
     }
     for (int i = 0; i < 3; ++i) p.target[i] = target ? target[i] : 0;
     p.prune = 1;
+    p.count_sets = 0;
     p.split = -1;
     p.app_az = p.app_el = 0;
     p.app_half = -1;
@@ -661,6 +668,18 @@ msc_status check_overflow(Lane* c, unsigned long long* ovf, const char* what) {
     return MSC_OK;
 }
 
+// Measurement (MSC_COUNT_SETS): the non-zero words of a set's structure, stored in
+// launch record rec (the count runs after the timed launch).
+msc_status count_words(Lane* c, const SetView& v, int rec) {
+    unsigned long long* ctr = take_counter(c);
+    if (!ctr) return fail(c, MSC_E_CAPACITY, "out of counters");
+    HIP_TRY(launch_count_words(v, ctr, c->stream));
+    uint64_t words = 0;
+    MSC_TRY(read_counter(c, ctr, &words));
+    prof_words(c, rec, (int64_t)words);
+    return MSC_OK;
+}
+
 // The staged reach search.  Returns MSC_OK with up to `want` solutions (steps) in the
 // canonical order, or MSC_NO_REACH.
 msc_status run_reach(Lane* c, const msc_scene* sc, const Plan& p, int want, bool capture, ReachOut& out) {
@@ -768,6 +787,7 @@ msc_status run_reach(Lane* c, const msc_scene* sc, const Plan& p, int want, bool
         const int rec = c->last_rec;
         MSC_TRY(read_counter(c, ctr, &out.count));
         prof_out(c, rec, (int64_t)out.count);
+        if (p.count_sets && rec >= 0) MSC_TRY(count_words(c, out.view, rec));
         return MSC_OK;
     };
     // The two pathways are expanded until they are one transition apart, then met
@@ -842,7 +862,7 @@ msc_status run_reach(Lane* c, const msc_scene* sc, const Plan& p, int want, bool
             // nothing): it is built without one, and without a host round trip, unless
             // the sets are captured.
             const bool last = p.split == 0 ? k - 1 == 0 : k - 1 - kf == 1;
-            const bool count = capture || !last;
+            const bool count = capture || !last || p.count_sets;
             unsigned long long* ctr = count ? take_counter(c) : nullptr;
             if (count && !ctr) return fail(c, MSC_E_CAPACITY, "out of counters");
             LAUNCH(MSC_K_EXPAND_BWD, k - 1, (int64_t)B[kb].count,
@@ -853,6 +873,7 @@ msc_status run_reach(Lane* c, const msc_scene* sc, const Plan& p, int want, bool
                 const int rec = c->last_rec;
                 MSC_TRY(read_counter(c, ctr, &B[k - 1].count));
                 prof_out(c, rec, (int64_t)B[k - 1].count);
+                if (p.count_sets && rec >= 0) MSC_TRY(count_words(c, B[k - 1].view, rec));
                 empty = B[k - 1].count == 0;
             } else {
                 B[k - 1].counted = false;
@@ -1160,6 +1181,7 @@ msc_status reach_on(Lane* c, const msc_scene* sc, const msc_arm* arm, const int3
     Plan p;
     make_plan(arm, target, p);
     p.prune = (o.flags & MSC_NO_PRUNE) ? 0 : 1;
+    p.count_sets = (o.flags & MSC_COUNT_SETS) ? 1 : 0;
     p.split = o.split_m;
     MSC_TRY(set_approach(c, o, p));
     ReachOut r;
@@ -1193,6 +1215,7 @@ msc_status path_on(Lane* c, const msc_scene* sc, const msc_arm* arm, const int32
     Plan p;
     make_plan(arm, target, p);
     p.prune = (o.flags & MSC_NO_PRUNE) ? 0 : 1;
+    p.count_sets = (o.flags & MSC_COUNT_SETS) ? 1 : 0;
     p.split = o.split_m;
     MSC_TRY(set_approach(c, o, p));
     const int n = p.n;
@@ -1433,6 +1456,7 @@ msc_status guided_prepare(Lane* c, const msc_scene* sc, const msc_arm* arm, cons
     Plan p;
     make_plan(arm, target, p);
     p.prune = (o.flags & MSC_NO_PRUNE) ? 0 : 1;
+    p.count_sets = (o.flags & MSC_COUNT_SETS) ? 1 : 0;
     p.split = o.split_m;
     MSC_TRY(set_approach(c, o, p));
     ReachOut r;

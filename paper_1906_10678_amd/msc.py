@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libmsc.so")
 MAX_DOF = 16
 OK, NO_REACH, NO_PATH = 0, 1, 2
 E_ARG, E_NOMEM, E_HIP, E_CAPACITY, E_STATE = -1, -2, -3, -4, -5
-CAPTURE_SETS, NO_PRUNE, PROFILE, FUSED_TRACK = 1, 2, 4, 8
+CAPTURE_SETS, NO_PRUNE, PROFILE, FUSED_TRACK, COUNT_SETS = 1, 2, 4, 8, 16
 KERNELS = ["fill", "tables", "raster", "orient", "seed", "expand_fwd", "expand_bwd", "compact", "join", "dmark",
            "dfs", "pose", "tube_valid", "tube_solve", "refine", "track"]
 SET_F, SET_B, SET_C, SET_D = 0, 1, 2, 3
@@ -59,7 +59,7 @@ class MscSphere(ctypes.Structure):
 
 class MscTiming(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int32), ("stage", ctypes.c_int32), ("in_count", ctypes.c_int64),
-                ("out_count", ctypes.c_int64), ("ms", ctypes.c_float)]
+                ("out_count", ctypes.c_int64), ("ms", ctypes.c_float), ("out_words", ctypes.c_int64)]
 
 
 class MscQuery(ctypes.Structure):
@@ -530,6 +530,14 @@ class Solver:
         buf = (MscTiming * max(1, cnt.value))()
         self._check(self.lib.msc_get_timings(self.ctx, buf, cnt.value, ctypes.byref(cnt)), "msc_get_timings")
         return [(KERNELS[t.kernel], t.stage, t.in_count, t.out_count, t.ms) for t in buf[:cnt.value]]
+
+    def timing_words(self) -> list:
+        """out_words of the last call's launch records (-1 where not counted)."""
+        cnt = ctypes.c_int32()
+        self._check(self.lib.msc_get_timings(self.ctx, None, 0, ctypes.byref(cnt)), "msc_get_timings")
+        buf = (MscTiming * max(1, cnt.value))()
+        self._check(self.lib.msc_get_timings(self.ctx, buf, cnt.value, ctypes.byref(cnt)), "msc_get_timings")
+        return [int(t.out_words) for t in buf[:cnt.value]]
 
     # -- lanes, batches, server ----------------------------------------------
     def set_lanes(self, nworkers: int):

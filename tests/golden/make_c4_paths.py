@@ -1,7 +1,8 @@
 """Writes c4_paths.json: the oracle's answers to the full-size batched-path plans of
 scene 0 (512^3 grid, 8-DOF chain with doubled lengths, 2.5 deg steps) whose waypoint
-count is at most 20 (the oracle needs seconds for those, far longer for the widest
-windows), with a fingerprint of each plan's inputs.
+count is at most 32 (seconds for up to 20 waypoints, up to about 5 minutes and 10 GB
+for 21 to 32; far longer for the widest windows), plus the plans listed in EXTRA (of
+later scenes), with a fingerprint of each plan's inputs.
 
 Only the oracle computes these values (reach at split 5).  Run from the repository
 root:  python tests/golden/make_c4_paths.py
@@ -22,12 +23,15 @@ from make_c2_paths import fingerprint  # noqa: E402
 from paper_1906_10678_amd import synth  # noqa: E402
 
 PLANS = 32
-MAX_W = 20
+MAX_W = 32
 SPLIT = 5
+EXTRA = []          # (scene, plan index within the scene) of later scenes
+WORKERS = 3         # memory: the widest windows hold up to about 10 GB each
 
 
 def plans():
-    return synth.queries_c4(oracle.pose_fn_for, scenes=1, per_scene=PLANS)
+    scenes = 1 + max([sc for sc, _ in EXTRA], default=0)
+    return synth.queries_c4(oracle.pose_fn_for, scenes=scenes, per_scene=PLANS)
 
 
 def solve(args):
@@ -41,12 +45,14 @@ def solve(args):
 def main():
     oracle.build()
     qs = plans()
-    todo = [(j, q) for j, q in enumerate(qs) if q.waypoints <= MAX_W]
-    with Pool(min(4, os.cpu_count() or 1)) as p:
-        rows = p.map(solve, todo)
+    todo = [(j, q) for j, q in enumerate(qs[:PLANS]) if q.waypoints <= MAX_W]
+    todo += [(sc * PLANS + j, qs[sc * PLANS + j]) for sc, j in EXTRA]
+    todo.sort(key=lambda t: -t[1].waypoints)   # the longest first
+    with Pool(min(WORKERS, os.cpu_count() or 1)) as p:
+        rows = sorted(p.map(solve, todo, chunksize=1), key=lambda r: r["plan"])
     out = os.path.join(os.path.dirname(os.path.abspath(__file__)), "c4_paths.json")
     with open(out, "w") as f:
-        json.dump({"split": SPLIT, "plans": PLANS, "max_waypoints": MAX_W, "rows": rows}, f)
+        json.dump({"split": SPLIT, "plans": PLANS, "max_waypoints": MAX_W, "extra": EXTRA, "rows": rows}, f)
     print("wrote", out, [(r["plan"], r["waypoints"], r["status"]) for r in rows])
 
 
