@@ -25,7 +25,7 @@ from paper_1906_10678_amd import synth  # noqa: E402
 PLANS = 32
 MAX_W = 32
 SPLIT = 5
-EXTRA = []          # (scene, plan index within the scene) of later scenes
+EXTRA = [(5, 3)]    # (scene, plan index within the scene) of later scenes (27 waypoints)
 WORKERS = 3         # memory: the widest windows hold up to about 10 GB each
 
 

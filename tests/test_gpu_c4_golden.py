@@ -29,8 +29,8 @@ def _golden():
 def test_c4_full_size_paths_match_oracle(solver):
     g = _golden()
     assert g["rows"], "no stored answers: run tests/golden/make_c4_paths.py"
-    scenes = 1 + max([sc for sc, _ in g.get("extra", [])], default=0)
-    qs = synth.queries_c4(solver.pose_fn_for, scenes=scenes, per_scene=g["plans"])
+    nsc = 1 + max([sc for sc, _ in g.get("extra", [])], default=0)
+    qs = synth.queries_c4(solver.pose_fn_for, scenes=nsc, per_scene=g["plans"])
     scenes = {}
     for row in g["rows"]:
         q = qs[row["plan"]]
