@@ -839,6 +839,57 @@ def bench_guided(args):
           flush=True)
 
 
+def bench_short(args):
+    """Short reaches on the 8-DOF workload's scenes: targets at the middle sample of
+    segment 3 or 4 of a drawn valid pose (reachable by a sublength of the arm), solved
+    with msc_short_path (hit radius 2 voxels, segments 2..4), one query per call."""
+    import torch
+
+    from paper_1906_10678_amd import msc, synth
+
+    solver = msc.Solver(0, workspace_bytes=args.workspace_gb << 30)
+    nq = args.queries
+    items = []
+    for sd in range(nq):
+        q = synth.query_c2(sd, solver.pose_fn_for)
+        scene = solver.scene(q.scene)
+        rng = synth.rng_for(12, sd, 0)
+        start, _, _ = synth.first_valid_pose(rng, q.arm, solver.pose_fn_for(q.arm, q.scene))
+        seg = 2 + sd % 2          # 0-based: segment 3 or 4
+        # about the middle of that segment: the end of the prefix with the segment halved,
+        # replayed by the library
+        half = synth.Arm(types=q.arm.types[:seg + 1], lens=q.arm.lens[:seg] + [q.arm.lens[seg] // 2],
+                         lo_cdeg=q.arm.lo_cdeg[:seg + 1], hi_cdeg=q.arm.hi_cdeg[:seg + 1],
+                         step_cdeg=q.arm.step_cdeg, base=q.arm.base)
+        _, t = solver.pose_check(scene, half, start[None, :seg + 1])
+        items.append((scene, q.arm, tuple(int(v) for v in t[0])))
+    first = [solver.short_path(sc, arm, t, 4, 4) for sc, arm, t in items]
+    torch.cuda.synchronize()
+    lat, per_kernel = [], {}
+    t0 = time.perf_counter()
+    for i in range(args.plain_steps):
+        sc, arm, t = items[i % nq]
+        ts = time.perf_counter()
+        st, _, _ = solver.short_path(sc, arm, t, 4, 4, flags=msc.PROFILE)
+        lat.append(time.perf_counter() - ts)
+        if st != first[i % nq][0]:
+            raise RuntimeError("query %d: status changed" % (i % nq))
+        for kname, stage, nin, nout, ms in solver.timings():
+            v = per_kernel.setdefault(kname, [0.0, 0])
+            v[0] += ms
+            v[1] += 1
+    wall = time.perf_counter() - t0
+    lat = np.array(lat) * 1e3
+    print(json.dumps({"metric": "8-DOF short-reach path solves/sec and p50/p99 ms", "queries": nq,
+                      "statuses": [f[0] for f in first], "hits": [None if f[2] is None else f[2]["k"] for f in first],
+                      "rows": [0 if f[1] is None else len(f[1]) for f in first],
+                      "solves_per_s": round(args.plain_steps / wall, 3),
+                      "p50_ms": round(float(np.percentile(lat, 50)), 4), "p99_ms": round(float(np.percentile(lat, 99)), 4),
+                      "kernel_ms_per_query": {k: round(v[0] / args.plain_steps, 4) for k, v in sorted(per_kernel.items())},
+                      "config": {"workload": "8-DOF path workload scenes; target at the middle of segment 3 or 4 of a "
+                                             "drawn valid pose; hit radius 2 voxels over segments 2..4"}}), flush=True)
+
+
 def bench_c5(args):
     """Serving with dynamic obstacles: Poisson arrivals, 70% reach / 30% path, moving
     boxes re-rasterised every 10 ms tick, midcourse replanning; p50/p99 per class."""
@@ -870,7 +921,7 @@ def main():
     ap.add_argument("--arm", choices=["chain", "gms"], default="chain",
                     help="gms: the same workload with the paper's arm model, two DOF per segment (a variant)")
     ap.add_argument("--workload", choices=["c2", "c2serve", "c3", "c4", "c5", "refine", "replan", "guided",
-                                           "posepath"], default="c2",
+                                           "posepath", "short"], default="c2",
                     help="c2: 8-DOF reach + path (default); c2serve: the same queries served under Poisson "
                          "arrivals, one lane vs several; c3: batched reach; c4: batched paths at 512^3; "
                          "c5: serving with moving obstacles")
@@ -942,6 +993,8 @@ def main():
         return bench_c5(args)
     if args.workload in ("guided", "posepath"):
         return bench_guided(args)
+    if args.workload == "short":
+        return bench_short(args)
 
     import torch
 

@@ -249,6 +249,30 @@ msc_status msc_pose_path(msc_ctx* ctx, const msc_scene* scene, const msc_arm* ar
                          const int32_t target[3], const msc_arm* virtual_arm, const msc_track* track,
                          const msc_opts* opts, int32_t* path_out, int32_t* rows_out);
 
+/* Short reaches ("Short Reaches"): as the reach search tests segment hypotheses for
+ * collision along their length, it also tests them for a near encounter with the target.
+ * A hypothesis of segment k (k = 2..segments; segment 1 is the column the first joint only
+ * spins) is a reachable state after joint k-1 and an angle of joint k; it hits the target
+ * at its first sample point within squared distance rho2_vox of the target when every
+ * earlier sample is free and inside the grid.  The shortcut is the hit with the least
+ * path length along the arm (samples * (L_1 + ... + L_{k-1}) + s * L_k, in 1/samples
+ * voxel), then the least squared distance, then the least k, realised by the first joint
+ * prefix in the canonical order (reference 0).  With a hit, the end effector walks the
+ * shortcut back from the target (the hit sample and the earlier samples of segment k,
+ * segments k-1..2 end to start, then the end of segment 1), from each of the first
+ * opts->reach_retries reach poses of msc_reach in turn, as msc_guided_path walks (the
+ * track parameters; the tracked joint is the end effector); without a hit the result is
+ * that of msc_guided_path.  path_out receives the rows (root waypoint pose first, reach
+ * pose last) and *rows_out their number; it must hold (samples * max(segments - 1,
+ * tracked - 1) + 2) * dof values.  hit_out[MSC_MAX_DOF + 3] receives k (0: no hit), the
+ * hit sample s, the length, then the prefix's k joint angles (centidegrees).
+ * Requirements: segments in 2..dof-1, rho2_vox in 0..65535, and ceil(sqrt(rho2_vox)) + 1
+ * no more than the reach of each segment 3..segments+1 (so the pruned search keeps every
+ * hit); else E_ARG.  MSC_NO_REACH / MSC_NO_PATH as msc_guided_path. */
+msc_status msc_short_path(msc_ctx* ctx, const msc_scene* scene, const msc_arm* arm, const int32_t target[3],
+                          int32_t rho2_vox, int32_t segments, const msc_track* track, const msc_opts* opts,
+                          int32_t* path_out, int32_t* rows_out, int32_t* hit_out);
+
 /* Forward-kinematics replay of `count` poses (poses_cdeg[count*dof]) on the GPU:
  * valid_out[i] = 1 if the base is free and every segment sample is inside the grid
  * and free, else 0; end_out[i*3..] = end voxel of the chain (computed even when

@@ -155,6 +155,35 @@ struct RefineArgs {
 hipError_t launch_refine(const RefineArgs& a, const int32_t* q_steps, const double* targets, int64_t count,
                          double* angles, int32_t* status, hipStream_t st);
 
+// Short-reach shortcut ("Short Reaches").  Hit key of a segment hypothesis: path length
+// (1/S voxel) << 40 | squared distance of the hit point << 24 | segment (1-based) << 16.
+struct HitArgs {
+    GridView g;
+    int na;
+    int tx, ty, tz;
+    int rho2;
+    int k;                  // segment (1-based) of the hypotheses
+    long long base_len;     // S * (L_1 + ... + L_{k-1})
+    int len;                // L_k
+};
+// Least hit key over F_{k-1}'s states x joint k's window into *best (atomicMin).
+hipError_t launch_hits(const uint64_t* in, uint64_t count, JointView j, HitArgs h, unsigned long long* best,
+                       hipStream_t st);
+// D_{k-1}: removes from fprev the states of its list with no angle whose hit key is *best.
+hipError_t launch_hit_mark(const uint64_t* in, uint64_t count, SetView fprev, JointView j, HitArgs h,
+                           const unsigned long long* best, hipStream_t st);
+struct HitWalkArgs {
+    SetView D[kMaxDof];     // D_1 .. D_{k-1} (index j)
+    JointView joints[kMaxDof];
+    HitArgs h;
+    int na, bx, by, bz, ia0, ie0;
+    const unsigned long long* best;
+    int32_t* out;           // out: k joint values (steps), then the hit sample s (1-based); s = 0: none
+};
+// The canonical walk from the root into the marked D sets, then the first angle of joint
+// k with the best hit (one wave).
+hipError_t launch_hit_walk(const HitWalkArgs& a, hipStream_t st);
+
 // Waypoint tracking of the workspace-guided paths ("Path Planning", "Smooth sequence
 // computation", "Filtering for smoothness", "Path between Arbitrary Poses").  One block
 // per query walks the waypoints of each candidate solution in turn.
@@ -169,7 +198,10 @@ struct TrackArgs {
     int tracked;                 // the joint that follows the waypoints (1..n)
     int delta, delta2;           // joint box per waypoint, relaxed box after a failure (steps)
     int eps2;                    // squared voxel tolerance at a waypoint
-    int mode;                    // 0: reach-pose-guided, backward; 1: virtual arm, forward from start
+    int mode;                    // 0: reach-pose-guided, backward; 1: virtual arm, forward from start;
+                                 // 2: shortcut, backward from each reach pose along guide[0..guide_k)
+    int guide[kMaxDof];          // mode 2: the shortcut's joint prefix (steps)
+    int guide_k, guide_s;        // mode 2: its segment and hit sample (1-based)
     int vn, vbx, vby, vbz, via0, vie0;
     int vlen[kMaxDof];
     int start[kMaxDof];          // mode 1: the start pose

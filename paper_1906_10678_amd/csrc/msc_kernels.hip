@@ -1613,6 +1613,167 @@ hipError_t launch_pose_check(const PoseArgs& a, const int32_t* q, int64_t count,
 }
 
 // ---------------------------------------------------------------------------
+// Short-reach shortcut ("Short Reaches"): a segment hypothesis (a state of F_{k-1} and an
+// angle of joint k) hits the target at its first sample within rho of the target when
+// every earlier sample is free and in the grid; the shortest hit wins.
+// ---------------------------------------------------------------------------
+// Hit key of one hypothesis from (x, y, z) along orientation o, or ~0 for no hit; *hs
+// receives the hit sample (1-based).
+__device__ __forceinline__ unsigned long long hit_key(const HitArgs& h, const JointView& j, int o, int x, int y,
+                                                      int z, int* hs = nullptr) {
+    const short4* sw = j.sweep + (size_t)o * j.S;
+    for (int s = 0; s < j.S; ++s) {
+        const short4 d = sw[s];
+        const int px = x + d.x, py = y + d.y, pz = z + d.z;
+        if (!cell_free(h.g, px, py, pz)) return ~0ull;
+        const int ex = px - h.tx, ey = py - h.ty, ez = pz - h.tz;
+        const int d2 = ex * ex + ey * ey + ez * ez;
+        if (d2 <= h.rho2) {
+            if (hs) *hs = s + 1;
+            const unsigned long long len = (unsigned long long)(h.base_len + (long long)(s + 1) * h.len);
+            return (len << 40) | ((unsigned long long)d2 << 24) | ((unsigned long long)h.k << 16);
+        }
+    }
+    return ~0ull;
+}
+
+// Orientation after joint j turns (ia, ie) by a.
+__device__ __forceinline__ int turn_o(const JointView& j, int na, int ia, int ie, int a) {
+    if (j.type == 0)
+        ia = wrap_na(ia + a, na);
+    else
+        ie = wrap_na(ie + a, na);
+    return ia * na + ie;
+}
+
+__global__ void __launch_bounds__(kBlock) k_hits(const uint64_t* __restrict__ in, uint64_t count, JointView j,
+                                                 HitArgs h, unsigned long long* best) {
+    const uint32_t nA = (uint32_t)(j.hi - j.lo + 1);
+    unsigned long long mine = ~0ull;
+    const uint64_t total = count * (uint64_t)nA;
+    for (uint64_t idx = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t i = idx / nA;
+        const int a = j.lo + (int)(idx - i * nA);
+        int x, y, z, ia, ie;
+        unpack_key(in[i], x, y, z, ia, ie);
+        if (ia >= h.na || ie >= h.na) continue;
+        const unsigned long long key = hit_key(h, j, turn_o(j, h.na, ia, ie, a), x, y, z);
+        mine = key < mine ? key : mine;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(mine, off, 64);
+        mine = o < mine ? o : mine;
+    }
+    if ((threadIdx.x & 63) == 0 && mine != ~0ull) atomicMin(best, mine);
+}
+
+hipError_t launch_hits(const uint64_t* in, uint64_t count, JointView j, HitArgs h, unsigned long long* best,
+                       hipStream_t st) {
+    const uint64_t work = count * (uint64_t)(j.hi - j.lo + 1);
+    if (work == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_hits, dim3(grid_for(work)), dim3(kBlock), 0, st, in, count, j, h, best);
+    return hipGetLastError();
+}
+
+// One thread per state of the list: kept when some angle gives the best key.
+__global__ void __launch_bounds__(kBlock) k_hit_mark(const uint64_t* __restrict__ in, uint64_t count, SetView fprev,
+                                                     JointView j, HitArgs h, const unsigned long long* best) {
+    const unsigned long long want = *best;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < count;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t key = in[i];
+        int x, y, z, ia, ie;
+        unpack_key(key, x, y, z, ia, ie);
+        bool keep = false;
+        if (ia < h.na && ie < h.na)
+            for (int a = j.lo; a <= j.hi && !keep; ++a)
+                keep = hit_key(h, j, turn_o(j, h.na, ia, ie, a), x, y, z) == want;
+        if (!keep) set_remove(fprev, key);
+    }
+}
+
+hipError_t launch_hit_mark(const uint64_t* in, uint64_t count, SetView fprev, JointView j, HitArgs h,
+                           const unsigned long long* best, hipStream_t st) {
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_hit_mark, dim3(grid_for(count)), dim3(kBlock), 0, st, in, count, fprev, j, h, best);
+    return hipGetLastError();
+}
+
+// One wave: at joint j (0-based) the lanes try the window's angles 64 at a time in the
+// canonical order (|a| then a); the first that steps into D_{j+1} with a clear segment
+// (or, at the hit's joint, gives the best key) is taken.
+__global__ void __launch_bounds__(64) k_hit_walk(HitWalkArgs a) {
+    __shared__ int order[kMaxNa];
+    const int lane = threadIdx.x;
+    const unsigned long long want = *a.best;
+    const int k = (int)((want >> 16) & 0xff);
+    int x = a.bx, y = a.by, z = a.bz, ia = a.ia0, ie = a.ie0;
+    for (int jj = 0; jj < k; ++jj) {
+        const JointView& J = a.joints[jj];
+        if (lane == 0) {
+            // the window in the canonical order: 0, -1, +1, -2, +2, ... inside [lo, hi]
+            const int nw = J.hi - J.lo + 1;
+            int m = 0;
+            if (J.lo <= 0 && 0 <= J.hi) order[m++] = 0;
+            for (int d = 1; m < nw; ++d) {
+                if (-d >= J.lo && -d <= J.hi) order[m++] = -d;
+                if (d >= J.lo && d <= J.hi) order[m++] = d;
+            }
+        }
+        __syncthreads();
+        const int nA = J.hi - J.lo + 1;
+        int pick = -1, pick_s = 0;
+        for (int base = 0; base < nA && pick < 0; base += 64) {
+            const int r = base + lane;
+            bool ok = false;
+            int s_hit = 0;
+            if (r < nA) {
+                const int ang = order[r];
+                const int o = turn_o(J, a.na, ia, ie, ang);
+                if (jj == k - 1) {
+                    ok = hit_key(a.h, J, o, x, y, z, &s_hit) == want;
+                } else {
+                    const short4 d = J.off[o];
+                    const int o_ia = o / a.na, o_ie = o % a.na;
+                    ok = set_member(a.D[jj + 1], pack_key(x + d.x, y + d.y, z + d.z, o_ia, o_ie)) &&
+                         segment_clear_all(a.h.g, J, o, x, y, z);
+                }
+            }
+            const uint64_t bal = __ballot(ok);
+            if (bal) {
+                const int first = __ffsll((long long)bal) - 1;
+                pick = base + first;
+                pick_s = __shfl(s_hit, first, 64);
+            }
+        }
+        if (pick < 0) {
+            if (lane == 0) a.out[kMaxDof] = -1;
+            return;
+        }
+        const int ang = order[pick];
+        const int o = turn_o(J, a.na, ia, ie, ang);
+        if (lane == 0) a.out[jj] = ang;
+        if (jj == k - 1) {
+            if (lane == 0) a.out[kMaxDof] = pick_s;
+            return;
+        }
+        const short4 d = J.off[o];
+        x += d.x;
+        y += d.y;
+        z += d.z;
+        ia = o / a.na;
+        ie = o % a.na;
+        __syncthreads();   // order is rewritten for the next joint
+    }
+}
+
+hipError_t launch_hit_walk(const HitWalkArgs& a, hipStream_t st) {
+    hipLaunchKernelGGL(k_hit_walk, dim3(1), dim3(64), 0, st, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Waypoint tracking ("Smooth sequence computation", "Filtering for smoothness", "Path
 // between Arbitrary Poses").  One block per query, persistent over the waypoints of
 // every candidate solution.  At a waypoint the block scores the joint box of radius d
@@ -1751,19 +1912,23 @@ __device__ void track_body(const TrackArgs& a) {
         a.status[2] = 0;
     }
     for (int i = 0; i < a.nsol; ++i) {
-        const int vn = a.mode == 0 ? n : a.vn;
-        const int32_t* sol = a.sols + (size_t)i * vn;
+        const int width = a.mode == 1 ? a.vn : n;
+        const int32_t* sol = a.sols + (size_t)i * width;
         if (threadIdx.x == 0) {
-            // the solution's sample points, in the order the path visits them
-            const JointView* J = a.mode == 0 ? a.joints : a.vjoints;
-            const int* len = a.mode == 0 ? a.len : a.vlen;
-            int ia = a.mode == 0 ? a.ia0 : a.via0, ie = a.mode == 0 ? a.ie0 : a.vie0;
-            int x = a.mode == 0 ? a.bx : a.vbx, y = a.mode == 0 ? a.by : a.vby, z = a.mode == 0 ? a.bz : a.vbz;
-            for (int k = 0; k < vn; ++k) {
+            // the pose whose sample points are the waypoints: the reach pose (mode 0), the
+            // virtual arm's pose (mode 1) or the shortcut's joint prefix (mode 2)
+            const bool virt = a.mode == 1;
+            const JointView* J = virt ? a.vjoints : a.joints;
+            const int* len = virt ? a.vlen : a.len;
+            const int* src = a.mode == 2 ? a.guide : sol;
+            const int sn = a.mode == 2 ? a.guide_k : width;
+            int ia = virt ? a.via0 : a.ia0, ie = virt ? a.vie0 : a.ie0;
+            int x = virt ? a.vbx : a.bx, y = virt ? a.vby : a.by, z = virt ? a.vbz : a.bz;
+            for (int k = 0; k < sn; ++k) {
                 if (J[k].type == 0)
-                    ia = wrap_na(ia + sol[k], a.na);
+                    ia = wrap_na(ia + src[k], a.na);
                 else
-                    ie = wrap_na(ie + sol[k], a.na);
+                    ie = wrap_na(ie + src[k], a.na);
                 const int o = ia * a.na + ie;
                 seg[4 * k] = o;
                 seg[4 * k + 1] = x;
@@ -1775,22 +1940,25 @@ __device__ void track_body(const TrackArgs& a) {
                 z += off.z;
             }
             int m = 0;
+            auto push = [&](int k, int s) {
+                const short4 d = J[k].sweep[(size_t)seg[4 * k] * J[k].S + s];
+                pts[3 * m] = seg[4 * k + 1] + d.x;
+                pts[3 * m + 1] = seg[4 * k + 2] + d.y;
+                pts[3 * m + 2] = seg[4 * k + 3] + d.z;
+                ++m;
+            };
             if (a.mode == 0) {
                 // segments tracked .. 2 from their ends back to their starts, then the end
                 // of segment 1; the first point (the tracked joint itself) is left out
                 bool first = true;
                 for (int k = a.tracked - 1; k >= 1; --k) {
                     if (len[k] == 0) continue;
-                    const short4* sw = J[k].sweep + (size_t)seg[4 * k] * J[k].S;
                     for (int s = J[k].S - 1; s >= 0; --s) {
                         if (first) {
                             first = false;
                             continue;
                         }
-                        pts[3 * m] = seg[4 * k + 1] + sw[s].x;
-                        pts[3 * m + 1] = seg[4 * k + 2] + sw[s].y;
-                        pts[3 * m + 2] = seg[4 * k + 3] + sw[s].z;
-                        ++m;
+                        push(k, s);
                     }
                 }
                 if (!first) {
@@ -1799,24 +1967,32 @@ __device__ void track_body(const TrackArgs& a) {
                     pts[3 * m + 2] = seg[4 * 1 + 3];
                     ++m;
                 }
-            } else {
-                for (int k = 0; k < vn; ++k) {
+            } else if (a.mode == 1) {
+                for (int k = 0; k < sn; ++k) {
                     if (len[k] == 0) continue;
-                    const short4* sw = J[k].sweep + (size_t)seg[4 * k] * J[k].S;
-                    for (int s = 0; s < J[k].S; ++s) {
-                        pts[3 * m] = seg[4 * k + 1] + sw[s].x;
-                        pts[3 * m + 1] = seg[4 * k + 2] + sw[s].y;
-                        pts[3 * m + 2] = seg[4 * k + 3] + sw[s].z;
-                        ++m;
-                    }
+                    for (int s = 0; s < J[k].S; ++s) push(k, s);
                 }
+            } else {
+                // the shortcut back from the target: the hit sample and the earlier ones of
+                // segment k, segments k-1 .. 2 end to start, then the end of segment 1
+                const int kk = a.guide_k - 1;
+                for (int s = a.guide_s - 1; s >= 0; --s) push(kk, s);
+                for (int k = kk - 1; k >= 1; --k) {
+                    if (len[k] == 0) continue;
+                    for (int s = J[k].S - 1; s >= 0; --s) push(k, s);
+                }
+                pts[3 * m] = seg[4 * 1 + 1];
+                pts[3 * m + 1] = seg[4 * 1 + 2];
+                pts[3 * m + 2] = seg[4 * 1 + 3];
+                ++m;
             }
             npts = m;
         }
-        if (threadIdx.x < n) qc[threadIdx.x] = a.mode == 0 ? sol[threadIdx.x] : a.start[threadIdx.x];
+        const bool backward = a.mode != 1;
+        if (threadIdx.x < n) qc[threadIdx.x] = backward ? sol[threadIdx.x] : a.start[threadIdx.x];
         __syncthreads();
         const int M = npts;
-        if (threadIdx.x < n) a.rows[(size_t)(a.mode == 0 ? M : 0) * n + threadIdx.x] = qc[threadIdx.x];
+        if (threadIdx.x < n) a.rows[(size_t)(backward ? M : 0) * n + threadIdx.x] = qc[threadIdx.x];
         int w = 0;
         for (; w < M; ++w) {
             const int px = pts[3 * w], py = pts[3 * w + 1], pz = pts[3 * w + 2];
@@ -1837,7 +2013,7 @@ __device__ void track_body(const TrackArgs& a) {
                 }
             }
             __syncthreads();
-            const int row = a.mode == 0 ? M - 1 - w : w + 1;
+            const int row = backward ? M - 1 - w : w + 1;
             if (threadIdx.x < n) a.rows[(size_t)row * n + threadIdx.x] = qc[threadIdx.x];
         }
         if (threadIdx.x == 0) a.status[2] = w;

@@ -1539,6 +1539,191 @@ msc_status pose_path_prepare(Lane* c, const msc_scene* sc, const msc_arm* arm, c
     return MSC_OK;
 }
 
+// The short-reach shortcut ("Short Reaches") of plan p on its own forward sets
+// F_0..F_{K-1} (the hit search marks them in place, so they are not the reach search's):
+// *found = 0 without a hit, else q[0..k) (steps), k, the hit sample and the length.
+struct ShortcutHit {
+    int found = 0, k = 0, s = 0;
+    long long length = 0;
+    int q[kMaxDof] = {};
+};
+
+msc_status shortcut_search(Lane* c, const msc_scene* sc, const Plan& p, int K, int rho2, ShortcutHit& hit) {
+    const int n = p.n, na = p.na, N = sc->n;
+    const GridView g = grid_view(sc);
+    hit = ShortcutHit();
+    LAUNCH(MSC_K_FILL, -1, 0, launch_fill((uint64_t*)c->counters, kCounters, 0ull, c->stream));
+    c->ovf = take_counter(c);
+    std::vector<JointView> jv(n);
+    std::vector<int64_t> R(n);
+    for (int k = 0; k < n; ++k) {
+        TableEntry t;
+        MSC_TRY(get_table(c, na, p.S, p.len[k], &t));
+        jv[k] = JointView{t.off, t.sweep, p.type[k], p.lo[k], p.hi[k], p.S};
+        R[k] = isqrt_ceil((int64_t)t.maxn2);
+    }
+    std::vector<StageSet> F(K);
+    {
+        Box b0{p.base[0], p.base[1], p.base[2], 1, 1, 1};
+        MSC_TRY(make_set(c, p, b0, 1, 0, false, F[0]));
+        void* l0;
+        MSC_TRY(arena_alloc(c, 8, &l0));
+        unsigned long long* ctr = take_counter(c);
+        if (!ctr) return fail(c, MSC_E_CAPACITY, "out of counters");
+        LAUNCH(MSC_K_SEED, 0, 0,
+               launch_seed_fwd(F[0].view, g, p.base[0], p.base[1], p.base[2], p.ia0, p.ie0, (uint64_t*)l0, ctr,
+                               c->stream));
+        MSC_TRY(read_counter(c, ctr, &F[0].count));
+        F[0].list = (uint64_t*)l0;
+        F[0].listed = true;
+    }
+    std::vector<long long> r2s(K, -1);
+    for (int k = 1; k < K && F[k - 1].count; ++k) {
+        MSC_TRY(ensure_list(c, F[k - 1]));
+        const uint64_t upper = F[k - 1].count * (uint64_t)(p.hi[k - 1] - p.lo[k - 1] + 1);
+        const int fast = p.type[k] == MSC_YAW ? 1 : 0;
+        MSC_TRY(make_set(c, p, stage_box(p, N, R, k), upper, fast, false, F[k]));
+        int64_t rt = 0;
+        for (int j = k; j < n; ++j) rt += R[j];
+        r2s[k] = p.prune ? (long long)(rt * rt) : -1;
+        unsigned long long* ctr = take_counter(c);
+        if (!ctr) return fail(c, MSC_E_CAPACITY, "out of counters");
+        LAUNCH(MSC_K_EXPAND_FWD, k, (int64_t)F[k - 1].count,
+               launch_expand_fwd(F[k - 1].list, F[k - 1].count, F[k].view, g, jv[k - 1], p.target[0], p.target[1],
+                                 p.target[2], r2s[k], ctr, c->ovf, c->stream,
+                                 shape_for(c, MSC_K_EXPAND_FWD, F[k - 1].count)));
+        MSC_TRY(read_counter(c, ctr, &F[k].count));
+    }
+    MSC_TRY(check_overflow(c, c->ovf, "a stage set of the shortcut search"));
+    for (int k = 1; k < K; ++k)
+        if (F[k].count) MSC_TRY(ensure_list(c, F[k]));
+    // the least hit key over segments 2..K
+    unsigned long long* best = take_counter(c);
+    if (!best) return fail(c, MSC_E_CAPACITY, "out of counters");
+    HIP_TRY(launch_fill((uint64_t*)best, 1, ~0ull, c->stream));
+    std::vector<HitArgs> ha(K + 1);
+    long long base_len = 0;
+    for (int k = 1; k <= K; ++k) {
+        HitArgs& h = ha[k];
+        h = HitArgs{};
+        h.g = g;
+        h.na = na;
+        h.tx = p.target[0];
+        h.ty = p.target[1];
+        h.tz = p.target[2];
+        h.rho2 = rho2;
+        h.k = k;
+        h.base_len = base_len;
+        h.len = p.len[k - 1];
+        base_len += (long long)p.S * p.len[k - 1];
+        if (k >= 2 && F[k - 1].count)
+            LAUNCH(MSC_K_JOIN, k, (int64_t)F[k - 1].count,
+                   launch_hits(F[k - 1].list, F[k - 1].count, jv[k - 1], h, best, c->stream));
+    }
+    uint64_t key = 0;
+    MSC_TRY(read_counter(c, best, &key));
+    if (key == ~0ull) return MSC_OK;
+    const int k = (int)((key >> 16) & 0xff);
+    // D_{k-1}: the states with a best hit; D_{j-1} from D_j back to the root
+    LAUNCH(MSC_K_DMARK, k - 1, (int64_t)F[k - 1].count,
+           launch_hit_mark(F[k - 1].list, F[k - 1].count, F[k - 1].view, jv[k - 1], ha[k], best, c->stream));
+    for (int j = k - 1; j >= 1; --j) {
+        unsigned long long* dc = take_counter(c);
+        if (!dc) return fail(c, MSC_E_CAPACITY, "out of counters");
+        LAUNCH(MSC_K_DMARK, j - 1, (int64_t)F[j - 1].count,
+               launch_dmark(F[j - 1].list, F[j - 1].count, F[j - 1].view, F[j].view, g, jv[j - 1], dc, p.target[0],
+                            p.target[1], p.target[2], r2s[j], c->stream));
+    }
+    HitWalkArgs wa{};
+    for (int j = 1; j < k; ++j) wa.D[j] = F[j].view;
+    for (int j = 0; j < k; ++j) wa.joints[j] = jv[j];
+    wa.h = ha[k];
+    wa.na = na;
+    wa.bx = p.base[0];
+    wa.by = p.base[1];
+    wa.bz = p.base[2];
+    wa.ia0 = p.ia0;
+    wa.ie0 = p.ie0;
+    wa.best = best;
+    void *h_out, *d_out;
+    MSC_TRY(host_area(c, (kMaxDof + 1) * 4, &h_out, &d_out));
+    wa.out = (int32_t*)d_out;
+    LAUNCH(MSC_K_DFS, -1, 0, launch_hit_walk(wa, c->stream));
+    MSC_TRY(sync_lane(c));
+    const volatile int32_t* ho = (const volatile int32_t*)h_out;
+    if (ho[kMaxDof] <= 0) return fail(c, MSC_E_STATE, "the shortcut walk found no move");
+    hit.found = 1;
+    hit.k = k;
+    hit.s = ho[kMaxDof];
+    hit.length = (long long)(key >> 40);
+    for (int j = 0; j < k; ++j) hit.q[j] = ho[j];
+    return MSC_OK;
+}
+
+// Short-reach path: the reach poses, the shortcut, then the end effector's walk back
+// along the shortcut from each reach pose (or, without a hit, the reach-pose-guided walk).
+msc_status short_on(Lane* c, const msc_scene* sc, const msc_arm* arm, const int32_t target[3], int32_t rho2,
+                    int32_t K, const msc_track* tr, const msc_opts* opts, int32_t* path_out, int32_t* rows_out,
+                    int32_t* hit_out) {
+    MSC_TRY(check_scene(c, sc));
+    MSC_TRY(check_arm(c, arm, sc->n));
+    if (!target || !path_out || !rows_out || !hit_out) return fail(c, MSC_E_ARG, "NULL argument");
+    for (int i = 0; i < 3; ++i)
+        if (target[i] < 0 || target[i] >= sc->n) return fail(c, MSC_E_ARG, "target outside the grid");
+    msc_opts o = opts_or_default(opts);
+    if (o.reach_retries < 1 || o.reach_retries > 64 || o.split_m < -1 || o.split_m > arm->dof)
+        return fail(c, MSC_E_ARG, "bad options");
+    const int n = arm->dof;
+    if (K < 2 || K > n - 1) return fail(c, MSC_E_ARG, "shortcut segments outside 2..dof-1");
+    if (rho2 < 0 || rho2 > 65535) return fail(c, MSC_E_ARG, "rho2 outside 0..65535");
+    TrackArgs ta{};
+    MSC_TRY(track_params(c, arm, tr, std::max(1, n - 2), ta));
+    const int fallback_tracked = ta.tracked;
+    const int max_rows = std::max(arm->samples * (K - 1) + 2, arm->samples * (fallback_tracked - 1) + 1);
+    if (max_rows > kTrackMaxPoints) return fail(c, MSC_E_ARG, "more than %d waypoints", kTrackMaxPoints);
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, MSC_E_HIP, "hipSetDevice");
+    begin_call(c);
+    Plan p;
+    make_plan(arm, target, p);
+    p.prune = (o.flags & MSC_NO_PRUNE) ? 0 : 1;
+    p.split = o.split_m;
+    // the pruned forward sets keep every hit when rho + 1 <= R_{k+1} for k = 2..K
+    int64_t rho = 0;
+    while (rho * rho < rho2) ++rho;
+    for (int k = 2; k <= K; ++k) {
+        TableEntry t;
+        MSC_TRY(get_table(c, p.na, p.S, p.len[k], &t));
+        if (rho + 1 > isqrt_ceil((int64_t)t.maxn2))
+            return fail(c, MSC_E_ARG, "rho + 1 exceeds the reach of segment %d", k + 1);
+    }
+    for (int i = 0; i < MSC_MAX_DOF + 3; ++i) hit_out[i] = 0;
+    ReachOut r;
+    msc_status st = run_reach(c, sc, p, o.reach_retries, false, r);
+    if (st != MSC_OK) return st;
+    const msc_stats keep = c->stats;
+    begin_call(c);
+    ShortcutHit hit;
+    MSC_TRY(shortcut_search(c, sc, p, K, rho2, hit));
+    c->stats = keep;
+    begin_call(c);
+    MSC_TRY(track_arm(c, sc, p, ta));
+    if (hit.found) {
+        ta.mode = 2;
+        ta.tracked = n;
+        for (int j = 0; j < hit.k; ++j) ta.guide[j] = hit.q[j];
+        ta.guide_k = hit.k;
+        ta.guide_s = hit.s;
+        hit_out[0] = hit.k;
+        hit_out[1] = hit.s;
+        hit_out[2] = (int32_t)hit.length;
+        for (int j = 0; j < hit.k; ++j) hit_out[3 + j] = hit.q[j] * arm->step_cdeg;
+    } else {
+        ta.mode = 0;
+        ta.tracked = fallback_tracked;
+    }
+    return track_run(c, ta, r.sols, r.nsol, n, max_rows, arm->step_cdeg, path_out, rows_out);
+}
+
 msc_status guided_on(Lane* c, const msc_scene* sc, const msc_arm* arm, const int32_t target[3], const msc_track* tr,
                      const msc_opts* opts, int32_t* path_out, int32_t* rows_out) {
     if (!path_out || !rows_out) return fail(c, MSC_E_ARG, "NULL output");
@@ -2035,6 +2220,17 @@ msc_status msc_guided_path(msc_ctx* o, const msc_scene* sc, const msc_arm* arm, 
     Lane* c = o->control;
     prof_reset(c, opts ? opts->flags : 0u);
     msc_status st = guided_on(c, sc, arm, target, track, opts, path_out, rows_out);
+    prof_finish(c);
+    return st;
+}
+
+msc_status msc_short_path(msc_ctx* o, const msc_scene* sc, const msc_arm* arm, const int32_t target[3],
+                          int32_t rho2_vox, int32_t segments, const msc_track* track, const msc_opts* opts,
+                          int32_t* path_out, int32_t* rows_out, int32_t* hit_out) {
+    if (!o) return MSC_E_ARG;
+    Lane* c = o->control;
+    prof_reset(c, opts ? opts->flags : 0u);
+    msc_status st = short_on(c, sc, arm, target, rho2_vox, segments, track, opts, path_out, rows_out, hit_out);
     prof_finish(c);
     return st;
 }

@@ -33,7 +33,7 @@ EXPORTS = [
     "msc_server_submit", "msc_server_poll", "msc_server_wait", "msc_server_stop", "msc_refine", "msc_replan",
     "msc_scene_bytes_dynamic", "msc_scene_set_dynamic", "msc_server_step", "msc_server_take_replans",
     "msc_refine_static", "msc_refine_static_max", "msc_track_default", "msc_guided_path", "msc_pose_path",
-    "msc_autotune", "msc_tune_load", "msc_tune_entries",
+    "msc_autotune", "msc_tune_load", "msc_tune_entries", "msc_short_path",
 ]
 
 
@@ -125,6 +125,8 @@ def load_library(path: str = LIB_PATH):
     L.msc_guided_path.argtypes = [c_void_p, c_void_p, P(MscArm), P(i32), P(MscTrack), P(MscOpts), P(i32), P(i32)]
     L.msc_pose_path.argtypes = [c_void_p, c_void_p, P(MscArm), P(i32), P(i32), P(MscArm), P(MscTrack), P(MscOpts),
                                 P(i32), P(i32)]
+    L.msc_short_path.argtypes = [c_void_p, c_void_p, P(MscArm), P(i32), i32, i32, P(MscTrack), P(MscOpts), P(i32),
+                                 P(i32), P(i32)]
     L.msc_autotune.argtypes = [c_void_p, P(MscQuery), i32, P(MscOpts), ctypes.c_char_p]
     L.msc_tune_load.argtypes = [c_void_p, ctypes.c_char_p]
     L.msc_tune_entries.argtypes = [c_void_p, P(i32), i32, P(i32)]
@@ -422,6 +424,32 @@ class Solver:
         if rc != OK:
             return rc, None
         return rc, out[:rows.value * a.dof].reshape(rows.value, a.dof) // a.step_cdeg
+
+    def short_path(self, scene: Scene, arm, target: Sequence[int], rho2: int = 4, segments: int = -1,
+                   tracked: int = -1, delta: int = -1, delta2: int = -1, eps2: int = 9, split_m: int = -1,
+                   retries: int = 4, flags: int = 0):
+        """msc_short_path: (status, rows[(M+1), dof] in steps or None, hit or None) with hit =
+        dict(k, s, length, q[k] in steps); segments -1: min(4, dof - 1)."""
+        a = make_arm(arm)
+        K = min(4, a.dof - 1) if segments < 0 else segments
+        t = np.ascontiguousarray(np.asarray(target, np.int32))
+        tr = make_track(a, tracked, delta, delta2, eps2)
+        k2 = a.dof - 2 if tracked < 0 else tracked
+        out = np.zeros((a.samples * max(K - 1, k2 - 1) + 2) * a.dof, np.int32)
+        rows = ctypes.c_int32()
+        hit = np.zeros(MAX_DOF + 3, np.int32)
+        o = make_opts(split_m, 1, 2, retries, flags)
+        rc = self.lib.msc_short_path(self.ctx, scene.handle, ctypes.byref(a), _ptr(t, ctypes.c_int32), int(rho2), K,
+                                     ctypes.byref(tr), ctypes.byref(o), _ptr(out, ctypes.c_int32), ctypes.byref(rows),
+                                     _ptr(hit, ctypes.c_int32))
+        self._check(rc, "msc_short_path")
+        h = None
+        if hit[0] > 0:
+            h = {"k": int(hit[0]), "s": int(hit[1]), "length": int(hit[2]),
+                 "q": hit[3:3 + hit[0]] // a.step_cdeg}
+        if rc != OK:
+            return rc, None, h
+        return rc, out[:rows.value * a.dof].reshape(rows.value, a.dof) // a.step_cdeg, h
 
     def pose_path(self, scene: Scene, arm, start: Sequence[int], target: Sequence[int], virtual_arm,
                   tracked: int = -1, delta: int = -1, delta2: int = -1, eps2: int = 9, split_m: int = -1,
