@@ -21,15 +21,16 @@ Readings of "Discretization of the segment articulations", "The gap in gMS" (eqs
   vector of the global frame except segment 3, the free vector v3 that spans the gap
   from the end p2 of segment 2 to the start p3 = t - L4 r_l of segment 4.  Constraints:
   segment 1's elevation at least e_min1 (upper hemisphere, say); the flexion between
-  consecutive segments at most theta_1, theta_2, theta_3 (u_k . u_{k+1} >= cos theta - 1e-9);
-  segment 4 inside the approach cone (r_l . a >= cos alpha - 1e-9) or, with alpha < 0,
-  every quiver vector; |v3| within eps of L3.
+  consecutive segments at most theta_1, theta_2, theta_3 (u_k . u_{k+1} >= cos theta - 1e-9,
+  for the free vector decided on squares without a square root: see flex_ok); segment 4
+  inside the approach cone (r_l . a >= cos alpha - 1e-9) or, with alpha < 0, every
+  quiver vector; |v3| within eps of L3, decided as (L3 - eps)^2 <= |v3|^2 <= (L3 + eps)^2.
 * Positions stay numerical: p1 = p0 + L1 r_i, p2 = p1 + L2 r_j, component by component,
   one multiply and one add each.  A segment from p along w is clear when its samples
   p + (s / S) w, s = 1..S, rounded per component (halves away from zero, 1e-9 band), are
   inside the grid and free.
-* Pruning (eqs 5-8, widened by eps so that no solution is lost): |p1 - t| <=
-  L2 + L3 + L4 + eps; |p2 - t| <= L3 + L4 + eps.
+* Pruning (eqs 5-8, widened by eps so that no solution is lost): |p1 - t|^2 <=
+  (L2 + L3 + L4 + eps)^2; |p2 - t|^2 <= (L3 + L4 + eps)^2 (bounds squared as b * b).
 * Steps 1, 2A, 2B: survivors of segment 1; then segment 2 from each; then every segment-4
   vector that is clear on its own; a triple (i, j, l) is a solution when all tests pass.
   The reach pose is the first solution in (i, j, l) order.  The exact end point of the
@@ -143,6 +144,27 @@ def _sub(a, b):
     return (a[0] - b[0], a[1] - b[1], a[2] - b[2])
 
 
+def gap_bounds(L3: float, eps: float):
+    """Squared bounds of the free vector's length: |v3| within eps of L3."""
+    lo = max(L3 - eps, 0.0)
+    hi = L3 + eps
+    return lo * lo, hi * hi
+
+
+def flex_ok(dot: float, c: float, n2: float) -> bool:
+    """u . v >= c |v| for a unit u, decided on squares: dot >= 0 and dot^2 >= c^2 |v|^2
+    when c >= 0; dot >= 0 or dot^2 <= c^2 |v|^2 when c < 0."""
+    if c >= 0:
+        return dot >= 0 and dot * dot >= (c * c) * n2
+    return dot >= 0 or dot * dot <= (c * c) * n2
+
+
+def _flex_arr(dot: np.ndarray, c: float, n2: np.ndarray) -> np.ndarray:
+    if c >= 0:
+        return (dot >= 0) & (dot * dot >= (c * c) * n2)
+    return (dot >= 0) | (dot * dot <= (c * c) * n2)
+
+
 def seg4_set(arm: GmsArm, occ, target, Q) -> List[int]:
     """Segment-4 vectors l inside the cone whose segment is clear on its own."""
     L4 = arm.lens[3]
@@ -179,6 +201,8 @@ def solutions_plain(arm: GmsArm, occ, target, prune: bool = True,
     ls = seg4_set(arm, occ, target, Q)
     min_el = math.sin(_rad(arm.seg1_min_el_cdeg / 100.0)) - BAND
     c1, c2, c3 = (_cosl(v) for v in arm.max_flex_cdeg)
+    g_lo, g_hi = gap_bounds(L3, eps)
+    r5, r7 = L2 + L3 + L4 + eps, L3 + L4 + eps
     out = []
     for i, ri in enumerate(Qt):
         if ri[2] < min_el:                                   # joint 1 limit
@@ -186,7 +210,7 @@ def solutions_plain(arm: GmsArm, occ, target, prune: bool = True,
         p1 = _add(p0, L1, ri)
         if prune:
             d = _sub(p1, t)
-            if _dot(d, d) > (L2 + L3 + L4 + eps) ** 2:        # eq 5
+            if _dot(d, d) > r5 * r5:                          # eq 5
                 continue
         if not _clear(occ, p0, (L1 * ri[0], L1 * ri[1], L1 * ri[2]), S):
             continue
@@ -196,7 +220,7 @@ def solutions_plain(arm: GmsArm, occ, target, prune: bool = True,
             p2 = _add(p1, L2, rj)
             if prune:
                 d = _sub(p2, t)
-                if _dot(d, d) > (L3 + L4 + eps) ** 2:         # eq 7
+                if _dot(d, d) > r7 * r7:                      # eq 7
                     continue
             if not _clear(occ, p1, (L2 * rj[0], L2 * rj[1], L2 * rj[2]), S):
                 continue
@@ -204,12 +228,12 @@ def solutions_plain(arm: GmsArm, occ, target, prune: bool = True,
                 rl = Qt[l]
                 p3 = (t[0] - L4 * rl[0], t[1] - L4 * rl[1], t[2] - L4 * rl[2])
                 v3 = _sub(p3, p2)
-                n3 = _norm(v3)
-                if abs(n3 - L3) > eps:                       # the gap's free vector
+                n2 = _dot(v3, v3)
+                if n2 < g_lo or n2 > g_hi:                   # the gap's free vector
                     continue
-                if _dot(rj, v3) < c2 * n3:                   # joint 3 limit
+                if not flex_ok(_dot(rj, v3), c2, n2):        # joint 3 limit
                     continue
-                if _dot(v3, rl) < c3 * n3:                   # joint 4 limit
+                if not flex_ok(_dot(v3, rl), c3, n2):        # joint 4 limit
                     continue
                 if not _clear(occ, p2, v3, S):
                     continue
@@ -263,6 +287,8 @@ def solutions(arm: GmsArm, occ, target, limit: Optional[int] = None) -> List[Tup
     P3 = t[None, :] - L4 * RL
     min_el = math.sin(_rad(arm.seg1_min_el_cdeg / 100.0)) - BAND
     c1, c2, c3 = (_cosl(v) for v in arm.max_flex_cdeg)
+    g_lo, g_hi = gap_bounds(L3, eps)
+    r5, r7 = L2 + L3 + L4 + eps, L3 + L4 + eps
     out = []
     for i in range(len(Q)):
         ri = Q[i]
@@ -270,7 +296,7 @@ def solutions(arm: GmsArm, occ, target, limit: Optional[int] = None) -> List[Tup
             continue
         p1 = p0 + L1 * ri
         d = p1 - t
-        if _dot(d, d) > (L2 + L3 + L4 + eps) ** 2:
+        if _dot(d, d) > r5 * r5:
             continue
         if not _clear_arr(occ, p0[None, :], (L1 * ri)[None, :], S)[0]:
             continue
@@ -279,7 +305,7 @@ def solutions(arm: GmsArm, occ, target, limit: Optional[int] = None) -> List[Tup
         P2 = p1[None, :] + L2 * Q[js]
         d = P2 - t[None, :]
         dd = d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1] + d[:, 2] * d[:, 2]
-        keep = dd <= (L3 + L4 + eps) ** 2
+        keep = dd <= r7 * r7
         js, P2 = js[keep], P2[keep]
         if len(js) == 0:
             continue
@@ -289,10 +315,10 @@ def solutions(arm: GmsArm, occ, target, limit: Optional[int] = None) -> List[Tup
             j, p2 = int(js[jj]), P2[jj]
             rj = Q[j]
             V3 = P3 - p2[None, :]
-            n3 = np.sqrt(V3[:, 0] * V3[:, 0] + V3[:, 1] * V3[:, 1] + V3[:, 2] * V3[:, 2])
-            ok = np.abs(n3 - L3) <= eps
-            ok &= (rj[0] * V3[:, 0] + rj[1] * V3[:, 1] + rj[2] * V3[:, 2]) >= c2 * n3
-            ok &= (V3[:, 0] * RL[:, 0] + V3[:, 1] * RL[:, 1] + V3[:, 2] * RL[:, 2]) >= c3 * n3
+            n2 = V3[:, 0] * V3[:, 0] + V3[:, 1] * V3[:, 1] + V3[:, 2] * V3[:, 2]
+            ok = (n2 >= g_lo) & (n2 <= g_hi)
+            ok &= _flex_arr(rj[0] * V3[:, 0] + rj[1] * V3[:, 1] + rj[2] * V3[:, 2], c2, n2)
+            ok &= _flex_arr(V3[:, 0] * RL[:, 0] + V3[:, 1] * RL[:, 1] + V3[:, 2] * RL[:, 2], c3, n2)
             cand = np.flatnonzero(ok)
             if len(cand) == 0:
                 continue
