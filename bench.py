@@ -890,6 +890,51 @@ def bench_short(args):
                                              "drawn valid pose; hit radius 2 voxels over segments 2..4"}}), flush=True)
 
 
+def bench_gms(args):
+    """The paper's own search (the gap search: 2 degree quiver, about 10^4 vectors;
+    segments 1, 2 and 4 from the quiver, segment 3 the free vector across the gap) on the
+    8-DOF workload's 256^3 scenes and targets: one query per call, all solutions counted
+    and the first 8 in order returned."""
+    import torch
+
+    from paper_1906_10678_amd import msc, synth
+
+    class Arm:
+        lens = [60.0, 50.0, 40.0, 25.0]
+        base = (128, 128, 0)
+        step_cdeg, m_min, samples, seg1_min_el_cdeg = 200, 4, 8, 0
+        max_flex_cdeg = (12000, 12000, 12000)
+        approach = (0, -9000, 4500)
+        eps = 0.5
+
+    solver = msc.Solver(0, workspace_bytes=args.workspace_gb << 30)
+    nq = args.queries
+    items = []
+    for sd in range(nq):
+        q = synth.query_c2(sd, solver.pose_fn_for)
+        items.append((solver.scene(q.scene), q.target))
+    first = [solver.gms_reach(sc, Arm, t, 8) for sc, t in items]
+    torch.cuda.synchronize()
+    lat = []
+    t0 = time.perf_counter()
+    for i in range(args.plain_steps):
+        sc, t = items[i % nq]
+        ts = time.perf_counter()
+        st, cnt, _, _ = solver.gms_reach(sc, Arm, t, 8)
+        lat.append(time.perf_counter() - ts)
+        if cnt != first[i % nq][1]:
+            raise RuntimeError("query %d: solution count changed" % (i % nq))
+    wall = time.perf_counter() - t0
+    lat = np.array(lat) * 1e3
+    print(json.dumps({"metric": "gap-search reach solves/sec and p50/p99 ms (paper's quiver method)", "queries": nq,
+                      "statuses": [f[0] for f in first], "solutions": [f[1] for f in first],
+                      "solves_per_s": round(args.plain_steps / wall, 3),
+                      "p50_ms": round(float(np.percentile(lat, 50)), 4), "p99_ms": round(float(np.percentile(lat, 99)), 4),
+                      "config": {"workload": "2 deg quiver (10313 vectors), segments 60/50/40/25 voxels, flexion limits "
+                                             "120 deg, approach cone 45 deg around straight down, eps 0.5 voxel, "
+                                             "8-DOF path workload scenes and targets (256^3)"}}), flush=True)
+
+
 def bench_c5(args):
     """Serving with dynamic obstacles: Poisson arrivals, 70% reach / 30% path, moving
     boxes re-rasterised every 10 ms tick, midcourse replanning; p50/p99 per class."""
@@ -921,7 +966,7 @@ def main():
     ap.add_argument("--arm", choices=["chain", "gms"], default="chain",
                     help="gms: the same workload with the paper's arm model, two DOF per segment (a variant)")
     ap.add_argument("--workload", choices=["c2", "c2serve", "c3", "c4", "c5", "refine", "replan", "guided",
-                                           "posepath", "short"], default="c2",
+                                           "posepath", "short", "gms"], default="c2",
                     help="c2: 8-DOF reach + path (default); c2serve: the same queries served under Poisson "
                          "arrivals, one lane vs several; c3: batched reach; c4: batched paths at 512^3; "
                          "c5: serving with moving obstacles")
@@ -995,6 +1040,8 @@ def main():
         return bench_guided(args)
     if args.workload == "short":
         return bench_short(args)
+    if args.workload == "gms":
+        return bench_gms(args)
 
     import torch
 

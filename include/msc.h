@@ -273,6 +273,47 @@ msc_status msc_short_path(msc_ctx* ctx, const msc_scene* scene, const msc_arm* a
                           int32_t rho2_vox, int32_t segments, const msc_track* track, const msc_opts* opts,
                           int32_t* path_out, int32_t* rows_out, int32_t* hit_out);
 
+/* The paper's own search ("Discretization of the segment articulations", "The gap in
+ * gMS" eqs 2-8, "The procedure for IK solution" Steps 1-3): a four-segment arm whose
+ * segments 1, 2 and 4 point along vectors of a quiver, an approximately equal-area tiling
+ * of the sphere, and whose segment 3 is a free vector across the gap.
+ *
+ * Quiver of step D = step_cdeg / 100 degrees (D divides 180, n = 360 / D): elevations
+ * e_i = -90 + i D, i = 0..180/D; ring i has 1 vector at a pole, else max(min_ring,
+ * round(n cos e_i)) (halves away from zero, 1e-9 band), azimuths a_ij = (j * 360) / m_i;
+ * vector (cos e cos a, cos e sin a, sin e) in FP64, radians = (degrees * pi) / 180; flat
+ * index = vectors of the rings below + j.
+ *
+ * Search (positions numerical, FP64): p1 = base + L1 r_i, p2 = p1 + L2 r_j, p3 = target -
+ * L4 r_l, v3 = p3 - p2.  (i, j, l) is a solution when: r_i's elevation >= seg1_min_el;
+ * |p1 - t|^2 <= (L2 + L3 + L4 + eps)^2 and |p2 - t|^2 <= (L3 + L4 + eps)^2 (eqs 5-8,
+ * widened by eps); (L3 - eps)^2 <= |v3|^2 <= (L3 + eps)^2; the flexion between
+ * consecutive segment directions is within max_flex_cdeg (u . v >= cos(limit) - 1e-9 |v|,
+ * for v3 decided on squares); r_l inside the approach cone (r_l . a >= cos(half) - 1e-9;
+ * half < 0: any); every segment clear: samples p + (s / samples) w, s = 1..samples,
+ * rounded per component (halves away, 1e-9 band) in the grid and free; base and target
+ * voxels free.  No operation is contracted into a fused multiply-add.
+ * Outputs: *count_out = number of solutions; the first min(want, count) in (i, j, l)
+ * order into sols_out[want*3] and their vectors into vec_out[want*18] (s1, s2, v3, s4,
+ * then the exact s3 = v3 L3 / |v3| and s4' = (t - p2) - s3 of the 8-DOF text);
+ * *nsol_out = how many were written.  MSC_NO_REACH when there is none. */
+typedef struct {
+    double len[4];
+    int32_t base[3];
+    int32_t step_cdeg;
+    int32_t min_ring;
+    int32_t samples;
+    int32_t seg1_min_el_cdeg;
+    int32_t max_flex_cdeg[3];
+    int32_t approach_az_cdeg, approach_el_cdeg, approach_half_cdeg;
+    double eps;
+} msc_gms_arm;
+/* The quiver's vectors (host only): fills min(cap, count) of them into out[cap*3] and
+ * returns the count (0 for a bad step or min_ring < 1). */
+int32_t msc_gms_quiver(int32_t step_cdeg, int32_t min_ring, double* out, int32_t cap);
+msc_status msc_gms_reach(msc_ctx* ctx, const msc_scene* scene, const msc_gms_arm* arm, const int32_t target[3],
+                         int32_t want, int64_t* count_out, int32_t* sols_out, double* vec_out, int32_t* nsol_out);
+
 /* Forward-kinematics replay of `count` poses (poses_cdeg[count*dof]) on the GPU:
  * valid_out[i] = 1 if the base is free and every segment sample is inside the grid
  * and free, else 0; end_out[i*3..] = end voxel of the chain (computed even when

@@ -184,6 +184,36 @@ struct HitWalkArgs {
 // k with the best hit (one wave).
 hipError_t launch_hit_walk(const HitWalkArgs& a, hipStream_t st);
 
+// The paper's gap search ("The gap in gMS"): quiver vectors (FP64, host-built) for
+// segments 1, 2 and 4, a free vector across the gap for segment 3.
+struct GmsArgs {
+    GridView g;
+    const double* Q;        // quiver vectors, 3 per entry
+    int nq;
+    double L1, L2, L3, L4;
+    double p0[3], t[3];
+    double ts[64];          // sample fractions s / S, s = 1..S
+    int S;
+    double min_el;          // sin(least elevation of segment 1) - band
+    double c1, c2, c3;      // cos(flexion limits) - band
+    double ax[3];           // approach axis (unit), cone_c = cos(half) - band; has_cone = 0: none
+    double cone_c;
+    int has_cone;
+    double r5sq, r7sq;      // squared pruning radii (eqs 5-8, widened by eps)
+    double glo, ghi;        // squared bounds of the free vector's length
+};
+// flags1[i] = 1 when quiver vector i is a segment-1 survivor (Step 1); flags4[l] = 1 when
+// it is an admissible, clear segment 4.
+hipError_t launch_gms_flags(const GmsArgs& a, uint8_t* flags1, uint8_t* flags4, hipStream_t st);
+// Steps 2A/2B over (survivor i, quiver j) pairs against the segment-4 list: every
+// solution key i << 40 | j << 20 | l is counted in *count and in per_i[ii] (ii = index of
+// i in s1) and stored (slot < cap); only ii <= max_ii are considered.
+hipError_t launch_gms_pairs(const GmsArgs& a, const int32_t* s1, int n1, const int32_t* s4, int n4,
+                            unsigned long long* count, unsigned int* per_i, uint64_t* keys, uint64_t cap, int max_ii,
+                            hipStream_t st);
+// The vectors of solutions keys[n]: 18 doubles each (s1, s2, v3, s4, s3, s4').
+hipError_t launch_gms_vectors(const GmsArgs& a, const uint64_t* keys, int n, double* out, hipStream_t st);
+
 // Waypoint tracking of the workspace-guided paths ("Path Planning", "Smooth sequence
 // computation", "Filtering for smoothness", "Path between Arbitrary Poses").  One block
 // per query walks the waypoints of each candidate solution in turn.

@@ -1613,6 +1613,155 @@ hipError_t launch_pose_check(const PoseArgs& a, const int32_t* q, int64_t count,
 }
 
 // ---------------------------------------------------------------------------
+// The paper's gap search ("The gap in gMS", "The procedure for IK solution"): arm
+// positions stay numerical (FP64); a segment is tested at its S sample points rounded to
+// voxels.  Every decision is made with the same multiplies and adds, in the same order,
+// as the host-side definition: no contraction into fused multiply-adds, no square root.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ long long gms_round(double v) {
+#pragma clang fp contract(off)
+    const double a = fabs(v);
+    const double f = floor(a);
+    const double frac = a - f;
+    const double r = (frac > 0.5 || fabs(frac - 0.5) <= 1e-9) ? f + 1.0 : f;
+    return v >= 0 ? (long long)r : -(long long)r;
+}
+
+// Segment from p along w: samples p + t_s w clear (in the grid and free).
+__device__ bool gms_clear(const GmsArgs& a, double px, double py, double pz, double wx, double wy, double wz) {
+#pragma clang fp contract(off)
+    for (int s = 0; s < a.S; ++s) {
+        const double t = a.ts[s];
+        const long long x = gms_round(px + t * wx), y = gms_round(py + t * wy), z = gms_round(pz + t * wz);
+        if (x < 0 || y < 0 || z < 0 || x >= a.g.n || y >= a.g.n || z >= a.g.n) return false;
+        if (!cell_free(a.g, (int)x, (int)y, (int)z)) return false;
+    }
+    return true;
+}
+
+__device__ __forceinline__ bool gms_flex(double dot, double c, double n2) {
+#pragma clang fp contract(off)
+    if (c >= 0) return dot >= 0 && dot * dot >= (c * c) * n2;
+    return dot >= 0 || dot * dot <= (c * c) * n2;
+}
+
+__global__ void __launch_bounds__(kBlock) k_gms_flags(GmsArgs a, uint8_t* flags1, uint8_t* flags4) {
+#pragma clang fp contract(off)
+    // the base and the target voxel must be free
+    const bool ends = cell_free(a.g, (int)a.p0[0], (int)a.p0[1], (int)a.p0[2]) &&
+                      cell_free(a.g, (int)a.t[0], (int)a.t[1], (int)a.t[2]);
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < a.nq; q += gridDim.x * blockDim.x) {
+        const double rx = a.Q[3 * q], ry = a.Q[3 * q + 1], rz = a.Q[3 * q + 2];
+        // Step 1: joint-1 limit, eq 5, collision
+        bool ok1 = ends && rz >= a.min_el;
+        if (ok1) {
+            const double x1 = a.p0[0] + a.L1 * rx, y1 = a.p0[1] + a.L1 * ry, z1 = a.p0[2] + a.L1 * rz;
+            const double dx = x1 - a.t[0], dy = y1 - a.t[1], dz = z1 - a.t[2];
+            ok1 = dx * dx + dy * dy + dz * dz <= a.r5sq;
+            ok1 = ok1 && gms_clear(a, a.p0[0], a.p0[1], a.p0[2], a.L1 * rx, a.L1 * ry, a.L1 * rz);
+        }
+        flags1[q] = ok1 ? 1 : 0;
+        // segment 4 backward from the target: inside the cone, clear
+        bool ok4 = ends && (!a.has_cone || rx * a.ax[0] + ry * a.ax[1] + rz * a.ax[2] >= a.cone_c);
+        if (ok4) {
+            const double wx = a.L4 * rx, wy = a.L4 * ry, wz = a.L4 * rz;
+            ok4 = gms_clear(a, a.t[0] - wx, a.t[1] - wy, a.t[2] - wz, wx, wy, wz);
+        }
+        flags4[q] = ok4 ? 1 : 0;
+    }
+}
+
+hipError_t launch_gms_flags(const GmsArgs& a, uint8_t* flags1, uint8_t* flags4, hipStream_t st) {
+    hipLaunchKernelGGL(k_gms_flags, dim3(grid_for((uint64_t)a.nq)), dim3(kBlock), 0, st, a, flags1, flags4);
+    return hipGetLastError();
+}
+
+// One work item per (survivor i, quiver vector j): joint-2 limit, p2, eq 7, segment 2's
+// collision, then the gap to every segment-4 vector of the list.
+__global__ void __launch_bounds__(kBlock) k_gms_pairs(GmsArgs a, const int32_t* __restrict__ s1, int n1,
+                                                      const int32_t* __restrict__ s4, int n4,
+                                                      unsigned long long* count, unsigned int* per_i,
+                                                      uint64_t* keys, uint64_t cap, int max_ii) {
+#pragma clang fp contract(off)
+    const uint64_t total = (uint64_t)min(n1, max_ii + 1) * (uint64_t)a.nq;
+    for (uint64_t idx = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (uint64_t)gridDim.x * blockDim.x) {
+        const int ii = (int)(idx / (uint64_t)a.nq);
+        const int j = (int)(idx - (uint64_t)ii * a.nq);
+        const int i = s1[ii];
+        const double rix = a.Q[3 * i], riy = a.Q[3 * i + 1], riz = a.Q[3 * i + 2];
+        const double rjx = a.Q[3 * j], rjy = a.Q[3 * j + 1], rjz = a.Q[3 * j + 2];
+        if (rix * rjx + riy * rjy + riz * rjz < a.c1) continue;   // joint 2 limit
+        const double x1 = a.p0[0] + a.L1 * rix, y1 = a.p0[1] + a.L1 * riy, z1 = a.p0[2] + a.L1 * riz;
+        const double x2 = x1 + a.L2 * rjx, y2 = y1 + a.L2 * rjy, z2 = z1 + a.L2 * rjz;
+        {
+            const double dx = x2 - a.t[0], dy = y2 - a.t[1], dz = z2 - a.t[2];
+            if (dx * dx + dy * dy + dz * dz > a.r7sq) continue;   // eq 7
+        }
+        if (!gms_clear(a, x1, y1, z1, a.L2 * rjx, a.L2 * rjy, a.L2 * rjz)) continue;
+        for (int ll = 0; ll < n4; ++ll) {
+            const int l = s4[ll];
+            const double rlx = a.Q[3 * l], rly = a.Q[3 * l + 1], rlz = a.Q[3 * l + 2];
+            const double vx = (a.t[0] - a.L4 * rlx) - x2, vy = (a.t[1] - a.L4 * rly) - y2,
+                         vz = (a.t[2] - a.L4 * rlz) - z2;
+            const double n2 = vx * vx + vy * vy + vz * vz;
+            if (n2 < a.glo || n2 > a.ghi) continue;                 // the gap's free vector
+            if (!gms_flex(rjx * vx + rjy * vy + rjz * vz, a.c2, n2)) continue;   // joint 3 limit
+            if (!gms_flex(vx * rlx + vy * rly + vz * rlz, a.c3, n2)) continue;   // joint 4 limit
+            if (!gms_clear(a, x2, y2, z2, vx, vy, vz)) continue;
+            const unsigned long long slot = atomicAdd(count, 1ull);
+            atomicAdd(&per_i[ii], 1u);
+            if (slot < cap) keys[slot] = ((uint64_t)i << 40) | ((uint64_t)j << 20) | (uint64_t)l;
+        }
+    }
+}
+
+hipError_t launch_gms_pairs(const GmsArgs& a, const int32_t* s1, int n1, const int32_t* s4, int n4,
+                            unsigned long long* count, unsigned int* per_i, uint64_t* keys, uint64_t cap, int max_ii,
+                            hipStream_t st) {
+    const uint64_t work = (uint64_t)std::min(n1, max_ii + 1) * (uint64_t)a.nq;
+    if (work == 0 || n4 == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gms_pairs, dim3(grid_for(work, kBlock, 65536)), dim3(kBlock), 0, st, a, s1, n1, s4, n4,
+                       count, per_i, keys, cap, max_ii);
+    return hipGetLastError();
+}
+
+// s1, s2, v3, s4 of a solution and the exact s3 = v3 L3 / |v3|, s4' = (t - p2) - s3.
+__global__ void k_gms_vectors(GmsArgs a, const uint64_t* keys, int n, double* out) {
+#pragma clang fp contract(off)
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const uint64_t key = keys[k];
+    const int i = (int)(key >> 40), j = (int)((key >> 20) & 0xfffff), l = (int)(key & 0xfffff);
+    const double* ri = a.Q + 3 * i;
+    const double* rj = a.Q + 3 * j;
+    const double* rl = a.Q + 3 * l;
+    double* o = out + (size_t)k * 18;
+    double p2[3], v3[3];
+    for (int c = 0; c < 3; ++c) {
+        const double p1 = a.p0[c] + a.L1 * ri[c];
+        p2[c] = p1 + a.L2 * rj[c];
+        v3[c] = (a.t[c] - a.L4 * rl[c]) - p2[c];
+        o[c] = a.L1 * ri[c];
+        o[3 + c] = a.L2 * rj[c];
+        o[6 + c] = v3[c];
+        o[9 + c] = a.L4 * rl[c];
+    }
+    const double n3 = sqrt(v3[0] * v3[0] + v3[1] * v3[1] + v3[2] * v3[2]);
+    for (int c = 0; c < 3; ++c) {
+        const double s3 = v3[c] * a.L3 / n3;
+        o[12 + c] = s3;
+        o[15 + c] = (a.t[c] - p2[c]) - s3;
+    }
+}
+
+hipError_t launch_gms_vectors(const GmsArgs& a, const uint64_t* keys, int n, double* out, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gms_vectors, dim3((n + 63) / 64), dim3(64), 0, st, a, keys, n, out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Short-reach shortcut ("Short Reaches"): a segment hypothesis (a state of F_{k-1} and an
 // angle of joint k) hits the target at its first sample within rho of the target when
 // every earlier sample is free and in the grid; the shortest hit wins.

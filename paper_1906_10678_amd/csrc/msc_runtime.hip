@@ -1660,6 +1660,172 @@ msc_status shortcut_search(Lane* c, const msc_scene* sc, const Plan& p, int K, i
     return MSC_OK;
 }
 
+// ---------------------------------------------------------------------------
+// The paper's gap search: the quiver on the host (FP64, the platform's libm), the
+// search in the gMS kernels.
+// ---------------------------------------------------------------------------
+double gms_rad(double deg) { return (deg * M_PI) / 180.0; }
+
+long long gms_round_host(double v) {
+    const double a = std::fabs(v);
+    const double f = std::floor(a);
+    const double frac = a - f;
+    const double r = (frac > 0.5 || std::fabs(frac - 0.5) <= 1e-9) ? f + 1.0 : f;
+    return v >= 0 ? (long long)r : -(long long)r;
+}
+
+bool build_quiver(int step_cdeg, int min_ring, std::vector<double>& Q) {
+    Q.clear();
+    if (step_cdeg <= 0 || 18000 % step_cdeg || min_ring < 1) return false;
+    const double D = step_cdeg / 100.0;
+    const int n = 36000 / step_cdeg;
+    for (int i = 0; i <= 18000 / step_cdeg; ++i) {
+        const double e = -90.0 + i * D;
+        int m = 1;
+        if (std::fabs(e) != 90.0) m = std::max<long long>(min_ring, gms_round_host(n * std::cos(gms_rad(e))));
+        const double ce = std::cos(gms_rad(e)), se = std::sin(gms_rad(e));
+        for (int j = 0; j < m; ++j) {
+            const double a = (j * 360.0) / m;
+            Q.push_back(ce * std::cos(gms_rad(a)));
+            Q.push_back(ce * std::sin(gms_rad(a)));
+            Q.push_back(se);
+        }
+    }
+    return true;
+}
+
+msc_status gms_on(Lane* c, const msc_scene* sc, const msc_gms_arm* arm, const int32_t target[3], int32_t want,
+                  int64_t* count_out, int32_t* sols_out, double* vec_out, int32_t* nsol_out) {
+    MSC_TRY(check_scene(c, sc));
+    if (!arm || !target || !count_out || !sols_out || !vec_out || !nsol_out) return fail(c, MSC_E_ARG, "NULL argument");
+    if (want < 1) return fail(c, MSC_E_ARG, "want < 1");
+    if (arm->samples < 1 || arm->samples > 64) return fail(c, MSC_E_ARG, "samples outside 1..64");
+    for (int k = 0; k < 4; ++k)
+        if (!(arm->len[k] > 0) || !std::isfinite(arm->len[k])) return fail(c, MSC_E_ARG, "segment length");
+    if (!(arm->eps >= 0) || !std::isfinite(arm->eps)) return fail(c, MSC_E_ARG, "eps");
+    for (int k = 0; k < 3; ++k)
+        if (arm->max_flex_cdeg[k] < 0 || arm->max_flex_cdeg[k] > 18000) return fail(c, MSC_E_ARG, "flexion limit");
+    if (arm->approach_half_cdeg > 18000) return fail(c, MSC_E_ARG, "approach half-angle");
+    for (int i = 0; i < 3; ++i) {
+        if (target[i] < 0 || target[i] >= sc->n) return fail(c, MSC_E_ARG, "target outside the grid");
+        if (arm->base[i] < 0 || arm->base[i] >= sc->n) return fail(c, MSC_E_ARG, "base outside the grid");
+    }
+    std::vector<double> Q;
+    if (!build_quiver(arm->step_cdeg, arm->min_ring, Q)) return fail(c, MSC_E_ARG, "bad quiver step or min_ring");
+    const int nq = (int)(Q.size() / 3);
+    if (nq >= (1 << 20)) return fail(c, MSC_E_ARG, "quiver of 2^20 vectors or more");
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, MSC_E_HIP, "hipSetDevice");
+    begin_call(c);
+    GmsArgs a{};
+    a.g = grid_view(sc);
+    a.nq = nq;
+    a.L1 = arm->len[0];
+    a.L2 = arm->len[1];
+    a.L3 = arm->len[2];
+    a.L4 = arm->len[3];
+    for (int i = 0; i < 3; ++i) {
+        a.p0[i] = (double)arm->base[i];
+        a.t[i] = (double)target[i];
+    }
+    a.S = arm->samples;
+    for (int s = 1; s <= a.S; ++s) a.ts[s - 1] = (double)s / a.S;
+    a.min_el = std::sin(gms_rad(arm->seg1_min_el_cdeg / 100.0)) - 1e-9;
+    a.c1 = std::cos(gms_rad(arm->max_flex_cdeg[0] / 100.0)) - 1e-9;
+    a.c2 = std::cos(gms_rad(arm->max_flex_cdeg[1] / 100.0)) - 1e-9;
+    a.c3 = std::cos(gms_rad(arm->max_flex_cdeg[2] / 100.0)) - 1e-9;
+    a.has_cone = arm->approach_half_cdeg >= 0;
+    if (a.has_cone) {
+        const double az = gms_rad(arm->approach_az_cdeg / 100.0), el = gms_rad(arm->approach_el_cdeg / 100.0);
+        a.ax[0] = std::cos(el) * std::cos(az);
+        a.ax[1] = std::cos(el) * std::sin(az);
+        a.ax[2] = std::sin(el);
+        a.cone_c = std::cos(gms_rad(arm->approach_half_cdeg / 100.0)) - 1e-9;
+    }
+    const double r5 = a.L2 + a.L3 + a.L4 + arm->eps, r7 = a.L3 + a.L4 + arm->eps;
+    a.r5sq = r5 * r5;
+    a.r7sq = r7 * r7;
+    const double glo = std::max(a.L3 - arm->eps, 0.0), ghi = a.L3 + arm->eps;
+    a.glo = glo * glo;
+    a.ghi = ghi * ghi;
+    void *d_q, *d_flags;
+    MSC_TRY(arena_alloc(c, Q.size() * 8, &d_q));
+    HIP_TRY(hipMemcpyAsync(d_q, Q.data(), Q.size() * 8, hipMemcpyHostToDevice, c->stream));
+    a.Q = (const double*)d_q;
+    MSC_TRY(arena_alloc(c, 2 * (uint64_t)nq, &d_flags));
+    LAUNCH(MSC_K_SEED, 0, nq, launch_gms_flags(a, (uint8_t*)d_flags, (uint8_t*)d_flags + nq, c->stream));
+    std::vector<uint8_t> flags(2 * (size_t)nq);
+    HIP_TRY(hipMemcpyAsync(flags.data(), d_flags, flags.size(), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    std::vector<int32_t> s1, s4;
+    for (int q = 0; q < nq; ++q) {
+        if (flags[q]) s1.push_back(q);
+        if (flags[nq + q]) s4.push_back(q);
+    }
+    *count_out = 0;
+    *nsol_out = 0;
+    if (s1.empty() || s4.empty()) return MSC_NO_REACH;
+    void *d_s1, *d_s4, *d_per;
+    MSC_TRY(arena_alloc(c, s1.size() * 4, &d_s1));
+    MSC_TRY(arena_alloc(c, s4.size() * 4, &d_s4));
+    MSC_TRY(arena_alloc(c, s1.size() * 4, &d_per));
+    HIP_TRY(hipMemcpyAsync(d_s1, s1.data(), s1.size() * 4, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(d_s4, s4.data(), s4.size() * 4, hipMemcpyHostToDevice, c->stream));
+    const uint64_t free_bytes = c->hi > c->lo ? c->hi - c->lo : 0;
+    const uint64_t cap = std::min<uint64_t>(4ull << 20, free_bytes / 16);
+    void* d_keys;
+    MSC_TRY(arena_alloc(c, std::max<uint64_t>(cap, 1) * 8, &d_keys));
+    LAUNCH(MSC_K_FILL, -1, 0, launch_fill((uint64_t*)c->counters, kCounters, 0ull, c->stream));
+    auto run = [&](int max_ii, uint64_t& count) -> msc_status {
+        unsigned long long* ctr = take_counter(c);
+        if (!ctr) return fail(c, MSC_E_CAPACITY, "out of counters");
+        LAUNCH(MSC_K_FILL, -1, 0, launch_fill((uint64_t*)d_per, (s1.size() + 1) / 2, 0ull, c->stream));
+        LAUNCH(MSC_K_JOIN, 2, (int64_t)s1.size(),
+               launch_gms_pairs(a, (const int32_t*)d_s1, (int)s1.size(), (const int32_t*)d_s4, (int)s4.size(), ctr,
+                                (unsigned int*)d_per, (uint64_t*)d_keys, cap, max_ii, c->stream));
+        MSC_TRY(read_counter(c, ctr, &count));
+        return MSC_OK;
+    };
+    uint64_t total = 0;
+    MSC_TRY(run((int)s1.size() - 1, total));
+    *count_out = (int64_t)total;
+    if (total == 0) return MSC_NO_REACH;
+    uint64_t stored = total;
+    if (total > cap) {
+        // too many to keep: the solutions of the first survivors that hold the first `want`
+        std::vector<uint32_t> per(s1.size());
+        HIP_TRY(hipMemcpyAsync(per.data(), d_per, per.size() * 4, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        uint64_t acc = 0;
+        int ii0 = 0;
+        for (; ii0 < (int)per.size(); ++ii0) {
+            acc += per[ii0];
+            if (acc >= (uint64_t)want) break;
+        }
+        MSC_TRY(run(ii0, stored));
+        if (stored > cap) return fail(c, MSC_E_CAPACITY, "one segment-1 vector has more than %llu solutions",
+                                      (unsigned long long)cap);
+    }
+    std::vector<uint64_t> keys(stored);
+    HIP_TRY(hipMemcpyAsync(keys.data(), d_keys, stored * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    std::sort(keys.begin(), keys.end());
+    const int nout = (int)std::min<uint64_t>((uint64_t)want, keys.size());
+    void *d_sel, *d_vec;
+    MSC_TRY(arena_alloc(c, (uint64_t)nout * 8, &d_sel));
+    MSC_TRY(arena_alloc(c, (uint64_t)nout * 18 * 8, &d_vec));
+    HIP_TRY(hipMemcpyAsync(d_sel, keys.data(), (size_t)nout * 8, hipMemcpyHostToDevice, c->stream));
+    LAUNCH(MSC_K_REFINE, -1, nout, launch_gms_vectors(a, (const uint64_t*)d_sel, nout, (double*)d_vec, c->stream));
+    HIP_TRY(hipMemcpyAsync(vec_out, d_vec, (size_t)nout * 18 * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (int k = 0; k < nout; ++k) {
+        sols_out[3 * k] = (int32_t)(keys[k] >> 40);
+        sols_out[3 * k + 1] = (int32_t)((keys[k] >> 20) & 0xfffff);
+        sols_out[3 * k + 2] = (int32_t)(keys[k] & 0xfffff);
+    }
+    *nsol_out = nout;
+    return MSC_OK;
+}
+
 // Short-reach path: the reach poses, the shortcut, then the end effector's walk back
 // along the shortcut from each reach pose (or, without a hit, the reach-pose-guided walk).
 msc_status short_on(Lane* c, const msc_scene* sc, const msc_arm* arm, const int32_t target[3], int32_t rho2,
@@ -2231,6 +2397,24 @@ msc_status msc_short_path(msc_ctx* o, const msc_scene* sc, const msc_arm* arm, c
     Lane* c = o->control;
     prof_reset(c, opts ? opts->flags : 0u);
     msc_status st = short_on(c, sc, arm, target, rho2_vox, segments, track, opts, path_out, rows_out, hit_out);
+    prof_finish(c);
+    return st;
+}
+
+int32_t msc_gms_quiver(int32_t step_cdeg, int32_t min_ring, double* out, int32_t cap) {
+    std::vector<double> Q;
+    if (!build_quiver(step_cdeg, min_ring, Q)) return 0;
+    const int32_t n = (int32_t)(Q.size() / 3);
+    if (out && cap > 0) std::memcpy(out, Q.data(), (size_t)std::min(n, cap) * 3 * sizeof(double));
+    return n;
+}
+
+msc_status msc_gms_reach(msc_ctx* o, const msc_scene* sc, const msc_gms_arm* arm, const int32_t target[3],
+                         int32_t want, int64_t* count_out, int32_t* sols_out, double* vec_out, int32_t* nsol_out) {
+    if (!o) return MSC_E_ARG;
+    Lane* c = o->control;
+    prof_reset(c, 0u);
+    msc_status st = gms_on(c, sc, arm, target, want, count_out, sols_out, vec_out, nsol_out);
     prof_finish(c);
     return st;
 }

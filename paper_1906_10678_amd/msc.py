@@ -33,7 +33,7 @@ EXPORTS = [
     "msc_server_submit", "msc_server_poll", "msc_server_wait", "msc_server_stop", "msc_refine", "msc_replan",
     "msc_scene_bytes_dynamic", "msc_scene_set_dynamic", "msc_server_step", "msc_server_take_replans",
     "msc_refine_static", "msc_refine_static_max", "msc_track_default", "msc_guided_path", "msc_pose_path",
-    "msc_autotune", "msc_tune_load", "msc_tune_entries", "msc_short_path",
+    "msc_autotune", "msc_tune_load", "msc_tune_entries", "msc_short_path", "msc_gms_quiver", "msc_gms_reach",
 ]
 
 
@@ -47,6 +47,39 @@ class MscArm(ctypes.Structure):
 class MscTrack(ctypes.Structure):
     _fields_ = [("tracked", ctypes.c_int32), ("max_delta_cdeg", ctypes.c_int32),
                 ("relaxed_delta_cdeg", ctypes.c_int32), ("eps2_vox", ctypes.c_int32)]
+
+
+class MscGmsArm(ctypes.Structure):
+    _fields_ = [("len", ctypes.c_double * 4), ("base", ctypes.c_int32 * 3), ("step_cdeg", ctypes.c_int32),
+                ("min_ring", ctypes.c_int32), ("samples", ctypes.c_int32), ("seg1_min_el_cdeg", ctypes.c_int32),
+                ("max_flex_cdeg", ctypes.c_int32 * 3), ("approach_az_cdeg", ctypes.c_int32),
+                ("approach_el_cdeg", ctypes.c_int32), ("approach_half_cdeg", ctypes.c_int32), ("eps", ctypes.c_double)]
+
+
+def make_gms_arm(arm) -> MscGmsArm:
+    """From an object with lens, base, step_cdeg, m_min, samples, seg1_min_el_cdeg,
+    max_flex_cdeg, approach (None or (az, el, half) cdeg) and eps."""
+    a = MscGmsArm()
+    for k in range(4):
+        a.len[k] = float(arm.lens[k])
+    for i in range(3):
+        a.base[i] = int(arm.base[i])
+        a.max_flex_cdeg[i] = int(arm.max_flex_cdeg[i])
+    a.step_cdeg, a.min_ring, a.samples = arm.step_cdeg, arm.m_min, arm.samples
+    a.seg1_min_el_cdeg = arm.seg1_min_el_cdeg
+    ap = arm.approach
+    a.approach_az_cdeg, a.approach_el_cdeg, a.approach_half_cdeg = (0, 0, -1) if ap is None else tuple(int(v) for v in ap)
+    a.eps = float(arm.eps)
+    return a
+
+
+def gms_quiver(step_cdeg: int, min_ring: int = 4) -> np.ndarray:
+    """The library's quiver (host code, no GPU needed): (count, 3) FP64."""
+    L = load_library()
+    n = L.msc_gms_quiver(step_cdeg, min_ring, None, 0)
+    out = np.zeros((max(n, 1), 3), np.float64)
+    L.msc_gms_quiver(step_cdeg, min_ring, _ptr(out, ctypes.c_double), n)
+    return out[:n]
 
 
 class MscBox(ctypes.Structure):
@@ -127,6 +160,10 @@ def load_library(path: str = LIB_PATH):
                                 P(i32), P(i32)]
     L.msc_short_path.argtypes = [c_void_p, c_void_p, P(MscArm), P(i32), i32, i32, P(MscTrack), P(MscOpts), P(i32),
                                  P(i32), P(i32)]
+    L.msc_gms_quiver.argtypes = [i32, i32, P(ctypes.c_double), i32]
+    L.msc_gms_quiver.restype = i32
+    L.msc_gms_reach.argtypes = [c_void_p, c_void_p, P(MscGmsArm), P(i32), i32, P(i64), P(i32), P(ctypes.c_double),
+                                P(i32)]
     L.msc_autotune.argtypes = [c_void_p, P(MscQuery), i32, P(MscOpts), ctypes.c_char_p]
     L.msc_tune_load.argtypes = [c_void_p, ctypes.c_char_p]
     L.msc_tune_entries.argtypes = [c_void_p, P(i32), i32, P(i32)]
@@ -158,7 +195,7 @@ def load_library(path: str = LIB_PATH):
     for name in EXPORTS:
         if name not in ("msc_opts_default", "msc_scene_bytes", "msc_last_error", "msc_lane_bytes",
                         "msc_query_bytes", "msc_scene_bytes_dynamic", "msc_refine_static_max",
-                        "msc_track_default"):
+                        "msc_track_default", "msc_gms_quiver"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -450,6 +487,21 @@ class Solver:
         if rc != OK:
             return rc, None, h
         return rc, out[:rows.value * a.dof].reshape(rows.value, a.dof) // a.step_cdeg, h
+
+    def gms_reach(self, scene: Scene, arm, target: Sequence[int], want: int = 1):
+        """msc_gms_reach: (status, total solutions, sols[n, 3] (i, j, l), vectors[n, 6, 3])."""
+        a = make_gms_arm(arm)
+        t = np.ascontiguousarray(np.asarray(target, np.int32))
+        cnt = ctypes.c_int64()
+        nsol = ctypes.c_int32()
+        sols = np.zeros(want * 3, np.int32)
+        vec = np.zeros(want * 18, np.float64)
+        rc = self.lib.msc_gms_reach(self.ctx, scene.handle, ctypes.byref(a), _ptr(t, ctypes.c_int32), int(want),
+                                    ctypes.byref(cnt), _ptr(sols, ctypes.c_int32), _ptr(vec, ctypes.c_double),
+                                    ctypes.byref(nsol))
+        self._check(rc, "msc_gms_reach")
+        n = nsol.value
+        return rc, int(cnt.value), sols[:3 * n].reshape(n, 3), vec[:18 * n].reshape(n, 6, 3)
 
     def pose_path(self, scene: Scene, arm, start: Sequence[int], target: Sequence[int], virtual_arm,
                   tracked: int = -1, delta: int = -1, delta2: int = -1, eps2: int = 9, split_m: int = -1,

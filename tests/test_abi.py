@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_1906_10678_amd import msc
@@ -62,7 +63,7 @@ def test_ctypes_layouts_match_a_c_compiler(tmp_path):
     structs = {"msc_arm": msc.MscArm, "msc_box": msc.MscBox, "msc_sphere": msc.MscSphere,
                "msc_opts": msc.MscOpts, "msc_query": msc.MscQuery, "msc_stats": msc.MscStats,
                "msc_timing": msc.MscTiming, "msc_step_report": msc.MscStepReport,
-               "msc_track": msc.MscTrack}
+               "msc_track": msc.MscTrack, "msc_gms_arm": msc.MscGmsArm}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "msc.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
@@ -81,3 +82,13 @@ def test_ctypes_layouts_match_a_c_compiler(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py), cname
         for fname, _ in py._fields_:
             assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
+
+
+@pytest.mark.parametrize("step", [3000, 2000, 1000, 500, 200, 100])
+def test_library_quiver_equals_the_oracles(step):
+    """The gap search's quiver is host code of the library: the same vectors as the
+    oracle's, bit for bit (both evaluate the same FP64 expressions with the platform's
+    libm), without a GPU."""
+    from oracle import gms
+    assert np.array_equal(msc.gms_quiver(step), gms.quiver(step))
+    assert msc.load_library().msc_gms_quiver(7000, 4, None, 0) == 0
