@@ -205,12 +205,24 @@ struct GmsArgs {
 // flags1[i] = 1 when quiver vector i is a segment-1 survivor (Step 1); flags4[l] = 1 when
 // it is an admissible, clear segment 4.
 hipError_t launch_gms_flags(const GmsArgs& a, uint8_t* flags1, uint8_t* flags4, hipStream_t st);
-// Steps 2A/2B over (survivor i, quiver j) pairs against the segment-4 list: every
-// solution key i << 40 | j << 20 | l is counted in *count and in per_i[ii] (ii = index of
-// i in s1) and stored (slot < cap); only ii <= max_ii are considered.
-hipError_t launch_gms_pairs(const GmsArgs& a, const int32_t* s1, int n1, const int32_t* s4, int n4,
-                            unsigned long long* count, unsigned int* per_i, uint64_t* keys, uint64_t cap, int max_ii,
-                            hipStream_t st);
+// The segment-4 list in cluster order (kGmsCluster points per cluster): p3 = t - L4 r_l.
+constexpr int kGmsCluster = 16;
+struct GmsPoint {
+    double x, y, z;
+    int32_t l, pad;
+};
+// A cluster's centre and the squared bounds on |centre - p2| outside which none of its
+// points can pass the gap's length test (lo2 < 0: no lower bound).
+struct GmsCluster {
+    double cx, cy, cz, lo2, hi2, pad;
+};
+hipError_t launch_gms_points(const GmsArgs& a, const int32_t* order, int n4, GmsPoint* pts, hipStream_t st);
+// Steps 2A/2B over (survivor ii, quiver j) pairs, ii <= max_ii, against the clustered
+// segment-4 list: per_i[ii] += the solutions of survivor ii; with store, keys i << 40 |
+// j << 20 | l are written to slots taken from *slots while they are below cap.
+hipError_t launch_gms_pairs(const GmsArgs& a, const int32_t* s1, int n1, const GmsPoint* pts, int n4,
+                            const GmsCluster* cl, int ncl, unsigned long long* slots, unsigned long long* per_i,
+                            uint64_t* keys, uint64_t cap, int max_ii, int store, hipStream_t st);
 // The vectors of solutions keys[n]: 18 doubles each (s1, s2, v3, s4, s3, s4').
 hipError_t launch_gms_vectors(const GmsArgs& a, const uint64_t* keys, int n, double* out, hipStream_t st);
 

@@ -1676,53 +1676,195 @@ hipError_t launch_gms_flags(const GmsArgs& a, uint8_t* flags1, uint8_t* flags4, 
     return hipGetLastError();
 }
 
-// One work item per (survivor i, quiver vector j): joint-2 limit, p2, eq 7, segment 2's
-// collision, then the gap to every segment-4 vector of the list.
-__global__ void __launch_bounds__(kBlock) k_gms_pairs(GmsArgs a, const int32_t* __restrict__ s1, int n1,
-                                                      const int32_t* __restrict__ s4, int n4,
-                                                      unsigned long long* count, unsigned int* per_i,
-                                                      uint64_t* keys, uint64_t cap, int max_ii) {
+// The segment-4 list in cluster order: pts[k] = (t - L4 r_l, l) for l = order[k].
+__global__ void k_gms_points(GmsArgs a, const int32_t* __restrict__ order, int n4, GmsPoint* pts) {
 #pragma clang fp contract(off)
-    const uint64_t total = (uint64_t)min(n1, max_ii + 1) * (uint64_t)a.nq;
-    for (uint64_t idx = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; idx < total;
-         idx += (uint64_t)gridDim.x * blockDim.x) {
-        const int ii = (int)(idx / (uint64_t)a.nq);
-        const int j = (int)(idx - (uint64_t)ii * a.nq);
-        const int i = s1[ii];
-        const double rix = a.Q[3 * i], riy = a.Q[3 * i + 1], riz = a.Q[3 * i + 2];
-        const double rjx = a.Q[3 * j], rjy = a.Q[3 * j + 1], rjz = a.Q[3 * j + 2];
-        if (rix * rjx + riy * rjy + riz * rjz < a.c1) continue;   // joint 2 limit
-        const double x1 = a.p0[0] + a.L1 * rix, y1 = a.p0[1] + a.L1 * riy, z1 = a.p0[2] + a.L1 * riz;
-        const double x2 = x1 + a.L2 * rjx, y2 = y1 + a.L2 * rjy, z2 = z1 + a.L2 * rjz;
-        {
-            const double dx = x2 - a.t[0], dy = y2 - a.t[1], dz = z2 - a.t[2];
-            if (dx * dx + dy * dy + dz * dz > a.r7sq) continue;   // eq 7
-        }
-        if (!gms_clear(a, x1, y1, z1, a.L2 * rjx, a.L2 * rjy, a.L2 * rjz)) continue;
-        for (int ll = 0; ll < n4; ++ll) {
-            const int l = s4[ll];
-            const double rlx = a.Q[3 * l], rly = a.Q[3 * l + 1], rlz = a.Q[3 * l + 2];
-            const double vx = (a.t[0] - a.L4 * rlx) - x2, vy = (a.t[1] - a.L4 * rly) - y2,
-                         vz = (a.t[2] - a.L4 * rlz) - z2;
-            const double n2 = vx * vx + vy * vy + vz * vz;
-            if (n2 < a.glo || n2 > a.ghi) continue;                 // the gap's free vector
-            if (!gms_flex(rjx * vx + rjy * vy + rjz * vz, a.c2, n2)) continue;   // joint 3 limit
-            if (!gms_flex(vx * rlx + vy * rly + vz * rlz, a.c3, n2)) continue;   // joint 4 limit
-            if (!gms_clear(a, x2, y2, z2, vx, vy, vz)) continue;
-            const unsigned long long slot = atomicAdd(count, 1ull);
-            atomicAdd(&per_i[ii], 1u);
-            if (slot < cap) keys[slot] = ((uint64_t)i << 40) | ((uint64_t)j << 20) | (uint64_t)l;
-        }
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n4) return;
+    const int l = order[k];
+    GmsPoint p;
+    p.x = a.t[0] - a.L4 * a.Q[3 * l];
+    p.y = a.t[1] - a.L4 * a.Q[3 * l + 1];
+    p.z = a.t[2] - a.L4 * a.Q[3 * l + 2];
+    p.l = l;
+    p.pad = 0;
+    pts[k] = p;
+}
+
+hipError_t launch_gms_points(const GmsArgs& a, const int32_t* order, int n4, GmsPoint* pts, hipStream_t st) {
+    if (n4 <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gms_points, dim3((n4 + 255) / 256), dim3(256), 0, st, a, order, n4, pts);
+    return hipGetLastError();
+}
+
+// Candidates of one wave that passed the free vector's length and flexion tests, waiting
+// for segment 3's sample test: at most 63 wait between drains and 64 arrive per pass.
+struct GmsQueue {
+    double px[128], py[128], pz[128], vx[128], vy[128], vz[128];
+    uint64_t key[128];
+    int32_t ii[128];
+};
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Segment 3's samples for queue entries [start, start + n), one per lane; the solutions
+// are counted per survivor and, while there is room, their keys stored.
+__device__ void gms_drain(const GmsArgs& a, GmsQueue& q, int start, int n, int lane, unsigned long long* slots,
+                          unsigned long long* per_i, uint64_t* keys, uint64_t cap, bool& room) {
+    wave_sync();
+    bool sol = false;
+    int ii = -1;
+    uint64_t key = 0;
+    if (lane < n) {
+        const int e = start + lane;
+        ii = q.ii[e];
+        key = q.key[e];
+        sol = gms_clear(a, q.px[e], q.py[e], q.pz[e], q.vx[e], q.vy[e], q.vz[e]);
+    }
+    wave_sync();
+    const unsigned long long got = __ballot(sol);
+    for (unsigned long long todo = got; todo;) {
+        const int x = __shfl(ii, __ffsll((long long)todo) - 1, 64);
+        const unsigned long long same = __ballot(sol && ii == x);
+        if (lane == 0) atomicAdd(&per_i[x], (unsigned long long)__popcll(same));
+        todo &= ~same;
+    }
+    if (room && got) {
+        unsigned long long first = 0;
+        if (lane == 0) first = atomicAdd(slots, (unsigned long long)__popcll(got));
+        first = __shfl(first, 0, 64);
+        if (first >= cap) room = false;
+        const uint64_t slot = first + (uint64_t)__popcll(got & ((1ull << lane) - 1));
+        if (sol && slot < cap) keys[slot] = key;
     }
 }
 
-hipError_t launch_gms_pairs(const GmsArgs& a, const int32_t* s1, int n1, const int32_t* s4, int n4,
-                            unsigned long long* count, unsigned int* per_i, uint64_t* keys, uint64_t cap, int max_ii,
-                            hipStream_t st) {
+// Steps 2A/2B.  Each lane of a wave first tests one (survivor ii, quiver vector j) pair:
+// joint-2 limit, p2, eq 7, segment 2's samples.  The wave then takes its surviving pairs
+// one at a time, all 64 lanes over the segment-4 list: a lane tests one cluster of
+// kGmsCluster points against the pair's p2 (the cluster's bounds on |p3 - p2|, widened,
+// against the gap's length: a skipped cluster holds no point that passes the exact test),
+// then four kept clusters are taken per pass, one point per lane, with the exact tests of
+// the free vector's length and the joint 3 and 4 limits (on squares).  Candidates that
+// pass wait in the wave's queue in LDS; 64 at a time take segment 3's sample test, so
+// that the longest test runs on full waves.  Solutions are counted per survivor from the
+// wave's ballots; the wave reserves key slots with one atomic per ballot until the key
+// array is full.
+__global__ void __launch_bounds__(kBlock) k_gms_pairs(GmsArgs a, const int32_t* __restrict__ s1, int n1,
+                                                      const GmsPoint* __restrict__ pts, int n4,
+                                                      const GmsCluster* __restrict__ cl, int ncl,
+                                                      unsigned long long* slots, unsigned long long* per_i,
+                                                      uint64_t* keys, uint64_t cap, int max_ii, int store) {
+#pragma clang fp contract(off)
+    __shared__ GmsQueue queues[kBlock / 64];
+    const int lane = threadIdx.x & 63;
+    GmsQueue& q = queues[threadIdx.x >> 6];
+    int qn = 0;
+    const uint64_t total = (uint64_t)min(n1, max_ii + 1) * (uint64_t)a.nq;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    bool room = store != 0;
+    for (uint64_t base = blockIdx.x * (uint64_t)blockDim.x + (threadIdx.x - lane); base < total; base += stride) {
+        const uint64_t idx = base + lane;
+        bool live = idx < total;
+        int ii = 0, j = 0;
+        double x2 = 0, y2 = 0, z2 = 0, rjx = 0, rjy = 0, rjz = 0;
+        if (live) {
+            ii = (int)(idx / (uint64_t)a.nq);
+            j = (int)(idx - (uint64_t)ii * a.nq);
+            const int i = s1[ii];
+            const double rix = a.Q[3 * i], riy = a.Q[3 * i + 1], riz = a.Q[3 * i + 2];
+            rjx = a.Q[3 * j];
+            rjy = a.Q[3 * j + 1];
+            rjz = a.Q[3 * j + 2];
+            live = rix * rjx + riy * rjy + riz * rjz >= a.c1;    // joint 2 limit
+            if (live) {
+                const double x1 = a.p0[0] + a.L1 * rix, y1 = a.p0[1] + a.L1 * riy, z1 = a.p0[2] + a.L1 * riz;
+                x2 = x1 + a.L2 * rjx;
+                y2 = y1 + a.L2 * rjy;
+                z2 = z1 + a.L2 * rjz;
+                const double dx = x2 - a.t[0], dy = y2 - a.t[1], dz = z2 - a.t[2];
+                live = dx * dx + dy * dy + dz * dz <= a.r7sq;       // eq 7
+                live = live && gms_clear(a, x1, y1, z1, a.L2 * rjx, a.L2 * rjy, a.L2 * rjz);
+            }
+        }
+        unsigned long long pending = __ballot(live);
+        while (pending) {
+            const int src = __ffsll((long long)pending) - 1;
+            pending &= pending - 1;
+            const double px = __shfl(x2, src, 64), py = __shfl(y2, src, 64), pz = __shfl(z2, src, 64);
+            const double ux = __shfl(rjx, src, 64), uy = __shfl(rjy, src, 64), uz = __shfl(rjz, src, 64);
+            const int pii = __shfl(ii, src, 64), pj = __shfl(j, src, 64);
+            const uint64_t pkey = ((uint64_t)s1[pii] << 40) | ((uint64_t)pj << 20);
+            for (int c0 = 0; c0 < ncl; c0 += 64) {
+                bool keep = false;
+                if (c0 + lane < ncl) {
+                    const GmsCluster& C = cl[c0 + lane];
+                    const double dx = C.cx - px, dy = C.cy - py, dz = C.cz - pz;
+                    const double d2 = dx * dx + dy * dy + dz * dz;
+                    keep = d2 >= C.lo2 && d2 <= C.hi2;
+                }
+                unsigned long long kept = __ballot(keep);
+                while (kept) {
+                    // up to four kept clusters, one per quarter of the wave
+                    int pick = -1;
+                    for (int r = 0; r < 4 && kept; ++r) {
+                        const int b = __ffsll((long long)kept) - 1;
+                        kept &= kept - 1;
+                        if ((lane >> 4) == r) pick = b;
+                    }
+                    bool cand = false;
+                    double vx = 0, vy = 0, vz = 0;
+                    int l = 0;
+                    const int k = (c0 + pick) * kGmsCluster + (lane & (kGmsCluster - 1));
+                    if (pick >= 0 && k < n4) {
+                        const GmsPoint P = pts[k];
+                        vx = P.x - px;
+                        vy = P.y - py;
+                        vz = P.z - pz;
+                        const double n2 = vx * vx + vy * vy + vz * vz;
+                        if (n2 >= a.glo && n2 <= a.ghi) {                    // the gap's free vector
+                            l = P.l;
+                            const double rlx = a.Q[3 * l], rly = a.Q[3 * l + 1], rlz = a.Q[3 * l + 2];
+                            cand = gms_flex(ux * vx + uy * vy + uz * vz, a.c2, n2) &&     // joint 3 limit
+                                   gms_flex(vx * rlx + vy * rly + vz * rlz, a.c3, n2);    // joint 4 limit
+                        }
+                    }
+                    const unsigned long long cm = __ballot(cand);
+                    if (cm) {
+                        if (cand) {
+                            const int e = qn + __popcll(cm & ((1ull << lane) - 1));
+                            q.px[e] = px;
+                            q.py[e] = py;
+                            q.pz[e] = pz;
+                            q.vx[e] = vx;
+                            q.vy[e] = vy;
+                            q.vz[e] = vz;
+                            q.key[e] = pkey | (uint64_t)l;
+                            q.ii[e] = pii;
+                        }
+                        qn += __popcll(cm);
+                        if (qn >= 64) {
+                            qn -= 64;
+                            gms_drain(a, q, qn, 64, lane, slots, per_i, keys, cap, room);
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if (qn > 0) gms_drain(a, q, 0, qn, lane, slots, per_i, keys, cap, room);
+}
+
+hipError_t launch_gms_pairs(const GmsArgs& a, const int32_t* s1, int n1, const GmsPoint* pts, int n4,
+                            const GmsCluster* cl, int ncl, unsigned long long* slots, unsigned long long* per_i,
+                            uint64_t* keys, uint64_t cap, int max_ii, int store, hipStream_t st) {
     const uint64_t work = (uint64_t)std::min(n1, max_ii + 1) * (uint64_t)a.nq;
     if (work == 0 || n4 == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gms_pairs, dim3(grid_for(work, kBlock, 65536)), dim3(kBlock), 0, st, a, s1, n1, s4, n4,
-                       count, per_i, keys, cap, max_ii);
+    hipLaunchKernelGGL(k_gms_pairs, dim3(grid_for(work, kBlock, 65536)), dim3(kBlock), 0, st, a, s1, n1, pts, n4, cl,
+                       ncl, slots, per_i, keys, cap, max_ii, store);
     return hipGetLastError();
 }
 

@@ -1764,47 +1764,106 @@ msc_status gms_on(Lane* c, const msc_scene* sc, const msc_gms_arm* arm, const in
     *count_out = 0;
     *nsol_out = 0;
     if (s1.empty() || s4.empty()) return MSC_NO_REACH;
-    void *d_s1, *d_s4, *d_per;
+    // Segment 4 in spatially compact clusters: p3 = t - L4 r_l sorted along a Morton curve
+    // and cut into groups of kGmsCluster.  Centres and radii are host estimates; the
+    // skip bounds are widened by a margin far above any rounding difference.
+    const int n4 = (int)s4.size();
+    std::vector<double> P(3 * (size_t)n4);
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int k = 0; k < n4; ++k)
+        for (int d = 0; d < 3; ++d) {
+            P[3 * k + d] = a.t[d] - a.L4 * Q[3 * (size_t)s4[k] + d];
+            lo[d] = std::min(lo[d], P[3 * k + d]);
+            hi[d] = std::max(hi[d], P[3 * k + d]);
+        }
+    auto morton = [&](int k) {
+        uint64_t code = 0;
+        for (int d = 0; d < 3; ++d) {
+            const double span = hi[d] - lo[d];
+            const uint64_t q = span > 0 ? (uint64_t)std::min(1023.0, (P[3 * k + d] - lo[d]) / span * 1023.0) : 0;
+            for (int b = 0; b < 10; ++b) code |= ((q >> b) & 1ull) << (3 * b + d);
+        }
+        return code;
+    };
+    std::vector<std::pair<uint64_t, int>> mk(n4);
+    for (int k = 0; k < n4; ++k) mk[k] = {morton(k), k};
+    std::sort(mk.begin(), mk.end());
+    std::vector<int32_t> order(n4);
+    for (int k = 0; k < n4; ++k) order[k] = s4[mk[k].second];
+    const int ncl = (n4 + kGmsCluster - 1) / kGmsCluster;
+    std::vector<GmsCluster> cls(ncl);
+    const double margin = 1e-6 * (1.0 + a.L3 + a.L4);
+    const double rlo = std::sqrt(a.glo), rhi = std::sqrt(a.ghi);
+    for (int c0 = 0; c0 < ncl; ++c0) {
+        const int b = c0 * kGmsCluster, e = std::min(n4, b + kGmsCluster);
+        double ctr[3] = {0, 0, 0};
+        for (int k = b; k < e; ++k)
+            for (int d = 0; d < 3; ++d) ctr[d] += P[3 * (size_t)mk[k].second + d];
+        for (int d = 0; d < 3; ++d) ctr[d] /= (e - b);
+        double rad = 0;
+        for (int k = b; k < e; ++k) {
+            double r2 = 0;
+            for (int d = 0; d < 3; ++d) {
+                const double u = P[3 * (size_t)mk[k].second + d] - ctr[d];
+                r2 += u * u;
+            }
+            rad = std::max(rad, std::sqrt(r2));
+        }
+        const double inner = rlo - rad - margin, outer = rhi + rad + margin;
+        cls[c0] = GmsCluster{ctr[0], ctr[1], ctr[2], inner > 0 ? inner * inner : -1.0, outer * outer, 0.0};
+    }
+    void *d_s1, *d_order, *d_pts, *d_cl, *d_per;
     MSC_TRY(arena_alloc(c, s1.size() * 4, &d_s1));
-    MSC_TRY(arena_alloc(c, s4.size() * 4, &d_s4));
-    MSC_TRY(arena_alloc(c, s1.size() * 4, &d_per));
+    MSC_TRY(arena_alloc(c, (uint64_t)n4 * 4, &d_order));
+    MSC_TRY(arena_alloc(c, (uint64_t)n4 * sizeof(GmsPoint), &d_pts));
+    MSC_TRY(arena_alloc(c, (uint64_t)ncl * sizeof(GmsCluster), &d_cl));
+    MSC_TRY(arena_alloc(c, s1.size() * 8, &d_per));
     HIP_TRY(hipMemcpyAsync(d_s1, s1.data(), s1.size() * 4, hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(hipMemcpyAsync(d_s4, s4.data(), s4.size() * 4, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(d_order, order.data(), (size_t)n4 * 4, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(d_cl, cls.data(), (size_t)ncl * sizeof(GmsCluster), hipMemcpyHostToDevice, c->stream));
+    LAUNCH(MSC_K_SEED, 1, n4, launch_gms_points(a, (const int32_t*)d_order, n4, (GmsPoint*)d_pts, c->stream));
     const uint64_t free_bytes = c->hi > c->lo ? c->hi - c->lo : 0;
     const uint64_t cap = std::min<uint64_t>(4ull << 20, free_bytes / 16);
     void* d_keys;
     MSC_TRY(arena_alloc(c, std::max<uint64_t>(cap, 1) * 8, &d_keys));
     LAUNCH(MSC_K_FILL, -1, 0, launch_fill((uint64_t*)c->counters, kCounters, 0ull, c->stream));
-    auto run = [&](int max_ii, uint64_t& count) -> msc_status {
+    std::vector<unsigned long long> per(s1.size());
+    // one pass over the survivors 0..max_ii: per[] filled, *slots = keys reserved
+    auto run = [&](int max_ii, uint64_t& slots) -> msc_status {
         unsigned long long* ctr = take_counter(c);
         if (!ctr) return fail(c, MSC_E_CAPACITY, "out of counters");
-        LAUNCH(MSC_K_FILL, -1, 0, launch_fill((uint64_t*)d_per, (s1.size() + 1) / 2, 0ull, c->stream));
+        LAUNCH(MSC_K_FILL, -1, 0, launch_fill((uint64_t*)d_per, s1.size(), 0ull, c->stream));
         LAUNCH(MSC_K_JOIN, 2, (int64_t)s1.size(),
-               launch_gms_pairs(a, (const int32_t*)d_s1, (int)s1.size(), (const int32_t*)d_s4, (int)s4.size(), ctr,
-                                (unsigned int*)d_per, (uint64_t*)d_keys, cap, max_ii, c->stream));
-        MSC_TRY(read_counter(c, ctr, &count));
+               launch_gms_pairs(a, (const int32_t*)d_s1, (int)s1.size(), (const GmsPoint*)d_pts, n4,
+                                (const GmsCluster*)d_cl, ncl, ctr, (unsigned long long*)d_per, (uint64_t*)d_keys, cap,
+                                max_ii, 1, c->stream));
+        HIP_TRY(hipMemcpyAsync(per.data(), d_per, per.size() * 8, hipMemcpyDeviceToHost, c->stream));
+        MSC_TRY(read_counter(c, ctr, &slots));
+        HIP_TRY(hipStreamSynchronize(c->stream));
         return MSC_OK;
     };
+    uint64_t slots = 0;
+    MSC_TRY(run((int)s1.size() - 1, slots));
     uint64_t total = 0;
-    MSC_TRY(run((int)s1.size() - 1, total));
+    for (unsigned long long v : per) total += v;
     *count_out = (int64_t)total;
     if (total == 0) return MSC_NO_REACH;
     uint64_t stored = total;
     if (total > cap) {
         // too many to keep: the solutions of the first survivors that hold the first `want`
-        std::vector<uint32_t> per(s1.size());
-        HIP_TRY(hipMemcpyAsync(per.data(), d_per, per.size() * 4, hipMemcpyDeviceToHost, c->stream));
-        HIP_TRY(hipStreamSynchronize(c->stream));
         uint64_t acc = 0;
         int ii0 = 0;
         for (; ii0 < (int)per.size(); ++ii0) {
             acc += per[ii0];
             if (acc >= (uint64_t)want) break;
         }
-        MSC_TRY(run(ii0, stored));
-        if (stored > cap) return fail(c, MSC_E_CAPACITY, "one segment-1 vector has more than %llu solutions",
-                                      (unsigned long long)cap);
+        if (acc > cap) return fail(c, MSC_E_CAPACITY, "the first segment-1 vectors hold more than %llu solutions",
+                                   (unsigned long long)cap);
+        MSC_TRY(run(ii0, slots));
+        stored = acc;
     }
+    if (slots != stored) return fail(c, MSC_E_STATE, "gap search: %llu keys stored, %llu counted",
+                                     (unsigned long long)slots, (unsigned long long)stored);
     std::vector<uint64_t> keys(stored);
     HIP_TRY(hipMemcpyAsync(keys.data(), d_keys, stored * 8, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
