@@ -313,6 +313,15 @@ typedef struct {
 int32_t msc_gms_quiver(int32_t step_cdeg, int32_t min_ring, double* out, int32_t cap);
 msc_status msc_gms_reach(msc_ctx* ctx, const msc_scene* scene, const msc_gms_arm* arm, const int32_t target[3],
                          int32_t want, int64_t* count_out, int32_t* sols_out, double* vec_out, int32_t* nsol_out);
+/* The same search when only the first solutions are wanted (the reach pose of Step 3 is
+ * the first): the segment-1 survivors are searched in order, in chunks (the first of
+ * about 4*2^20 (survivor, segment-2 vector) pairs, each next one twice the last), and the
+ * search stops after the chunk in which the solutions found reach `want`.  The outputs are those of msc_gms_reach (the same first
+ * min(want, total) solutions, vectors and status), except that *count_out is the number
+ * of solutions of the survivors searched, between min(want, total) and total. */
+msc_status msc_gms_reach_first(msc_ctx* ctx, const msc_scene* scene, const msc_gms_arm* arm, const int32_t target[3],
+                               int32_t want, int64_t* count_out, int32_t* sols_out, double* vec_out,
+                               int32_t* nsol_out);
 
 /* Forward-kinematics replay of `count` poses (poses_cdeg[count*dof]) on the GPU:
  * valid_out[i] = 1 if the base is free and every segment sample is inside the grid

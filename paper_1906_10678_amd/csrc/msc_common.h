@@ -217,12 +217,12 @@ struct GmsCluster {
     double cx, cy, cz, lo2, hi2, pad;
 };
 hipError_t launch_gms_points(const GmsArgs& a, const int32_t* order, int n4, GmsPoint* pts, hipStream_t st);
-// Steps 2A/2B over (survivor ii, quiver j) pairs, ii <= max_ii, against the clustered
-// segment-4 list: per_i[ii] += the solutions of survivor ii; with store, keys i << 40 |
-// j << 20 | l are written to slots taken from *slots while they are below cap.
+// Steps 2A/2B over (survivor ii, quiver j) pairs, min_ii <= ii <= max_ii, against the
+// clustered segment-4 list: per_i[ii] += the solutions of survivor ii; with store, keys
+// i << 40 | j << 20 | l are written to slots taken from *slots while they are below cap.
 hipError_t launch_gms_pairs(const GmsArgs& a, const int32_t* s1, int n1, const GmsPoint* pts, int n4,
                             const GmsCluster* cl, int ncl, unsigned long long* slots, unsigned long long* per_i,
-                            uint64_t* keys, uint64_t cap, int max_ii, int store, hipStream_t st);
+                            uint64_t* keys, uint64_t cap, int min_ii, int max_ii, int store, hipStream_t st);
 // The vectors of solutions keys[n]: 18 doubles each (s1, s2, v3, s4, s3, s4').
 hipError_t launch_gms_vectors(const GmsArgs& a, const uint64_t* keys, int n, double* out, hipStream_t st);
 

@@ -973,6 +973,7 @@ __global__ void __launch_bounds__(kBlock) k_compact(SetView s, uint64_t* list, u
 #pragma unroll
             for (int j = 0; j < kCompactWords; ++j) {
                 const uint64_t w = wv[j];
+                if (__ballot(w != 0) == 0) continue;   // nothing in this round
                 const unsigned int cj = (unsigned int)__popcll(w);
                 unsigned int ij = cj;
                 for (int off = 1; off < 64; off <<= 1) {
@@ -1757,13 +1758,14 @@ __global__ void __launch_bounds__(kBlock) k_gms_pairs(GmsArgs a, const int32_t* 
                                                       const GmsPoint* __restrict__ pts, int n4,
                                                       const GmsCluster* __restrict__ cl, int ncl,
                                                       unsigned long long* slots, unsigned long long* per_i,
-                                                      uint64_t* keys, uint64_t cap, int max_ii, int store) {
+                                                      uint64_t* keys, uint64_t cap, int min_ii, int max_ii,
+                                                      int store) {
 #pragma clang fp contract(off)
     __shared__ GmsQueue queues[kBlock / 64];
     const int lane = threadIdx.x & 63;
     GmsQueue& q = queues[threadIdx.x >> 6];
     int qn = 0;
-    const uint64_t total = (uint64_t)min(n1, max_ii + 1) * (uint64_t)a.nq;
+    const uint64_t total = (uint64_t)(min(n1, max_ii + 1) - min_ii) * (uint64_t)a.nq;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     bool room = store != 0;
     for (uint64_t base = blockIdx.x * (uint64_t)blockDim.x + (threadIdx.x - lane); base < total; base += stride) {
@@ -1772,8 +1774,9 @@ __global__ void __launch_bounds__(kBlock) k_gms_pairs(GmsArgs a, const int32_t* 
         int ii = 0, j = 0;
         double x2 = 0, y2 = 0, z2 = 0, rjx = 0, rjy = 0, rjz = 0;
         if (live) {
-            ii = (int)(idx / (uint64_t)a.nq);
-            j = (int)(idx - (uint64_t)ii * a.nq);
+            const int di = (int)(idx / (uint64_t)a.nq);
+            j = (int)(idx - (uint64_t)di * a.nq);
+            ii = min_ii + di;
             const int i = s1[ii];
             const double rix = a.Q[3 * i], riy = a.Q[3 * i + 1], riz = a.Q[3 * i + 2];
             rjx = a.Q[3 * j];
@@ -1860,11 +1863,12 @@ __global__ void __launch_bounds__(kBlock) k_gms_pairs(GmsArgs a, const int32_t* 
 
 hipError_t launch_gms_pairs(const GmsArgs& a, const int32_t* s1, int n1, const GmsPoint* pts, int n4,
                             const GmsCluster* cl, int ncl, unsigned long long* slots, unsigned long long* per_i,
-                            uint64_t* keys, uint64_t cap, int max_ii, int store, hipStream_t st) {
-    const uint64_t work = (uint64_t)std::min(n1, max_ii + 1) * (uint64_t)a.nq;
-    if (work == 0 || n4 == 0) return hipSuccess;
+                            uint64_t* keys, uint64_t cap, int min_ii, int max_ii, int store, hipStream_t st) {
+    const int hi = std::min(n1, max_ii + 1);
+    if (min_ii < 0 || hi <= min_ii || n4 == 0) return hipSuccess;
+    const uint64_t work = (uint64_t)(hi - min_ii) * (uint64_t)a.nq;
     hipLaunchKernelGGL(k_gms_pairs, dim3(grid_for(work, kBlock, 65536)), dim3(kBlock), 0, st, a, s1, n1, pts, n4, cl,
-                       ncl, slots, per_i, keys, cap, max_ii, store);
+                       ncl, slots, per_i, keys, cap, min_ii, max_ii, store);
     return hipGetLastError();
 }
 

@@ -607,13 +607,13 @@ msc_status make_set(Lane* c, const Plan& p, const Box& box, uint64_t upper, int 
         s.view.cap = dense_words;
         MSC_TRY(arena_alloc(c, dense_words * 8, &mem));
         s.view.words = (uint64_t*)mem;
-        LAUNCH(MSC_K_FILL, -1, 0, launch_fill(s.view.words, dense_words, 0ull, c->stream));
+        LAUNCH(MSC_K_FILL, -1, (int64_t)dense_words, launch_fill(s.view.words, dense_words, 0ull, c->stream));
     } else {
         s.view.kind = kHash;
         s.view.cap = hash_slots;
         MSC_TRY(arena_alloc(c, hash_slots * 8, &mem));
         s.view.words = (uint64_t*)mem;
-        LAUNCH(MSC_K_FILL, -1, 0, launch_fill(s.view.words, hash_slots, kEmpty, c->stream));
+        LAUNCH(MSC_K_FILL, -2, (int64_t)hash_slots, launch_fill(s.view.words, hash_slots, kEmpty, c->stream));
     }
     return MSC_OK;
 }
@@ -1694,8 +1694,11 @@ bool build_quiver(int step_cdeg, int min_ring, std::vector<double>& Q) {
     return true;
 }
 
+// Solutions whose keys are copied to the host and ordered there without a second pass.
+constexpr uint64_t kGmsFewKeys = 1u << 16;
+
 msc_status gms_on(Lane* c, const msc_scene* sc, const msc_gms_arm* arm, const int32_t target[3], int32_t want,
-                  int64_t* count_out, int32_t* sols_out, double* vec_out, int32_t* nsol_out) {
+                  bool first_only, int64_t* count_out, int32_t* sols_out, double* vec_out, int32_t* nsol_out) {
     MSC_TRY(check_scene(c, sc));
     if (!arm || !target || !count_out || !sols_out || !vec_out || !nsol_out) return fail(c, MSC_E_ARG, "NULL argument");
     if (want < 1) return fail(c, MSC_E_ARG, "want < 1");
@@ -1828,47 +1831,61 @@ msc_status gms_on(Lane* c, const msc_scene* sc, const msc_gms_arm* arm, const in
     MSC_TRY(arena_alloc(c, std::max<uint64_t>(cap, 1) * 8, &d_keys));
     LAUNCH(MSC_K_FILL, -1, 0, launch_fill((uint64_t*)c->counters, kCounters, 0ull, c->stream));
     std::vector<unsigned long long> per(s1.size());
-    // one pass over the survivors 0..max_ii: per[] filled, *slots = keys reserved
-    auto run = [&](int max_ii, uint64_t& slots) -> msc_status {
+    // one pass over the survivors lo..hi: per[] filled, *slots = keys reserved
+    auto run = [&](int lo, int hi, uint64_t& slots) -> msc_status {
         unsigned long long* ctr = take_counter(c);
         if (!ctr) return fail(c, MSC_E_CAPACITY, "out of counters");
         LAUNCH(MSC_K_FILL, -1, 0, launch_fill((uint64_t*)d_per, s1.size(), 0ull, c->stream));
-        LAUNCH(MSC_K_JOIN, 2, (int64_t)s1.size(),
+        LAUNCH(MSC_K_JOIN, 2, (int64_t)(hi - lo + 1),
                launch_gms_pairs(a, (const int32_t*)d_s1, (int)s1.size(), (const GmsPoint*)d_pts, n4,
                                 (const GmsCluster*)d_cl, ncl, ctr, (unsigned long long*)d_per, (uint64_t*)d_keys, cap,
-                                max_ii, 1, c->stream));
+                                lo, hi, 1, c->stream));
         HIP_TRY(hipMemcpyAsync(per.data(), d_per, per.size() * 8, hipMemcpyDeviceToHost, c->stream));
         MSC_TRY(read_counter(c, ctr, &slots));
         HIP_TRY(hipStreamSynchronize(c->stream));
         return MSC_OK;
     };
-    uint64_t slots = 0;
-    MSC_TRY(run((int)s1.size() - 1, slots));
-    uint64_t total = 0;
-    for (unsigned long long v : per) total += v;
-    *count_out = (int64_t)total;
-    if (total == 0) return MSC_NO_REACH;
-    uint64_t stored = total;
-    if (total > cap) {
-        // too many to keep: the solutions of the first survivors that hold the first `want`
-        uint64_t acc = 0;
-        int ii0 = 0;
-        for (; ii0 < (int)per.size(); ++ii0) {
-            acc += per[ii0];
-            if (acc >= (uint64_t)want) break;
+    // Survivors in chunks (one chunk holding all of them unless first_only; with it, the
+    // first chunk covers about 4*2^20 pairs and each next one twice the last).  A chunk's
+    // keys are kept when there are few of them; otherwise the chunk's first survivors that,
+    // with the earlier chunks, hold the first `want` are searched again and only their
+    // keys are kept.
+    const int n1 = (int)s1.size();
+    int chunk = first_only ? std::max(16, (int)std::min<uint64_t>(n1, (4ull << 20) / (uint64_t)nq)) : n1;
+    std::vector<uint64_t> keys;
+    uint64_t found = 0;
+    for (int lo = 0; lo < n1 && !(first_only && found >= (uint64_t)want); lo += chunk, chunk = std::min(n1, 2 * chunk)) {
+        const int hi = std::min(n1, lo + chunk) - 1;
+        uint64_t slots = 0;
+        MSC_TRY(run(lo, hi, slots));
+        uint64_t here = 0;
+        for (int ii = lo; ii <= hi; ++ii) here += per[ii];
+        uint64_t keep = here;
+        if (here > std::min<uint64_t>(cap, kGmsFewKeys)) {
+            uint64_t acc = 0;
+            int ii0 = lo;
+            for (; ii0 <= hi; ++ii0) {
+                acc += per[ii0];
+                if (found + acc >= (uint64_t)want) break;
+            }
+            ii0 = std::min(ii0, hi);
+            if (acc > cap) return fail(c, MSC_E_CAPACITY, "the first segment-1 vectors hold more than %llu solutions",
+                                       (unsigned long long)cap);
+            MSC_TRY(run(lo, ii0, slots));
+            keep = acc;
         }
-        if (acc > cap) return fail(c, MSC_E_CAPACITY, "the first segment-1 vectors hold more than %llu solutions",
-                                   (unsigned long long)cap);
-        MSC_TRY(run(ii0, slots));
-        stored = acc;
+        if (slots != keep) return fail(c, MSC_E_STATE, "gap search: %llu keys stored, %llu counted",
+                                       (unsigned long long)slots, (unsigned long long)keep);
+        const size_t old = keys.size();
+        keys.resize(old + keep);
+        if (keep) HIP_TRY(hipMemcpyAsync(keys.data() + old, d_keys, keep * 8, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        found += here;
     }
-    if (slots != stored) return fail(c, MSC_E_STATE, "gap search: %llu keys stored, %llu counted",
-                                     (unsigned long long)slots, (unsigned long long)stored);
-    std::vector<uint64_t> keys(stored);
-    HIP_TRY(hipMemcpyAsync(keys.data(), d_keys, stored * 8, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    std::sort(keys.begin(), keys.end());
+    *count_out = (int64_t)found;
+    if (found == 0) return MSC_NO_REACH;
     const int nout = (int)std::min<uint64_t>((uint64_t)want, keys.size());
+    std::partial_sort(keys.begin(), keys.begin() + nout, keys.end());
     void *d_sel, *d_vec;
     MSC_TRY(arena_alloc(c, (uint64_t)nout * 8, &d_sel));
     MSC_TRY(arena_alloc(c, (uint64_t)nout * 18 * 8, &d_vec));
@@ -2473,7 +2490,18 @@ msc_status msc_gms_reach(msc_ctx* o, const msc_scene* sc, const msc_gms_arm* arm
     if (!o) return MSC_E_ARG;
     Lane* c = o->control;
     prof_reset(c, 0u);
-    msc_status st = gms_on(c, sc, arm, target, want, count_out, sols_out, vec_out, nsol_out);
+    msc_status st = gms_on(c, sc, arm, target, want, false, count_out, sols_out, vec_out, nsol_out);
+    prof_finish(c);
+    return st;
+}
+
+msc_status msc_gms_reach_first(msc_ctx* o, const msc_scene* sc, const msc_gms_arm* arm, const int32_t target[3],
+                               int32_t want, int64_t* count_out, int32_t* sols_out, double* vec_out,
+                               int32_t* nsol_out) {
+    if (!o) return MSC_E_ARG;
+    Lane* c = o->control;
+    prof_reset(c, 0u);
+    msc_status st = gms_on(c, sc, arm, target, want, true, count_out, sols_out, vec_out, nsol_out);
     prof_finish(c);
     return st;
 }

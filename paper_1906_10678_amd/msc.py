@@ -33,7 +33,7 @@ EXPORTS = [
     "msc_server_submit", "msc_server_poll", "msc_server_wait", "msc_server_stop", "msc_refine", "msc_replan",
     "msc_scene_bytes_dynamic", "msc_scene_set_dynamic", "msc_server_step", "msc_server_take_replans",
     "msc_refine_static", "msc_refine_static_max", "msc_track_default", "msc_guided_path", "msc_pose_path",
-    "msc_autotune", "msc_tune_load", "msc_tune_entries", "msc_short_path", "msc_gms_quiver", "msc_gms_reach",
+    "msc_autotune", "msc_tune_load", "msc_tune_entries", "msc_short_path", "msc_gms_quiver", "msc_gms_reach", "msc_gms_reach_first",
 ]
 
 
@@ -164,6 +164,8 @@ def load_library(path: str = LIB_PATH):
     L.msc_gms_quiver.restype = i32
     L.msc_gms_reach.argtypes = [c_void_p, c_void_p, P(MscGmsArm), P(i32), i32, P(i64), P(i32), P(ctypes.c_double),
                                 P(i32)]
+    L.msc_gms_reach_first.argtypes = [c_void_p, c_void_p, P(MscGmsArm), P(i32), i32, P(i64), P(i32),
+                                      P(ctypes.c_double), P(i32)]
     L.msc_autotune.argtypes = [c_void_p, P(MscQuery), i32, P(MscOpts), ctypes.c_char_p]
     L.msc_tune_load.argtypes = [c_void_p, ctypes.c_char_p]
     L.msc_tune_entries.argtypes = [c_void_p, P(i32), i32, P(i32)]
@@ -488,18 +490,19 @@ class Solver:
             return rc, None, h
         return rc, out[:rows.value * a.dof].reshape(rows.value, a.dof) // a.step_cdeg, h
 
-    def gms_reach(self, scene: Scene, arm, target: Sequence[int], want: int = 1):
-        """msc_gms_reach: (status, total solutions, sols[n, 3] (i, j, l), vectors[n, 6, 3])."""
+    def gms_reach(self, scene: Scene, arm, target: Sequence[int], want: int = 1, first_only: bool = False):
+        """msc_gms_reach (msc_gms_reach_first with first_only): (status, solutions counted,
+        sols[n, 3] (i, j, l), vectors[n, 6, 3])."""
         a = make_gms_arm(arm)
         t = np.ascontiguousarray(np.asarray(target, np.int32))
         cnt = ctypes.c_int64()
         nsol = ctypes.c_int32()
         sols = np.zeros(want * 3, np.int32)
         vec = np.zeros(want * 18, np.float64)
-        rc = self.lib.msc_gms_reach(self.ctx, scene.handle, ctypes.byref(a), _ptr(t, ctypes.c_int32), int(want),
-                                    ctypes.byref(cnt), _ptr(sols, ctypes.c_int32), _ptr(vec, ctypes.c_double),
-                                    ctypes.byref(nsol))
-        self._check(rc, "msc_gms_reach")
+        fn = self.lib.msc_gms_reach_first if first_only else self.lib.msc_gms_reach
+        rc = fn(self.ctx, scene.handle, ctypes.byref(a), _ptr(t, ctypes.c_int32), int(want), ctypes.byref(cnt),
+                _ptr(sols, ctypes.c_int32), _ptr(vec, ctypes.c_double), ctypes.byref(nsol))
+        self._check(rc, "msc_gms_reach_first" if first_only else "msc_gms_reach")
         n = nsol.value
         return rc, int(cnt.value), sols[:3 * n].reshape(n, 3), vec[:18 * n].reshape(n, 6, 3)
 

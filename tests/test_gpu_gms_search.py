@@ -17,13 +17,17 @@ from test_gpu_parity import say
 pytestmark = pytest.mark.gpu
 
 
-def compare(solver, scene, arm, occ, t, want=16, full=True):
-    st, count, sols, vec = solver.gms_reach(scene, arm, t, want)
+def compare(solver, scene, arm, occ, t, want=16, full=True, first_only=False):
+    st, count, sols, vec = solver.gms_reach(scene, arm, t, want, first_only=first_only)
     if full:
         ref = gms.solutions(arm, occ, t)
-        assert count == len(ref), (count, len(ref))
+        if first_only:
+            assert min(want, len(ref)) <= count <= len(ref), (count, len(ref))
+        else:
+            assert count == len(ref), (count, len(ref))
     else:
         ref = gms.solutions(arm, occ, t, limit=want)
+        assert count >= len(ref)
     if not ref:
         assert st == msc.NO_REACH
         return 0
@@ -70,6 +74,7 @@ def test_gms_small(solver, step):
         for t in targets_of(arm, occ, rng, 3):
             say("gms small", step, seed, tuple(t))
             total += compare(solver, scene, arm, occ, t)
+            compare(solver, scene, arm, occ, t, want=4, first_only=True)
     assert total > 0
 
 
@@ -113,3 +118,28 @@ def test_gms_two_degrees_full_size(solver):
     say("gms 2 deg", tuple(q.target))
     found = compare(solver, scene, arm, occ, np.asarray(q.target), want=8, full=False)
     assert found > 0
+
+
+def test_gms_first_solutions_full_size(solver):
+    """msc_gms_reach_first on the 2 degree quiver: the first solutions and their vectors
+    equal the oracle's and the full search's; the count is at least the number wanted and
+    at most the full search's."""
+    arm = gms.GmsArm([60.0, 50.0, 40.0, 25.0], (128, 128, 0), step_cdeg=200, samples=8, seg1_min_el_cdeg=0,
+                     max_flex_cdeg=(12000, 12000, 12000), approach=(0, -9000, 4500), eps=0.5)
+    answered = 0
+    for seed in (0, 1, 2, 3):
+        q = synth.query_c2(seed, solver.pose_fn_for)
+        occ = oracle.raster(q.scene)
+        scene = solver.scene(q.scene)
+        t = np.asarray(q.target)
+        say("gms first", seed, tuple(t))
+        st_a, count_a, sols_a, vec_a = solver.gms_reach(scene, arm, t, 8)
+        st_f, count_f, sols_f, vec_f = solver.gms_reach(scene, arm, t, 8, first_only=True)
+        assert st_f == st_a
+        assert np.array_equal(sols_f, sols_a) and np.array_equal(vec_f, vec_a)
+        assert min(8, count_a) <= count_f <= count_a
+        if st_a == msc.OK:
+            answered += 1
+            ref = gms.solutions(arm, occ, t, limit=8)
+            assert [tuple(x) for x in sols_f] == ref[:len(sols_f)]
+    assert answered >= 2
