@@ -75,6 +75,14 @@ struct Shape {
 hipError_t launch_fill(uint64_t* p, uint64_t n, uint64_t value, hipStream_t st);
 hipError_t launch_tables(int na, int S, int L, short4* off, short4* sweep, unsigned int* maxn2,
                          hipStream_t st);
+// Obstacle lists carried in the raster kernel's arguments: boxes (lo x, y, z, extent x,
+// y, z) then spheres (centre x, y, z, radius), at most kRasterInline values.
+constexpr int kRasterInline = 720;
+struct RasterInline {
+    int32_t v[kRasterInline];
+};
+hipError_t launch_raster_inline(uint64_t* occ, int n, int wpr, int r, const RasterInline& inl, int nbox, int nsph,
+                                hipStream_t st);
 hipError_t launch_raster(uint64_t* occ, int n, int wpr, int r, const int32_t* boxes, int nbox,
                          const int32_t* spheres, int nsph, hipStream_t st);
 // Moving boxes of one tick, passed by value: (lo x, y, z, ext x, y, z) per box.

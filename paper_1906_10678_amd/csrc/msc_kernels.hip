@@ -360,8 +360,9 @@ __device__ uint64_t span_bits(long long lo, long long hi, long long x0) {
 constexpr int kObsChunk = 256;
 
 __global__ void k_raster(uint64_t* occ, int n, int wpr, int r, const int32_t* boxes, int nbox,
-                         const int32_t* spheres, int nsph) {
-    // obstacle lists (possibly in mapped host memory) are staged through LDS in chunks
+                         const int32_t* spheres, int nsph, RasterInline inl, int use_inl) {
+    // obstacle lists (in the kernel arguments, or in memory, possibly mapped host memory)
+    // are staged through LDS in chunks
     __shared__ int32_t sb[kObsChunk * 6];
     __shared__ int32_t ss[kObsChunk * 4];
     const uint64_t total = (uint64_t)n * n * wpr;
@@ -380,7 +381,8 @@ __global__ void k_raster(uint64_t* occ, int n, int wpr, int r, const int32_t* bo
         for (int b0 = 0; b0 < nbox; b0 += kObsChunk) {
             const int cnt = min(kObsChunk, nbox - b0);
             __syncthreads();
-            for (int t = threadIdx.x; t < cnt * 6; t += blockDim.x) sb[t] = boxes[b0 * 6 + t];
+            for (int t = threadIdx.x; t < cnt * 6; t += blockDim.x)
+                sb[t] = use_inl ? inl.v[b0 * 6 + t] : boxes[b0 * 6 + t];
             __syncthreads();
             if (!live) continue;
             for (int b = 0; b < cnt; ++b) {
@@ -398,7 +400,8 @@ __global__ void k_raster(uint64_t* occ, int n, int wpr, int r, const int32_t* bo
         for (int s0 = 0; s0 < nsph; s0 += kObsChunk) {
             const int cnt = min(kObsChunk, nsph - s0);
             __syncthreads();
-            for (int t = threadIdx.x; t < cnt * 4; t += blockDim.x) ss[t] = spheres[s0 * 4 + t];
+            for (int t = threadIdx.x; t < cnt * 4; t += blockDim.x)
+                ss[t] = use_inl ? inl.v[nbox * 6 + s0 * 4 + t] : spheres[s0 * 4 + t];
             __syncthreads();
             if (!live) continue;
             for (int b = 0; b < cnt; ++b) {
@@ -420,8 +423,18 @@ __global__ void k_raster(uint64_t* occ, int n, int wpr, int r, const int32_t* bo
 hipError_t launch_raster(uint64_t* occ, int n, int wpr, int r, const int32_t* boxes, int nbox,
                          const int32_t* spheres, int nsph, hipStream_t st) {
     uint64_t total = (uint64_t)n * n * wpr;
+    RasterInline none{};
     hipLaunchKernelGGL(k_raster, dim3(grid_for(total)), dim3(kBlock), 0, st, occ, n, wpr, r, boxes, nbox,
-                       spheres, nsph);
+                       spheres, nsph, none, 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_raster_inline(uint64_t* occ, int n, int wpr, int r, const RasterInline& inl, int nbox, int nsph,
+                                hipStream_t st) {
+    if (nbox < 0 || nsph < 0 || nbox * 6 + nsph * 4 > kRasterInline) return hipErrorInvalidValue;
+    uint64_t total = (uint64_t)n * n * wpr;
+    hipLaunchKernelGGL(k_raster, dim3(grid_for(total)), dim3(kBlock), 0, st, occ, n, wpr, r, (const int32_t*)nullptr,
+                       nbox, (const int32_t*)nullptr, nsph, inl, 1);
     return hipGetLastError();
 }
 

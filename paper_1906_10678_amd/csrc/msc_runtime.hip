@@ -162,6 +162,9 @@ struct msc_scene {
     uint64_t* grid = nullptr;   // the grid of the current tick
     uint64_t bytes = 0;
     SceneDyn* dyn = nullptr;    // null when the buffer holds only the static grid
+    // recorded after the static grid's raster on the control lane's stream (which is
+    // ordered after it); other lanes wait for it before their first use of the scene
+    hipEvent_t ready = nullptr;
 };
 
 namespace {
@@ -1075,6 +1078,8 @@ msc_status pose_check_steps(Lane* c, const msc_scene* sc, const Plan& p, const i
 msc_status check_scene(Lane* c, const msc_scene* s) {
     if (!s) return fail(c, MSC_E_ARG, "scene is NULL");
     if (s->ctx != c->owner) return fail(c, MSC_E_ARG, "scene belongs to another context");
+    if (s->ready && c != c->owner->control && hipStreamWaitEvent(c->stream, s->ready, 0) != hipSuccess)
+        return fail(c, MSC_E_HIP, "hipStreamWaitEvent");
     return MSC_OK;
 }
 
@@ -2292,31 +2297,6 @@ msc_status msc_scene_create(msc_ctx* o, int32_t n, int32_t dilate_r, const msc_b
     if (grid_bytes < msc_scene_bytes(n)) return fail(c, MSC_E_NOMEM, "grid buffer too small");
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, MSC_E_HIP, "hipSetDevice");
     begin_call(c);
-    std::vector<int32_t> hb((size_t)std::max(nbox, 1) * 6), hs((size_t)std::max(nsph, 1) * 4);
-    for (int i = 0; i < nbox; ++i)
-        for (int a = 0; a < 3; ++a) {
-            hb[i * 6 + a] = boxes[i].lo[a];
-            hb[i * 6 + 3 + a] = boxes[i].ext[a];
-        }
-    for (int i = 0; i < nsph; ++i) {
-        for (int a = 0; a < 3; ++a) hs[i * 4 + a] = spheres[i].c[a];
-        hs[i * 4 + 3] = spheres[i].r;
-    }
-    // the raster kernel reads the obstacle lists from mapped host memory when they fit
-    // the staging buffer, else from a device copy
-    void *hbp, *db, *hsp, *ds;
-    const size_t obytes = (hb.size() + hs.size()) * 4;
-    if (obytes + 1024 <= kStagingBytes / 2) {
-        MSC_TRY(host_area(c, hb.size() * 4, &hbp, &db));
-        MSC_TRY(host_area(c, hs.size() * 4, &hsp, &ds));
-        std::memcpy(hbp, hb.data(), hb.size() * 4);
-        std::memcpy(hsp, hs.data(), hs.size() * 4);
-    } else {
-        MSC_TRY(arena_alloc(c, hb.size() * 4, &db));
-        MSC_TRY(arena_alloc(c, hs.size() * 4, &ds));
-        HIP_TRY(hipMemcpyAsync(db, hb.data(), hb.size() * 4, hipMemcpyHostToDevice, c->stream));
-        HIP_TRY(hipMemcpyAsync(ds, hs.data(), hs.size() * 4, hipMemcpyHostToDevice, c->stream));
-    }
     msc_scene* s = new (std::nothrow) msc_scene();
     if (!s) return fail(c, MSC_E_NOMEM, "host allocation");
     s->ctx = c->owner;
@@ -2325,10 +2305,64 @@ msc_status msc_scene_create(msc_ctx* o, int32_t n, int32_t dilate_r, const msc_b
     s->dilate = dilate_r;
     s->grid = (uint64_t*)dev_grid;
     s->bytes = grid_bytes;
-    hipError_t e = launch_raster(s->grid, n, s->wpr, dilate_r, (const int32_t*)db, nbox, (const int32_t*)ds, nsph,
-                                 c->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    hipError_t e = hipSuccess;
+    if (nbox * 6 + nsph * 4 <= kRasterInline) {
+        // the obstacle lists travel in the kernel's arguments: nothing on the host has to
+        // outlive the launch, so the call does not wait for the raster
+        RasterInline inl{};
+        for (int i = 0; i < nbox; ++i)
+            for (int a = 0; a < 3; ++a) {
+                inl.v[i * 6 + a] = boxes[i].lo[a];
+                inl.v[i * 6 + 3 + a] = boxes[i].ext[a];
+            }
+        for (int i = 0; i < nsph; ++i) {
+            for (int a = 0; a < 3; ++a) inl.v[nbox * 6 + i * 4 + a] = spheres[i].c[a];
+            inl.v[nbox * 6 + i * 4 + 3] = spheres[i].r;
+        }
+        e = launch_raster_inline(s->grid, n, s->wpr, dilate_r, inl, nbox, nsph, c->stream);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ready, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(s->ready, c->stream);
+    } else {
+        std::vector<int32_t> hb((size_t)std::max(nbox, 1) * 6), hs((size_t)std::max(nsph, 1) * 4);
+        for (int i = 0; i < nbox; ++i)
+            for (int a = 0; a < 3; ++a) {
+                hb[i * 6 + a] = boxes[i].lo[a];
+                hb[i * 6 + 3 + a] = boxes[i].ext[a];
+            }
+        for (int i = 0; i < nsph; ++i) {
+            for (int a = 0; a < 3; ++a) hs[i * 4 + a] = spheres[i].c[a];
+            hs[i * 4 + 3] = spheres[i].r;
+        }
+        // long lists: read from mapped host memory when they fit the staging buffer, else
+        // from a device copy; the call waits for the raster before the staging is reused
+        void *hbp, *db, *hsp, *ds;
+        const size_t obytes = (hb.size() + hs.size()) * 4;
+        msc_status st = MSC_OK;
+        if (obytes + 1024 <= kStagingBytes / 2) {
+            st = host_area(c, hb.size() * 4, &hbp, &db);
+            if (st == MSC_OK) st = host_area(c, hs.size() * 4, &hsp, &ds);
+            if (st == MSC_OK) {
+                std::memcpy(hbp, hb.data(), hb.size() * 4);
+                std::memcpy(hsp, hs.data(), hs.size() * 4);
+            }
+        } else {
+            st = arena_alloc(c, hb.size() * 4, &db);
+            if (st == MSC_OK) st = arena_alloc(c, hs.size() * 4, &ds);
+            if (st == MSC_OK) e = hipMemcpyAsync(db, hb.data(), hb.size() * 4, hipMemcpyHostToDevice, c->stream);
+            if (st == MSC_OK && e == hipSuccess)
+                e = hipMemcpyAsync(ds, hs.data(), hs.size() * 4, hipMemcpyHostToDevice, c->stream);
+        }
+        if (st != MSC_OK) {
+            delete s;
+            return st;
+        }
+        if (e == hipSuccess)
+            e = launch_raster(s->grid, n, s->wpr, dilate_r, (const int32_t*)db, nbox, (const int32_t*)ds, nsph,
+                              c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    }
     if (e != hipSuccess) {
+        if (s->ready) (void)hipEventDestroy(s->ready);
         delete s;
         return fail(c, MSC_E_HIP, "raster: %s", hipGetErrorString(e));
     }
@@ -2339,7 +2373,7 @@ msc_status msc_scene_create(msc_ctx* o, int32_t n, int32_t dilate_r, const msc_b
     if (slots >= 2) {
         s->dyn = new (std::nothrow) SceneDyn();
         if (!s->dyn) {
-            delete s;
+            msc_scene_destroy(s);
             return fail(c, MSC_E_NOMEM, "host allocation");
         }
         s->dyn->slot.resize(slots);
@@ -2359,6 +2393,7 @@ msc_status msc_scene_create(msc_ctx* o, int32_t n, int32_t dilate_r, const msc_b
 
 msc_status msc_scene_destroy(msc_scene* s) {
     if (!s) return MSC_E_ARG;
+    if (s->ready) (void)hipEventDestroy(s->ready);
     if (s->dyn) {
         for (GridSlot& g : s->dyn->slot)
             if (g.ready) (void)hipEventDestroy(g.ready);

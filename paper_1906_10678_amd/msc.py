@@ -90,6 +90,17 @@ class MscSphere(ctypes.Structure):
     _fields_ = [("c", ctypes.c_int32 * 3), ("r", ctypes.c_int32)]
 
 
+def _struct_array(cls, rows: np.ndarray):
+    """A ctypes array of `cls` (a struct of int32 fields only) holding the rows of an
+    int32 array in field order (at least one element)."""
+    rows = np.ascontiguousarray(rows, np.int32)
+    assert rows.size * 4 == len(rows) * ctypes.sizeof(cls)
+    out = (cls * max(1, len(rows)))()
+    if len(rows):
+        ctypes.memmove(out, rows.ctypes.data, rows.nbytes)
+    return out
+
+
 class MscTiming(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int32), ("stage", ctypes.c_int32), ("in_count", ctypes.c_int64),
                 ("out_count", ctypes.c_int64), ("ms", ctypes.c_float), ("out_words", ctypes.c_int64)]
@@ -392,16 +403,8 @@ class Solver:
         grid = self.torch.empty(nbytes, dtype=self.torch.uint8, device=self.dev)
         boxes = np.asarray(sc.boxes, np.int32).reshape(-1, 6)
         sph = np.asarray(sc.spheres, np.int32).reshape(-1, 4)
-        B = (MscBox * max(1, len(boxes)))()
-        for i, b in enumerate(boxes):
-            for a in range(3):
-                B[i].lo[a] = int(b[a])
-                B[i].ext[a] = int(b[3 + a])
-        S = (MscSphere * max(1, len(sph)))()
-        for i, s in enumerate(sph):
-            for a in range(3):
-                S[i].c[a] = int(s[a])
-            S[i].r = int(s[3])
+        B = _struct_array(MscBox, boxes)
+        S = _struct_array(MscSphere, sph)
         h = ctypes.c_void_p()
         rc = self.lib.msc_scene_create(self.ctx, n, int(sc.dilate), B, len(boxes), S, len(sph),
                                        ctypes.c_void_p(grid.data_ptr()), nbytes, ctypes.byref(h))
@@ -412,11 +415,7 @@ class Solver:
         """msc_scene_set_dynamic: the scene's grid of `tick` = static obstacles + boxes
         (k, 6) int (lo x, y, z, extent x, y, z), dilated like the static ones."""
         boxes = np.asarray(boxes, np.int32).reshape(-1, 6)
-        B = (MscBox * max(1, len(boxes)))()
-        for i, b in enumerate(boxes):
-            for a in range(3):
-                B[i].lo[a] = int(b[a])
-                B[i].ext[a] = int(b[3 + a])
+        B = _struct_array(MscBox, boxes)
         self._check(self.lib.msc_scene_set_dynamic(scene.handle, B, len(boxes), int(tick)), "msc_scene_set_dynamic")
 
     # -- solving ------------------------------------------------------------

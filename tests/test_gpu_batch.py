@@ -118,3 +118,27 @@ def test_server_states(solver):
     with pytest.raises(msc.MscError) as e:
         solver.server_start()
     assert e.value.status == msc.E_STATE
+
+
+def test_fresh_scenes_on_worker_lanes(solver):
+    """Scenes created just before a batch: the raster runs on the control lane's stream
+    without the call waiting for it, and the worker lanes wait for it before they read
+    the grid.  Every batched answer equals the answer on the same scene solved alone."""
+    solver.set_lanes(8)
+    try:
+        qs = [synth.query_c2(seed, solver.pose_fn_for) for seed in range(8)]
+        for rnd in range(3):
+            say("fresh scenes round", rnd)
+            specs = []
+            for q in qs:
+                sc = solver.scene(q.scene)   # rasterised now, not waited for
+                specs.append(msc.QuerySpec(sc, q.arm, q.target, start=q.start, waypoints=q.waypoints,
+                                           delta=q.max_delta))
+            got = solver.batch(specs)
+            for (st, res, _lat), spec, q in zip(got, specs, qs):
+                est, eres = solver.path(spec.scene, q.arm, q.start, q.target, q.waypoints, q.max_delta)
+                assert st == est
+                if st == msc.OK:
+                    assert np.array_equal(res, eres)
+    finally:
+        solver.set_lanes(0)

@@ -40,6 +40,17 @@ def test_raster(solver, n, seed):
     assert np.array_equal(solver.debug_raster(scene), oracle.raster(sc))
 
 
+def test_raster_long_obstacle_lists(solver):
+    """Lists longer than the kernel arguments carry (here 130 boxes and 40 spheres) take
+    the staged path; short ones travel in the arguments: both equal the oracle."""
+    for nbox, nsph in ((130, 40), (8, 2)):
+        say("raster lists", nbox, nsph)
+        rng = synth.rng_for(78, nbox)
+        sc = synth.random_scene(rng, 96, 1, nbox, (1, 12), nsph, (1, 6))
+        scene = solver.scene(sc)
+        assert np.array_equal(solver.debug_raster(scene), oracle.raster(sc))
+
+
 def test_raster_workload_scenes(solver):
     for sc in (synth.scene_c1(0), synth.scene_c2(0)):
         say("raster workload", sc.n)
