@@ -112,6 +112,9 @@ hipError_t launch_seed_bwd(SetView s, GridView g, int x, int y, int z, const uin
 hipError_t launch_expand_fwd(const uint64_t* in, uint64_t count, SetView out, GridView g, JointView j,
                              int tx, int ty, int tz, long long r2, unsigned long long* counter,
                              unsigned long long* overflow, hipStream_t st, Shape sh = Shape{});
+// Zeroes every orientation row of a dense set (fast axis = the joint's) that a backward
+// stage from `in` can have written.
+hipError_t launch_unexpand_bwd(const uint64_t* in, uint64_t count, SetView out, JointView j, hipStream_t st);
 hipError_t launch_expand_bwd(const uint64_t* in, uint64_t count, SetView out, GridView g, JointView j,
                              int bx, int by, int bz, long long r2, const uint64_t* orows,
                              unsigned long long* counter, unsigned long long* overflow,

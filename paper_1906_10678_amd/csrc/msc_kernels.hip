@@ -835,6 +835,33 @@ __global__ void __launch_bounds__(kBlock) k_expand_bwd_set(const uint64_t* __res
     if (ovf) atomicAdd(overflow, ovf);
 }
 
+// Clearing of a dense set built by k_expand_bwd from the list `in`: for every input
+// state, the whole orientation row of its predecessor voxel that the stage may have
+// touched is set to zero (tests skipped: a superset of the written words, all inside
+// the set), so the set is all zero afterwards without a pass over all of its words.
+__global__ void __launch_bounds__(kBlock) k_unexpand_bwd(const uint64_t* __restrict__ in, uint64_t count,
+                                                         SetView out, JointView j) {
+    const int na = out.na;
+    const bool yaw = j.type == 0;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < count;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        int x2, y2, z2, ia2, ie2;
+        unpack_key(in[i], x2, y2, z2, ia2, ie2);
+        if (ia2 >= na || ie2 >= na) continue;
+        const short4 d = j.off[ia2 * na + ie2];
+        uint64_t bit0;
+        if (!dense_bit(out, x2 - d.x, y2 - d.y, z2 - d.z, yaw ? 0 : ia2, yaw ? ie2 : 0, bit0)) continue;
+        const uint64_t w1 = (bit0 + (uint64_t)na - 1) >> 6;
+        for (uint64_t w = bit0 >> 6; w <= w1; ++w) out.words[w] = 0;
+    }
+}
+
+hipError_t launch_unexpand_bwd(const uint64_t* in, uint64_t count, SetView out, JointView j, hipStream_t st) {
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_unexpand_bwd, dim3(grid_for(count, kBlock, 16384)), dim3(kBlock), 0, st, in, count, out, j);
+    return hipGetLastError();
+}
+
 template <bool COUNT>
 void launch_bwd_dense(int np, dim3 grid, hipStream_t st, const uint64_t* in, uint64_t count, SetView out,
                       GridView g, JointView j, int bx, int by, int bz, long long r2, const uint64_t* orows,

@@ -81,6 +81,7 @@ struct StageSet {
     uint64_t count = 0;
     bool listed = false;
     bool used = false;
+    bool at_top = false;   // dense, at the lane window's top (cleared after its last use)
     bool counted = true;   // false: built without a member count (count is meaningless)
 };
 
@@ -98,6 +99,12 @@ struct Lane {
     char* ws = nullptr;       // this lane's window of the workspace
     uint64_t lo = 0;          // per-call region grows up from 0
     uint64_t hi = 0;          // window size
+    // The set the meet probes may sit at the window's top, [hi - top, hi).  [clean, hi)
+    // is known to hold zeros once the work queued so far has run (clean == hi: nothing
+    // known); the top set is cleared after its last use, so that the next one needs no
+    // fill where it overlaps that region.
+    uint64_t top = 0;
+    uint64_t clean = 0;
     std::string err;
     unsigned long long* counters = nullptr;  // device
     int next_counter = 0;
@@ -286,14 +293,17 @@ Shape shape_for(Lane* c, int kernel, uint64_t count) {
 
 msc_status arena_alloc(Lane* c, uint64_t bytes, void** out) {
     uint64_t b = align_up(bytes ? bytes : 1);
-    if (c->lo + b > c->hi) {
+    if (c->lo + b > c->hi - c->top) {
         return fail(c, MSC_E_NOMEM, "workspace exhausted: need %llu more bytes (used %llu of %llu)",
-                    (unsigned long long)b, (unsigned long long)c->lo, (unsigned long long)c->hi);
+                    (unsigned long long)b, (unsigned long long)(c->lo + c->top), (unsigned long long)c->hi);
     }
     *out = c->ws + c->lo;
     c->lo += b;
+    if (c->lo > c->clean) c->clean = c->lo;   // what this region held may be overwritten
     return MSC_OK;
 }
+
+uint64_t free_bytes(const Lane* c) { return c->hi - c->top > c->lo ? c->hi - c->top - c->lo : 0; }
 
 // Shared table region at the top of the workspace (caller holds owner->table_mu).
 msc_status persist_alloc(Lane* c, uint64_t bytes, void** out) {
@@ -307,6 +317,7 @@ msc_status persist_alloc(Lane* c, uint64_t bytes, void** out) {
 
 void begin_call(Lane* c) {
     c->lo = 0;
+    c->top = 0;   // a top set not released by its call left clean == hi
     c->staging_used = 0;
     c->next_counter = 0;
     c->err.clear();
@@ -582,17 +593,34 @@ Box stage_box(const Plan& p, int N, const std::vector<int64_t>& R, int k) {
 
 // Allocate and clear the structure of one stage set: a dense bitset over the stage box
 // when it is no larger than a hash table sized for `upper` states, else the hash table.
+// A dense set at the lane window's top (the set the meet probes): only the part of it
+// not known to be clear is filled; it stays dirty (clean = hi) until release_top.
+msc_status top_alloc(Lane* c, uint64_t words, uint64_t** out) {
+    const uint64_t b = align_up(words * 8);
+    if (c->top) return fail(c, MSC_E_STATE, "a set already sits at the window's top");
+    if (b > c->hi || c->hi - b < c->lo) return fail(c, MSC_E_NOMEM, "workspace exhausted: need %llu more bytes",
+                                                  (unsigned long long)b);
+    const uint64_t base = c->hi - b;
+    if (base < c->clean)
+        LAUNCH(MSC_K_FILL, -1, (int64_t)((c->clean - base) / 8),
+               launch_fill((uint64_t*)(c->ws + base), (c->clean - base) / 8, 0ull, c->stream));
+    c->top = b;
+    c->clean = c->hi;
+    *out = (uint64_t*)(c->ws + base);
+    return MSC_OK;
+}
+
 msc_status make_set(Lane* c, const Plan& p, const Box& box, uint64_t upper, int fast_ia, bool force_dense,
-                    StageSet& s) {
+                    StageSet& s, bool at_top = false) {
     const uint64_t na2 = (uint64_t)p.na * p.na;
     uint64_t dense_words = box.empty() ? 0 : (box.voxels() * na2 + 63) / 64 + 1;
     uint64_t hash_slots = pow2_at_least(std::max<uint64_t>(2 * upper, 64));
     // Dense sets take a run of predecessors in 1-3 atomicOr and a membership test in one
     // load, where a hash set needs a CAS chain per state: dense is preferred up to 8x the
     // hash table's bytes, as long as it leaves half of the lane's free workspace.
-    const uint64_t free_bytes = c->hi > c->lo ? c->hi - c->lo : 0;
+    const uint64_t room = free_bytes(c);
     bool dense = !box.empty() &&
-                 (force_dense || (dense_words <= 8 * hash_slots && dense_words * 8 <= free_bytes / 2) ||
+                 (force_dense || (dense_words <= 8 * hash_slots && dense_words * 8 <= room / 2) ||
                   dense_words <= hash_slots);
     s = StageSet();
     s.view.na = p.na;
@@ -608,9 +636,14 @@ msc_status make_set(Lane* c, const Plan& p, const Box& box, uint64_t upper, int 
         s.view.ny = box.ny;
         s.view.nz = box.nz;
         s.view.cap = dense_words;
-        MSC_TRY(arena_alloc(c, dense_words * 8, &mem));
-        s.view.words = (uint64_t*)mem;
-        LAUNCH(MSC_K_FILL, -1, (int64_t)dense_words, launch_fill(s.view.words, dense_words, 0ull, c->stream));
+        if (at_top) {
+            MSC_TRY(top_alloc(c, dense_words, &s.view.words));
+            s.at_top = true;
+        } else {
+            MSC_TRY(arena_alloc(c, dense_words * 8, &mem));
+            s.view.words = (uint64_t*)mem;
+            LAUNCH(MSC_K_FILL, -1, (int64_t)dense_words, launch_fill(s.view.words, dense_words, 0ull, c->stream));
+        }
     } else {
         s.view.kind = kHash;
         s.view.cap = hash_slots;
@@ -857,14 +890,16 @@ msc_status run_reach(Lane* c, const msc_scene* sc, const Plan& p, int want, bool
             MSC_TRY(ensure_list(c, B[kb]));
             uint64_t upper = B[kb].count * (uint64_t)(p.hi[k - 1] - p.lo[k - 1] + 1);
             int yaw = p.type[k - 1] == MSC_YAW ? 1 : 0;
-            MSC_TRY(make_set(c, p, box[k - 1], upper, yaw, false, B[k - 1]));
+            // The set the meet probes needs no member count (an empty one simply meets
+            // nothing): it is built without one, and without a host round trip, unless
+            // the sets are captured.  It is the largest set of most queries: it sits at
+            // the window's top and is cleared after its last use by the words its stage
+            // can have written, not by a fill of the whole set.
+            const bool last = p.split == 0 ? k - 1 == 0 : k - 1 - kf == 1;
+            MSC_TRY(make_set(c, p, box[k - 1], upper, yaw, false, B[k - 1], last));
             int64_t rb = 0;
             for (int j = 0; j < k - 1; ++j) rb += R[j];
             long long r2 = p.prune ? (long long)(rb * rb) : -1;
-            // The set the meet probes needs no member count (an empty one simply meets
-            // nothing): it is built without one, and without a host round trip, unless
-            // the sets are captured.
-            const bool last = p.split == 0 ? k - 1 == 0 : k - 1 - kf == 1;
             const bool count = capture || !last || p.count_sets;
             unsigned long long* ctr = count ? take_counter(c) : nullptr;
             if (count && !ctr) return fail(c, MSC_E_CAPACITY, "out of counters");
@@ -883,6 +918,18 @@ msc_status run_reach(Lane* c, const msc_scene* sc, const Plan& p, int want, bool
             }
         }
     }
+    // Clears the top set B_m (the words its stage can have written, from the stage's
+    // input list) once nothing reads it any more; the window's top is then clean again.
+    auto release_top = [&]() -> msc_status {
+        const int mb = kb;
+        if (!B[mb].at_top) return MSC_OK;
+        LAUNCH(MSC_K_FILL, mb, (int64_t)B[mb + 1].count,
+               launch_unexpand_bwd(B[mb + 1].list, B[mb + 1].count, B[mb].view, jv[mb], c->stream));
+        B[mb].at_top = false;
+        c->clean = c->hi - c->top;
+        c->top = 0;
+        return MSC_OK;
+    };
     MSC_TRY(check_overflow(c, ovf, "a stage set"));
     const int m = kb;
     c->stats.split_m = m;
@@ -898,7 +945,10 @@ msc_status run_reach(Lane* c, const msc_scene* sc, const Plan& p, int want, bool
             if (B[k].used) MSC_TRY(capture_set(c, B[k], N, 1, k));
         }
     }
-    if (empty) return MSC_NO_REACH;
+    if (empty) {
+        MSC_TRY(release_top());
+        return MSC_NO_REACH;
+    }
 
     // C_m and the D sets.  Stage sets used by the canonical walk: D_k (k < m) in F_k's
     // structure, C_m (or B_m, equivalent for the walk) at stage m, B_k for k > m.
@@ -976,7 +1026,10 @@ msc_status run_reach(Lane* c, const msc_scene* sc, const Plan& p, int want, bool
         c->captured[{3, m}] = c->captured[{2, m}];
         if (m >= 1) MSC_TRY(capture_set(c, F[m - 1], N, 3, m - 1));
     }
-    if (joined == 0) return MSC_NO_REACH;
+    if (joined == 0) {
+        MSC_TRY(release_top());
+        return MSC_NO_REACH;
+    }
     for (int k = m - 1; k >= 1; --k) {
         // D_{k-1} from D_k (D_k is Cset for k == m, else F_k's marked structure)
         unsigned long long* dc = take_counter(c);
@@ -1007,6 +1060,7 @@ msc_status run_reach(Lane* c, const msc_scene* sc, const Plan& p, int want, bool
     da.sols = (int32_t*)d_sols;
     da.nsol = (int32_t*)d_nsol;
     LAUNCH(MSC_K_DFS, -1, 0, launch_dfs(da, c->stream));
+    MSC_TRY(release_top());   // after the canonical walk, the last reader of B_m
     MSC_TRY(check_overflow(c, ovf, "a stage set"));   // synchronises the stream
     int32_t nsol = *(volatile int32_t*)h_nsol;
     if (nsol <= 0) return fail(c, MSC_E_STATE, "join not empty but no pose traced");
@@ -1112,6 +1166,8 @@ msc_status lane_init(Lane* L, msc_ctx* o, int index, hipStream_t stream, bool ow
     L->ws = base + kLaneReserved;
     L->hi = size - kLaneReserved;
     L->lo = 0;
+    L->top = 0;
+    L->clean = L->hi;
     // coherent: the host polls values that kernels write while the stream runs on
     if (hipHostMalloc((void**)&L->staging, kStagingBytes, hipHostMallocMapped | hipHostMallocCoherent) !=
         hipSuccess)
@@ -1147,6 +1203,8 @@ msc_status layout_lanes(msc_ctx* o, int nworkers) {
         o->control->ws = o->ws + kLaneReserved;
         o->control->hi = win - kLaneReserved;
         o->control->lo = 0;
+        o->control->top = 0;
+        o->control->clean = o->control->hi;
     }
     for (int i = 0; i < nworkers; ++i) {
         Lane* L = new (std::nothrow) Lane();
@@ -1830,8 +1888,7 @@ msc_status gms_on(Lane* c, const msc_scene* sc, const msc_gms_arm* arm, const in
     HIP_TRY(hipMemcpyAsync(d_order, order.data(), (size_t)n4 * 4, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(hipMemcpyAsync(d_cl, cls.data(), (size_t)ncl * sizeof(GmsCluster), hipMemcpyHostToDevice, c->stream));
     LAUNCH(MSC_K_SEED, 1, n4, launch_gms_points(a, (const int32_t*)d_order, n4, (GmsPoint*)d_pts, c->stream));
-    const uint64_t free_bytes = c->hi > c->lo ? c->hi - c->lo : 0;
-    const uint64_t cap = std::min<uint64_t>(4ull << 20, free_bytes / 16);
+    const uint64_t cap = std::min<uint64_t>(4ull << 20, free_bytes(c) / 16);
     void* d_keys;
     MSC_TRY(arena_alloc(c, std::max<uint64_t>(cap, 1) * 8, &d_keys));
     LAUNCH(MSC_K_FILL, -1, 0, launch_fill((uint64_t*)c->counters, kCounters, 0ull, c->stream));
