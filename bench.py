@@ -149,9 +149,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per expansion launch from the committed counter summary, or None when
-    the summary is missing or was taken on other kernel sources."""
+def measured_traffic(field: str = "HBM bytes per expansion launch"):
+    """A figure of the committed counter summary (default: HBM bytes per expansion
+    launch), or None when the summary is missing, lacks it, or was taken on other kernel
+    sources."""
     try:
         with open(TRAFFIC_PROFILE) as f:
             text = f.read()
@@ -165,7 +166,7 @@ def measured_traffic():
     if fields.get("kernel sources sha256") != kernel_source_hash():
         return None
     try:
-        return float(fields["HBM bytes per expansion launch"])
+        return float(fields[field])
     except (KeyError, ValueError):
         return None
 
@@ -198,10 +199,14 @@ def traffic_run(args):
     from paper_1906_10678_amd import msc, synth
 
     solver = msc.Solver(0, workspace_bytes=args.workspace_gb << 30)
-    queries = [synth.query_c2(s, solver.pose_fn_for) for s in range(args.queries)]
+    queries = []
+    for s in range(args.queries):
+        queries.append(synth.query_c2(s, solver.pose_fn_for))
+        print("traffic run: query %d drawn" % s, flush=True)
     n, na = queries[0].scene.n, queries[0].arm.na
     alg_total, launches = 0, 0
-    for q in queries:
+    for i, q in enumerate(queries):
+        print("traffic run: capturing query %d" % i, flush=True)
         sc = solver.scene(q.scene)
         solver.path(sc, q.arm, q.start, q.target, q.waypoints, q.max_delta, flags=msc.CAPTURE_SETS)
         st = solver.stats()
@@ -216,7 +221,8 @@ def traffic_run(args):
     for _ in range(3):
         y.copy_(x)
     torch.cuda.synchronize()
-    for q in queries:
+    for i, q in enumerate(queries):
+        print("traffic run: solving query %d" % i, flush=True)
         sc = solver.scene(q.scene)
         solver.path(sc, q.arm, q.start, q.target, q.waypoints, q.max_delta)
     torch.cuda.synchronize()
@@ -399,7 +405,10 @@ def traffic_summary(args):
     import csv
     import collections
 
-    fetch_csv, write_csv, alg_json = args.traffic_summary
+    if len(args.traffic_summary) not in (3, 4):
+        raise SystemExit("--traffic-summary takes FETCH_CSV WRITE_CSV ALG_JSON [TCC_CSV]")
+    fetch_csv, write_csv, alg_json = args.traffic_summary[:3]
+    tcc_csv = args.traffic_summary[3] if len(args.traffic_summary) == 4 else None
     alg = json.load(open(alg_json))
 
     def per_kernel(path, counter):
@@ -418,30 +427,86 @@ def traffic_summary(args):
 
     ff, fper = per_kernel(fetch_csv, "FETCH_SIZE")
     wf, wper = per_kernel(write_csv, "WRITE_SIZE")
+    hper = mper = None
+    if tcc_csv:
+        _, hper = per_kernel(tcc_csv, "TCC_HIT_sum")
+        _, mper = per_kernel(tcc_csv, "TCC_MISS_sum")
     expand = [k for k in fper if is_expansion(k)]
     tot = sum(fper[k][0] * ff * 1024 + wper[k][0] * wf * 1024 for k in expand)
     nl = sum(fper[k][1] for k in expand)
     lines = ["# HBM traffic of the stage expansions, 8-DOF reach + path workload (%d queries)" % alg["queries"], "",
-             "Two rocprofv3 counter passes over the same program (`bench.py --traffic-run`):", "",
-             "```", "timeout -s KILL 240 rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o run "
-             "-- python -u bench.py --traffic-run",
-             "timeout -s KILL 240 rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o run "
-             "-- python -u bench.py --traffic-run",
+             "Three rocprofv3 counter passes over the same program (`bench.py --traffic-run`):", "",
+             "```", "timeout -s KILL 420 rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o run "
+             "-- python -u bench.py --traffic-run --queries 16",
+             "timeout -s KILL 420 rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o run "
+             "-- python -u bench.py --traffic-run --queries 16",
+             "timeout -s KILL 420 rocprofv3 --pmc TCC_HIT_sum TCC_MISS_sum --output-format csv "
+             "-d gpurun_out/pmc_tcc -o run -- python -u bench.py --traffic-run --queries 16",
              "python bench.py --traffic-summary gpurun_out/pmc_fetch/run_counter_collection.csv "
-             "gpurun_out/pmc_write/run_counter_collection.csv gpurun_out/traffic_alg.json", "```", "",
+             "gpurun_out/pmc_write/run_counter_collection.csv gpurun_out/traffic_alg.json "
+             "gpurun_out/pmc_tcc/run_counter_collection.csv", "```", "",
              "Counters are KiB per dispatch.  Calibration: a 1 GiB device-to-device copy reads "
              "%.4f x its FETCH_SIZE and writes %.4f x its WRITE_SIZE; both factors are applied." % (ff, wf), "",
-             "| kernel | dispatches | fetch MB | write MB |", "|---|---|---|---|"]
+             "| kernel | dispatches | fetch MB | write MB | L2 requests (10^6) | L2 hit rate |",
+             "|---|---|---|---|---|---|"]
     for k in sorted(set(fper) | set(wper)):
-        lines.append("| %s | %d | %.1f | %.1f |" % (k, fper[k][1], fper[k][0] * ff * 1024 / 1e6,
-                                                    wper[k][0] * wf * 1024 / 1e6))
+        l2 = "| - | - |"
+        if hper is not None and k in hper:
+            req = hper[k][0] + mper[k][0]
+            l2 = "| %.2f | %.3f |" % (req / 1e6, hper[k][0] / req if req else 0.0)
+        lines.append("| %s | %d | %.1f | %.1f %s" % (k, fper[k][1], fper[k][0] * ff * 1024 / 1e6,
+                                                      wper[k][0] * wf * 1024 / 1e6, l2))
     lines += ["", "- expansion launches: %d (algorithmic record: %d)" % (nl, alg["expand_launches"]),
               "- algorithmic bytes per expansion launch: %.0f" % (alg["alg_bytes_total"] / alg["expand_launches"]),
               "- HBM bytes per expansion launch: %.0f" % (tot / max(nl, 1)),
+              ] + ([] if hper is None else [
+              "- L2 requests per expansion launch: %.0f" % (sum(hper[k][0] + mper[k][0] for k in expand) / max(nl, 1)),
+              "- L2 hit rate of the expansions: %.3f" % (sum(hper[k][0] for k in expand) /
+                                                        max(1.0, sum(hper[k][0] + mper[k][0] for k in expand)))]) + [
               "- kernel sources sha256: `%s`" % kernel_source_hash(), ""]
     with open(TRAFFIC_PROFILE, "w") as f:
         f.write("\n".join(lines))
     print("wrote", TRAFFIC_PROFILE, flush=True)
+
+
+GMS_PROFILE = os.path.join(ROOT, "profiles", "gap_search_2deg.md")
+
+
+def gms_summary(args):
+    """Writes the gap search's kernel summary from rocprofv3's kernel statistics of a
+    `--workload gms` run and the JSON line that run printed."""
+    import csv
+
+    stats_csv, bench_json = args.gms_summary
+    res = None
+    for line in open(bench_json):
+        line = line.strip()
+        if line.startswith("{"):
+            res = json.loads(line)
+    rows = list(csv.DictReader(open(stats_csv)))
+    lines = ["# Gap search (the paper's quiver method), 2 degree quiver on the 8-DOF workload's scenes", "",
+             "```", "rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_gms -o run "
+             "-- python -u bench.py --workload gms --queries %d --plain-steps %d" % (res["queries"], args.plain_steps),
+             "python bench.py --gms-summary gpurun_out/prof_gms/run_kernel_stats.csv gpurun_out/gms_bench.json",
+             "```", "",
+             "%s.  Each step solves one target with every solution counted (msc_gms_reach), then "
+             "again searching only until the first 8 are known (msc_gms_reach_first)." % res["config"]["workload"], "",
+             "- solutions per target: %s" % res["solutions"],
+             "- every solution counted, in the profiled run: %.1f solves/s, p50 %.2f ms, p99 %.2f ms"
+             % (res["all_solutions"]["solves_per_s"], res["all_solutions"]["p50_ms"], res["all_solutions"]["p99_ms"]),
+             "- first 8 solutions, in the profiled run: %.1f solves/s, p50 %.2f ms, p99 %.2f ms"
+             % (res["first_8_solutions"]["solves_per_s"], res["first_8_solutions"]["p50_ms"],
+                res["first_8_solutions"]["p99_ms"]),
+             "- kernel sources sha256: `%s`" % kernel_source_hash(), "",
+             "| kernel | calls | total ms | avg us | share |", "|---|---|---|---|---|"]
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"]))[:12]:
+        lines.append("| %s | %s | %.2f | %.1f | %.1f %% |" % (r["Name"].split("(")[0], r["Calls"],
+                                                               float(r["TotalDurationNs"]) / 1e6,
+                                                               float(r["AverageNs"]) / 1e3, float(r["Percentage"])))
+    lines.append("")
+    with open(GMS_PROFILE, "w") as f:
+        f.write("\n".join(lines))
+    print("wrote", GMS_PROFILE, flush=True)
 
 
 TRACE_PROFILE = os.path.join(ROOT, "profiles", "expand_trace_c2.md")
@@ -455,9 +520,11 @@ def is_expansion(kernel_name: str) -> bool:
 
 
 def trace_summary(args):
-    """Kernel-trace summary of a --plain-only run: per-kernel statistics over the whole
-    run, and the average duration of the expansion kernels over the plain timed region
-    (its last expansion dispatches), next to the HIP-event average the run printed."""
+    """Kernel-trace summary of a --plain-only run, restricted to the plain timed region
+    (the last `plain_steps` queries; each starts with its start-pose check): per-kernel
+    statistics, and the average duration of the expansion dispatches of the queries the
+    roofline counts (those with algorithmic bytes), next to the HIP-event average of the
+    same launches that the run printed."""
     import csv
     import collections
 
@@ -469,25 +536,35 @@ def trace_summary(args):
             res = json.loads(line)
     rows = list(csv.DictReader(open(trace_csv)))
     rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    starts = [i for i, r in enumerate(rows) if "k_pose_check" in r["Kernel_Name"]][-args.plain_steps:]
+    nq, n_alg = res["queries"], res["roofline"]["alg_queries"]
+    timed = rows[starts[0]:]
+    t_first = int(rows[starts[0]]["Start_Timestamp"])
+    tail = []
+    for s_idx, a in enumerate(starts):
+        b = starts[s_idx + 1] if s_idx + 1 < len(starts) else len(rows)
+        if s_idx % nq < n_alg:
+            tail += [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in rows[a:b]
+                     if is_expansion(r["Kernel_Name"])]
+    nl = len(tail)
     stats = collections.defaultdict(list)
-    for r in rows:
+    for r in timed:
         stats[r["Kernel_Name"].split("(")[0]].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
-    ex = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in rows
-          if is_expansion(r["Kernel_Name"])]
-    nl = res["roofline"]["launches"]
-    tail = ex[-nl:]
     lines = ["# Kernel trace, 8-DOF reach + 16-waypoint path queries (plain phase of bench.py)", "",
              "```", "rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof -o run "
              "-- python -u bench.py --plain-only --no-cpu-baseline",
              "python bench.py --trace-summary gpurun_out/prof/run_kernel_trace.csv gpurun_out/prof_bench.json", "```", "",
-             "The run captures stage sets of the %d queries (algorithmic bytes), warms up, then times %d "
-             "plain queries; the expansion kernels of that timed region are its last %d expansion dispatches."
-             % (res["queries"], args.plain_steps, nl), "",
-             "- expansion dispatches in the timed region: %d" % nl,
+             "The run captures the stage sets of the first %d of its %d queries (algorithmic bytes), warms up, "
+             "then times %d plain queries (query i %% %d); the roofline's launches are the expansion dispatches "
+             "of the timed queries with algorithmic bytes." % (n_alg, nq, args.plain_steps, nq), "",
+             "- expansion dispatches counted: %d (the run's HIP-event record: %d)" % (nl, res["roofline"]["launches"]),
              "- their average duration, kernel trace (us): %.2f" % (sum(tail) / max(len(tail), 1)),
              "- their average duration, HIP events in the run (us): %.2f" % res["roofline"]["avg_launch_us"],
              "- algorithmic bytes per expansion launch: %d" % res["roofline"]["alg_bytes_per_launch"],
-             "- plain solves/s in the traced run: %.1f" % res["plain"]["solves_per_s"], "",
+             "- plain solves/s in the traced run: %.1f" % res["plain"]["solves_per_s"],
+             "- kernel sources sha256: `%s`" % kernel_source_hash(), "",
+             "Per-kernel statistics of the timed region (%d dispatches, %.1f ms from its first expansion "
+             "dispatch to the end of the run):" % (len(timed), (int(timed[-1]["End_Timestamp"]) - t_first) / 1e6), "",
              "| kernel | calls | total ms | avg us | min us | max us |", "|---|---|---|---|---|---|"]
     for k, v in sorted(stats.items(), key=lambda kv: -sum(kv[1])):
         lines.append("| %s | %d | %.2f | %.1f | %.1f | %.1f |" % (k, len(v), sum(v) / 1e3, sum(v) / len(v), min(v),
@@ -1017,9 +1094,14 @@ def main():
     ap.add_argument("--traffic-run", action="store_true",
                     help="run the program of the HBM counter passes (see profiles/expand_traffic_c2.md)")
     ap.add_argument("--traffic-out", default="gpurun_out/traffic_alg.json")
-    ap.add_argument("--traffic-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "ALG_JSON"),
-                    help="write profiles/expand_traffic_c2.md from the counter passes")
+    ap.add_argument("--gms-summary", nargs=2, metavar=("KERNEL_STATS_CSV", "BENCH_JSON"),
+                    help="write profiles/gap_search_2deg.md from a kernel-statistics run of --workload gms")
+    ap.add_argument("--traffic-summary", nargs="+", metavar="CSV_OR_JSON",
+                    help="FETCH_CSV WRITE_CSV ALG_JSON [TCC_CSV]: write profiles/expand_traffic_c2.md from the "
+                         "counter passes (the optional third pass: TCC_HIT_sum and TCC_MISS_sum)")
     args = ap.parse_args()
+    if args.gms_summary:
+        return gms_summary(args)
     if args.traffic_summary:
         return traffic_summary(args)
     if args.trace_summary:
@@ -1142,6 +1224,7 @@ def main():
     achieved = b_sum / (ms_sum * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": measured_traffic(),
+                "l2_hit_rate": measured_traffic("L2 hit rate of the expansions"),
                 "kernel": "expand (k_expand_fwd + k_expand_bwd)", "launches": cnt,
                 "avg_launch_us": round(1e3 * ms_sum / max(cnt, 1), 2),
                 "alg_bytes_per_launch": round(b_sum / max(cnt, 1)),
