@@ -918,13 +918,19 @@ msc_status run_reach(Lane* c, const msc_scene* sc, const Plan& p, int want, bool
             }
         }
     }
-    // Clears the top set B_m (the words its stage can have written, from the stage's
-    // input list) once nothing reads it any more; the window's top is then clean again.
+    // Clears the top set B_m once nothing reads it any more, so that the window's top is
+    // clean again: by the words its stage can have written, from the stage's input list
+    // (one state costs about as much as a fill of 8 words), or by a fill when the input
+    // list is longer than an eighth of the set's words.
     auto release_top = [&]() -> msc_status {
         const int mb = kb;
         if (!B[mb].at_top) return MSC_OK;
-        LAUNCH(MSC_K_FILL, mb, (int64_t)B[mb + 1].count,
-               launch_unexpand_bwd(B[mb + 1].list, B[mb + 1].count, B[mb].view, jv[mb], c->stream));
+        if (B[mb + 1].count < B[mb].view.cap / 8)
+            LAUNCH(MSC_K_FILL, mb, (int64_t)B[mb + 1].count,
+                   launch_unexpand_bwd(B[mb + 1].list, B[mb + 1].count, B[mb].view, jv[mb], c->stream));
+        else
+            LAUNCH(MSC_K_FILL, -1, (int64_t)B[mb].view.cap,
+                   launch_fill(B[mb].view.words, B[mb].view.cap, 0ull, c->stream));
         B[mb].at_top = false;
         c->clean = c->hi - c->top;
         c->top = 0;
