@@ -143,3 +143,56 @@ def test_gms_first_solutions_full_size(solver):
             ref = gms.solutions(arm, occ, t, limit=8)
             assert [tuple(x) for x in sols_f] == ref[:len(sols_f)]
     assert answered >= 2
+
+
+def test_gms_argument_errors(solver):
+    """Bad arguments are rejected before any GPU work, with E_ARG."""
+    arm, sc, rng = small_case(0, 3000, 24, 2)
+    scene = solver.scene(sc)
+    t = (12, 12, 10)
+
+    def bad(**kw):
+        a = gms.GmsArm(arm.lens, arm.base, step_cdeg=arm.step_cdeg, samples=arm.samples,
+                       max_flex_cdeg=arm.max_flex_cdeg, eps=arm.eps)
+        for k, v in kw.items():
+            setattr(a, k, v)
+        return a
+
+    cases = [(bad(step_cdeg=7000), t), (bad(m_min=0), t), (bad(samples=0), t), (bad(samples=65), t),
+             (bad(eps=-0.1), t), (bad(eps=float("nan")), t), (bad(lens=[3.0, 0.0, 3.0, 3.0]), t),
+             (bad(max_flex_cdeg=(18001, 9000, 9000)), t), (bad(approach=(0, -9000, 18001)), t),
+             (bad(base=(24, 0, 0)), t), (arm, (-1, 3, 3)), (arm, (3, 3, 24))]
+    for a, tt in cases:
+        with pytest.raises(msc.MscError) as e:
+            solver.gms_reach(scene, a, tt, 4)
+        assert e.value.status == msc.E_ARG
+    with pytest.raises(msc.MscError) as e:
+        solver.gms_reach(scene, arm, t, 0)
+    assert e.value.status == msc.E_ARG
+
+
+def test_gms_degenerate_settings(solver):
+    """Limits at their edges, against the oracle's full solution sets: no length slack
+    (eps 0), a zero-width approach cone, no flexion allowed (a straight arm), segment 1
+    straight up only, and more solutions wanted than exist."""
+    checked = 0
+    for seed in range(3):
+        arm, sc, rng = small_case(seed + 40, 2000, 24, 3)
+        occ = oracle.raster(sc)
+        scene = solver.scene(sc)
+        ts = targets_of(arm, occ, rng, 2)
+        straight = (arm.base[0], arm.base[1], arm.base[2] + int(round(sum(arm.lens))))
+        if straight[2] < 24 and occ[straight[2], straight[1], straight[0]] == 0:
+            ts.append(np.array(straight))
+        variants = [dict(eps=0.0), dict(approach=(0, -9000, 0)), dict(max_flex_cdeg=(0, 0, 0), eps=1e-6),
+                    dict(seg1_min_el_cdeg=9000)]
+        for kw in variants:
+            a = gms.GmsArm(arm.lens, arm.base, step_cdeg=arm.step_cdeg, samples=arm.samples,
+                           max_flex_cdeg=arm.max_flex_cdeg, eps=arm.eps)
+            for k, v in kw.items():
+                setattr(a, k, v)
+            for t in ts:
+                say("gms degenerate", seed, kw, tuple(t))
+                compare(solver, scene, a, occ, t, want=64)
+                checked += 1
+    assert checked >= 24
