@@ -1031,13 +1031,15 @@ def bench_c5(args):
     solver.set_lanes(lanes)
     rows = []
     for rate in args.c5_rates:
-        loop = serve.ServingLoop(solver, nscenes=16, seed=0, rate=rate, templates=args.c5_templates)
+        loop = serve.ServingLoop(solver, nscenes=16, seed=0, rate=rate, templates=args.c5_templates,
+                                 max_pending=args.c5_max_pending)
         rep = loop.run(seconds=args.c5_seconds, warmup_s=1.0)
         row = {"rate_per_s": rate}
         row.update(rep.summary())
         rows.append(row)
         print(json.dumps(row), file=sys.stderr, flush=True)
-    out = {"metric": "served solves/sec and p50/p99 ms", "lanes": lanes, "seconds": args.c5_seconds, "rows": rows,
+    out = {"metric": "served solves/sec and p50/p99 ms", "lanes": lanes, "seconds": args.c5_seconds,
+           "max_pending": args.c5_max_pending, "rows": rows,
            "config": {"workload": "serving: 16 scenes 256^3 + 1..8 moving boxes, 70% reach / 30% path (8..32 "
                                   "waypoints), DOF 6..8, 10 ms ticks, replans on collision"}}
     print(json.dumps(out), flush=True)
@@ -1063,6 +1065,8 @@ def main():
     ap.add_argument("--c5-rates", type=float, nargs="+", default=[200.0, 500.0, 1000.0, 2000.0])
     ap.add_argument("--c5-seconds", type=float, default=10.0)
     ap.add_argument("--c5-templates", type=int, default=3000)
+    ap.add_argument("--c5-max-pending", type=int, default=32,
+                    help="serving: the server refuses requests while this many wait for a lane (0: no limit)")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=8, help="timed batches")
     ap.add_argument("--warmup", type=int, default=2, help="untimed batches")

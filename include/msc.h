@@ -457,6 +457,13 @@ uint64_t msc_query_bytes(const msc_query* q);
  * the server is not running.  poll sets *done = 1 once q->status is written. */
 msc_status msc_server_start(msc_ctx* ctx, const msc_opts* opts);
 msc_status msc_server_submit(msc_ctx* ctx, msc_query* q, uint64_t* ticket);
+/* Admission by queue depth ("Dynamic Obstacles": an answer is only useful while the
+ * arm can still act on it): while max_pending submitted queries wait for a lane,
+ * msc_server_submit refuses new ones with MSC_E_CAPACITY (no ticket, nothing queued),
+ * so that the answers given stay timely under overload; 0 (the default when the server
+ * starts) sets no limit.  Replans queued by msc_server_step are always admitted.
+ * E_STATE if the server is not running, E_ARG if max_pending < 0. */
+msc_status msc_server_set_limit(msc_ctx* ctx, int32_t max_pending);
 /* *done = 1 once (and only the first time) the ticket's query has completed; E_STATE for
  * a ticket that was never issued or whose completion was already reported. */
 msc_status msc_server_poll(msc_ctx* ctx, uint64_t ticket, int32_t* done);

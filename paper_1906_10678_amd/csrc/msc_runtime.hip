@@ -2193,6 +2193,7 @@ struct ServerState {
     std::mutex mu;
     std::condition_variable cv;
     std::deque<Job> queue;
+    size_t max_pending = 0;                  // submissions refused while this many wait (0: no limit)
     std::map<uint64_t, double> submitted;   // ticket -> submission time (ms), until finished
     std::set<uint64_t> done;                 // finished, not yet reported by poll / wait
     std::condition_variable done_cv;
@@ -2887,6 +2888,16 @@ msc_status msc_server_start(msc_ctx* o, const msc_opts* opts) {
     return MSC_OK;
 }
 
+msc_status msc_server_set_limit(msc_ctx* o, int32_t max_pending) {
+    if (!o) return MSC_E_ARG;
+    if (max_pending < 0) return ctx_fail(o, MSC_E_ARG, "max_pending < 0");
+    ServerState* S = o->server;
+    if (!S) return ctx_fail(o, MSC_E_STATE, "the server is not running");
+    std::lock_guard<std::mutex> lock(S->mu);
+    S->max_pending = (size_t)max_pending;
+    return MSC_OK;
+}
+
 msc_status msc_server_submit(msc_ctx* o, msc_query* q, uint64_t* ticket) {
     if (!o || !q || !ticket) return MSC_E_ARG;
     ServerState* S = o->server;
@@ -2898,12 +2909,22 @@ msc_status msc_server_submit(msc_ctx* o, msc_query* q, uint64_t* ticket) {
     Job job;
     job.q = q;
     job.bind = bind_scene(q->scene);   // the grid of the scene's current tick
+    bool refused = false;
     {
         std::lock_guard<std::mutex> lock(S->mu);
-        job.ticket = S->next_ticket++;
-        *ticket = job.ticket;
-        S->submitted[job.ticket] = now_ms();
-        S->queue.push_back(std::move(job));
+        // admission by queue depth: a submission that would wait behind max_pending
+        // others is refused (the caller sheds it); replans issued by msc_server_step are not
+        refused = S->max_pending && S->queue.size() >= S->max_pending;
+        if (!refused) {
+            job.ticket = S->next_ticket++;
+            *ticket = job.ticket;
+            S->submitted[job.ticket] = now_ms();
+            S->queue.push_back(std::move(job));
+        }
+    }
+    if (refused) {
+        unbind_scene(job.bind);
+        return MSC_E_CAPACITY;
     }
     S->cv.notify_one();
     return MSC_OK;

@@ -33,7 +33,7 @@ EXPORTS = [
     "msc_server_submit", "msc_server_poll", "msc_server_wait", "msc_server_stop", "msc_refine", "msc_replan",
     "msc_scene_bytes_dynamic", "msc_scene_set_dynamic", "msc_server_step", "msc_server_take_replans",
     "msc_refine_static", "msc_refine_static_max", "msc_track_default", "msc_guided_path", "msc_pose_path",
-    "msc_autotune", "msc_tune_load", "msc_tune_entries", "msc_short_path", "msc_gms_quiver", "msc_gms_reach", "msc_gms_reach_first",
+    "msc_autotune", "msc_tune_load", "msc_tune_entries", "msc_short_path", "msc_gms_quiver", "msc_gms_reach", "msc_gms_reach_first", "msc_server_set_limit",
 ]
 
 
@@ -171,6 +171,7 @@ def load_library(path: str = LIB_PATH):
                                 P(i32), P(i32)]
     L.msc_short_path.argtypes = [c_void_p, c_void_p, P(MscArm), P(i32), i32, i32, P(MscTrack), P(MscOpts), P(i32),
                                  P(i32), P(i32)]
+    L.msc_server_set_limit.argtypes = [c_void_p, i32]
     L.msc_gms_quiver.argtypes = [i32, i32, P(ctypes.c_double), i32]
     L.msc_gms_quiver.restype = i32
     L.msc_gms_reach.argtypes = [c_void_p, c_void_p, P(MscGmsArm), P(i32), i32, P(i64), P(i32), P(ctypes.c_double),
@@ -673,9 +674,18 @@ class Solver:
         self._check(self.lib.msc_server_start(self.ctx, ctypes.byref(o)), "msc_server_start")
         self._inflight = {}
 
-    def submit(self, spec: QuerySpec) -> int:
+    def server_set_limit(self, max_pending: int):
+        """msc_server_set_limit: refuse submissions while max_pending queries wait (0: none)."""
+        self._check(self.lib.msc_server_set_limit(self.ctx, int(max_pending)), "msc_server_set_limit")
+
+    def submit(self, spec: QuerySpec, shed: bool = False) -> Optional[int]:
+        """msc_server_submit: the ticket; with shed, None when the server refuses the query
+        for its queue depth (E_CAPACITY) instead of raising."""
         t = ctypes.c_uint64()
-        self._check(self.lib.msc_server_submit(self.ctx, ctypes.byref(spec.c), ctypes.byref(t)), "msc_server_submit")
+        rc = self.lib.msc_server_submit(self.ctx, ctypes.byref(spec.c), ctypes.byref(t))
+        if shed and rc == E_CAPACITY:
+            return None
+        self._check(rc, "msc_server_submit")
         self._inflight[t.value] = spec
         return t.value
 

@@ -20,7 +20,9 @@ this module only draws the workload and drives the clock:
   (NO_REACH), which are served outcomes like any other.  Solved paths execute on the
   server;
 * latency of every request (submission to completion, measured by the library) is
-  recorded per class: reach, path, and the replans the server issued.
+  recorded per class: reach, path, and the replans the server issued; with
+  ``max_pending`` the server refuses new requests while that many wait for a lane
+  (admission by queue depth), and the refused ones are counted as shed.
 
 Random draws come from `synth`; kinematics, rasterisation, re-validation and search
 all run in the library.
@@ -160,6 +162,7 @@ class ServeReport:
     stale_ticks: int = 0       # ticks whose grid could not be written (every grid of a tick in use)
     replans: int = 0
     stopped: int = 0
+    shed: int = 0              # requests the server refused for its queue depth
     unserved: int = 0          # requests or replans still in flight when the drain timed out
     tick_ms: List[float] = field(default_factory=list)   # host time spent in each tick's work
     done_log: List[tuple] = field(default_factory=list)   # (kind, scene_idx, tick, status, result, spec)
@@ -173,7 +176,7 @@ class ServeReport:
         out = {"served": self.served, "submitted": self.submitted, "wall_s": round(self.wall_s, 3),
                "solves_per_s": round(self.served / max(self.wall_s, 1e-9), 2), "ticks": self.ticks,
                "late_ticks": self.late_ticks, "stale_ticks": self.stale_ticks, "replans": self.replans,
-               "stopped": self.stopped}
+               "stopped": self.stopped, "shed": self.shed}
         if self.tick_ms:
             t = np.array(self.tick_ms)
             out["tick_work_ms"] = {"p50": round(float(np.percentile(t, 50)), 3),
@@ -192,7 +195,8 @@ class ServingLoop:
                  tick_ms: float = 10.0, path_frac: float = 0.3, ticks_per_waypoint: int = 8,
                  keep_log: bool = False, templates: int = 2000, n: int = 256,
                  dof_range: Tuple[int, int] = (6, 8), w_range: Tuple[int, int] = (8, 32),
-                 arm_for: Optional[Callable[[int], synth.Arm]] = None, tick_grids: int = 24):
+                 arm_for: Optional[Callable[[int], synth.Arm]] = None, tick_grids: int = 24,
+                 max_pending: int = 0):
         self.solver = solver
         self.rng = synth.rng_for(6, seed)
         column = (arm_for(dof_range[1]) if arm_for else c5_arm(dof_range[1], n)).lens[0]
@@ -209,6 +213,7 @@ class ServingLoop:
         self.report = ServeReport()
         self.mover_log: Dict[int, List[np.ndarray]] = {}   # tick -> moving boxes per scene (keep_log)
         self.replans_inflight = 0
+        self.max_pending = max_pending   # > 0: the server sheds submissions beyond this queue depth
 
     # -- scenes -----------------------------------------------------------------
     def advance_tick(self):
@@ -249,7 +254,10 @@ class ServingLoop:
         return Request("reach", msc.QuerySpec(scene, tp.arm, tp.target), scene_idx=tp.scene_idx)
 
     def submit(self, req: Request):
-        req.ticket = self.solver.submit(req.spec)
+        req.ticket = self.solver.submit(req.spec, shed=self.max_pending > 0)
+        if req.ticket is None:
+            self.report.shed += 1
+            return
         self.pending.append(req)
         self.report.submitted += 1
 
@@ -278,6 +286,8 @@ class ServingLoop:
     # -- loop -------------------------------------------------------------------
     def run(self, seconds: float, warmup_s: float = 1.0, drain_s: float = 30.0) -> ServeReport:
         self.solver.server_start()
+        if self.max_pending:
+            self.solver.server_set_limit(self.max_pending)
         try:
             t_begin = time.perf_counter()
             next_tick_at = t_begin

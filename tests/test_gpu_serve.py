@@ -197,3 +197,43 @@ def test_tickets_and_error_messages(solver):
     finally:
         solver.server_stop()
         solver.set_lanes(0)
+
+
+def test_admission_by_queue_depth(solver):
+    """With a queue limit the server refuses submissions (E_CAPACITY, no ticket) while that
+    many wait for a lane; every admitted query completes with the oracle's answer, and a
+    refused one can be submitted again later."""
+    arm = small_arm(4)
+    dyn = serve.make_dyn_scene(5, 64, column=10)
+    scene = solver.scene(dyn.static)
+    occ = oracle.raster(dyn.static)
+    rng = synth.rng_for(9, 3)
+    targets = []
+    for _ in range(6):
+        _, end, _ = synth.first_valid_pose(rng, arm, lambda q: oracle.poses(arm, occ, q))
+        targets.append(end)
+    solver.set_lanes(1)
+    solver.server_start()
+    try:
+        solver.server_set_limit(1)
+        admitted, refused = [], []
+        for t in targets * 4:
+            spec = msc.QuerySpec(scene, arm, t)
+            ticket = solver.submit(spec, shed=True)
+            (refused if ticket is None else admitted).append((ticket, spec, t))
+        assert admitted
+        for ticket, spec, t in admitted:
+            st, pose, _ = solver.wait(ticket)
+            r = oracle.reach(arm, occ, t, keep_sets=False)
+            assert st == r.status
+            if st == msc.OK:
+                assert np.array_equal(pose, r.pose)
+        if refused:
+            _, spec, t = refused[0]
+            st, pose, _ = solver.wait(solver.submit(spec))
+            assert st == oracle.reach(arm, occ, t, keep_sets=False).status
+        assert solver.lib.msc_server_set_limit(solver.ctx, -1) == msc.E_ARG
+        solver.server_set_limit(0)
+    finally:
+        solver.server_stop()
+        solver.set_lanes(0)
