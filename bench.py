@@ -662,6 +662,21 @@ def bench_c3(args):
             specs.append(msc.QuerySpec(scenes[id(q.scene)], q.arm, q.target))
         return solver.batch(specs)
 
+    tuned = None
+    if args.autotune and args.autotune != "none":
+        # launch shapes tuned on the first 32 queries (a cache of its own: other sizes)
+        cache = args.autotune.replace("msc_tune_c2", "msc_tune_c3")
+        ts = time.perf_counter()
+        scenes = {}
+        specs = []
+        for q in qs[:32]:
+            if id(q.scene) not in scenes:
+                scenes[id(q.scene)] = solver.scene(q.scene)
+            specs.append(msc.QuerySpec(scenes[id(q.scene)], q.arm, q.target))
+        entries = solver.autotune(specs, cache)
+        tuned = {"entries": len(entries), "non_default": sum(1 for e in entries if e[2] != 0),
+                 "seconds": round(time.perf_counter() - ts, 2), "cache": cache}
+        print("autotune", tuned, file=sys.stderr, flush=True)
     lanes = args.lanes if args.lanes > 0 else 8
     solver.set_lanes(lanes)
     step()
@@ -679,6 +694,7 @@ def bench_c3(args):
            "queries": len(qs), "solved_fraction": round(sts.count(msc.OK) / len(sts), 4),
            "statuses": {str(k): sts.count(k) for k in set(sts)},
            "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+           "autotune": tuned,
            "config": {"workload": "batched reach: 64 scenes 128^3/256^3, 8 queries each, DOF 5..8, unwindowed, 5 deg"}}
     print(json.dumps(out), flush=True)
 
@@ -1216,15 +1232,21 @@ def main():
             t = per_kernel.setdefault(kname, [0.0, 0])
             t[0] += ms
             t[1] += 1
-    b_sum, ms_sum, cnt = 0.0, 0.0, 0
+    b_sum, ms_sum, cnt, transitions = 0.0, 0.0, 0, 0
     for qi, recs in launches:
         if alg[qi] is None:
             continue
+        q = queries[qi]
+        # the joint windows of the query's reach search: start +- W * delta, within the limits
+        wlo = np.maximum(q.arm.lo_steps(), np.asarray(q.start) - q.waypoints * q.max_delta)
+        whi = np.minimum(q.arm.hi_steps(), np.asarray(q.start) + q.waypoints * q.max_delta)
         for kname, stage, nin, nout, ms in recs:
             if kname in ("expand_fwd", "expand_bwd"):
                 b_sum += alg[qi][(kname, stage)]
                 ms_sum += ms
                 cnt += 1
+                j = stage - 1 if kname == "expand_fwd" else stage   # the joint the stage turns
+                transitions += nin * int(whi[j] - wlo[j] + 1)
     achieved = b_sum / (ms_sum * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": measured_traffic(),
@@ -1233,6 +1255,8 @@ def main():
                 "avg_launch_us": round(1e3 * ms_sum / max(cnt, 1), 2),
                 "alg_bytes_per_launch": round(b_sum / max(cnt, 1)),
                 "alg_bytes_max_launch": int(max(v for a in alg if a is not None for v in a.values())),
+                "transitions_per_s": round(transitions / (ms_sum * 1e-3), 1),
+                "transitions_per_launch": round(transitions / max(cnt, 1)),
                 "alg_queries": sum(1 for a in alg if a is not None)}
     plain_lat = np.array(lat) * 1e3
     plain = {"solves_per_s": round(args.plain_steps / plain_wall, 3),
