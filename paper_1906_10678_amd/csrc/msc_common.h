@@ -71,6 +71,12 @@ struct Shape {
     int lg_bias = 0;
 };
 
+// Timing of the next set-expansion launch (launch_expand_fwd / launch_expand_bwd) by
+// events attached to its dispatch; host thread local.  take_launch_events_used clears
+// them and tells whether a launch used them.
+void set_launch_events(hipEvent_t start, hipEvent_t stop);
+bool take_launch_events_used();
+
 // Launch wrappers (msc_kernels.hip).  All enqueue on `st`.
 hipError_t launch_fill(uint64_t* p, uint64_t n, uint64_t value, hipStream_t st);
 hipError_t launch_tables(int na, int S, int L, short4* off, short4* sweep, unsigned int* maxn2,

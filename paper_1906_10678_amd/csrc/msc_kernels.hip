@@ -8,6 +8,7 @@
 // "The procedure for IK solution").  Everything here is integer / bitwise work: no
 // kernel is a dense contraction, so none uses the matrix cores.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <mutex>
@@ -238,6 +239,23 @@ int group_log2_for(uint64_t count, int nA) {
     return lg;
 }
 
+// Events for the next set-expansion launch (host thread local): when set, the launch
+// carries them on its own dispatch (hipExtLaunchKernelGGL), so they time the kernel
+// itself rather than the kernel plus the gap before it.
+thread_local hipEvent_t t_ev_start = nullptr, t_ev_stop = nullptr;
+thread_local bool t_ev_used = false;
+
+template <typename K, typename... A>
+void launch_timed(K kernel, dim3 grid, dim3 block, uint32_t shmem, hipStream_t st, A... args) {
+    if (t_ev_start) {
+        hipExtLaunchKernelGGL(kernel, grid, block, shmem, st, t_ev_start, t_ev_stop, 0u, args...);
+        t_ev_used = true;
+        t_ev_start = t_ev_stop = nullptr;
+    } else {
+        hipLaunchKernelGGL(kernel, grid, block, shmem, st, args...);
+    }
+}
+
 uint32_t grid_for(uint64_t work, uint32_t block = kBlock, uint32_t max_blocks = 16384) {
     uint64_t b = (work + block - 1) / block;
     if (b < 1) b = 1;
@@ -282,6 +300,19 @@ __global__ void k_fill16nt(uint64_t* p, uint64_t n, uint64_t v) {
     if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) p[n - 1] = v;
 }
 constexpr uint64_t kFillNtWords = (64ull << 20) / 8;
+void set_launch_events(hipEvent_t start, hipEvent_t stop) {
+    t_ev_start = start;
+    t_ev_stop = stop;
+    t_ev_used = false;
+}
+
+bool take_launch_events_used() {
+    const bool used = t_ev_used;
+    t_ev_used = false;
+    t_ev_start = t_ev_stop = nullptr;
+    return used;
+}
+
 hipError_t launch_fill(uint64_t* p, uint64_t n, uint64_t value, hipStream_t st) {
     if (n == 0) return hipSuccess;
     if (((uintptr_t)p & 15) == 0 && n >= kFillNtWords)
@@ -690,7 +721,7 @@ hipError_t launch_expand_fwd(const uint64_t* in, uint64_t count, SetView out, Gr
                              unsigned long long* overflow, hipStream_t st, Shape sh) {
     uint64_t work = count * (uint64_t)(j.hi - j.lo + 1);
     if (work == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_expand_fwd, dim3(grid_for(work, kBlock, sh.max_blocks)), dim3(kBlock), 0, st, in, count,
+    launch_timed(k_expand_fwd, dim3(grid_for(work, kBlock, sh.max_blocks)), dim3(kBlock), 0, st, in, count,
                        out, g, j, tx, ty, tz, r2, counter, overflow);
     return hipGetLastError();
 }
@@ -867,16 +898,16 @@ void launch_bwd_dense(int np, dim3 grid, hipStream_t st, const uint64_t* in, uin
                       GridView g, JointView j, int bx, int by, int bz, long long r2, const uint64_t* orows,
                       unsigned long long* counter, unsigned long long* overflow) {
     if (np == 2)
-        hipLaunchKernelGGL((k_expand_bwd<2, COUNT>), grid, dim3(kBlock), 0, st, in, count, out, g, j, bx, by, bz, r2,
+        launch_timed(k_expand_bwd<2, COUNT>, grid, dim3(kBlock), 0, st, in, count, out, g, j, bx, by, bz, r2,
                            orows, counter, overflow);
     else if (np == 3)
-        hipLaunchKernelGGL((k_expand_bwd<3, COUNT>), grid, dim3(kBlock), 0, st, in, count, out, g, j, bx, by, bz, r2,
+        launch_timed(k_expand_bwd<3, COUNT>, grid, dim3(kBlock), 0, st, in, count, out, g, j, bx, by, bz, r2,
                            orows, counter, overflow);
     else if (np == 4)
-        hipLaunchKernelGGL((k_expand_bwd<4, COUNT>), grid, dim3(kBlock), 0, st, in, count, out, g, j, bx, by, bz, r2,
+        launch_timed(k_expand_bwd<4, COUNT>, grid, dim3(kBlock), 0, st, in, count, out, g, j, bx, by, bz, r2,
                            orows, counter, overflow);
     else
-        hipLaunchKernelGGL((k_expand_bwd<5, COUNT>), grid, dim3(kBlock), 0, st, in, count, out, g, j, bx, by, bz, r2,
+        launch_timed(k_expand_bwd<5, COUNT>, grid, dim3(kBlock), 0, st, in, count, out, g, j, bx, by, bz, r2,
                            orows, counter, overflow);
 }
 
@@ -894,7 +925,7 @@ hipError_t launch_expand_bwd(const uint64_t* in, uint64_t count, SetView out, Gr
             launch_bwd_dense<false>(np, grid, st, in, count, out, g, j, bx, by, bz, r2, orows, counter, overflow);
     } else {
         const int lg = std::clamp(group_log2_for(count, j.hi - j.lo + 1) + sh.lg_bias, 0, 6);
-        hipLaunchKernelGGL(k_expand_bwd_set, dim3(grid_for(count << lg, kBlock, sh.max_blocks)), dim3(kBlock), 0, st,
+        launch_timed(k_expand_bwd_set, dim3(grid_for(count << lg, kBlock, sh.max_blocks)), dim3(kBlock), 0, st,
                            in, count, out, g, j, bx, by, bz, r2, orows, counter, overflow, lg);
     }
     return hipGetLastError();

@@ -213,8 +213,13 @@ msc_status fail(Lane* c, msc_status st, const char* fmt, ...) {
 uint64_t align_up(uint64_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
 // Launch timing (MSC_PROFILE).
+// The set expansions are timed by events carried on their own dispatch; other launches
+// by events recorded on the stream around them.
+bool timed_on_dispatch(int kernel) { return kernel == MSC_K_EXPAND_FWD || kernel == MSC_K_EXPAND_BWD; }
+
 int prof_begin(Lane* c, int kernel, int stage, int64_t in) {
     c->last_rec = -1;
+    (void)take_launch_events_used();
     if (!c->profiling) return -1;
     size_t idx = c->recs.size();
     while (c->events.size() < 2 * (idx + 1)) {
@@ -222,7 +227,10 @@ int prof_begin(Lane* c, int kernel, int stage, int64_t in) {
         if (hipEventCreate(&e) != hipSuccess) return -1;
         c->events.push_back(e);
     }
-    if (hipEventRecord(c->events[2 * idx], c->stream) != hipSuccess) return -1;
+    if (timed_on_dispatch(kernel))
+        set_launch_events(c->events[2 * idx], c->events[2 * idx + 1]);
+    else if (hipEventRecord(c->events[2 * idx], c->stream) != hipSuccess)
+        return -1;
     msc_timing t{};
     t.kernel = kernel;
     t.stage = stage;
@@ -236,7 +244,12 @@ int prof_begin(Lane* c, int kernel, int stage, int64_t in) {
 }
 
 void prof_end(Lane* c, int idx) {
-    if (idx >= 0) (void)hipEventRecord(c->events[2 * idx + 1], c->stream);
+    if (idx < 0) return;
+    if (timed_on_dispatch(c->recs[idx].kernel)) {
+        if (take_launch_events_used()) return;
+        (void)hipEventRecord(c->events[2 * idx], c->stream);   // nothing was launched
+    }
+    (void)hipEventRecord(c->events[2 * idx + 1], c->stream);
 }
 
 void prof_out(Lane* c, int idx, int64_t out) {
