@@ -278,7 +278,8 @@ msc_status msc_short_path(msc_ctx* ctx, const msc_scene* scene, const msc_arm* a
  * segments 1, 2 and 4 point along vectors of a quiver, an approximately equal-area tiling
  * of the sphere, and whose segment 3 is a free vector across the gap.
  *
- * Quiver of step D = step_cdeg / 100 degrees (D divides 180, n = 360 / D): elevations
+ * Quiver of step D = step_cdeg / 100 degrees (D divides 180 and is at least 0.2, so
+ * that the quiver has fewer than 2^20 vectors; n = 360 / D): elevations
  * e_i = -90 + i D, i = 0..180/D; ring i has 1 vector at a pole, else max(min_ring,
  * round(n cos e_i)) (halves away from zero, 1e-9 band), azimuths a_ij = (j * 360) / m_i;
  * vector (cos e cos a, cos e sin a, sin e) in FP64, radians = (degrees * pi) / 180; flat
@@ -309,7 +310,7 @@ typedef struct {
     double eps;
 } msc_gms_arm;
 /* The quiver's vectors (host only): fills min(cap, count) of them into out[cap*3] and
- * returns the count (0 for a bad step or min_ring < 1). */
+ * returns the count (0 for a bad step, below 20 or not dividing 18000, or min_ring < 1). */
 int32_t msc_gms_quiver(int32_t step_cdeg, int32_t min_ring, double* out, int32_t cap);
 msc_status msc_gms_reach(msc_ctx* ctx, const msc_scene* scene, const msc_gms_arm* arm, const int32_t target[3],
                          int32_t want, int64_t* count_out, int32_t* sols_out, double* vec_out, int32_t* nsol_out);

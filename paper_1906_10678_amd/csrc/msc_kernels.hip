@@ -462,7 +462,7 @@ hipError_t launch_raster(uint64_t* occ, int n, int wpr, int r, const int32_t* bo
 
 hipError_t launch_raster_inline(uint64_t* occ, int n, int wpr, int r, const RasterInline& inl, int nbox, int nsph,
                                 hipStream_t st) {
-    if (nbox < 0 || nsph < 0 || nbox * 6 + nsph * 4 > kRasterInline) return hipErrorInvalidValue;
+    if (nbox < 0 || nsph < 0 || (int64_t)nbox * 6 + (int64_t)nsph * 4 > kRasterInline) return hipErrorInvalidValue;
     uint64_t total = (uint64_t)n * n * wpr;
     hipLaunchKernelGGL(k_raster, dim3(grid_for(total)), dim3(kBlock), 0, st, occ, n, wpr, r, (const int32_t*)nullptr,
                        nbox, (const int32_t*)nullptr, nsph, inl, 1);

@@ -1758,7 +1758,8 @@ long long gms_round_host(double v) {
 
 bool build_quiver(int step_cdeg, int min_ring, std::vector<double>& Q) {
     Q.clear();
-    if (step_cdeg <= 0 || 18000 % step_cdeg || min_ring < 1) return false;
+    // steps below 0.2 degrees would give 2^20 vectors or more
+    if (step_cdeg < 20 || 18000 % step_cdeg || min_ring < 1) return false;
     const double D = step_cdeg / 100.0;
     const int n = 36000 / step_cdeg;
     for (int i = 0; i <= 18000 / step_cdeg; ++i) {
@@ -2383,7 +2384,7 @@ msc_status msc_scene_create(msc_ctx* o, int32_t n, int32_t dilate_r, const msc_b
     s->grid = (uint64_t*)dev_grid;
     s->bytes = grid_bytes;
     hipError_t e = hipSuccess;
-    if (nbox * 6 + nsph * 4 <= kRasterInline) {
+    if ((int64_t)nbox * 6 + (int64_t)nsph * 4 <= kRasterInline) {
         // the obstacle lists travel in the kernel's arguments: nothing on the host has to
         // outlive the launch, so the call does not wait for the raster
         RasterInline inl{};

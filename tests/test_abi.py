@@ -92,3 +92,5 @@ def test_library_quiver_equals_the_oracles(step):
     from oracle import gms
     assert np.array_equal(msc.gms_quiver(step), gms.quiver(step))
     assert msc.load_library().msc_gms_quiver(7000, 4, None, 0) == 0
+    assert msc.load_library().msc_gms_quiver(10, 4, None, 0) == 0      # 0.1 degree: too many vectors
+    assert msc.load_library().msc_gms_quiver(20, 4, None, 0) > 10 ** 6
