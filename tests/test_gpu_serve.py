@@ -201,37 +201,33 @@ def test_tickets_and_error_messages(solver):
 
 def test_admission_by_queue_depth(solver):
     """With a queue limit the server refuses submissions (E_CAPACITY, no ticket) while that
-    many wait for a lane; every admitted query completes with the oracle's answer, and a
-    refused one can be submitted again later."""
-    arm = small_arm(4)
-    dyn = serve.make_dyn_scene(5, 64, column=10)
-    scene = solver.scene(dyn.static)
-    occ = oracle.raster(dyn.static)
-    rng = synth.rng_for(9, 3)
-    targets = []
-    for _ in range(6):
-        _, end, _ = synth.first_valid_pose(rng, arm, lambda q: oracle.poses(arm, occ, q))
-        targets.append(end)
+    many wait for a lane; every admitted query completes with the answer it has alone
+    (the parity tests tie those to the oracle), and a refused one can be submitted again.
+    Eight-DOF path queries on one lane keep the queue full while the submissions arrive."""
+    qs = [synth.query_c2(seed, solver.pose_fn_for) for seed in range(4)]
+    scenes = [solver.scene(q.scene) for q in qs]
+    alone = [solver.path(sc, q.arm, q.start, q.target, q.waypoints, q.max_delta) for sc, q in zip(scenes, qs)]
     solver.set_lanes(1)
     solver.server_start()
     try:
         solver.server_set_limit(1)
         admitted, refused = [], []
-        for t in targets * 4:
-            spec = msc.QuerySpec(scene, arm, t)
+        for k in range(16):
+            i = k % len(qs)
+            q = qs[i]
+            spec = msc.QuerySpec(scenes[i], q.arm, q.target, start=q.start, waypoints=q.waypoints, delta=q.max_delta)
             ticket = solver.submit(spec, shed=True)
-            (refused if ticket is None else admitted).append((ticket, spec, t))
-        assert admitted
-        for ticket, spec, t in admitted:
-            st, pose, _ = solver.wait(ticket)
-            r = oracle.reach(arm, occ, t, keep_sets=False)
-            assert st == r.status
+            (refused if ticket is None else admitted).append((ticket, spec, i))
+        say("admitted", len(admitted), "refused", len(refused))
+        assert admitted and refused
+        for ticket, spec, i in admitted:
+            st, path, _ = solver.wait(ticket)
+            assert st == alone[i][0]
             if st == msc.OK:
-                assert np.array_equal(pose, r.pose)
-        if refused:
-            _, spec, t = refused[0]
-            st, pose, _ = solver.wait(solver.submit(spec))
-            assert st == oracle.reach(arm, occ, t, keep_sets=False).status
+                assert np.array_equal(path, alone[i][1])
+        _, spec, i = refused[0]
+        st, path, _ = solver.wait(solver.submit(spec))
+        assert st == alone[i][0]
         assert solver.lib.msc_server_set_limit(solver.ctx, -1) == msc.E_ARG
         solver.server_set_limit(0)
     finally:
