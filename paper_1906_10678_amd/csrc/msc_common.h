@@ -120,6 +120,8 @@ hipError_t launch_expand_fwd(const uint64_t* in, uint64_t count, SetView out, Gr
                              unsigned long long* overflow, hipStream_t st, Shape sh = Shape{});
 // Zeroes every orientation row of a dense set (fast axis = the joint's) that a backward
 // stage from `in` can have written.
+// Zeroes the word of every state of a dense set's member list.
+hipError_t launch_unlist(const uint64_t* list, uint64_t count, SetView s, hipStream_t st);
 hipError_t launch_unexpand_bwd(const uint64_t* in, uint64_t count, SetView out, JointView j, hipStream_t st);
 hipError_t launch_expand_bwd(const uint64_t* in, uint64_t count, SetView out, GridView g, JointView j,
                              int bx, int by, int bz, long long r2, const uint64_t* orows,

@@ -887,6 +887,25 @@ __global__ void __launch_bounds__(kBlock) k_unexpand_bwd(const uint64_t* __restr
     }
 }
 
+// Clearing of a dense set by its own member list: the word of every listed state is set
+// to zero (the list holds every member the set ever had: members are only removed after
+// it was made).
+__global__ void __launch_bounds__(kBlock) k_unlist(const uint64_t* __restrict__ list, uint64_t count, SetView s) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < count;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        int x, y, z, ia, ie;
+        unpack_key(list[i], x, y, z, ia, ie);
+        uint64_t bit;
+        if (ia < s.na && ie < s.na && dense_bit(s, x, y, z, ia, ie, bit)) s.words[bit >> 6] = 0;
+    }
+}
+
+hipError_t launch_unlist(const uint64_t* list, uint64_t count, SetView s, hipStream_t st) {
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_unlist, dim3(grid_for(count, kBlock, 16384)), dim3(kBlock), 0, st, list, count, s);
+    return hipGetLastError();
+}
+
 hipError_t launch_unexpand_bwd(const uint64_t* in, uint64_t count, SetView out, JointView j, hipStream_t st) {
     if (count == 0) return hipSuccess;
     hipLaunchKernelGGL(k_unexpand_bwd, dim3(grid_for(count, kBlock, 16384)), dim3(kBlock), 0, st, in, count, out, j);

@@ -81,7 +81,7 @@ struct StageSet {
     uint64_t count = 0;
     bool listed = false;
     bool used = false;
-    bool at_top = false;   // dense, at the lane window's top (cleared after its last use)
+    bool at_top = false;   // dense, in the lane window's top stack (cleared after its last use)
     bool counted = true;   // false: built without a member count (count is meaningless)
 };
 
@@ -99,10 +99,10 @@ struct Lane {
     char* ws = nullptr;       // this lane's window of the workspace
     uint64_t lo = 0;          // per-call region grows up from 0
     uint64_t hi = 0;          // window size
-    // The set the meet probes may sit at the window's top, [hi - top, hi).  [clean, hi)
-    // is known to hold zeros once the work queued so far has run (clean == hi: nothing
-    // known); the top set is cleared after its last use, so that the next one needs no
-    // fill where it overlaps that region.
+    // Dense stage sets of a reach search are stacked down from the window's top and take
+    // [hi - top, hi).  Below them, [clean, hi - top) is known to hold zeros once the work
+    // queued so far has run.  The stacked sets are cleared after their last use, so the
+    // next search's sets need no fill where they land in that region.
     uint64_t top = 0;
     uint64_t clean = 0;
     std::string err;
@@ -330,7 +330,8 @@ msc_status persist_alloc(Lane* c, uint64_t bytes, void** out) {
 
 void begin_call(Lane* c) {
     c->lo = 0;
-    c->top = 0;   // a top set not released by its call left clean == hi
+    if (c->top) c->clean = c->hi;   // sets left in the top stack by a failed call: nothing known
+    c->top = 0;
     c->staging_used = 0;
     c->next_counter = 0;
     c->err.clear();
@@ -606,19 +607,19 @@ Box stage_box(const Plan& p, int N, const std::vector<int64_t>& R, int k) {
 
 // Allocate and clear the structure of one stage set: a dense bitset over the stage box
 // when it is no larger than a hash table sized for `upper` states, else the hash table.
-// A dense set at the lane window's top (the set the meet probes): only the part of it
-// not known to be clear is filled; it stays dirty (clean = hi) until release_top.
+// A dense set pushed onto the lane window's top stack: only the part of it not known to
+// hold zeros is filled.
 msc_status top_alloc(Lane* c, uint64_t words, uint64_t** out) {
     const uint64_t b = align_up(words * 8);
-    if (c->top) return fail(c, MSC_E_STATE, "a set already sits at the window's top");
-    if (b > c->hi || c->hi - b < c->lo) return fail(c, MSC_E_NOMEM, "workspace exhausted: need %llu more bytes",
-                                                  (unsigned long long)b);
-    const uint64_t base = c->hi - b;
-    if (base < c->clean)
-        LAUNCH(MSC_K_FILL, -1, (int64_t)((c->clean - base) / 8),
-               launch_fill((uint64_t*)(c->ws + base), (c->clean - base) / 8, 0ull, c->stream));
-    c->top = b;
-    c->clean = c->hi;
+    const uint64_t end = c->hi - c->top;   // the stack's current bottom
+    if (b > end || end - b < c->lo)
+        return fail(c, MSC_E_NOMEM, "workspace exhausted: need %llu more bytes", (unsigned long long)b);
+    const uint64_t base = end - b;
+    const uint64_t known = std::min(std::max(c->clean, base), end);   // [known, end) holds zeros
+    if (base < known)
+        LAUNCH(MSC_K_FILL, -1, (int64_t)((known - base) / 8),
+               launch_fill((uint64_t*)(c->ws + base), (known - base) / 8, 0ull, c->stream));
+    c->top += b;
     *out = (uint64_t*)(c->ws + base);
     return MSC_OK;
 }
@@ -820,11 +821,11 @@ msc_status run_reach(Lane* c, const msc_scene* sc, const Plan& p, int want, bool
     int kf = 0, kb = n;
     unsigned long long* ovf = c->ovf;
     // Forward stage k from F_{k-1}'s list into `out`.
-    auto expand_forward = [&](int k, StageSet& out) -> msc_status {
+    auto expand_forward = [&](int k, StageSet& out, bool top) -> msc_status {
         MSC_TRY(ensure_list(c, F[k - 1]));
         uint64_t upper = F[k - 1].count * (uint64_t)(p.hi[k - 1] - p.lo[k - 1] + 1);
         int fast = (k < n && p.type[k] == MSC_YAW) ? 1 : 0;
-        MSC_TRY(make_set(c, p, box[k], upper, fast, false, out));
+        MSC_TRY(make_set(c, p, box[k], upper, fast, false, out, top));
         int64_t rt = 0;
         for (int j = k; j < n; ++j) rt += R[j];
         long long r2 = p.prune ? (long long)(rt * rt) : -1;
@@ -885,7 +886,7 @@ msc_status run_reach(Lane* c, const msc_scene* sc, const Plan& p, int want, bool
             }
         }
         if (forward) {
-            MSC_TRY(expand_forward(kf + 1, F[kf + 1]));
+            MSC_TRY(expand_forward(kf + 1, F[kf + 1], true));
             kf = kf + 1;
             empty = F[kf].count == 0;
             // The step before the meet, checked with the real size: when the meet from F_kf
@@ -905,11 +906,9 @@ msc_status run_reach(Lane* c, const msc_scene* sc, const Plan& p, int want, bool
             int yaw = p.type[k - 1] == MSC_YAW ? 1 : 0;
             // The set the meet probes needs no member count (an empty one simply meets
             // nothing): it is built without one, and without a host round trip, unless
-            // the sets are captured.  It is the largest set of most queries: it sits at
-            // the window's top and is cleared after its last use by the words its stage
-            // can have written, not by a fill of the whole set.
+            // the sets are captured.
             const bool last = p.split == 0 ? k - 1 == 0 : k - 1 - kf == 1;
-            MSC_TRY(make_set(c, p, box[k - 1], upper, yaw, false, B[k - 1], last));
+            MSC_TRY(make_set(c, p, box[k - 1], upper, yaw, false, B[k - 1], true));
             int64_t rb = 0;
             for (int j = 0; j < k - 1; ++j) rb += R[j];
             long long r2 = p.prune ? (long long)(rb * rb) : -1;
@@ -931,21 +930,32 @@ msc_status run_reach(Lane* c, const msc_scene* sc, const Plan& p, int want, bool
             }
         }
     }
-    // Clears the top set B_m once nothing reads it any more, so that the window's top is
-    // clean again: by the words its stage can have written, from the stage's input list
-    // (one state costs about as much as a fill of 8 words), or by a fill when the input
-    // list is longer than an eighth of the set's words.
+    // Clears the stage sets in the window's top stack once nothing reads them any more
+    // (after the canonical walk), so that the top of the window is clean again: a set
+    // built by the backward stage from the words that stage can have written (its input
+    // list), a forward set from its own list (the words of its members), each only when
+    // that list is shorter than an eighth of the set's words (a state costs about as much
+    // as a fill of 8 words), else by a fill.
     auto release_top = [&]() -> msc_status {
-        const int mb = kb;
-        if (!B[mb].at_top) return MSC_OK;
-        if (B[mb + 1].count < B[mb].view.cap / 8)
-            LAUNCH(MSC_K_FILL, mb, (int64_t)B[mb + 1].count,
-                   launch_unexpand_bwd(B[mb + 1].list, B[mb + 1].count, B[mb].view, jv[mb], c->stream));
-        else
-            LAUNCH(MSC_K_FILL, -1, (int64_t)B[mb].view.cap,
-                   launch_fill(B[mb].view.words, B[mb].view.cap, 0ull, c->stream));
-        B[mb].at_top = false;
-        c->clean = c->hi - c->top;
+        for (int k = 0; k <= n; ++k) {
+            StageSet* sets[2] = {&F[k], &B[k]};
+            for (int side = 0; side < 2; ++side) {
+                StageSet& st = *sets[side];
+                if (!st.at_top) continue;
+                const uint64_t cap = st.view.cap;
+                const bool run_rows = side == 1 && k < n && B[k + 1].listed && B[k + 1].count < cap / 8 &&
+                                      ((st.view.fast_ia != 0) == (jv[k].type == MSC_YAW));
+                if (run_rows)
+                    LAUNCH(MSC_K_FILL, k, (int64_t)B[k + 1].count,
+                           launch_unexpand_bwd(B[k + 1].list, B[k + 1].count, st.view, jv[k], c->stream));
+                else if (side == 0 && st.listed && st.count < cap / 8)
+                    LAUNCH(MSC_K_FILL, k, (int64_t)st.count, launch_unlist(st.list, st.count, st.view, c->stream));
+                else
+                    LAUNCH(MSC_K_FILL, -1, (int64_t)cap, launch_fill(st.view.words, cap, 0ull, c->stream));
+                st.at_top = false;
+            }
+        }
+        c->clean = std::min(c->clean, c->hi - c->top);
         c->top = 0;
         return MSC_OK;
     };
@@ -983,7 +993,7 @@ msc_status run_reach(Lane* c, const msc_scene* sc, const Plan& p, int want, bool
         if (capture) {
             // F_m itself is only built for the dump
             StageSet Fm;
-            MSC_TRY(expand_forward(m, Fm));
+            MSC_TRY(expand_forward(m, Fm, false));
             MSC_TRY(capture_set(c, Fm, N, 0, m));
         }
         MSC_TRY(ensure_list(c, F[m - 1]));
@@ -1079,7 +1089,7 @@ msc_status run_reach(Lane* c, const msc_scene* sc, const Plan& p, int want, bool
     da.sols = (int32_t*)d_sols;
     da.nsol = (int32_t*)d_nsol;
     LAUNCH(MSC_K_DFS, -1, 0, launch_dfs(da, c->stream));
-    MSC_TRY(release_top());   // after the canonical walk, the last reader of B_m
+    MSC_TRY(release_top());   // after the canonical walk, the last reader of the sets
     MSC_TRY(check_overflow(c, ovf, "a stage set"));   // synchronises the stream
     int32_t nsol = *(volatile int32_t*)h_nsol;
     if (nsol <= 0) return fail(c, MSC_E_STATE, "join not empty but no pose traced");
