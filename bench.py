@@ -351,7 +351,7 @@ def c4_stages_summary(args):
              "second solve with MSC_COUNT_SETS); HBM bytes from FETCH_SIZE and WRITE_SIZE passes scaled by a "
              "1 GiB device copy (x %.4f, x %.4f); L2 hit rate = TCC_HIT / (TCC_HIT + TCC_MISS) from a third "
              "pass; time from HIP events of the timed solve.  The table lists the launches above 256 MB "
-             "algorithmic (larger than the MALL), where the 50%% target is judged." % (ff, wf), "",
+             "algorithmic (larger than the MALL), the stages that stream from HBM." % (ff, wf), "",
              "```",
              "python -u bench.py --c4-stages-run gpurun_out/c4_times.json --workspace-gb 200",
              "timeout -s KILL 300 rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/c4_fetch -o run "
