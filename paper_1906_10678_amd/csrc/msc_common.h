@@ -286,7 +286,10 @@ struct TubeArgs {
 hipError_t launch_tube_valid(const TubeArgs& a, uint8_t* valid, hipStream_t st);
 // Bit-parallel search in the blocked frame layout: the plan (lds == 0: does not apply),
 // then the launch (validity bits + dynamic program + backward choice in one block).
-// vbits and rbits hold (W + 1) * nw words each.
+// vbits and rbits hold (W + 1) * nw words each.  With A > 1 the launch searches A
+// attempts that differ only in their goal (goals: A * n values, device-readable) at once,
+// one block each: attempt i's frames start (W + 1) * nw * i words into vbits and rbits,
+// its rows (W + 1) * n * i values into path, its status at status[i].
 struct TubeBlk {
     int q, no, b;              // inner joints, outer joints, words per block
     uint32_t Bq, nblk;         // cells per block (B^q), blocks per frame (B^no)
@@ -296,7 +299,7 @@ struct TubeBlk {
 };
 TubeBlk tube_blk_plan(const TubeArgs& a);
 hipError_t launch_tube_bits(const TubeArgs& a, const TubeBlk& t, uint64_t* vbits, uint64_t* rbits, int32_t* path,
-                            int32_t* status, hipStream_t st);
+                            int32_t* status, hipStream_t st, int A = 1, const int32_t* goals = nullptr);
 hipError_t launch_tube_solve(const TubeArgs& a, const uint8_t* valid, uint8_t* reach, uint8_t* tmp0,
                              uint8_t* tmp1, int32_t* path, int32_t* status, hipStream_t st);
 

@@ -2444,8 +2444,8 @@ hipError_t launch_track_batch(const TrackArgs* args, int count, hipStream_t st) 
 // ---------------------------------------------------------------------------
 // 32-bit arithmetic is exact here: W <= 4096 and |goal - start| < 2 * 256 steps, so
 // 2 |w (goal - start)| + W < 2^31 (the host rejects larger W).
-__device__ __forceinline__ int guide_at(const TubeArgs& a, int w, int k) {
-    const int num = w * (a.goal[k] - a.start[k]);
+__device__ __forceinline__ int guide_at(const TubeArgs& a, const int* goal, int w, int k) {
+    const int num = w * (goal[k] - a.start[k]);
     const uint32_t mag = (2u * (uint32_t)(num < 0 ? -num : num) + (uint32_t)a.W) / (2u * (uint32_t)a.W);
     return a.start[k] + (num < 0 ? -(int)mag : (int)mag);
 }
@@ -2457,10 +2457,10 @@ __device__ __forceinline__ int guide_at(const TubeArgs& a, int w, int k) {
 // when every joint is in its range (the start pose at waypoint 0, the reach pose at
 // waypoint W) and the replay of the pose is clear.  Output: bytes, or bits OR-ed into a
 // zeroed bitset (completions of one prefix are consecutive cells).
-__device__ __forceinline__ bool tube_angle(const TubeArgs& a, int w, int k, int d, int& q) {
-    q = guide_at(a, w, k) - a.r + d;
+__device__ __forceinline__ bool tube_angle(const TubeArgs& a, const int* goal, int w, int k, int d, int& q) {
+    q = guide_at(a, goal, w, k) - a.r + d;
     if (w == 0) return q == a.start[k];
-    if (w == a.W) return q == a.goal[k];
+    if (w == a.W) return q == goal[k];
     return q >= a.lim_lo[k] && q <= a.lim_hi[k];
 }
 
@@ -2483,8 +2483,15 @@ __device__ __forceinline__ bool fk_step(const TubeArgs& a, int k, int qk, FkStat
     return ok;
 }
 
-__global__ void k_tube_valid_tree(TubeArgs a, int L, uint8_t* vbytes, uint64_t* vbits, TubeBlk tb) {
+// With `goals` (attempt-major, n values each) the grid's y index is an attempt: its goal
+// replaces a.goal and its frames lie vstride words further in vbits.
+__global__ void k_tube_valid_tree(TubeArgs a, int L, uint8_t* vbytes, uint64_t* vbits, TubeBlk tb,
+                                  const int32_t* goals, uint64_t vstride) {
     const int n = a.n, B = 2 * a.r + 1, np = n - L;
+    __shared__ int goal[kMaxDof];
+    if ((int)threadIdx.x < n) goal[threadIdx.x] = goals ? goals[blockIdx.y * n + threadIdx.x] : a.goal[threadIdx.x];
+    __syncthreads();
+    if (goals) vbits += blockIdx.y * vstride;
     uint32_t P = 1, BL = 1;
     for (int k = 0; k < np; ++k) P *= (uint32_t)B;
     for (int k = 0; k < L; ++k) BL *= (uint32_t)B;
@@ -2501,7 +2508,7 @@ __global__ void k_tube_valid_tree(TubeArgs a, int L, uint8_t* vbytes, uint64_t* 
             const int d = (int)(rest / div);
             rest -= (uint32_t)d * div;
             int qk;
-            ok = tube_angle(a, w, k, d, qk) && fk_step(a, k, qk, s);
+            ok = tube_angle(a, goal, w, k, d, qk) && fk_step(a, k, qk, s);
         }
         uint32_t bits = 0;   // bit l: completion l (BL <= 32)
         if (ok) {
@@ -2511,17 +2518,18 @@ __global__ void k_tube_valid_tree(TubeArgs a, int L, uint8_t* vbytes, uint64_t* 
                 for (int d = 0; d < B; ++d) {
                     FkState t = s;
                     int qk;
-                    if (tube_angle(a, w, n - 1, d, qk) && fk_step(a, n - 1, qk, t)) bits |= 1u << d;
+                    if (tube_angle(a, goal, w, n - 1, d, qk) && fk_step(a, n - 1, qk, t)) bits |= 1u << d;
                 }
             } else {
                 for (int d1 = 0; d1 < B; ++d1) {
                     FkState t = s;
                     int q1;
-                    if (!(tube_angle(a, w, n - 2, d1, q1) && fk_step(a, n - 2, q1, t))) continue;
+                    if (!(tube_angle(a, goal, w, n - 2, d1, q1) && fk_step(a, n - 2, q1, t))) continue;
                     for (int d2 = 0; d2 < B; ++d2) {
                         FkState u = t;
                         int q2;
-                        if (tube_angle(a, w, n - 1, d2, q2) && fk_step(a, n - 1, q2, u)) bits |= 1u << (d1 * B + d2);
+                        if (tube_angle(a, goal, w, n - 1, d2, q2) && fk_step(a, n - 1, q2, u))
+                            bits |= 1u << (d1 * B + d2);
                     }
                 }
             }
@@ -2566,7 +2574,7 @@ uint64_t tube_prefix_threads(const TubeArgs& a, int L) {
 hipError_t launch_tube_valid(const TubeArgs& a, uint8_t* valid, hipStream_t st) {
     const int L = tube_leaf_joints(a);
     hipLaunchKernelGGL(k_tube_valid_tree, dim3(grid_for(tube_prefix_threads(a, L))), dim3(kBlock), 0, st, a, L, valid,
-                       (uint64_t*)nullptr, TubeBlk{});
+                       (uint64_t*)nullptr, TubeBlk{}, (const int32_t*)nullptr, 0ull);
     return hipGetLastError();
 }
 
@@ -2628,7 +2636,7 @@ __device__ void tube_trace_block(const TubeArgs& a, const uint8_t* frame0, const
     const uint32_t span = (uint32_t)(2 * a.delta + 1);
     for (int w = a.W; w >= 1; --w) {
         const uint8_t* R = (w - 1 == 0) ? frame0 : reach + (uint64_t)(w - 1) * slab;
-        if (tid < a.n) flo[tid] = guide_at(a, w - 1, tid) - a.r;
+        if (tid < a.n) flo[tid] = guide_at(a, a.goal, w - 1, tid) - a.r;
         __syncthreads();
         unsigned long long best = ~0ull;
         for (uint32_t t = tid; t < ncand; t += blockDim.x) {
@@ -2718,7 +2726,7 @@ __global__ void __launch_bounds__(kTubeThreads) k_tube_small(TubeArgs a, const u
         for (int k = 0; k < a.n; ++k) {
             const uint8_t* src = (k == 0) ? A : ((k & 1) ? T0 : T1);
             uint8_t* dst = (k == a.n - 1) ? A : ((k & 1) ? T1 : T0);
-            const int shift = guide_at(a, w, k) - guide_at(a, w - 1, k);
+            const int shift = guide_at(a, a.goal, w, k) - guide_at(a, a.goal, w - 1, k);
             // the last pass writes A in place of R_{w-1}: read every source cell of
             // this pass before any thread writes
             constexpr int kPer = (kSmallSlab + kTubeThreads - 1) / kTubeThreads;
@@ -2765,7 +2773,7 @@ __global__ void k_tube_pass(TubeArgs a, int w, int k, const uint8_t* src, uint8_
     const int B = 2 * a.r + 1;
     uint32_t stride = 1;
     for (int j = a.n - 1; j > k; --j) stride *= (uint32_t)B;
-    const int shift = guide_at(a, w, k) - guide_at(a, w - 1, k);
+    const int shift = guide_at(a, a.goal, w, k) - guide_at(a, a.goal, w - 1, k);
     const uint32_t slab = (uint32_t)a.slab;
     for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < slab; c += gridDim.x * blockDim.x) {
         uint8_t any = dilate_cell(src, c, stride, B, shift, a.delta);
@@ -2869,7 +2877,17 @@ __device__ __forceinline__ void shl128(uint64_t x0, uint64_t x1, int s, uint64_t
 
 template <int DL, bool FL>
 __global__ void __launch_bounds__(kBlkThreads) k_tube_blk(TubeArgs a, TubeBlk tb, const uint64_t* vbits,
-                                                          uint64_t* rbits, int32_t* path, int32_t* status) {
+                                                          uint64_t* rbits, int32_t* path, int32_t* status,
+                                                          const int32_t* goals, uint64_t vstride) {
+    // with `goals`, block i searches attempt i: its goal, frames vstride words further,
+    // its own path rows and status
+    if (goals) {
+        const uint64_t att = blockIdx.x;
+        vbits += att * vstride;
+        rbits += att * vstride;
+        path += att * (uint64_t)(a.W + 1) * a.n;
+        status += att;
+    }
     extern __shared__ uint64_t sm[];
     const int n = a.n, B = 2 * a.r + 1, r = a.r, dl = DL > 0 ? DL : a.delta;
     const int no = tb.no, q = tb.q, b = tb.b;
@@ -2912,7 +2930,7 @@ __global__ void __launch_bounds__(kBlkThreads) k_tube_blk(TubeArgs a, TubeBlk tb
     }
     if (tid < n) {
         gstart[tid] = a.start[tid];
-        gdiff[tid] = a.goal[tid] - a.start[tid];
+        gdiff[tid] = (goals ? goals[blockIdx.x * n + tid] : a.goal[tid]) - a.start[tid];
     }
     __syncthreads();
     // inner patterns, one thread per inner cell c: its bit goes into "digit of inner joint
@@ -3128,7 +3146,8 @@ __global__ void __launch_bounds__(kBlkThreads) k_tube_blk(TubeArgs a, TubeBlk tb
 
 template <int DL, bool FL>
 hipError_t launch_tube_blk_dl(const TubeArgs& a, const TubeBlk& t, const uint64_t* vbits, uint64_t* rbits,
-                              int32_t* path, int32_t* status, hipStream_t st) {
+                              int32_t* path, int32_t* status, hipStream_t st, int A, const int32_t* goals,
+                              uint64_t vstride) {
     static std::once_flag once;
     static hipError_t attr = hipSuccess;
     std::call_once(once, [] {
@@ -3138,28 +3157,32 @@ hipError_t launch_tube_blk_dl(const TubeArgs& a, const TubeBlk& t, const uint64_
     if (attr != hipSuccess) return attr;
     // threads: one per block of the frame, rounded to waves (barriers of idle waves cost)
     const uint32_t threads = std::min<uint32_t>(kBlkThreads, std::max<uint32_t>(64u, (t.nblk + 63u) & ~63u));
-    hipLaunchKernelGGL((k_tube_blk<DL, FL>), dim3(1), dim3(threads), t.lds, st, a, t, vbits, rbits, path, status);
+    hipLaunchKernelGGL((k_tube_blk<DL, FL>), dim3(A), dim3(threads), t.lds, st, a, t, vbits, rbits, path, status,
+                       goals, vstride);
     return hipGetLastError();
 }
 
 template <int DL>
 hipError_t launch_tube_blk_dl(const TubeArgs& a, const TubeBlk& t, const uint64_t* vbits, uint64_t* rbits,
-                              int32_t* path, int32_t* status, hipStream_t st) {
-    if (t.frames_lds) return launch_tube_blk_dl<DL, true>(a, t, vbits, rbits, path, status, st);
-    return launch_tube_blk_dl<DL, false>(a, t, vbits, rbits, path, status, st);
+                              int32_t* path, int32_t* status, hipStream_t st, int A, const int32_t* goals,
+                              uint64_t vstride) {
+    if (t.frames_lds) return launch_tube_blk_dl<DL, true>(a, t, vbits, rbits, path, status, st, A, goals, vstride);
+    return launch_tube_blk_dl<DL, false>(a, t, vbits, rbits, path, status, st, A, goals, vstride);
 }
 
 hipError_t launch_tube_bits(const TubeArgs& a, const TubeBlk& t, uint64_t* vbits, uint64_t* rbits, int32_t* path,
-                            int32_t* status, hipStream_t st) {
+                            int32_t* status, hipStream_t st, int A, const int32_t* goals) {
+    if (A < 1 || (A > 1 && !goals) || A > 65535) return hipErrorInvalidValue;
     const int L = std::min(tube_leaf_joints(a), t.q);
-    hipError_t e = launch_fill(vbits, (uint64_t)(a.W + 1) * t.nw, 0ull, st);
+    const uint64_t stride = (uint64_t)(a.W + 1) * t.nw;   // words of one attempt's frames
+    hipError_t e = launch_fill(vbits, (uint64_t)A * stride, 0ull, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_tube_valid_tree, dim3(grid_for(tube_prefix_threads(a, L))), dim3(kBlock), 0, st, a, L,
-                       (uint8_t*)nullptr, vbits, t);
+    hipLaunchKernelGGL(k_tube_valid_tree, dim3(grid_for(tube_prefix_threads(a, L)), A), dim3(kBlock), 0, st, a, L,
+                       (uint8_t*)nullptr, vbits, t, goals, stride);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (a.delta == 1) return launch_tube_blk_dl<1>(a, t, vbits, rbits, path, status, st);
-    if (a.delta == 2) return launch_tube_blk_dl<2>(a, t, vbits, rbits, path, status, st);
-    return launch_tube_blk_dl<0>(a, t, vbits, rbits, path, status, st);
+    if (a.delta == 1) return launch_tube_blk_dl<1>(a, t, vbits, rbits, path, status, st, A, goals, stride);
+    if (a.delta == 2) return launch_tube_blk_dl<2>(a, t, vbits, rbits, path, status, st, A, goals, stride);
+    return launch_tube_blk_dl<0>(a, t, vbits, rbits, path, status, st, A, goals, stride);
 }
 
 hipError_t launch_tube_solve(const TubeArgs& a, const uint8_t* valid, uint8_t* reach, uint8_t* tmp0,

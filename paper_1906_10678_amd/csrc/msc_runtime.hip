@@ -1347,8 +1347,6 @@ msc_status path_on(Lane* c, const msc_scene* sc, const msc_arm* arm, const int32
         for (int k = 0; k < n; ++k) path_out[k] = start[k] * arm->step_cdeg;
         return MSC_OK;
     }
-    std::vector<int32_t> best;
-    int64_t best_cost = -1;
     std::vector<JointView> jv;
     for (int k = 0; k < n; ++k) {
         p.lo[k] = lim_lo[k];
@@ -1357,95 +1355,230 @@ msc_status path_on(Lane* c, const msc_scene* sc, const msc_arm* arm, const int32
     MSC_TRY(joint_views(c, p, jv));
     const uint64_t mark = c->lo;
     const size_t stage_mark = c->staging_used;
-    int radii[2] = {o.tube_r0, o.tube_r1};
-    int nr = o.tube_r1 == o.tube_r0 ? 1 : 2;
-    std::vector<int32_t> path((size_t)(waypoints + 1) * n);
-    for (int i = 0; i < r.nsol; ++i) {
-        for (int ri = 0; ri < nr; ++ri) {
-            c->lo = mark;
-            c->staging_used = stage_mark;
-            const int rad = radii[ri];
-            uint64_t slab = 1;
-            for (int k = 0; k < n; ++k) {
-                slab *= (uint64_t)(2 * rad + 1);
-                if (slab > (1ull << 28)) return fail(c, MSC_E_CAPACITY, "tube of radius %d too large", rad);
+    const int radii[2] = {o.tube_r0, o.tube_r1};
+    const int nr = o.tube_r1 == o.tube_r0 ? 1 : 2;
+    const int nsol = r.nsol;
+    if (nsol < 1) return MSC_NO_PATH;
+    const size_t rows = (size_t)(waypoints + 1) * n;
+    // The attempts in search order: reach pose i at radius index ri is attempt i * nr + ri.
+    // res: -1 not searched, 0 no path, 1 a path (kept in found).
+    std::vector<int8_t> res((size_t)nsol * nr, -1);
+    std::vector<std::vector<int32_t>> found((size_t)nsol * nr);
+    auto tube_args = [&](int rad, int pose, TubeArgs& ta) -> msc_status {
+        uint64_t slab = 1;
+        for (int k = 0; k < n; ++k) {
+            slab *= (uint64_t)(2 * rad + 1);
+            if (slab > (1ull << 28)) return fail(c, MSC_E_CAPACITY, "tube of radius %d too large", rad);
+        }
+        ta = TubeArgs{};
+        for (int k = 0; k < n; ++k) ta.joints[k] = jv[k];
+        ta.g = grid_view(sc);
+        ta.n = n;
+        ta.na = p.na;
+        ta.bx = p.base[0];
+        ta.by = p.base[1];
+        ta.bz = p.base[2];
+        ta.ia0 = p.ia0;
+        ta.ie0 = p.ie0;
+        ta.W = waypoints;
+        ta.delta = delta;
+        ta.r = rad;
+        for (int k = 0; k < n; ++k) {
+            ta.start[k] = start[k];
+            ta.goal[k] = r.sols[(size_t)pose * n + k];
+            ta.lim_lo[k] = lim_lo[k];
+            ta.lim_hi[k] = lim_hi[k];
+        }
+        ta.slab = slab;
+        return MSC_OK;
+    };
+    // A group of attempts: the tubes toward the reach poses `poses` at radius index ri.
+    // In the blocked layout the attempts of a group differ only in their goal, so they
+    // run at once, one block each; each is the search a lone attempt would make.
+    struct Group {
+        int ri = 0;
+        std::vector<int> poses;
+        int32_t* h_path = nullptr;
+        int32_t* h_status = nullptr;
+    };
+    // Launches a group (ok = false, nothing allocated, when a group of several attempts
+    // does not fit the lane's workspace or staging buffer).
+    auto launch_group = [&](Group& gr, bool& ok) -> msc_status {
+        ok = true;
+        const int rad = radii[gr.ri];
+        const int A = (int)gr.poses.size();
+        TubeArgs ta;
+        MSC_TRY(tube_args(rad, gr.poses[0], ta));
+        const TubeBlk tb = tube_blk_plan(ta);
+        const uint64_t words = (uint64_t)(waypoints + 1) * tb.nw;   // one attempt's frames
+        if (A > 1) {
+            const size_t host = 4 * 256 + (size_t)A * (rows * 4 + 4 + 2 * (size_t)n * 4);
+            ok = tb.lds && 2 * words * 8 * (uint64_t)A + ((uint64_t)A * n * 4 + 4096) <= free_bytes(c) &&
+                 c->staging_used + host + 4096 <= kStagingBytes;
+            if (!ok) return MSC_OK;
+        }
+        void *h_path, *d_path, *h_status, *d_status;
+        MSC_TRY(host_area(c, (size_t)A * rows * 4, &h_path, &d_path));
+        MSC_TRY(host_area(c, (size_t)A * 4, &h_status, &d_status));
+        gr.h_path = (int32_t*)h_path;
+        gr.h_status = (int32_t*)h_status;
+        for (int i = 0; i < A; ++i) ((volatile int32_t*)h_status)[i] = 0;
+        const uint64_t cells = (uint64_t)(waypoints + 1) * ta.slab;
+        if (tb.lds) {
+            // frames that fit LDS: bit-parallel search in one block per attempt
+            const int32_t* d_goals = nullptr;
+            if (A > 1) {
+                std::vector<int32_t> goals((size_t)A * n);
+                for (int i = 0; i < A; ++i)
+                    for (int k = 0; k < n; ++k) goals[(size_t)i * n + k] = r.sols[(size_t)gr.poses[i] * n + k];
+                void* dg;
+                MSC_TRY(upload(c, goals.data(), goals.size() * 4, &dg));
+                d_goals = (const int32_t*)dg;
             }
-            TubeArgs ta{};
-            for (int k = 0; k < n; ++k) ta.joints[k] = jv[k];
-            ta.g = grid_view(sc);
-            ta.n = n;
-            ta.na = p.na;
-            ta.bx = p.base[0];
-            ta.by = p.base[1];
-            ta.bz = p.base[2];
-            ta.ia0 = p.ia0;
-            ta.ie0 = p.ie0;
-            ta.W = waypoints;
-            ta.delta = delta;
-            ta.r = rad;
-            for (int k = 0; k < n; ++k) {
-                ta.start[k] = start[k];
-                ta.goal[k] = r.sols[(size_t)i * n + k];
-                ta.lim_lo[k] = lim_lo[k];
-                ta.lim_hi[k] = lim_hi[k];
+            void *d_vbits, *d_rbits;
+            MSC_TRY(arena_alloc(c, words * 8 * (uint64_t)A, &d_vbits));
+            MSC_TRY(arena_alloc(c, words * 8 * (uint64_t)A, &d_rbits));
+            LAUNCH(MSC_K_TUBE_SOLVE, rad, (int64_t)cells * A,
+                   launch_tube_bits(ta, tb, (uint64_t*)d_vbits, (uint64_t*)d_rbits, (int32_t*)d_path,
+                                    (int32_t*)d_status, c->stream, A, d_goals));
+        } else {
+            void *d_valid, *d_reach, *d_t0, *d_t1;
+            MSC_TRY(arena_alloc(c, cells, &d_valid));
+            MSC_TRY(arena_alloc(c, cells, &d_reach));
+            MSC_TRY(arena_alloc(c, ta.slab, &d_t0));
+            MSC_TRY(arena_alloc(c, ta.slab, &d_t1));
+            LAUNCH(MSC_K_TUBE_VALID, rad, (int64_t)cells, launch_tube_valid(ta, (uint8_t*)d_valid, c->stream));
+            LAUNCH(MSC_K_TUBE_SOLVE, rad, (int64_t)cells,
+                   launch_tube_solve(ta, (const uint8_t*)d_valid, (uint8_t*)d_reach, (uint8_t*)d_t0,
+                                     (uint8_t*)d_t1, (int32_t*)d_path, (int32_t*)d_status, c->stream));
+        }
+        return MSC_OK;
+    };
+    auto collect = [&](const Group& gr) {
+        for (size_t i = 0; i < gr.poses.size(); ++i) {
+            const size_t at = (size_t)gr.poses[i] * nr + gr.ri;
+            res[at] = ((volatile int32_t*)gr.h_status)[i] ? 1 : 0;
+            if (res[at]) {
+                const int32_t* src = gr.h_path + i * rows;
+                found[at].assign(src, src + rows);
             }
-            ta.slab = slab;
-            void *h_path, *d_path, *h_status, *d_status;
-            uint64_t cells = (uint64_t)(waypoints + 1) * slab;
-            MSC_TRY(host_area(c, path.size() * 4, &h_path, &d_path));
-            MSC_TRY(host_area(c, 4, &h_status, &d_status));
-            *(volatile int32_t*)h_status = 0;
-            const TubeBlk tb = tube_blk_plan(ta);
-            if (tb.lds) {
-                // frames that fit LDS: bit-parallel search in one block
-                void *d_vbits, *d_rbits;
-                const uint64_t words = (uint64_t)(waypoints + 1) * tb.nw;
-                MSC_TRY(arena_alloc(c, words * 8, &d_vbits));
-                MSC_TRY(arena_alloc(c, words * 8, &d_rbits));
-                LAUNCH(MSC_K_TUBE_SOLVE, rad, (int64_t)cells,
-                       launch_tube_bits(ta, tb, (uint64_t*)d_vbits, (uint64_t*)d_rbits, (int32_t*)d_path,
-                                        (int32_t*)d_status, c->stream));
-            } else {
-                void *d_valid, *d_reach, *d_t0, *d_t1;
-                MSC_TRY(arena_alloc(c, cells, &d_valid));
-                MSC_TRY(arena_alloc(c, cells, &d_reach));
-                MSC_TRY(arena_alloc(c, slab, &d_t0));
-                MSC_TRY(arena_alloc(c, slab, &d_t1));
-                LAUNCH(MSC_K_TUBE_VALID, rad, (int64_t)cells, launch_tube_valid(ta, (uint8_t*)d_valid, c->stream));
-                LAUNCH(MSC_K_TUBE_SOLVE, rad, (int64_t)cells,
-                       launch_tube_solve(ta, (const uint8_t*)d_valid, (uint8_t*)d_reach, (uint8_t*)d_t0,
-                                         (uint8_t*)d_t1, (int32_t*)d_path, (int32_t*)d_status, c->stream));
-            }
-            MSC_TRY(sync_lane(c));
-            int32_t ok2 = *(volatile int32_t*)h_status;
-            c->stats.attempts++;
-            if (ok2) {
-                std::memcpy(path.data(), h_path, path.size() * 4);
-                if (ref.empty()) {
-                    for (size_t j = 0; j < path.size(); ++j) path_out[j] = path[j] * arm->step_cdeg;
-                    c->stats.tube_r = rad;
-                    c->stats.reach_index = i;
-                    return MSC_OK;
-                }
-                // replanning: the sum over the waypoints of the L1 distance (steps) to the
-                // original path; the earlier reach pose keeps a tie
-                int64_t cost = 0;
-                for (size_t j = 0; j < path.size(); ++j) cost += std::abs((int64_t)path[j] - ref[j]);
-                if (best_cost < 0 || cost < best_cost) {
-                    best = path;
-                    best_cost = cost;
-                    c->stats.tube_r = rad;
-                    c->stats.reach_index = i;
-                }
+        }
+    };
+    // Runs the groups of one phase together (one wait for all); when they do not all fit,
+    // their attempts one at a time, as lone attempts.
+    auto phase = [&](std::vector<Group> groups) -> msc_status {
+        c->lo = mark;
+        c->staging_used = stage_mark;
+        bool all = true;
+        for (Group& gr : groups) {
+            if (gr.poses.empty()) continue;
+            bool ok;
+            MSC_TRY(launch_group(gr, ok));
+            if (!ok) {
+                all = false;
                 break;
             }
         }
-    }
-    if (best_cost >= 0) {
-        for (size_t j = 0; j < best.size(); ++j) path_out[j] = best[j] * arm->step_cdeg;
+        if (all) {
+            MSC_TRY(sync_lane(c));
+            for (const Group& gr : groups)
+                if (!gr.poses.empty()) collect(gr);
+            return MSC_OK;
+        }
+        MSC_TRY(sync_lane(c));   // what was launched ends before its buffers are reused
+        for (const Group& gr : groups)
+            for (int pose : gr.poses) {
+                c->lo = mark;
+                c->staging_used = stage_mark;
+                Group one;
+                one.ri = gr.ri;
+                one.poses = {pose};
+                bool ok;
+                MSC_TRY(launch_group(one, ok));
+                MSC_TRY(sync_lane(c));
+                collect(one);
+            }
+        return MSC_OK;
+    };
+    auto group = [](int ri, std::vector<int> poses) {
+        Group g;
+        g.ri = ri;
+        g.poses = std::move(poses);
+        return g;
+    };
+    auto succeeded = [&](int pose, int ri) { return res[(size_t)pose * nr + ri] == 1; };
+    int win_pose = -1, win_ri = -1;
+    if (ref.empty()) {
+        // The first path in search order.  The first attempt runs alone; when it fails,
+        // the other poses' first radius and the first pose's second radius run together,
+        // then the second radius of the poses before the first pose that had a path.
+        MSC_TRY(phase({group(0, {0})}));
+        if (!succeeded(0, 0) && (nsol > 1 || nr > 1)) {
+            std::vector<int> rest;
+            for (int i = 1; i < nsol; ++i) rest.push_back(i);
+            std::vector<Group> ga{group(0, rest)};
+            if (nr > 1) ga.push_back(group(1, {0}));
+            MSC_TRY(phase(ga));
+            if (nr > 1 && !succeeded(0, 1)) {
+                std::vector<int> second;
+                for (int i = 1; i < nsol && !succeeded(i, 0); ++i) second.push_back(i);
+                MSC_TRY(phase({group(1, second)}));
+            }
+        }
+        int tried = 0;
+        for (int i = 0; i < nsol && win_pose < 0; ++i)
+            for (int ri = 0; ri < nr; ++ri) {
+                ++tried;
+                if (succeeded(i, ri)) {
+                    win_pose = i;
+                    win_ri = ri;
+                    break;
+                }
+            }
+        c->stats.attempts = tried;
+        if (win_pose < 0) return MSC_NO_PATH;
+        const std::vector<int32_t>& path = found[(size_t)win_pose * nr + win_ri];
+        for (size_t j = 0; j < path.size(); ++j) path_out[j] = path[j] * arm->step_cdeg;
+        c->stats.tube_r = radii[win_ri];
+        c->stats.reach_index = win_pose;
         return MSC_OK;
     }
-    return MSC_NO_PATH;
+    // Replanning: every reach pose is tried (its first radius with a path counts) and the
+    // path nearest the original one is kept, by the sum over the waypoints of the L1
+    // distance (steps); the earlier reach pose keeps a tie.  All first radii run together,
+    // then the second radius of the poses that had none.
+    std::vector<int> all, second;
+    for (int i = 0; i < nsol; ++i) all.push_back(i);
+    MSC_TRY(phase({group(0, all)}));
+    if (nr > 1) {
+        for (int i = 0; i < nsol; ++i)
+            if (!succeeded(i, 0)) second.push_back(i);
+        MSC_TRY(phase({group(1, second)}));
+    }
+    int64_t best_cost = -1;
+    int tried = 0;
+    for (int i = 0; i < nsol; ++i) {
+        for (int ri = 0; ri < nr; ++ri) {
+            ++tried;
+            if (!succeeded(i, ri)) continue;
+            const std::vector<int32_t>& path = found[(size_t)i * nr + ri];
+            int64_t cost = 0;
+            for (size_t j = 0; j < path.size(); ++j) cost += std::abs((int64_t)path[j] - ref[j]);
+            if (best_cost < 0 || cost < best_cost) {
+                best_cost = cost;
+                win_pose = i;
+                win_ri = ri;
+            }
+            break;
+        }
+    }
+    c->stats.attempts = tried;
+    if (win_pose < 0) return MSC_NO_PATH;
+    const std::vector<int32_t>& best = found[(size_t)win_pose * nr + win_ri];
+    for (size_t j = 0; j < best.size(); ++j) path_out[j] = best[j] * arm->step_cdeg;
+    c->stats.tube_r = radii[win_ri];
+    c->stats.reach_index = win_pose;
+    return MSC_OK;
 }
 
 // ---------------------------------------------------------------------------
