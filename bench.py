@@ -283,6 +283,18 @@ def c4_stages_run(args):
     print("c4 stages run done", len(plans), flush=True)
 
 
+def calibration_copies(dispatches):
+    """Dispatch ids of the three 1 GiB calibration copies among (id, kernel name, grid
+    size): the copy dispatches of the largest grid (the library's own small uploads and
+    the set captures are copies too)."""
+    copies = [(i, g) for i, name, g in dispatches if "copyBuffer" in name]
+    top = max(g for _, g in copies)
+    ids = sorted({i for i, g in copies if g == top})
+    if len(ids) != 3:
+        raise RuntimeError("expected three calibration copies, found %d" % len(ids))
+    return ids
+
+
 def c4_stages_summary(args):
     """Per expansion launch of the six full-size plans: algorithmic bytes (8 x (input
     states read from the list + non-zero words of the output structure)), HBM bytes (two
@@ -298,16 +310,16 @@ def c4_stages_summary(args):
     def dispatches(path, counters):
         """Counter values of the timed runs' dispatches after the calibration copies:
         [(kernel name, {counter: value})] in dispatch order."""
-        by_id = {}
+        by_id, grid = {}, {}
         for r in csv.DictReader(open(path)):
             if r["Counter_Name"] in counters:
                 d = by_id.setdefault(int(r["Dispatch_Id"]), [r["Kernel_Name"], {}])
                 d[1][r["Counter_Name"]] = d[1].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+                grid[int(r["Dispatch_Id"])] = int(r["Grid_Size"])
         ids = sorted(by_id)
-        copies = [i for i in ids if "copyBuffer" in by_id[i][0]]
-        last = max(copies)
-        cal = [by_id[i][1] for i in copies if i > last - 3]
-        return cal, [by_id[i] for i in ids if i > last]
+        cal_ids = calibration_copies([(i, by_id[i][0], grid[i]) for i in ids])
+        last = max(cal_ids)
+        return [by_id[i][1] for i in cal_ids], [by_id[i] for i in ids if i > last]
 
     def set_kernels(rows):
         return [(name, v) for name, v in rows
@@ -414,9 +426,9 @@ def traffic_summary(args):
     def per_kernel(path, counter):
         rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
         rows.sort(key=lambda r: int(r["Dispatch_Id"]))
-        copies = [r for r in rows if "copyBuffer" in r["Kernel_Name"]]
-        last = max(int(r["Dispatch_Id"]) for r in copies)
-        cal = [float(r["Counter_Value"]) for r in copies if int(r["Dispatch_Id"]) > last - 3]
+        cal_ids = calibration_copies([(int(r["Dispatch_Id"]), r["Kernel_Name"], int(r["Grid_Size"])) for r in rows])
+        last = max(cal_ids)
+        cal = [float(r["Counter_Value"]) for r in rows if int(r["Dispatch_Id"]) in cal_ids]
         per = collections.defaultdict(lambda: [0.0, 0])
         for r in rows:
             if int(r["Dispatch_Id"]) > last:
