@@ -1404,6 +1404,7 @@ msc_status path_on(Lane* c, const msc_scene* sc, const msc_arm* arm, const int32
     // Launches a group (ok = false, nothing allocated, when a group of several attempts
     // does not fit the lane's workspace or staging buffer).
     auto launch_group = [&](Group& gr, bool& ok) -> msc_status {
+        const hipStream_t stream = c->stream;
         ok = true;
         const int rad = radii[gr.ri];
         const int A = (int)gr.poses.size();
@@ -1431,8 +1432,11 @@ msc_status path_on(Lane* c, const msc_scene* sc, const msc_arm* arm, const int32
                 std::vector<int32_t> goals((size_t)A * n);
                 for (int i = 0; i < A; ++i)
                     for (int k = 0; k < n; ++k) goals[(size_t)i * n + k] = r.sols[(size_t)gr.poses[i] * n + k];
-                void* dg;
-                MSC_TRY(upload(c, goals.data(), goals.size() * 4, &dg));
+                void *hg, *hgd, *dg;
+                MSC_TRY(host_area(c, goals.size() * 4, &hg, &hgd));
+                std::memcpy(hg, goals.data(), goals.size() * 4);
+                MSC_TRY(arena_alloc(c, goals.size() * 4, &dg));
+                HIP_TRY(hipMemcpyAsync(dg, hg, goals.size() * 4, hipMemcpyHostToDevice, stream));
                 d_goals = (const int32_t*)dg;
             }
             void *d_vbits, *d_rbits;
@@ -1440,17 +1444,17 @@ msc_status path_on(Lane* c, const msc_scene* sc, const msc_arm* arm, const int32
             MSC_TRY(arena_alloc(c, words * 8 * (uint64_t)A, &d_rbits));
             LAUNCH(MSC_K_TUBE_SOLVE, rad, (int64_t)cells * A,
                    launch_tube_bits(ta, tb, (uint64_t*)d_vbits, (uint64_t*)d_rbits, (int32_t*)d_path,
-                                    (int32_t*)d_status, c->stream, A, d_goals));
+                                    (int32_t*)d_status, stream, A, d_goals));
         } else {
             void *d_valid, *d_reach, *d_t0, *d_t1;
             MSC_TRY(arena_alloc(c, cells, &d_valid));
             MSC_TRY(arena_alloc(c, cells, &d_reach));
             MSC_TRY(arena_alloc(c, ta.slab, &d_t0));
             MSC_TRY(arena_alloc(c, ta.slab, &d_t1));
-            LAUNCH(MSC_K_TUBE_VALID, rad, (int64_t)cells, launch_tube_valid(ta, (uint8_t*)d_valid, c->stream));
+            LAUNCH(MSC_K_TUBE_VALID, rad, (int64_t)cells, launch_tube_valid(ta, (uint8_t*)d_valid, stream));
             LAUNCH(MSC_K_TUBE_SOLVE, rad, (int64_t)cells,
                    launch_tube_solve(ta, (const uint8_t*)d_valid, (uint8_t*)d_reach, (uint8_t*)d_t0,
-                                     (uint8_t*)d_t1, (int32_t*)d_path, (int32_t*)d_status, c->stream));
+                                     (uint8_t*)d_t1, (int32_t*)d_path, (int32_t*)d_status, stream));
         }
         return MSC_OK;
     };
@@ -1464,34 +1468,28 @@ msc_status path_on(Lane* c, const msc_scene* sc, const msc_arm* arm, const int32
             }
         }
     };
-    // Runs the groups of one phase together (one wait for all); when they do not all fit,
-    // their attempts one at a time, as lone attempts.
+    // Runs the groups of one phase on the lane's stream with one wait for all (a second
+    // stream per lane would share the few hardware queues with the other lanes' streams);
+    // when the groups do not all fit, their attempts one at a time, as lone attempts.
     auto phase = [&](std::vector<Group> groups) -> msc_status {
         c->lo = mark;
         c->staging_used = stage_mark;
+        std::vector<Group*> live;
+        for (Group& gr : groups)
+            if (!gr.poses.empty()) live.push_back(&gr);
         bool all = true;
-        for (Group& gr : groups) {
-            if (gr.poses.empty()) continue;
-            bool ok;
-            MSC_TRY(launch_group(gr, ok));
-            if (!ok) {
-                all = false;
-                break;
-            }
-        }
+        for (size_t g = 0; g < live.size() && all; ++g) MSC_TRY(launch_group(*live[g], all));
+        MSC_TRY(sync_lane(c));   // also what was launched before a group did not fit
         if (all) {
-            MSC_TRY(sync_lane(c));
-            for (const Group& gr : groups)
-                if (!gr.poses.empty()) collect(gr);
+            for (Group* gr : live) collect(*gr);
             return MSC_OK;
         }
-        MSC_TRY(sync_lane(c));   // what was launched ends before its buffers are reused
-        for (const Group& gr : groups)
-            for (int pose : gr.poses) {
+        for (Group* gr : live)
+            for (int pose : gr->poses) {
                 c->lo = mark;
                 c->staging_used = stage_mark;
                 Group one;
-                one.ri = gr.ri;
+                one.ri = gr->ri;
                 one.poses = {pose};
                 bool ok;
                 MSC_TRY(launch_group(one, ok));
@@ -1508,18 +1506,23 @@ msc_status path_on(Lane* c, const msc_scene* sc, const msc_arm* arm, const int32
     };
     auto succeeded = [&](int pose, int ri) { return res[(size_t)pose * nr + ri] == 1; };
     int win_pose = -1, win_ri = -1;
+    // A lone query on the control lane has the device to itself: after a failed first
+    // attempt every other attempt is searched in one phase.  A worker lane shares the
+    // device with the other lanes, so it runs no more attempts than the search order can
+    // need: the first radius of the other poses and the first pose's second radius, then
+    // the second radius of the poses before the first pose whose first radius gave a path.
+    const bool eager = c == c->owner->control;
+    std::vector<int> rest, every;
+    for (int i = 1; i < nsol; ++i) rest.push_back(i);
+    for (int i = 0; i < nsol; ++i) every.push_back(i);
     if (ref.empty()) {
-        // The first path in search order.  The first attempt runs alone; when it fails,
-        // the other poses' first radius and the first pose's second radius run together,
-        // then the second radius of the poses before the first pose that had a path.
+        // the first path in search order
         MSC_TRY(phase({group(0, {0})}));
         if (!succeeded(0, 0) && (nsol > 1 || nr > 1)) {
-            std::vector<int> rest;
-            for (int i = 1; i < nsol; ++i) rest.push_back(i);
             std::vector<Group> ga{group(0, rest)};
-            if (nr > 1) ga.push_back(group(1, {0}));
+            if (nr > 1) ga.push_back(group(1, eager ? every : std::vector<int>{0}));
             MSC_TRY(phase(ga));
-            if (nr > 1 && !succeeded(0, 1)) {
+            if (!eager && nr > 1 && !succeeded(0, 1)) {
                 std::vector<int> second;
                 for (int i = 1; i < nsol && !succeeded(i, 0); ++i) second.push_back(i);
                 MSC_TRY(phase({group(1, second)}));
@@ -1545,12 +1548,14 @@ msc_status path_on(Lane* c, const msc_scene* sc, const msc_arm* arm, const int32
     }
     // Replanning: every reach pose is tried (its first radius with a path counts) and the
     // path nearest the original one is kept, by the sum over the waypoints of the L1
-    // distance (steps); the earlier reach pose keeps a tie.  All first radii run together,
-    // then the second radius of the poses that had none.
-    std::vector<int> all, second;
-    for (int i = 0; i < nsol; ++i) all.push_back(i);
-    MSC_TRY(phase({group(0, all)}));
-    if (nr > 1) {
+    // distance (steps); the earlier reach pose keeps a tie.  The first radius of every pose
+    // is searched in one phase, with (control lane) or before (worker lane, only where it
+    // is needed) the second radius.
+    std::vector<Group> ga{group(0, every)};
+    if (nr > 1 && eager) ga.push_back(group(1, every));
+    MSC_TRY(phase(ga));
+    if (nr > 1 && !eager) {
+        std::vector<int> second;
         for (int i = 0; i < nsol; ++i)
             if (!succeeded(i, 0)) second.push_back(i);
         MSC_TRY(phase({group(1, second)}));

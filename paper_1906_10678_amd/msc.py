@@ -629,12 +629,13 @@ class Solver:
     def lane_bytes(self) -> int:
         return int(self.lib.msc_lane_bytes(self.ctx))
 
-    def batch(self, specs, split_m: int = -1, flags: int = 0, approach=None):
+    def batch(self, specs, split_m: int = -1, flags: int = 0, approach=None, tube_r0: int = 1, tube_r1: int = 2,
+              retries: int = 4):
         """Solve QuerySpecs with msc_batch; returns their results."""
         arr = (MscQuery * max(1, len(specs)))()
         for i, sp in enumerate(specs):
             arr[i] = sp.c
-        o = make_opts(split_m=split_m, flags=flags, approach=approach)
+        o = make_opts(split_m, tube_r0, tube_r1, retries, flags, approach)
         self._check(self.lib.msc_batch(self.ctx, arr, len(specs), ctypes.byref(o)), "msc_batch")
         for i, sp in enumerate(specs):
             sp.c.status = arr[i].status

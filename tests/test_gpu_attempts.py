@@ -51,10 +51,12 @@ def retry_scene(seed):
 def test_first_path_in_search_order(solver, seed):
     arm, occ, start, target, W = retry_case(seed)
     scene = solver.scene(retry_scene(seed))
-    for r0, r1, retries in ((0, 1, 4), (0, 0, 6), (0, 2, 8)):
-        say("attempts", seed, r0, r1, retries)
+    # PROFILE times every launch of the groups of attempts
+    for r0, r1, retries, flags in ((0, 1, 4, 0), (0, 1, 4, msc.PROFILE), (0, 0, 6, 0), (0, 2, 8, 0)):
+        say("attempts", seed, r0, r1, retries, flags)
         res, tries = one_at_a_time(arm, occ, start, target, W, r0, r1, retries)
-        st, path = solver.path(scene, arm, start, target, W, 1, tube_r0=r0, tube_r1=r1, retries=retries)
+        st, path = solver.path(scene, arm, start, target, W, 1, tube_r0=r0, tube_r1=r1, retries=retries,
+                               flags=flags)
         if res.status != oracle.OK:
             assert st == msc.NO_REACH
             continue
@@ -95,3 +97,24 @@ def test_cases_exercise_later_attempts():
         if res.status == oracle.OK and (tries[0][2] is None):
             later += 1
     assert later >= 3, later
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("lanes", [0, 3])
+def test_batched_attempts(solver, lanes):
+    """The same order on worker lanes (no more attempts than the order can need) and on
+    the control lane of a batch (every attempt after a failed first one)."""
+    say("batched attempts, lanes", lanes)
+    cases = [retry_case(seed) for seed in SEEDS]
+    specs = [msc.QuerySpec(solver.scene(retry_scene(seed)), arm, target, start=start, waypoints=W, delta=1)
+             for seed, (arm, occ, start, target, W) in zip(SEEDS, cases)]
+    solver.set_lanes(lanes)
+    try:
+        got = solver.batch(specs, tube_r0=0, tube_r1=1, retries=4)
+    finally:
+        solver.set_lanes(0)
+    for (arm, occ, start, target, W), (st, path, _lat) in zip(cases, got):
+        rst, rpath, _ = oracle.plan_path(arm, occ, start, target, W, 1, r0=0, r1=1, retries=4)
+        assert st == rst
+        if st == msc.OK:
+            assert np.array_equal(path, rpath)
