@@ -1549,12 +1549,11 @@ msc_status path_on(Lane* c, const msc_scene* sc, const msc_arm* arm, const int32
     // Replanning: every reach pose is tried (its first radius with a path counts) and the
     // path nearest the original one is kept, by the sum over the waypoints of the L1
     // distance (steps); the earlier reach pose keeps a tie.  The first radius of every pose
-    // is searched in one phase, with (control lane) or before (worker lane, only where it
-    // is needed) the second radius.
-    std::vector<Group> ga{group(0, every)};
-    if (nr > 1 && eager) ga.push_back(group(1, every));
-    MSC_TRY(phase(ga));
-    if (nr > 1 && !eager) {
+    // is searched in one phase, then the second radius of the poses where it is needed
+    // (on any lane: most poses have a path at the first radius, and the second radius
+    // costs several times as much).
+    MSC_TRY(phase({group(0, every)}));
+    if (nr > 1) {
         std::vector<int> second;
         for (int i = 0; i < nsol; ++i)
             if (!succeeded(i, 0)) second.push_back(i);
