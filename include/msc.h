@@ -177,7 +177,10 @@ msc_status msc_reach(msc_ctx* ctx, const msc_scene* scene, const msc_arm* arm,
  * every joint by at most max_delta_cdeg, chosen backward from the reach pose (closest
  * to the guide, L1 in steps, ties by joint values); the tube radius is relaxed from
  * tube_r0 to tube_r1 after a failure, then the next reach pose is tried, up to
- * reach_retries.  path_out receives (waypoints+1)*dof centidegrees, row 0 = start,
+ * reach_retries; the path returned is that of the first attempt in this order that has
+ * one (after a failed first attempt, later attempts are searched in groups, one launch
+ * per radius, which changes no answer).  path_out receives (waypoints+1)*dof
+ * centidegrees, row 0 = start,
  * last row = reach pose.  max_delta_cdeg must be a positive multiple of step_cdeg.
  * Returns MSC_NO_REACH or MSC_NO_PATH when no result exists. */
 msc_status msc_path(msc_ctx* ctx, const msc_scene* scene, const msc_arm* arm,
@@ -510,7 +513,9 @@ typedef struct {
     int64_t join_count;                  /* |C_m|; -1 when C_m was not built (split >= 1 without MSC_CAPTURE_SETS) */
     int32_t fwd_dense[MSC_MAX_DOF + 1];  /* 1 if F_k used a dense bitset, 0 if a hash set */
     int32_t bwd_dense[MSC_MAX_DOF + 1];
-    int32_t attempts;                    /* path: tube searches run */
+    int32_t attempts;                    /* path: (reach pose, radius) attempts in search order up to
+                                            the returned one, all of them without a path (the
+                                            library may have searched more at the same time) */
     int32_t tube_r;                      /* path: tube radius of the returned path */
     int32_t reach_index;                 /* path: index of the reach pose used (0 = first) */
 } msc_stats;
