@@ -91,6 +91,7 @@ def test_walk_stays_put_when_every_move_is_refused():
     arm = synth.arm_c2()
     rng = synth.rng_for(98)
     start = synth.candidate_poses(rng, arm, 1)[0]
+
     def only_start(q):
         q = np.asarray(q)
         ok = np.all(q == start, axis=1)
